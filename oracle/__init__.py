@@ -1,0 +1,263 @@
+"""CPU oracle for the multi-RHS AMG-Krylov solve (TEST INFRASTRUCTURE ONLY).
+
+Only the tests, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never loads it and
+shares no code with it.  The arithmetic lives in ``oracle.c`` (plain FP64 C,
+see its header for the definitions followed); this module is argument
+marshalling through ctypes plus small NumPy helpers.
+
+Functions with no independent pin: none in the solve path; the Chebyshev
+interval constants and the Lanczos start vector are readings (not fixed by
+the paper) and are checked only for their stated properties.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EBREAKDOWN = 0, 1, -1, -2, -5
+CG, BICGSTAB = 0, 1
+JACOBI, CHEBYSHEV = 0, 1
+A_, P_, R_ = 0, 1, 2
+
+
+def build(force=True):
+    """Compile oracle.c into liboracle.so (gcc, OpenMP over row loops)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_c_int, _c_dbl, _vp = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.orc_build.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _c_int,
+                                _c_int, _c_int, ctypes.POINTER(_vp)]
+        L.orc_hier_free.argtypes = [_vp]
+        L.orc_hier_nlev.argtypes = [_vp]
+        L.orc_hier_info.argtypes = [_vp, _c_int, _c_int, _i32p]
+        L.orc_hier_copy.argtypes = [_vp, _c_int, _c_int, _i32p, _i32p, _f64p]
+        L.orc_hier_cf.argtypes = [_vp, _c_int, _i32p]
+        L.orc_hier_lmax.argtypes = [_vp, _c_int]
+        L.orc_hier_lmax.restype = _c_dbl
+        L.orc_vcycle.argtypes = [_vp, _c_int, _c_dbl, _c_int, _c_dbl, _c_dbl,
+                                 _c_int, _f64p, _f64p]
+        L.orc_solve.argtypes = [_vp, _c_int, _c_int, _c_dbl, _c_int, _c_dbl,
+                                _c_dbl, _c_int, _c_int, _c_int, _c_dbl, _c_int,
+                                _c_int, _f64p, _f64p, _i32p, _f64p, _f64p, _i32p]
+        L.orc_spmm.argtypes = [_c_int, _c_int, _i32p, _i32p, _f64p, _c_int,
+                               _f64p, _f64p]
+        L.orc_jacobi.argtypes = [_c_int, _i32p, _i32p, _f64p, _f64p, _c_dbl,
+                                 _c_int, _f64p, _f64p]
+        L.orc_chebyshev.argtypes = [_c_int, _i32p, _i32p, _f64p, _f64p, _c_dbl,
+                                    _c_dbl, _c_int, _c_int, _f64p, _f64p]
+        L.orc_lanczos.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_int,
+                                  ctypes.c_ulonglong]
+        L.orc_lanczos.restype = _c_dbl
+        L.orc_sm64_uniform.argtypes = [ctypes.c_ulonglong, ctypes.c_ulonglong]
+        L.orc_sm64_uniform.restype = _c_dbl
+        L.orc_dense_solve.argtypes = [_c_int, _f64p, _c_int, _f64p]
+        L.orc_rs_split.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _i32p]
+        L.orc_strength_count.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl,
+                                         _i32p]
+        _lib = L
+    return _lib
+
+
+def _csr(rp, ci, v):
+    return (np.ascontiguousarray(rp, np.int32), np.ascontiguousarray(ci, np.int32),
+            np.ascontiguousarray(v, np.float64))
+
+
+# --------------------------------------------------------------------------
+# single operations
+# --------------------------------------------------------------------------
+def spmm(rp, ci, v, X, ncols=None):
+    rp, ci, v = _csr(rp, ci, v)
+    X = np.ascontiguousarray(X, np.float64)
+    n = rp.size - 1
+    m = 1 if X.ndim == 1 else X.shape[1]
+    Y = np.empty((n, m))
+    lib().orc_spmm(n, ncols if ncols is not None else X.shape[0], rp, ci, v, m,
+                   X.reshape(-1, m), Y)
+    return Y if X.ndim > 1 else Y[:, 0]
+
+
+def jacobi(rp, ci, v, dinv, omega, B, X):
+    rp, ci, v = _csr(rp, ci, v)
+    X = np.array(X, np.float64, order="C", copy=True)
+    B = np.ascontiguousarray(B, np.float64)
+    m = X.shape[1]
+    lib().orc_jacobi(rp.size - 1, rp, ci, v, np.ascontiguousarray(dinv, np.float64),
+                     omega, m, B, X)
+    return X
+
+
+def chebyshev(rp, ci, v, dinv, lo, hi, degree, B, X):
+    rp, ci, v = _csr(rp, ci, v)
+    X = np.array(X, np.float64, order="C", copy=True)
+    B = np.ascontiguousarray(B, np.float64)
+    lib().orc_chebyshev(rp.size - 1, rp, ci, v, np.ascontiguousarray(dinv, np.float64),
+                        lo, hi, degree, X.shape[1], B, X)
+    return X
+
+
+def lanczos_lmax(rp, ci, v, steps=10, key=7 << 32):
+    rp, ci, v = _csr(rp, ci, v)
+    return lib().orc_lanczos(rp.size - 1, rp, ci, v, steps, key)
+
+
+def sm64_uniform(key, i):
+    return lib().orc_sm64_uniform(key, i)
+
+
+def dense_solve(A, B):
+    A = np.ascontiguousarray(A, np.float64)
+    B = np.array(B, np.float64, order="C", copy=True)
+    vec = B.ndim == 1
+    if vec:
+        B = B[:, None].copy()
+    rc = lib().orc_dense_solve(A.shape[0], A, B.shape[1], B)
+    if rc:
+        raise np.linalg.LinAlgError("singular")
+    return B[:, 0] if vec else B
+
+
+def rs_split(rp, ci, v, theta=0.25):
+    """C/F split of the first Ruge-Stueben pass: 1 = C, 2 = F."""
+    rp, ci, v = _csr(rp, ci, v)
+    st = np.empty(rp.size - 1, np.int32)
+    rc = lib().orc_rs_split(rp.size - 1, rp, ci, v, theta, st)
+    assert rc == 0
+    return st
+
+
+def strength_counts(rp, ci, v, theta=0.25):
+    rp, ci, v = _csr(rp, ci, v)
+    c = np.empty(rp.size - 1, np.int32)
+    lib().orc_strength_count(rp.size - 1, rp, ci, v, theta, c)
+    return c
+
+
+# --------------------------------------------------------------------------
+# hierarchy + solve
+# --------------------------------------------------------------------------
+class Hierarchy:
+    """Owns an oracle hierarchy handle; exports its arrays as NumPy."""
+
+    def __init__(self, rp, ci, v, theta=0.25, max_coarse=64, max_levels=40,
+                 lanczos_steps=10):
+        rp, ci, v = _csr(rp, ci, v)
+        h = _vp()
+        rc = lib().orc_build(rp.size - 1, rp, ci, v, theta, max_coarse,
+                             max_levels, lanczos_steps, ctypes.byref(h))
+        if rc != 0:
+            raise RuntimeError(f"oracle hierarchy build failed: {rc}")
+        self._h = h
+        self.nlev = lib().orc_hier_nlev(h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().orc_hier_free(self._h)
+            self._h = None
+
+    def csr(self, which, level):
+        info = np.empty(3, np.int32)
+        rc = lib().orc_hier_info(self._h, which, level, info)
+        if rc:
+            raise IndexError(level)
+        nr, nc, nnz = (int(x) for x in info)
+        rp = np.empty(nr + 1, np.int32)
+        ci = np.empty(max(nnz, 1), np.int32)
+        v = np.empty(max(nnz, 1), np.float64)
+        lib().orc_hier_copy(self._h, which, level, rp, ci, v)
+        return rp, ci[:nnz], v[:nnz], (nr, nc)
+
+    def A(self, l):
+        return self.csr(A_, l)
+
+    def P(self, l):
+        return self.csr(P_, l)
+
+    def R(self, l):
+        return self.csr(R_, l)
+
+    def cf(self, l):
+        n = self.A(l)[3][0]
+        out = np.empty(n, np.int32)
+        lib().orc_hier_cf(self._h, l, out)
+        return out
+
+    def lmax(self, l):
+        return lib().orc_hier_lmax(self._h, l)
+
+    def sizes(self):
+        return [self.A(l)[3][0] for l in range(self.nlev)]
+
+    def export(self):
+        """Plain-array form {A: [...], P: [...], R: [...], lmax: [...]} used to
+        hand the same hierarchy to another implementation."""
+        return {
+            "A": [self.A(l)[:3] for l in range(self.nlev)],
+            "P": [self.P(l)[:3] + (self.P(l)[3][1],) for l in range(self.nlev - 1)],
+            "R": [self.R(l)[:3] for l in range(self.nlev - 1)],
+            "lmax": [self.lmax(l) for l in range(self.nlev)],
+        }
+
+    def vcycle(self, B, smoother=JACOBI, omega=2.0 / 3.0, degree=2,
+               lo_frac=0.3, hi_frac=1.1):
+        B = np.ascontiguousarray(B, np.float64)
+        vec = B.ndim == 1
+        if vec:
+            B = B[:, None].copy()
+        X = np.zeros_like(B)
+        lib().orc_vcycle(self._h, smoother, omega, degree, lo_frac, hi_frac,
+                         B.shape[1], B, X)
+        return X[:, 0] if vec else X
+
+    def solve(self, B, X0=None, method=CG, smoother=JACOBI, omega=2.0 / 3.0,
+              degree=2, lo_frac=0.3, hi_frac=1.1, flexible=False, precond=True,
+              max_iters=1000, tol=1e-8):
+        """Returns (X, stats dict, return code)."""
+        B = np.ascontiguousarray(B, np.float64)
+        vec = B.ndim == 1
+        if vec:
+            B = B[:, None].copy()
+        n, m = B.shape
+        if X0 is None:
+            X = np.zeros_like(B)
+            given = 0
+        else:
+            X = np.array(X0, np.float64, order="C", copy=True).reshape(n, m)
+            given = 1
+        it = np.zeros(m, np.int32)
+        rr = np.zeros(m)
+        tr = np.zeros(m)
+        cv = np.zeros(m, np.int32)
+        rc = lib().orc_solve(self._h, method, smoother, omega, degree, lo_frac,
+                             hi_frac, int(flexible), int(precond), max_iters,
+                             tol, given, m, B, X, it, rr, tr, cv)
+        st = {"iters": it, "relres": rr, "true_relres": tr,
+              "converged": cv.astype(bool)}
+        return (X[:, 0] if vec else X), st, rc

@@ -1,0 +1,1347 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the multi-RHS AMG-Krylov solve.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code with the GPU path.
+ *
+ * What it computes, and where each step comes from:
+ *
+ *  - A X = B with n x m blocks (paper, Section 1, the equation A X = B); the m
+ *    columns are solved as simultaneous *independent* problems with their
+ *    own Krylov scalars (paper, Section 2.2), stored interleaved X[i*m + j]
+ *    so a matrix entry is loaded once for all m columns (Sections 2.2-2.3).
+ *  - Classical algebraic multigrid (paper, Section 2.1, citing Trottenberg et
+ *    al.), set up the Ruge-Stueben way: classical strength of connection,
+ *    the first coarsening pass, direct interpolation, Galerkin coarse
+ *    operators R A P with R = P^T, stopping at a small coarse grid solved by
+ *    a dense LU (the paper's "direct" method, Section 2.1, Table 1).
+ *  - Jacobi and Chebyshev smoothers (Section 2.1, Table 1); Chebyshev with
+ *    polynomial order 2 as in the configuration example of Section 2.4.
+ *  - V(1,1) cycle as the preconditioner of CG (Hestenes-Stiefel) or of
+ *    right-preconditioned BiCGStab (van der Vorst), both cited in Section 2.1.
+ *
+ * The paper gives no formulas for these methods; each routine below says
+ * which textbook definition it follows.  Everything is sequential FP64
+ * except that independent row loops carry an OpenMP pragma (each row is
+ * computed by exactly one thread with a fixed order of operations, so the
+ * results do not depend on the thread count).  Dot products are plain
+ * sequential sums over rows.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_NOT_CONVERGED 1
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EBREAKDOWN (-5)
+
+#define ORC_MAXLEV 64
+
+/* ------------------------------------------------------------------------ */
+/* CSR container                                                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int nr, nc;      /* rows, columns */
+    int *rp;         /* nr + 1 */
+    int *ci;         /* nnz, sorted per row */
+    double *v;       /* nnz */
+} ocsr;
+
+static int nnz_of(const ocsr *a) { return a->rp[a->nr]; }
+
+static void csr_free(ocsr *a)
+{
+    free(a->rp); free(a->ci); free(a->v);
+    a->rp = NULL; a->ci = NULL; a->v = NULL;
+}
+
+static int csr_alloc(ocsr *a, int nr, int nc, int nnz)
+{
+    a->nr = nr; a->nc = nc;
+    a->rp = (int *)calloc((size_t)nr + 1, sizeof(int));
+    a->ci = (int *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int));
+    a->v = (double *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    return (a->rp && a->ci && a->v) ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multi-column products: Y = A X with X, Y interleaved (row-major n x m).   */
+/* The "blas2" operation of the paper's Section 2.3 for NV columns.          */
+/* ------------------------------------------------------------------------ */
+static void spmm(const ocsr *a, int m, const double *X, double *Y)
+{
+    int i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < a->nr; i++) {
+        double *y = Y + (size_t)i * m;
+        int j, k;
+        for (j = 0; j < m; j++) y[j] = 0.0;
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+            const double aik = a->v[k];
+            const double *x = X + (size_t)a->ci[k] * m;
+            for (j = 0; j < m; j++) y[j] += aik * x[j];
+        }
+    }
+}
+
+/* R = B - A X */
+static void residual(const ocsr *a, int m, const double *B, const double *X,
+                     double *R)
+{
+    int i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < a->nr; i++) {
+        double *r = R + (size_t)i * m;
+        const double *b = B + (size_t)i * m;
+        int j, k;
+        for (j = 0; j < m; j++) r[j] = 0.0;
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+            const double aik = a->v[k];
+            const double *x = X + (size_t)a->ci[k] * m;
+            for (j = 0; j < m; j++) r[j] += aik * x[j];
+        }
+        for (j = 0; j < m; j++) r[j] = b[j] - r[j];
+    }
+}
+
+/* column j of  b - A x  (one column only), returned as its 2-norm squared */
+static double residual_col_norm2(const ocsr *a, int m, int j, const double *B,
+                                 const double *X)
+{
+    double s = 0.0;
+    int i, k;
+    for (i = 0; i < a->nr; i++) {
+        double ax = 0.0, r;
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+            ax += a->v[k] * X[(size_t)a->ci[k] * m + j];
+        r = B[(size_t)i * m + j] - ax;
+        s += r * r;
+    }
+    return s;
+}
+
+static double dot_col(int n, int m, int j, const double *X, const double *Y)
+{
+    double s = 0.0;
+    int i;
+    for (i = 0; i < n; i++) s += X[(size_t)i * m + j] * Y[(size_t)i * m + j];
+    return s;
+}
+
+/* all m column dots in one pass over the rows; column j is summed over
+ * i = 0..n-1 in order, exactly as dot_col does */
+static void dots(int n, int m, const double *X, const double *Y, double *out)
+{
+    int i, j;
+    for (j = 0; j < m; j++) out[j] = 0.0;
+    for (i = 0; i < n; i++) {
+        const double *x = X + (size_t)i * m, *y = Y + (size_t)i * m;
+        for (j = 0; j < m; j++) out[j] += x[j] * y[j];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Setup step 1: strength of connection.                                     */
+/* Classical (Ruge-Stueben) negative-coupling form: j is a strong            */
+/* connection of i when -a_ij >= theta * max_{k != i} (-a_ik).  Rows with no */
+/* negative off-diagonal have no strong connections.                         */
+/* ------------------------------------------------------------------------ */
+static int strength(const ocsr *a, double theta, int **srp_out, int **sci_out)
+{
+    int n = a->nr, i, k;
+    int *srp = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *sci;
+    if (!srp) return -1;
+    for (i = 0; i < n; i++) {
+        double mx = 0.0;
+        int cnt = 0;
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+            if (a->ci[k] != i && -a->v[k] > mx) mx = -a->v[k];
+        if (mx > 0.0)
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+                if (a->ci[k] != i && -a->v[k] >= theta * mx) cnt++;
+        srp[i + 1] = srp[i] + cnt;
+    }
+    sci = (int *)malloc((size_t)(srp[n] > 0 ? srp[n] : 1) * sizeof(int));
+    if (!sci) { free(srp); return -1; }
+    for (i = 0; i < n; i++) {
+        double mx = 0.0;
+        int pos = srp[i];
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+            if (a->ci[k] != i && -a->v[k] > mx) mx = -a->v[k];
+        if (mx > 0.0)
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+                if (a->ci[k] != i && -a->v[k] >= theta * mx) sci[pos++] = a->ci[k];
+    }
+    *srp_out = srp; *sci_out = sci;
+    return 0;
+}
+
+/* pattern transpose of an n x n pattern */
+static int pattern_transpose(int n, const int *rp, const int *ci, int **trp_out,
+                             int **tci_out)
+{
+    int i, k;
+    int nnz = rp[n];
+    int *trp = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *tci = (int *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int));
+    int *fill = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    if (!trp || !tci || !fill) { free(trp); free(tci); free(fill); return -1; }
+    for (k = 0; k < nnz; k++) trp[ci[k] + 1]++;
+    for (i = 0; i < n; i++) trp[i + 1] += trp[i];
+    memcpy(fill, trp, (size_t)n * sizeof(int));
+    for (i = 0; i < n; i++)
+        for (k = rp[i]; k < rp[i + 1]; k++) tci[fill[ci[k]]++] = i;
+    free(fill);
+    *trp_out = trp; *tci_out = tci;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Setup step 2: Ruge-Stueben first coarsening pass (Trottenberg et al.,     */
+/* Multigrid, Appendix A).  Weight lambda_i = |S_i^T| initially; repeatedly  */
+/* take the undecided point of largest weight (ties: lowest index) as C,     */
+/* make every undecided point that depends strongly on it F and raise the    */
+/* weights of the undecided points those new F points depend on, then lower  */
+/* the weights of the undecided points the new C point depends on.  No      */
+/* second pass.  A binary max-heap with lazy deletion finds the next point.  */
+/* ------------------------------------------------------------------------ */
+typedef struct { int lam, idx; } hent;
+typedef struct { hent *a; size_t n, cap; } heap_t;
+
+static int hbetter(hent x, hent y)   /* x before y ? */
+{
+    return x.lam > y.lam || (x.lam == y.lam && x.idx < y.idx);
+}
+
+static int hpush(heap_t *h, int lam, int idx)
+{
+    size_t c;
+    if (h->n == h->cap) {
+        size_t nc = h->cap ? 2 * h->cap : 1024;
+        hent *na = (hent *)realloc(h->a, nc * sizeof(hent));
+        if (!na) return -1;
+        h->a = na; h->cap = nc;
+    }
+    c = h->n++;
+    h->a[c].lam = lam; h->a[c].idx = idx;
+    while (c > 0) {
+        size_t p = (c - 1) / 2;
+        if (!hbetter(h->a[c], h->a[p])) break;
+        { hent t = h->a[c]; h->a[c] = h->a[p]; h->a[p] = t; }
+        c = p;
+    }
+    return 0;
+}
+
+static hent hpop(heap_t *h)
+{
+    hent top = h->a[0];
+    size_t c = 0;
+    h->a[0] = h->a[--h->n];
+    for (;;) {
+        size_t l = 2 * c + 1, r = l + 1, b = c;
+        if (l < h->n && hbetter(h->a[l], h->a[b])) b = l;
+        if (r < h->n && hbetter(h->a[r], h->a[b])) b = r;
+        if (b == c) break;
+        { hent t = h->a[c]; h->a[c] = h->a[b]; h->a[b] = t; }
+        c = b;
+    }
+    return top;
+}
+
+enum { PT_U = 0, PT_C = 1, PT_F = 2 };
+
+static int rs_first_pass(int n, const int *srp, const int *sci, const int *trp,
+                         const int *tci, int *state)
+{
+    int *lam = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    heap_t h = {NULL, 0, 0};
+    int i, k, kk;
+    if (!lam) return -1;
+    for (i = 0; i < n; i++) {
+        state[i] = PT_U;
+        lam[i] = trp[i + 1] - trp[i];
+        if (hpush(&h, lam[i], i)) { free(lam); free(h.a); return -1; }
+    }
+    while (h.n > 0) {
+        hent e = hpop(&h);
+        i = e.idx;
+        if (state[i] != PT_U || e.lam != lam[i]) continue;   /* stale */
+        state[i] = PT_C;
+        for (k = trp[i]; k < trp[i + 1]; k++) {              /* j in S_i^T */
+            int j = tci[k];
+            if (state[j] != PT_U) continue;
+            state[j] = PT_F;
+            for (kk = srp[j]; kk < srp[j + 1]; kk++) {       /* l in S_j */
+                int l = sci[kk];
+                if (state[l] == PT_U) {
+                    lam[l]++;
+                    if (hpush(&h, lam[l], l)) { free(lam); free(h.a); return -1; }
+                }
+            }
+        }
+        for (k = srp[i]; k < srp[i + 1]; k++) {              /* j in S_i */
+            int j = sci[k];
+            if (state[j] == PT_U) {
+                lam[j]--;
+                if (hpush(&h, lam[j], j)) { free(lam); free(h.a); return -1; }
+            }
+        }
+    }
+    free(lam); free(h.a);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Setup step 3: direct interpolation (Stueben, "Algebraic multigrid: an     */
+/* introduction with applications", 2001).  C rows are unit rows.  For an F  */
+/* point i with interpolatory set P_i = C n S_i and neighbourhood N_i:       */
+/*   w_ik = -alpha_i a_ik / a_ii (a_ik < 0),                                */
+/*   alpha_i = sum_{N_i} a_ij^- / sum_{P_i} a_ik^-,                         */
+/*   w_ik = -beta_i a_ik / a_ii (a_ik > 0),                                 */
+/*   beta_i = sum_{N_i} a_ij^+ / sum_{P_i} a_ik^+;                          */
+/* when P_i has no positive entry the positive part of N_i is added to the   */
+/* diagonal instead.  Coarse points are numbered by increasing fine index.   */
+/* ------------------------------------------------------------------------ */
+static int direct_interp(const ocsr *a, const int *srp, const int *sci,
+                         const int *state, ocsr *P)
+{
+    int n = a->nr, i, k, nc = 0, nnz = 0;
+    int *cidx = (int *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    if (!cidx) return -1;
+    for (i = 0; i < n; i++) cidx[i] = (state[i] == PT_C) ? nc++ : -1;
+    /* count */
+    for (i = 0; i < n; i++) {
+        if (state[i] == PT_C) { nnz++; continue; }
+        for (k = srp[i]; k < srp[i + 1]; k++)
+            if (state[sci[k]] == PT_C) nnz++;
+    }
+    if (csr_alloc(P, n, nc, nnz)) { free(cidx); return -1; }
+    nnz = 0;
+    for (i = 0; i < n; i++) {
+        if (state[i] == PT_C) {
+            P->ci[nnz] = cidx[i]; P->v[nnz] = 1.0; nnz++;
+        } else {
+            double aii = 0.0, sneg_n = 0.0, spos_n = 0.0, sneg_p = 0.0,
+                   spos_p = 0.0, alpha, beta, d;
+            int s;
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k];
+                double aij = a->v[k];
+                if (j == i) { aii += aij; continue; }
+                if (aij < 0.0) sneg_n += aij; else spos_n += aij;
+            }
+            /* interpolatory set: strong C neighbours, values from row i */
+            s = srp[i];
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k];
+                while (s < srp[i + 1] && sci[s] < j) s++;
+                if (s < srp[i + 1] && sci[s] == j && state[j] == PT_C) {
+                    if (a->v[k] < 0.0) sneg_p += a->v[k]; else spos_p += a->v[k];
+                }
+            }
+            d = aii;
+            if (spos_p == 0.0) d += spos_n;
+            alpha = (sneg_p != 0.0) ? sneg_n / sneg_p : 0.0;
+            beta = (spos_p != 0.0) ? spos_n / spos_p : 0.0;
+            s = srp[i];
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k];
+                while (s < srp[i + 1] && sci[s] < j) s++;
+                if (s < srp[i + 1] && sci[s] == j && state[j] == PT_C) {
+                    double aij = a->v[k];
+                    P->ci[nnz] = cidx[j];
+                    P->v[nnz] = (aij < 0.0) ? -alpha * aij / d : -beta * aij / d;
+                    nnz++;
+                }
+            }
+        }
+        P->rp[i + 1] = nnz;
+    }
+    free(cidx);
+    return 0;
+}
+
+/* full transpose of a CSR matrix (values included) */
+static int csr_transpose(const ocsr *a, ocsr *t)
+{
+    int i, k, nnz = nnz_of(a);
+    int *fill;
+    if (csr_alloc(t, a->nc, a->nr, nnz)) return -1;
+    fill = (int *)malloc((size_t)(a->nc > 0 ? a->nc : 1) * sizeof(int));
+    if (!fill) return -1;
+    for (k = 0; k < nnz; k++) t->rp[a->ci[k] + 1]++;
+    for (i = 0; i < a->nc; i++) t->rp[i + 1] += t->rp[i];
+    memcpy(fill, t->rp, (size_t)a->nc * sizeof(int));
+    for (i = 0; i < a->nr; i++)
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+            int p = fill[a->ci[k]]++;
+            t->ci[p] = i;
+            t->v[p] = a->v[k];
+        }
+    free(fill);
+    return 0;
+}
+
+static int cmp_int(const void *x, const void *y)
+{
+    int a = *(const int *)x, b = *(const int *)y;
+    return (a > b) - (a < b);
+}
+
+/* C = A B (Gustavson row by row with a dense accumulator; entries that come
+ * out exactly 0.0 are dropped; columns sorted). */
+static int csr_matmul(const ocsr *A, const ocsr *B, ocsr *C)
+{
+    int n = A->nr, nc = B->nc, i, k, kk;
+    double *acc = (double *)calloc((size_t)(nc > 0 ? nc : 1), sizeof(double));
+    int *mark = (int *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int));
+    int *list = (int *)malloc((size_t)(nc > 0 ? nc : 1) * sizeof(int));
+    size_t cap = 1024, nnz = 0;
+    int *ci = (int *)malloc(cap * sizeof(int));
+    double *v = (double *)malloc(cap * sizeof(double));
+    int *rp = (int *)calloc((size_t)n + 1, sizeof(int));
+    if (!acc || !mark || !list || !ci || !v || !rp) return -1;
+    for (k = 0; k < nc; k++) mark[k] = -1;
+    for (i = 0; i < n; i++) {
+        int len = 0, t;
+        for (k = A->rp[i]; k < A->rp[i + 1]; k++) {
+            int j = A->ci[k];
+            double aij = A->v[k];
+            for (kk = B->rp[j]; kk < B->rp[j + 1]; kk++) {
+                int c = B->ci[kk];
+                if (mark[c] != i) { mark[c] = i; acc[c] = 0.0; list[len++] = c; }
+                acc[c] += aij * B->v[kk];
+            }
+        }
+        qsort(list, (size_t)len, sizeof(int), cmp_int);
+        if (nnz + (size_t)len > cap) {
+            while (nnz + (size_t)len > cap) cap *= 2;
+            ci = (int *)realloc(ci, cap * sizeof(int));
+            v = (double *)realloc(v, cap * sizeof(double));
+            if (!ci || !v) return -1;
+        }
+        for (t = 0; t < len; t++) {
+            double x = acc[list[t]];
+            if (x != 0.0) { ci[nnz] = list[t]; v[nnz] = x; nnz++; }
+        }
+        rp[i + 1] = (int)nnz;
+    }
+    free(acc); free(mark); free(list);
+    C->nr = n; C->nc = nc; C->rp = rp; C->ci = ci; C->v = v;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU with partial pivoting (row-major n x n), in place.               */
+/* ------------------------------------------------------------------------ */
+static int dense_lu(int n, double *a, int *piv)
+{
+    int i, j, k;
+    for (k = 0; k < n; k++) {
+        int p = k;
+        double mx = fabs(a[(size_t)k * n + k]);
+        for (i = k + 1; i < n; i++)
+            if (fabs(a[(size_t)i * n + k]) > mx) { mx = fabs(a[(size_t)i * n + k]); p = i; }
+        piv[k] = p;
+        if (mx == 0.0) return -1;
+        if (p != k)
+            for (j = 0; j < n; j++) {
+                double t = a[(size_t)k * n + j];
+                a[(size_t)k * n + j] = a[(size_t)p * n + j];
+                a[(size_t)p * n + j] = t;
+            }
+        for (i = k + 1; i < n; i++) {
+            double l = a[(size_t)i * n + k] / a[(size_t)k * n + k];
+            a[(size_t)i * n + k] = l;
+            for (j = k + 1; j < n; j++) a[(size_t)i * n + j] -= l * a[(size_t)k * n + j];
+        }
+    }
+    return 0;
+}
+
+/* solve with the factors for one right-hand side x (in place) */
+static void dense_lu_solve(int n, const double *lu, const int *piv, double *x)
+{
+    int i, j;
+    for (i = 0; i < n; i++)
+        if (piv[i] != i) { double t = x[i]; x[i] = x[piv[i]]; x[piv[i]] = t; }
+    for (i = 0; i < n; i++) {
+        double s = x[i];
+        for (j = 0; j < i; j++) s -= lu[(size_t)i * n + j] * x[j];
+        x[i] = s;
+    }
+    for (i = n - 1; i >= 0; i--) {
+        double s = x[i];
+        for (j = i + 1; j < n; j++) s -= lu[(size_t)i * n + j] * x[j];
+        x[i] = s / lu[(size_t)i * n + i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based uniform numbers for the Lanczos start vector: SplitMix64    */
+/* (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",    */
+/* OOPSLA 2014).  Element i of stream `key` is the finaliser applied to      */
+/* key*G + (i+1)*G with G = 0x9E3779B97F4A7C15, mapped to [-1, 1) through    */
+/* its top 53 bits.                                                          */
+/* ------------------------------------------------------------------------ */
+static double sm64_uniform(uint64_t key, uint64_t i)
+{
+    const uint64_t G = 0x9E3779B97F4A7C15ULL;
+    uint64_t z = key * G + (i + 1) * G;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+}
+
+/* number of eigenvalues of the symmetric tridiagonal (a, b) below x
+ * (Sturm sequence count) */
+static int sturm_count(int k, const double *a, const double *b, double x)
+{
+    int i, c = 0;
+    double q = 1.0;
+    for (i = 0; i < k; i++) {
+        double bb = (i > 0) ? b[i] * b[i] : 0.0;
+        q = a[i] - x - ((i > 0) ? bb / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) c++;
+    }
+    return c;
+}
+
+/* Largest Ritz value of `steps` Lanczos steps on D^{-1/2} A D^{-1/2}, start
+ * vector from SplitMix64 stream `key` (no reorthogonalisation; the largest
+ * eigenvalue of the tridiagonal found by bisection on the Sturm count). */
+static double lanczos_lmax(const ocsr *a, int steps, uint64_t key)
+{
+    int n = a->nr, i, j, k = 0;
+    double *dsq = (double *)malloc((size_t)n * sizeof(double));
+    double *v = (double *)calloc((size_t)n, sizeof(double));
+    double *vp = (double *)calloc((size_t)n, sizeof(double));
+    double *w = (double *)malloc((size_t)n * sizeof(double));
+    double *t = (double *)malloc((size_t)n * sizeof(double));
+    double al[64], be[64], nrm = 0.0, lo, hi;
+    if (steps > n) steps = n;
+    if (steps > 63) steps = 63;
+    for (i = 0; i < n; i++) {
+        double d = 0.0;
+        for (j = a->rp[i]; j < a->rp[i + 1]; j++)
+            if (a->ci[j] == i) d += a->v[j];
+        dsq[i] = 1.0 / sqrt(d);
+        v[i] = sm64_uniform(key, (uint64_t)i);
+        nrm += v[i] * v[i];
+    }
+    nrm = sqrt(nrm);
+    for (i = 0; i < n; i++) v[i] /= nrm;
+    be[0] = 0.0;
+    for (j = 0; j < steps; j++) {
+        double alpha = 0.0, beta = 0.0;
+        for (i = 0; i < n; i++) t[i] = dsq[i] * v[i];
+        spmm(a, 1, t, w);
+        for (i = 0; i < n; i++) w[i] *= dsq[i];
+        for (i = 0; i < n; i++) alpha += w[i] * v[i];
+        for (i = 0; i < n; i++) w[i] -= alpha * v[i] + be[j] * vp[i];
+        for (i = 0; i < n; i++) beta += w[i] * w[i];
+        beta = sqrt(beta);
+        al[j] = alpha;
+        k = j + 1;
+        if (j + 1 < steps) {
+            be[j + 1] = beta;
+            if (beta == 0.0) break;
+            for (i = 0; i < n; i++) { vp[i] = v[i]; v[i] = w[i] / beta; }
+        }
+    }
+    /* Gershgorin interval, then bisection for the k-th (largest) eigenvalue */
+    lo = 1e300; hi = -1e300;
+    for (i = 0; i < k; i++) {
+        double r = ((i > 0) ? fabs(be[i]) : 0.0) + ((i + 1 < k) ? fabs(be[i + 1]) : 0.0);
+        if (al[i] - r < lo) lo = al[i] - r;
+        if (al[i] + r > hi) hi = al[i] + r;
+    }
+    for (i = 0; i < 200; i++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(k, al, be, mid) >= k) hi = mid; else lo = mid;
+    }
+    free(dsq); free(v); free(vp); free(w); free(t);
+    return hi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchy                                                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int nlev;                 /* levels 0..nlev-1; level nlev-1 is coarsest */
+    ocsr A[ORC_MAXLEV];
+    ocsr P[ORC_MAXLEV];       /* P[l]: n_l x n_{l+1}, l < nlev-1 */
+    ocsr R[ORC_MAXLEV];       /* R[l] = P[l]^T */
+    int *cf[ORC_MAXLEV];      /* C/F marker of level l (l < nlev-1) */
+    double *dinv[ORC_MAXLEV]; /* 1 / a_ii */
+    double lmax[ORC_MAXLEV];  /* Lanczos estimate of lambda_max(D^-1 A) */
+    double *lu;               /* LU factors of the coarsest matrix */
+    int *piv;
+} ohier;
+
+#define ORC_LANCZOS_KEY 7ULL
+
+static int csr_copy(const ocsr *src, ocsr *dst)
+{
+    int nnz = nnz_of(src);
+    if (csr_alloc(dst, src->nr, src->nc, nnz)) return -1;
+    memcpy(dst->rp, src->rp, ((size_t)src->nr + 1) * sizeof(int));
+    memcpy(dst->ci, src->ci, (size_t)nnz * sizeof(int));
+    memcpy(dst->v, src->v, (size_t)nnz * sizeof(double));
+    return 0;
+}
+
+void orc_hier_free(ohier *h)
+{
+    int l;
+    if (!h) return;
+    for (l = 0; l < h->nlev; l++) {
+        csr_free(&h->A[l]);
+        if (l + 1 < h->nlev) { csr_free(&h->P[l]); csr_free(&h->R[l]); }
+        free(h->cf[l]);
+        free(h->dinv[l]);
+    }
+    free(h->lu); free(h->piv);
+    free(h);
+}
+
+/*
+ * Build the hierarchy: levels are added while the current level has more
+ * than `max_coarse` rows.  Returns ORC_EBREAKDOWN when more than
+ * `max_levels` levels would be needed, when a level fails to shrink below
+ * 0.9 of its parent, or when the coarsest matrix is singular.
+ */
+int orc_build(int n, const int *rp, const int *ci, const double *v, double theta,
+              int max_coarse, int max_levels, int lanczos_steps, ohier **out)
+{
+    ohier *h = (ohier *)calloc(1, sizeof(ohier));
+    ocsr a0;
+    int l, i, k, nL;
+    if (!h) return ORC_ENOMEM;
+    if (max_levels > ORC_MAXLEV) max_levels = ORC_MAXLEV;
+    a0.nr = n; a0.nc = n; a0.rp = (int *)rp; a0.ci = (int *)ci; a0.v = (double *)v;
+    if (csr_copy(&a0, &h->A[0])) { free(h); return ORC_ENOMEM; }
+    h->nlev = 1;
+    for (l = 0; h->A[l].nr > max_coarse; l++) {
+        int *srp, *sci, *trp, *tci;
+        ocsr AP;
+        if (l + 1 >= max_levels) { orc_hier_free(h); return ORC_EBREAKDOWN; }
+        if (strength(&h->A[l], theta, &srp, &sci)) { orc_hier_free(h); return ORC_ENOMEM; }
+        if (pattern_transpose(h->A[l].nr, srp, sci, &trp, &tci)) { orc_hier_free(h); return ORC_ENOMEM; }
+        h->cf[l] = (int *)malloc((size_t)h->A[l].nr * sizeof(int));
+        if (!h->cf[l] || rs_first_pass(h->A[l].nr, srp, sci, trp, tci, h->cf[l])) {
+            orc_hier_free(h); return ORC_ENOMEM;
+        }
+        if (direct_interp(&h->A[l], srp, sci, h->cf[l], &h->P[l])) { orc_hier_free(h); return ORC_ENOMEM; }
+        free(srp); free(sci); free(trp); free(tci);
+        if (csr_transpose(&h->P[l], &h->R[l])) { orc_hier_free(h); return ORC_ENOMEM; }
+        if (csr_matmul(&h->A[l], &h->P[l], &AP)) { orc_hier_free(h); return ORC_ENOMEM; }
+        if (csr_matmul(&h->R[l], &AP, &h->A[l + 1])) { orc_hier_free(h); return ORC_ENOMEM; }
+        csr_free(&AP);
+        h->nlev = l + 2;
+        if (h->A[l + 1].nr == 0 || (double)h->A[l + 1].nr > 0.9 * (double)h->A[l].nr) {
+            orc_hier_free(h); return ORC_EBREAKDOWN;
+        }
+    }
+    for (l = 0; l < h->nlev; l++) {
+        ocsr *a = &h->A[l];
+        h->dinv[l] = (double *)malloc((size_t)a->nr * sizeof(double));
+        for (i = 0; i < a->nr; i++) {
+            double d = 0.0;
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+                if (a->ci[k] == i) d += a->v[k];
+            h->dinv[l][i] = 1.0 / d;
+        }
+        h->lmax[l] = (l + 1 < h->nlev)
+                         ? lanczos_lmax(a, lanczos_steps, (ORC_LANCZOS_KEY << 32) + (uint64_t)l)
+                         : 0.0;
+    }
+    nL = h->A[h->nlev - 1].nr;
+    h->lu = (double *)calloc((size_t)nL * nL + 1, sizeof(double));
+    h->piv = (int *)malloc(((size_t)nL + 1) * sizeof(int));
+    {
+        ocsr *a = &h->A[h->nlev - 1];
+        for (i = 0; i < nL; i++)
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+                h->lu[(size_t)i * nL + a->ci[k]] = a->v[k];
+    }
+    if (dense_lu(nL, h->lu, h->piv)) { orc_hier_free(h); return ORC_EBREAKDOWN; }
+    *out = h;
+    return ORC_OK;
+}
+
+/* ---- accessors (copy out) ------------------------------------------------ */
+int orc_hier_nlev(const ohier *h) { return h->nlev; }
+
+/* which: 0 = A, 1 = P, 2 = R.  info[0..2] = rows, cols, nnz */
+int orc_hier_info(const ohier *h, int which, int l, int *info)
+{
+    const ocsr *a;
+    if (l < 0 || l >= h->nlev) return ORC_EINVAL;
+    if (which != 0 && l >= h->nlev - 1) return ORC_EINVAL;
+    a = which == 0 ? &h->A[l] : which == 1 ? &h->P[l] : &h->R[l];
+    info[0] = a->nr; info[1] = a->nc; info[2] = nnz_of(a);
+    return ORC_OK;
+}
+
+int orc_hier_copy(const ohier *h, int which, int l, int *rp, int *ci, double *v)
+{
+    const ocsr *a;
+    if (l < 0 || l >= h->nlev) return ORC_EINVAL;
+    if (which != 0 && l >= h->nlev - 1) return ORC_EINVAL;
+    a = which == 0 ? &h->A[l] : which == 1 ? &h->P[l] : &h->R[l];
+    memcpy(rp, a->rp, ((size_t)a->nr + 1) * sizeof(int));
+    memcpy(ci, a->ci, (size_t)nnz_of(a) * sizeof(int));
+    memcpy(v, a->v, (size_t)nnz_of(a) * sizeof(double));
+    return ORC_OK;
+}
+
+int orc_hier_cf(const ohier *h, int l, int *cf)
+{
+    if (l < 0 || l >= h->nlev - 1) return ORC_EINVAL;
+    memcpy(cf, h->cf[l], (size_t)h->A[l].nr * sizeof(int));
+    return ORC_OK;
+}
+
+double orc_hier_lmax(const ohier *h, int l) { return h->lmax[l]; }
+
+/* ------------------------------------------------------------------------ */
+/* Smoothers (on D^-1 A)                                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int smoother;      /* 0 = Jacobi, 1 = Chebyshev */
+    double omega;      /* Jacobi damping */
+    int degree;        /* Chebyshev degree */
+    double lo_frac;    /* Chebyshev interval [lo_frac*hi, hi] */
+    double hi_frac;    /* hi = hi_frac * lambda_max estimate */
+} smopt;
+
+/* damped Jacobi: x <- x + omega D^-1 (b - A x); t is an n x m temporary */
+static void jacobi(const ocsr *a, const double *dinv, double omega, int m,
+                   const double *b, double *x, double *t)
+{
+    int i;
+    residual(a, m, b, x, t);
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < a->nr; i++) {
+        int j;
+        for (j = 0; j < m; j++)
+            x[(size_t)i * m + j] += omega * dinv[i] * t[(size_t)i * m + j];
+    }
+}
+
+/*
+ * Chebyshev acceleration of Jacobi on [lo, hi] (Saad, Iterative Methods for
+ * Sparse Linear Systems, 2nd ed., Algorithm 12.1, applied to D^-1 A):
+ *   theta = (hi+lo)/2, delta = (hi-lo)/2, sigma = theta/delta, rho = 1/sigma,
+ *   r = D^-1 (b - A x), d = r / theta,
+ *   for k = 1..degree: x += d; if k < degree:
+ *      r -= D^-1 A d; rho' = 1/(2 sigma - rho);
+ *      d = rho' rho d + (2 rho'/delta) r; rho = rho'.
+ * r, d, t are n x m temporaries.
+ */
+static void chebyshev(const ocsr *a, const double *dinv, double lo, double hi,
+                      int degree, int m, const double *b, double *x, double *r,
+                      double *d, double *t)
+{
+    double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    double sigma = theta / delta, rho = 1.0 / sigma;
+    size_t nm = (size_t)a->nr * m, q;
+    int k, i;
+    residual(a, m, b, x, r);
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < a->nr; i++) {
+        int j;
+        for (j = 0; j < m; j++) {
+            r[(size_t)i * m + j] *= dinv[i];
+            d[(size_t)i * m + j] = r[(size_t)i * m + j] / theta;
+        }
+    }
+    for (k = 1; k <= degree; k++) {
+        for (q = 0; q < nm; q++) x[q] += d[q];
+        if (k < degree) {
+            double rn;
+            spmm(a, m, d, t);
+            rn = 1.0 / (2.0 * sigma - rho);
+#pragma omp parallel for schedule(static)
+            for (i = 0; i < a->nr; i++) {
+                int j;
+                for (j = 0; j < m; j++) {
+                    size_t p = (size_t)i * m + j;
+                    r[p] -= dinv[i] * t[p];
+                    d[p] = rn * rho * d[p] + (2.0 * rn / delta) * r[p];
+                }
+            }
+            rho = rn;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* V(1,1) cycle from a zero initial guess:                                   */
+/*   pre-smooth, r = b - A x, b_c = R r, recurse (coarsest: direct LU),      */
+/*   x += P x_c, post-smooth.                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int m;
+    double *b[ORC_MAXLEV], *x[ORC_MAXLEV], *r[ORC_MAXLEV], *d[ORC_MAXLEV],
+        *t[ORC_MAXLEV];
+    double *col;   /* nL scratch */
+} vws;
+
+static void vws_free(vws *w, int nlev)
+{
+    int l;
+    for (l = 0; l < nlev; l++) {
+        free(w->b[l]); free(w->x[l]); free(w->r[l]); free(w->d[l]); free(w->t[l]);
+    }
+    free(w->col);
+}
+
+static int vws_alloc(vws *w, const ohier *h, int m)
+{
+    int l;
+    memset(w, 0, sizeof(*w));
+    w->m = m;
+    for (l = 0; l < h->nlev; l++) {
+        size_t nm = (size_t)h->A[l].nr * m + 1;
+        w->b[l] = (double *)calloc(nm, sizeof(double));
+        w->x[l] = (double *)calloc(nm, sizeof(double));
+        w->r[l] = (double *)calloc(nm, sizeof(double));
+        w->d[l] = (double *)calloc(nm, sizeof(double));
+        w->t[l] = (double *)calloc(nm, sizeof(double));
+        if (!w->b[l] || !w->x[l] || !w->r[l] || !w->d[l] || !w->t[l]) return -1;
+    }
+    w->col = (double *)malloc(((size_t)h->A[h->nlev - 1].nr + 1) * sizeof(double));
+    return w->col ? 0 : -1;
+}
+
+static void smooth(const ohier *h, int l, const smopt *so, int m, const double *b,
+                   double *x, vws *w)
+{
+    if (so->smoother == 0)
+        jacobi(&h->A[l], h->dinv[l], so->omega, m, b, x, w->t[l]);
+    else
+        chebyshev(&h->A[l], h->dinv[l], so->lo_frac * so->hi_frac * h->lmax[l],
+                  so->hi_frac * h->lmax[l], so->degree, m, b, x, w->r[l], w->d[l],
+                  w->t[l]);
+}
+
+static void coarse_solve(const ohier *h, int m, const double *b, double *x, double *col)
+{
+    int nL = h->A[h->nlev - 1].nr, i, j;
+    for (j = 0; j < m; j++) {
+        for (i = 0; i < nL; i++) col[i] = b[(size_t)i * m + j];
+        dense_lu_solve(nL, h->lu, h->piv, col);
+        for (i = 0; i < nL; i++) x[(size_t)i * m + j] = col[i];
+    }
+}
+
+static void vcycle_level(const ohier *h, int l, const smopt *so, int m,
+                         const double *b, double *x, vws *w)
+{
+    size_t nm = (size_t)h->A[l].nr * m;
+    if (l == h->nlev - 1) { coarse_solve(h, m, b, x, w->col); return; }
+    memset(x, 0, nm * sizeof(double));
+    smooth(h, l, so, m, b, x, w);
+    residual(&h->A[l], m, b, x, w->r[l]);
+    spmm(&h->R[l], m, w->r[l], w->b[l + 1]);
+    vcycle_level(h, l + 1, so, m, w->b[l + 1], w->x[l + 1], w);
+    {
+        /* x += P x_c */
+        spmm(&h->P[l], m, w->x[l + 1], w->t[l]);
+        size_t q;
+        for (q = 0; q < nm; q++) x[q] += w->t[l][q];
+    }
+    smooth(h, l, so, m, b, x, w);
+}
+
+int orc_vcycle(const ohier *h, int smoother, double omega, int degree,
+               double lo_frac, double hi_frac, int m, const double *b, double *x)
+{
+    vws w;
+    smopt so = {smoother, omega, degree, lo_frac, hi_frac};
+    if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
+    vcycle_level(h, 0, &so, m, b, x, &w);
+    vws_free(&w, h->nlev);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Krylov solvers, one independent set of scalars per column.                */
+/* Stopping test: ||r_j|| / ||b_j|| <= tol on the recurrence residual; when  */
+/* it passes, the true residual of that column is recomputed, and if it does */
+/* not pass the column restarts from its current iterate.  A zero column of  */
+/* B gives a zero solution in 0 iterations.                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int method;        /* 0 = CG, 1 = BiCGStab */
+    int flexible;      /* CG: 0 Fletcher-Reeves beta, 1 flexible (Polak-Ribiere) */
+    int max_iters;
+    double tol;
+    int x0_given;
+    int precond;       /* 1 = V-cycle, 0 = none (identity) */
+} kopt;
+
+static void apply_prec(const ohier *h, const kopt *ko, const smopt *so, int m,
+                       const double *r, double *z, vws *w)
+{
+    if (ko->precond) vcycle_level(h, 0, so, m, r, z, w);
+    else memcpy(z, r, (size_t)h->A[0].nr * m * sizeof(double));
+}
+
+static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
+               const double *B, double *X, int *iters, double *relres,
+               int *conv, vws *w)
+{
+    const ocsr *A = &h->A[0];
+    int n = A->nr, j, it, i, rc = ORC_OK;
+    size_t nm = (size_t)n * m;
+    double *r = (double *)malloc(nm * sizeof(double));
+    double *z = (double *)malloc(nm * sizeof(double));
+    double *p = (double *)malloc(nm * sizeof(double));
+    double *q = (double *)malloc(nm * sizeof(double));
+    double *bn = (double *)malloc((size_t)m * sizeof(double));
+    double *rz = (double *)malloc((size_t)m * sizeof(double));
+    double *rzn = (double *)malloc((size_t)m * sizeof(double));
+    double *zq = (double *)malloc((size_t)m * sizeof(double));
+    double *pq = (double *)malloc((size_t)m * sizeof(double));
+    double *rr = (double *)malloc((size_t)m * sizeof(double));
+    double *alpha = (double *)malloc((size_t)m * sizeof(double));
+    double *beta = (double *)malloc((size_t)m * sizeof(double));
+    int *act = (int *)malloc((size_t)m * sizeof(int));
+    int *rst = (int *)calloc((size_t)m, sizeof(int));
+    if (!r || !z || !p || !q || !bn || !rz || !rzn || !zq || !pq || !rr || !alpha ||
+        !beta || !act || !rst)
+        return ORC_ENOMEM;
+
+    if (!ko->x0_given) memset(X, 0, nm * sizeof(double));
+    residual(A, m, B, X, r);
+    dots(n, m, B, B, bn);
+    dots(n, m, r, r, rr);
+    for (j = 0; j < m; j++) {
+        bn[j] = sqrt(bn[j]);
+        iters[j] = 0; conv[j] = 0; act[j] = 1;
+        if (bn[j] == 0.0) {
+            for (i = 0; i < n; i++) X[(size_t)i * m + j] = 0.0;
+            relres[j] = 0.0; conv[j] = 1; act[j] = 0;
+            continue;
+        }
+        relres[j] = sqrt(rr[j]) / bn[j];
+        if (relres[j] <= ko->tol) { conv[j] = 1; act[j] = 0; }
+    }
+    apply_prec(h, ko, so, m, r, z, w);
+    memcpy(p, z, nm * sizeof(double));
+    dots(n, m, r, z, rz);
+
+    for (it = 1; it <= ko->max_iters; it++) {
+        int any = 0;
+        for (j = 0; j < m; j++) any |= act[j];
+        if (!any) break;
+        /* q = A p, alpha = (r, z) / (p, q) */
+        spmm(A, m, p, q);
+        dots(n, m, p, q, pq);
+        for (j = 0; j < m; j++) {
+            alpha[j] = 0.0;
+            if (!act[j]) continue;
+            if (!(pq[j] > 0.0) || !isfinite(pq[j])) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
+            alpha[j] = rz[j] / pq[j];
+        }
+        /* x += alpha p, r -= alpha q (active columns) */
+        for (i = 0; i < n; i++)
+            for (j = 0; j < m; j++)
+                if (act[j]) {
+                    size_t k = (size_t)i * m + j;
+                    X[k] += alpha[j] * p[k];
+                    r[k] -= alpha[j] * q[k];
+                }
+        dots(n, m, r, r, rr);
+        for (j = 0; j < m; j++) {
+            if (!act[j]) continue;
+            iters[j] = it;
+            relres[j] = sqrt(rr[j]) / bn[j];
+            if (relres[j] <= ko->tol) {
+                double tr = sqrt(residual_col_norm2(A, m, j, B, X)) / bn[j];
+                if (tr <= ko->tol) { conv[j] = 1; act[j] = 0; }
+                else {
+                    /* recurrence drifted: restart column j from its iterate */
+                    for (i = 0; i < n; i++) {
+                        double ax = 0.0;
+                        int k;
+                        for (k = A->rp[i]; k < A->rp[i + 1]; k++)
+                            ax += A->v[k] * X[(size_t)A->ci[k] * m + j];
+                        r[(size_t)i * m + j] = B[(size_t)i * m + j] - ax;
+                    }
+                    relres[j] = tr;
+                    rst[j] = 1;
+                }
+            }
+        }
+        /* z = M r, beta, p = z + beta p */
+        apply_prec(h, ko, so, m, r, z, w);
+        dots(n, m, r, z, rzn);
+        if (ko->flexible) dots(n, m, z, q, zq);
+        for (j = 0; j < m; j++) {
+            beta[j] = 0.0;
+            if (!act[j]) continue;
+            if (rst[j]) {
+                beta[j] = 0.0; rst[j] = 0;
+            } else if (ko->flexible) {
+                /* (z_new, r_new - r_old) = -alpha (z_new, q) */
+                beta[j] = -alpha[j] * zq[j] / rz[j];
+            } else {
+                beta[j] = rzn[j] / rz[j];
+            }
+            rz[j] = rzn[j];
+        }
+        for (i = 0; i < n; i++)
+            for (j = 0; j < m; j++)
+                if (act[j]) {
+                    size_t k = (size_t)i * m + j;
+                    p[k] = z[k] + beta[j] * p[k];
+                }
+    }
+    for (j = 0; j < m; j++) if (!conv[j] && rc == ORC_OK) rc = ORC_NOT_CONVERGED;
+    free(r); free(z); free(p); free(q); free(bn); free(rz); free(rzn); free(zq);
+    free(pq); free(rr); free(alpha); free(beta); free(act); free(rst);
+    return rc;
+}
+
+/*
+ * Right-preconditioned BiCGStab (van der Vorst 1992), per column:
+ *   r = b - A x, rh = r, rho = alpha = omega = 1, v = p = 0;
+ *   loop: rho' = (rh, r); beta = (rho'/rho)(alpha/omega);
+ *         p = r + beta (p - omega v); ph = M p; v = A ph;
+ *         alpha = rho' / (rh, v); s = r - alpha v;
+ *         if ||s||/||b|| <= tol: x += alpha ph, done;
+ *         sh = M s; t = A sh; omega = (t, s)/(t, t);
+ *         x += alpha ph + omega sh; r = s - omega t; rho = rho'.
+ * Breakdown (|rho'| or |(rh, v)| <= 1e-300 ||b||^2, or omega == 0)
+ * restarts the column with rh = r, rho = alpha = omega = 1, p = v = 0; two
+ * breakdowns without a completed iteration in between stop the column with
+ * ORC_EBREAKDOWN.
+ */
+static void bicg_reset(int n, int m, int j, const double *r, double *rh, double *p,
+                       double *v)
+{
+    size_t i, k;
+    for (i = 0; i < (size_t)n; i++) {
+        k = i * m + j;
+        rh[k] = r[k]; p[k] = 0.0; v[k] = 0.0;
+    }
+}
+
+static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
+                    const double *B, double *X, int *iters, double *relres,
+                    int *conv, vws *w)
+{
+    const ocsr *A = &h->A[0];
+    int n = A->nr, j, it, rc = ORC_OK;
+    size_t nm = (size_t)n * m, k, i;
+    double *r = (double *)malloc(nm * sizeof(double));
+    double *rh = (double *)malloc(nm * sizeof(double));
+    double *p = (double *)calloc(nm, sizeof(double));
+    double *v = (double *)calloc(nm, sizeof(double));
+    double *ph = (double *)calloc(nm, sizeof(double));
+    double *s = (double *)calloc(nm, sizeof(double));
+    double *sh = (double *)calloc(nm, sizeof(double));
+    double *t = (double *)calloc(nm, sizeof(double));
+    double *bn = (double *)malloc((size_t)m * sizeof(double));
+    double *rho = (double *)malloc((size_t)m * sizeof(double));
+    double *alp = (double *)malloc((size_t)m * sizeof(double));
+    double *omg = (double *)malloc((size_t)m * sizeof(double));
+    double *beta = (double *)malloc((size_t)m * sizeof(double));
+    double *d1 = (double *)malloc((size_t)m * sizeof(double));
+    double *d2 = (double *)malloc((size_t)m * sizeof(double));
+    int *act = (int *)malloc((size_t)m * sizeof(int));
+    int *brk = (int *)calloc((size_t)m, sizeof(int));   /* breakdowns in a row */
+    int *rst = (int *)calloc((size_t)m, sizeof(int));   /* restart pending */
+    int *skip = (int *)calloc((size_t)m, sizeof(int));  /* rest of iteration skipped */
+    int *half = (int *)calloc((size_t)m, sizeof(int));  /* converged at s */
+    int *upd = (int *)calloc((size_t)m, sizeof(int));   /* column updated this step */
+    if (!r || !rh || !p || !v || !ph || !s || !sh || !t || !bn || !rho || !alp ||
+        !omg || !beta || !d1 || !d2 || !act || !brk || !rst || !skip || !half || !upd)
+        return ORC_ENOMEM;
+
+    if (!ko->x0_given) memset(X, 0, nm * sizeof(double));
+    residual(A, m, B, X, r);
+    memcpy(rh, r, nm * sizeof(double));
+    dots(n, m, B, B, bn);
+    dots(n, m, r, r, d1);
+    for (j = 0; j < m; j++) {
+        bn[j] = sqrt(bn[j]);
+        rho[j] = alp[j] = omg[j] = 1.0;
+        iters[j] = 0; conv[j] = 0; act[j] = 1;
+        if (bn[j] == 0.0) {
+            for (i = 0; i < (size_t)n; i++) X[i * m + j] = 0.0;
+            relres[j] = 0.0; conv[j] = 1; act[j] = 0;
+            continue;
+        }
+        relres[j] = sqrt(d1[j]) / bn[j];
+        if (relres[j] <= ko->tol) { conv[j] = 1; act[j] = 0; }
+    }
+
+    for (it = 1; it <= ko->max_iters; it++) {
+        int any = 0;
+        for (j = 0; j < m; j++) any |= act[j];
+        if (!any) break;
+        /* rho' = (rh, r), beta, p = r + beta (p - omega v) */
+        for (j = 0; j < m; j++)
+            if (act[j] && rst[j]) {
+                bicg_reset(n, m, j, r, rh, p, v);
+                rho[j] = alp[j] = omg[j] = 1.0;
+                rst[j] = 0;
+            }
+        dots(n, m, rh, r, d1);
+        for (j = 0; j < m; j++) {
+            double tiny;
+            upd[j] = 0;
+            if (!act[j]) continue;
+            tiny = 1e-300 * bn[j] * bn[j];
+            if (fabs(d1[j]) <= tiny) {
+                if (++brk[j] >= 2) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
+                bicg_reset(n, m, j, r, rh, p, v);
+                rho[j] = alp[j] = omg[j] = 1.0;
+                d1[j] = dot_col(n, m, j, rh, r);
+            }
+            beta[j] = (d1[j] / rho[j]) * (alp[j] / omg[j]);
+            rho[j] = d1[j];
+            upd[j] = 1;
+        }
+        for (i = 0; i < (size_t)n; i++)
+            for (j = 0; j < m; j++)
+                if (upd[j]) {
+                    k = i * m + j;
+                    p[k] = r[k] + beta[j] * (p[k] - omg[j] * v[k]);
+                }
+        apply_prec(h, ko, so, m, p, ph, w);
+        spmm(A, m, ph, v);
+        /* alpha = rho' / (rh, v), s = r - alpha v */
+        dots(n, m, rh, v, d1);
+        for (j = 0; j < m; j++) {
+            double tiny;
+            upd[j] = 0;
+            if (!act[j]) continue;
+            iters[j] = it;
+            tiny = 1e-300 * bn[j] * bn[j];
+            if (fabs(d1[j]) <= tiny) {
+                if (++brk[j] >= 2) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
+                rst[j] = 1; skip[j] = 1;
+                continue;
+            }
+            alp[j] = rho[j] / d1[j];
+            upd[j] = 1;
+        }
+        for (i = 0; i < (size_t)n; i++)
+            for (j = 0; j < m; j++)
+                if (upd[j]) {
+                    k = i * m + j;
+                    s[k] = r[k] - alp[j] * v[k];
+                }
+        dots(n, m, s, s, d2);
+        for (j = 0; j < m; j++)
+            if (upd[j] && sqrt(d2[j]) / bn[j] <= ko->tol) {
+                for (i = 0; i < (size_t)n; i++) {
+                    k = i * m + j;
+                    X[k] += alp[j] * ph[k];
+                    r[k] = s[k];
+                }
+                half[j] = 1;
+            }
+        apply_prec(h, ko, so, m, s, sh, w);
+        spmm(A, m, sh, t);
+        /* omega = (t, s)/(t, t); x += alpha ph + omega sh; r = s - omega t */
+        dots(n, m, t, s, d1);
+        dots(n, m, t, t, d2);
+        for (j = 0; j < m; j++) {
+            upd[j] = 0;
+            if (!act[j]) continue;
+            if (skip[j] || half[j]) continue;
+            omg[j] = (d2[j] > 0.0) ? d1[j] / d2[j] : 0.0;
+            upd[j] = 1;
+        }
+        for (i = 0; i < (size_t)n; i++)
+            for (j = 0; j < m; j++)
+                if (upd[j]) {
+                    k = i * m + j;
+                    X[k] += alp[j] * ph[k] + omg[j] * sh[k];
+                    r[k] = s[k] - omg[j] * t[k];
+                }
+        dots(n, m, r, r, d1);
+        for (j = 0; j < m; j++) {
+            if (!act[j]) continue;
+            if (skip[j]) { skip[j] = 0; continue; }
+            if (upd[j]) {
+                if (omg[j] == 0.0) {
+                    if (++brk[j] >= 2) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
+                    rst[j] = 1;
+                } else {
+                    brk[j] = 0;
+                }
+            }
+            relres[j] = sqrt(d1[j]) / bn[j];
+            if (half[j] || relres[j] <= ko->tol) {
+                double tr = sqrt(residual_col_norm2(A, m, j, B, X)) / bn[j];
+                half[j] = 0;
+                if (tr <= ko->tol) { conv[j] = 1; act[j] = 0; }
+                else {
+                    /* recurrence drifted: restart column j from its iterate */
+                    for (i = 0; i < (size_t)n; i++) {
+                        double ax = 0.0;
+                        int kk;
+                        for (kk = A->rp[i]; kk < A->rp[i + 1]; kk++)
+                            ax += A->v[kk] * X[(size_t)A->ci[kk] * m + j];
+                        r[i * m + j] = B[i * m + j] - ax;
+                    }
+                    relres[j] = tr;
+                    rst[j] = 1;
+                }
+            }
+        }
+    }
+    for (j = 0; j < m; j++) if (!conv[j] && rc == ORC_OK) rc = ORC_NOT_CONVERGED;
+    free(r); free(rh); free(p); free(v); free(ph); free(s); free(sh); free(t);
+    free(bn); free(rho); free(alp); free(omg); free(beta); free(d1); free(d2);
+    free(act); free(brk); free(rst); free(skip); free(half); free(upd);
+    return rc;
+}
+
+/*
+ * Solve A X = B (A = level 0 of h).  X is the initial guess when x0_given,
+ * the solution on return.  Per-column outputs: iterations, recurrence
+ * relative residual, true relative residual, converged flag.
+ */
+int orc_solve(const ohier *h, int method, int smoother, double omega, int degree,
+              double lo_frac, double hi_frac, int flexible, int precond,
+              int max_iters, double tol, int x0_given, int m, const double *B,
+              double *X, int *iters, double *relres, double *true_relres, int *conv)
+{
+    vws w;
+    kopt ko = {method, flexible, max_iters, tol, x0_given, precond};
+    smopt so = {smoother, omega, degree, lo_frac, hi_frac};
+    int rc, j, n = h->A[0].nr;
+    size_t q, nm = (size_t)n * m;
+    double *t;
+    if (m < 1) return ORC_EINVAL;
+    for (q = 0; q < nm; q++) if (!isfinite(B[q])) return ORC_EINVAL;
+    if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
+    if (method == 0) rc = pcg(h, &ko, &so, m, B, X, iters, relres, conv, &w);
+    else rc = bicgstab(h, &ko, &so, m, B, X, iters, relres, conv, &w);
+    vws_free(&w, h->nlev);
+    t = (double *)malloc(nm * sizeof(double));
+    if (!t) return ORC_ENOMEM;
+    residual(&h->A[0], m, B, X, t);
+    {
+        double *bb = (double *)malloc((size_t)m * sizeof(double));
+        double *tt = (double *)malloc((size_t)m * sizeof(double));
+        dots(n, m, B, B, bb);
+        dots(n, m, t, t, tt);
+        for (j = 0; j < m; j++)
+            true_relres[j] = bb[j] > 0.0 ? sqrt(tt[j]) / sqrt(bb[j]) : 0.0;
+        free(bb); free(tt);
+    }
+    free(t);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single operations on caller CSR arrays, for the tests.                    */
+/* ------------------------------------------------------------------------ */
+void orc_spmm(int n, int ncols, const int *rp, const int *ci, const double *v, int m,
+              const double *X, double *Y)
+{
+    ocsr a;
+    a.nr = n; a.nc = ncols; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    spmm(&a, m, X, Y);
+}
+
+void orc_jacobi(int n, const int *rp, const int *ci, const double *v,
+                const double *dinv, double omega, int m, const double *b, double *x)
+{
+    ocsr a;
+    double *t = (double *)malloc((size_t)n * m * sizeof(double) + 8);
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    jacobi(&a, dinv, omega, m, b, x, t);
+    free(t);
+}
+
+void orc_chebyshev(int n, const int *rp, const int *ci, const double *v,
+                   const double *dinv, double lo, double hi, int degree, int m,
+                   const double *b, double *x)
+{
+    ocsr a;
+    size_t nm = (size_t)n * m + 1;
+    double *r = (double *)malloc(nm * sizeof(double));
+    double *d = (double *)malloc(nm * sizeof(double));
+    double *t = (double *)malloc(nm * sizeof(double));
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    chebyshev(&a, dinv, lo, hi, degree, m, b, x, r, d, t);
+    free(r); free(d); free(t);
+}
+
+double orc_lanczos(int n, const int *rp, const int *ci, const double *v, int steps,
+                   unsigned long long key)
+{
+    ocsr a;
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    return lanczos_lmax(&a, steps, (uint64_t)key);
+}
+
+double orc_sm64_uniform(unsigned long long key, unsigned long long i)
+{
+    return sm64_uniform((uint64_t)key, (uint64_t)i);
+}
+
+/* dense LU solve of an n x n row-major system, m columns of b (n x m) */
+int orc_dense_solve(int n, const double *a, int m, double *b)
+{
+    double *lu = (double *)malloc((size_t)n * n * sizeof(double) + 8);
+    int *piv = (int *)malloc((size_t)n * sizeof(int) + 4);
+    double *col = (double *)malloc((size_t)n * sizeof(double) + 8);
+    int i, j, rc = 0;
+    memcpy(lu, a, (size_t)n * n * sizeof(double));
+    if (dense_lu(n, lu, piv)) rc = ORC_EBREAKDOWN;
+    else
+        for (j = 0; j < m; j++) {
+            for (i = 0; i < n; i++) col[i] = b[(size_t)i * m + j];
+            dense_lu_solve(n, lu, piv, col);
+            for (i = 0; i < n; i++) b[(size_t)i * m + j] = col[i];
+        }
+    free(lu); free(piv); free(col);
+    return rc;
+}
+
+/* strength pattern and RS split of a caller matrix (for pin tests) */
+int orc_rs_split(int n, const int *rp, const int *ci, const double *v, double theta,
+                 int *state)
+{
+    ocsr a;
+    int *srp, *sci, *trp, *tci, rc;
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    if (strength(&a, theta, &srp, &sci)) return ORC_ENOMEM;
+    if (pattern_transpose(n, srp, sci, &trp, &tci)) return ORC_ENOMEM;
+    rc = rs_first_pass(n, srp, sci, trp, tci, state);
+    free(srp); free(sci); free(trp); free(tci);
+    return rc ? ORC_ENOMEM : ORC_OK;
+}
+
+int orc_strength_count(int n, const int *rp, const int *ci, const double *v,
+                       double theta, int *counts)
+{
+    ocsr a;
+    int *srp, *sci, i;
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    if (strength(&a, theta, &srp, &sci)) return ORC_ENOMEM;
+    for (i = 0; i < n; i++) counts[i] = srp[i + 1] - srp[i];
+    free(srp); free(sci);
+    return ORC_OK;
+}

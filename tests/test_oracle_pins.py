@@ -1,0 +1,595 @@
+"""Pins of the CPU oracle against facts fixed by mathematics (CPU only).
+
+Nothing here compares the oracle with itself: each check is a closed form,
+a textbook special case, a dense brute-force computation with NumPy, or an
+invariant that a dropped term, wrong sign, wrong index or transposed operand
+in the oracle would break.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2103_07329_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense(rp, ci, v, shape=None):
+    n = len(rp) - 1
+    if shape is None:
+        shape = (n, n)
+    return sp.csr_matrix((v, ci, rp), shape=shape).toarray()
+
+
+def lap1d(n):
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1],
+                 format="csr")
+    A.sort_indices()
+    return (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+            A.data.astype(np.float64))
+
+
+def eigpair(N, p, q, r, c=(1.0, 1.0, 1.0)):
+    """Closed-form eigenpair of the Dirichlet 7-point operator on N^3 with
+    axis weights c: v = prod sin(p pi (i+1)/(N+1)), lambda = 4 sum c s^2."""
+    ax = np.arange(1, N + 1)
+    sx = np.sin(p * np.pi * ax / (N + 1))
+    sy = np.sin(q * np.pi * ax / (N + 1))
+    sz = np.sin(r * np.pi * ax / (N + 1))
+    v = (sz[:, None, None] * sy[None, :, None] * sx[None, None, :]).ravel()
+    s = lambda t: np.sin(t * np.pi / (2 * (N + 1))) ** 2
+    lam = 4 * (c[0] * s(p) + c[1] * s(q) + c[2] * s(r))
+    return v, lam
+
+
+# --------------------------------------------------------------------------
+# assembly (input generator) and SpMM
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [3, 4, 5, 7])
+def test_poisson_assembly(N):
+    p = inputs.poisson7(N)
+    assert p.nnz == 7 * N ** 3 - 6 * N ** 2
+    A = dense(*p.csr())
+    assert np.array_equal(A, A.T)
+    rs = A.sum(axis=1).reshape(N, N, N)
+    kk, jj, ii = np.meshgrid(*(np.arange(N),) * 3, indexing="ij")
+    nb = sum(((x == 0) | (x == N - 1)).astype(int) for x in (ii, jj, kk))
+    if N > 1:
+        # interior 0, face 1, edge 2, corner 3 (points on 0..3 boundary planes)
+        assert np.array_equal(rs, nb.astype(float))
+    for r_ in range(p.n):
+        cols = p.col[p.rowptr[r_]:p.rowptr[r_ + 1]]
+        assert np.all(np.diff(cols) > 0)
+
+
+@pytest.mark.parametrize("gen,c", [(inputs.poisson7, (1, 1, 1)),
+                                   (inputs.anisotropic7, (1, 1, 0.01))])
+def test_spmm_eigenvectors(orc, gen, c):
+    N = 9
+    p = gen(N)
+    modes = [(1, 1, 1), (2, 3, 1), (9, 1, 4), (5, 5, 5), (9, 9, 9)]
+    V = np.stack([eigpair(N, *md, c=c)[0] for md in modes], axis=1)
+    lam = np.array([eigpair(N, *md, c=c)[1] for md in modes])
+    Y = orc.spmm(*p.csr(), V)
+    assert np.allclose(Y, V * lam[None, :], rtol=0, atol=1e-13 * np.abs(V).max() * lam.max())
+
+
+def test_spmm_bruteforce_rectangular(orc):
+    rng = np.random.default_rng(3)
+    for (nr, nc, m) in [(17, 11, 1), (64, 200, 3), (130, 70, 8), (5, 5, 32)]:
+        M = sp.random(nr, nc, density=0.2, random_state=rng, format="csr")
+        M.sort_indices()
+        X = rng.standard_normal((nc, m))
+        Y = orc.spmm(M.indptr, M.indices, M.data, X, ncols=nc)
+        assert np.allclose(Y, M.toarray() @ X, rtol=1e-14, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# setup: strength, RS split, direct interpolation, Galerkin
+# --------------------------------------------------------------------------
+def _read_golden_1d():
+    d = {}
+    with open(os.path.join(GOLDEN, "rs_1d_model.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.split()
+    return d
+
+
+def test_rs_1d_textbook(orc):
+    g = _read_golden_1d()
+    n = int(g["n"][0])
+    rp, ci, v = lap1d(n)
+    st = orc.rs_split(rp, ci, v)
+    assert list(np.nonzero(st == 1)[0]) == [int(x) for x in g["cpoints"]]
+    H = orc.Hierarchy(rp, ci, v, max_coarse=3)
+    assert H.nlev == 2
+    prp, pci, pv, (pr, pc) = H.P(0)
+    Pd = dense(prp, pci, pv, (pr, pc))
+    Pg = np.zeros((n, len(g["cpoints"])))
+    for i in range(n):
+        for ent in g[f"P{i}"]:
+            c_, w = ent.split(":")
+            Pg[i, int(c_)] = float(w)
+    assert np.array_equal(Pd, Pg)
+    arp, aci, av, _ = H.A(1)
+    Ac = dense(arp, aci, av)
+    Ag = np.array([float(x) for x in g["Ac"]]).reshape(Ac.shape)
+    assert np.allclose(Ac, Ag, rtol=0, atol=1e-15)
+    # R = P^T explicitly
+    rrp, rci, rv, (rr, rc) = H.R(0)
+    assert np.array_equal(dense(rrp, rci, rv, (rr, rc)), Pg.T)
+
+
+@pytest.mark.parametrize("N", [4, 5, 6])
+def test_rs_3d_red_black(orc, N):
+    """On the isotropic 7-point stencil with lowest-index ties, the first
+    pass picks exactly the points with i+j+k odd, and every F point (all of
+    whose neighbours are then C) interpolates with weight 1/6 from each."""
+    p = inputs.poisson7(N)
+    st = orc.rs_split(*p.csr())
+    kk, jj, ii = np.meshgrid(*(np.arange(N),) * 3, indexing="ij")
+    odd = ((ii + jj + kk) % 2 == 1).ravel()
+    assert np.array_equal(st == 1, odd)
+    assert (st == 1).sum() == p.n // 2
+    H = orc.Hierarchy(*p.csr(), max_coarse=8)
+    prp, pci, pv, _ = H.P(0)
+    for i in np.nonzero(~odd)[0]:
+        w = pv[prp[i]:prp[i + 1]]
+        deg = p.rowptr[i + 1] - p.rowptr[i] - 1
+        assert len(w) == deg
+        assert np.allclose(w, 1.0 / 6.0, rtol=0, atol=1e-15)
+
+
+def _problems_small():
+    rng = np.random.default_rng(11)
+    return [inputs.poisson7(7), inputs.anisotropic7(7),
+            inputs.jump7(8, inputs.jump_kappa(8, rng, block=2))]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_galerkin_and_invariants(orc, k):
+    p = _problems_small()[k]
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    assert H.nlev >= 2
+    for l in range(H.nlev - 1):
+        arp, aci, av, (n, _) = H.A(l)
+        A = dense(arp, aci, av)
+        prp, pci, pv, (pr, pc) = H.P(l)
+        P = dense(prp, pci, pv, (pr, pc))
+        rrp, rci, rv, (rr, rc) = H.R(l)
+        R = dense(rrp, rci, rv, (rr, rc))
+        Ac = dense(*H.A(l + 1)[:3])
+        assert np.array_equal(R, P.T)
+        ref = P.T @ A @ P
+        assert np.allclose(Ac, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+        assert np.allclose(Ac, Ac.T, rtol=0, atol=1e-13 * np.abs(Ac).max())
+        assert np.linalg.eigvalsh(Ac).min() > 0
+        cf = H.cf(l)
+        assert pc == (cf == 1).sum()
+        # C rows are unit rows at the coarse index (increasing fine order)
+        cidx = np.cumsum(cf == 1) - 1
+        for i in range(n):
+            row = P[i]
+            if cf[i] == 1:
+                e = np.zeros(pc); e[cidx[i]] = 1.0
+                assert np.array_equal(row, e)
+            else:
+                # every F point interpolates from >= 1 strong C neighbour,
+                # only from C points it is connected to
+                nzc = np.nonzero(row)[0]
+                assert len(nzc) >= 1
+                fine = np.nonzero(cf == 1)[0][nzc]
+                assert np.all(A[i, fine] < 0)
+                # zero-row-sum rows interpolate constants exactly
+                if abs(A[i].sum()) < 1e-12 * A[i, i]:
+                    assert abs(row.sum() - 1.0) < 1e-13
+
+
+def test_direct_interpolation_weights_formula(orc):
+    """Direct interpolation on a row where only part of the neighbourhood
+    is interpolatory: weights must be alpha * |a_ik| / a_ii with
+    alpha = sum of all negative off-diagonals / sum over the C set."""
+    p = inputs.jump7(8, inputs.jump_kappa(8, np.random.default_rng(5), block=2))
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    A = dense(*H.A(0)[:3])
+    prp, pci, pv, (pr, pc) = H.P(0)
+    P = dense(prp, pci, pv, (pr, pc))
+    cf = H.cf(0)
+    cpts = np.nonzero(cf == 1)[0]
+    checked = 0
+    for i in np.nonzero(cf == 2)[0]:
+        row = A[i].copy()
+        off = row.copy(); off[i] = 0
+        nz = np.nonzero(P[i])[0]
+        Ci = cpts[nz]
+        alpha = off[off < 0].sum() / row[Ci].sum()
+        expect = -alpha * row[Ci] / A[i, i]
+        assert np.allclose(P[i, nz], expect, rtol=1e-13, atol=0)
+        if len(Ci) < (off < 0).sum():
+            checked += 1
+    assert checked > 10
+
+
+def test_coarse_dense_solve(orc):
+    p = inputs.poisson7(12)
+    H = orc.Hierarchy(*p.csr())
+    L = H.nlev - 1
+    arp, aci, av, (nL, _) = H.A(L)
+    assert nL <= 64
+    AL = dense(arp, aci, av)
+    b = np.random.default_rng(2).standard_normal((nL, 3))
+    x = orc.dense_solve(AL, b)
+    assert np.allclose(x, np.linalg.solve(AL, b), rtol=1e-12, atol=1e-13)
+    # the coarsest correction of a V-cycle on a one-level hierarchy is A^-1
+    H1 = orc.Hierarchy(arp, aci, av)
+    assert H1.nlev == 1
+    assert np.allclose(H1.vcycle(b), np.linalg.solve(AL, b), rtol=1e-12, atol=1e-13)
+
+
+def test_hierarchy_stops_and_sizes(orc):
+    p = inputs.poisson7(32)
+    H = orc.Hierarchy(*p.csr())
+    sz = H.sizes()
+    assert sz[-1] <= 64 and sz[-2] > 64
+    assert sz[1] == p.n // 2
+    assert all(sz[l + 1] <= 0.9 * sz[l] for l in range(len(sz) - 1))
+
+
+# --------------------------------------------------------------------------
+# smoothers
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("gen,c,dg", [(inputs.poisson7, (1, 1, 1), 6.0),
+                                      (inputs.anisotropic7, (1, 1, 0.01), 4.02)])
+def test_jacobi_error_factor(orc, gen, c, dg):
+    N = 8
+    p = gen(N)
+    modes = [(1, 1, 1), (3, 2, 7), (8, 8, 8), (4, 6, 1)]
+    V = np.stack([eigpair(N, *md, c=c)[0] for md in modes], axis=1)
+    lam = np.array([eigpair(N, *md, c=c)[1] for md in modes])
+    B = V * lam
+    dinv = np.full(p.n, 1.0 / dg)
+    omega = 2.0 / 3.0
+    X = orc.jacobi(*p.csr(), dinv, omega, B, np.zeros_like(B))
+    E = V - X
+    fac = 1 - omega * lam / dg
+    assert np.allclose(E, V * fac, rtol=0, atol=1e-13)
+    # second sweep squares the factor
+    X2 = orc.jacobi(*p.csr(), dinv, omega, B, X)
+    assert np.allclose(V - X2, V * fac ** 2, rtol=0, atol=1e-13)
+
+
+def test_chebyshev_error_factor(orc):
+    N = 8
+    p = inputs.poisson7(N)
+    modes = [(1, 1, 1), (3, 2, 7), (8, 8, 8), (4, 6, 1), (6, 6, 6)]
+    V = np.stack([eigpair(N, *md)[0] for md in modes], axis=1)
+    lam = np.array([eigpair(N, *md)[1] for md in modes])
+    B = V * lam
+    dinv = np.full(p.n, 1.0 / 6.0)
+    mu = lam / 6.0
+    hi, lo = 2.1, 0.63
+    theta, delta = (hi + lo) / 2, (hi - lo) / 2
+    T1 = lambda x: x
+    T2 = lambda x: 2 * x * x - 1
+    T3 = lambda x: 4 * x ** 3 - 3 * x
+    for deg, T in [(1, T1), (2, T2), (3, T3)]:
+        X = orc.chebyshev(*p.csr(), dinv, lo, hi, deg, B, np.zeros_like(B))
+        fac = T((theta - mu) / delta) / T(theta / delta)
+        assert np.allclose(V - X, V * fac, rtol=0, atol=1e-12), deg
+
+
+def test_splitmix64_golden(orc):
+    vals = []
+    with open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                vals.append(int(line, 16))
+    for i, z in enumerate(vals):
+        expect = (z >> 11) * 2.0 ** -53 * 2.0 - 1.0
+        assert orc.sm64_uniform(0, i) == expect
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_lanczos_estimate(orc, N):
+    p = inputs.poisson7(N)
+    lam = orc.lanczos_lmax(*p.csr(), 10)
+    # lambda_max(D^-1 A) = 4 * 3 sin^2(N pi / (2 (N+1))) / 6
+    exact = 12 * np.sin(N * np.pi / (2 * (N + 1))) ** 2 / 6
+    assert lam <= exact * (1 + 1e-12)
+    assert lam >= 0.97 * exact
+    # more steps can only move the largest Ritz value up (interlacing)
+    assert orc.lanczos_lmax(*p.csr(), 20) >= lam - 1e-12
+
+
+# --------------------------------------------------------------------------
+# V-cycle
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("k", [0, 2])
+def test_vcycle_symmetric_positive(orc, smoother, k):
+    p = _problems_small()[k]
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    assert H.nlev >= 3
+    rng = np.random.default_rng(4)
+    U = rng.standard_normal((p.n, 6))
+    MU = H.vcycle(U, smoother=smoother)
+    G = U.T @ MU
+    assert np.allclose(G, G.T, rtol=0, atol=1e-12 * np.abs(G).max())
+    assert np.linalg.eigvalsh(0.5 * (G + G.T)).min() > 0
+
+
+def test_vcycle_is_contraction(orc):
+    """With exact coarse solve and convergent smoothers, the V-cycle error
+    operator I - M A has A-norm < 1."""
+    p = inputs.poisson7(10)
+    A = dense(*p.csr())
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    for smoother in (0, 1):
+        MA = H.vcycle(A, smoother=smoother)        # columns: M A e_i
+        E = np.eye(p.n) - MA
+        L = np.linalg.cholesky(A)
+        # ||E||_A = ||L^T E L^-T||_2
+        M2 = L.T @ E @ np.linalg.inv(L.T)
+        assert np.linalg.norm(M2, 2) < 0.5
+
+
+# --------------------------------------------------------------------------
+# Krylov
+# --------------------------------------------------------------------------
+def test_one_level_pcg_one_iteration(orc):
+    p = inputs.poisson7(4)           # n = 64: the hierarchy is one level
+    H = orc.Hierarchy(*p.csr())
+    assert H.nlev == 1
+    B = inputs.uniform_rhs(p.n, 3, 5)
+    X, st, rc = H.solve(B, tol=1e-12)
+    assert rc == 0 and np.all(st["iters"] == 1)
+    assert np.allclose(X, np.linalg.solve(dense(*p.csr()), B), rtol=1e-12, atol=1e-14)
+    X, st, rc = H.solve(B, method=orc.BICGSTAB, tol=1e-12)
+    assert rc == 0 and np.all(st["iters"] == 1)
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_krylov_dense_bruteforce(orc, method, smoother, k):
+    p = _problems_small()[k]
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    B = inputs.uniform_rhs(p.n, 4, 9)
+    X, st, rc = H.solve(B, method=method, smoother=smoother, tol=1e-12)
+    assert rc == 0
+    Xd = np.linalg.solve(dense(*p.csr()), B)
+    assert np.allclose(X, Xd, rtol=0, atol=1e-10 * np.abs(Xd).max())
+    assert np.all(st["true_relres"] <= 1e-12)
+
+
+def test_pcg_a_norm_error_monotone(orc):
+    p = inputs.jump7(8, inputs.jump_kappa(8, np.random.default_rng(7), block=2))
+    A = dense(*p.csr())
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    b = inputs.uniform_rhs(p.n, 1, 3)[:, 0]
+    xs = np.linalg.solve(A, b)
+    prev = np.inf
+    for k in range(1, 12):
+        x, st, rc = H.solve(b, max_iters=k, tol=1e-300)
+        e = x - xs
+        en = np.sqrt(e @ A @ e)
+        assert en <= prev * (1 + 1e-10)
+        prev = en
+    # unpreconditioned too
+    prev = np.inf
+    for k in range(1, 30):
+        x, st, rc = H.solve(b, max_iters=k, tol=1e-300, precond=False)
+        e = x - xs
+        en = np.sqrt(e @ A @ e)
+        assert en <= prev * (1 + 1e-10)
+        prev = en
+
+
+def test_cg_eigenvector_one_iteration(orc):
+    N = 8
+    p = inputs.poisson7(N)
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    v, lam = eigpair(N, 2, 5, 3)
+    for method in (0, 1):
+        x, st, rc = H.solve(v, method=method, precond=False, tol=1e-12)
+        assert rc == 0 and st["iters"][0] == 1
+        assert np.allclose(x, v / lam, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("method,smoother", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_column_independence_bitwise(orc, method, smoother):
+    p = inputs.poisson7(12)
+    H = orc.Hierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 5, 21)
+    X, st, rc = H.solve(B, method=method, smoother=smoother)
+    for j in range(5):
+        xj, sj, _ = H.solve(B[:, j].copy(), method=method, smoother=smoother)
+        assert np.array_equal(xj, X[:, j])
+        assert sj["iters"][0] == st["iters"][j]
+
+
+def test_edge_cases(orc):
+    p = inputs.poisson7(10)
+    H = orc.Hierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 3, 1)
+    B[:, 1] = 0.0
+    X, st, rc = H.solve(B)
+    assert rc == 0
+    assert np.all(X[:, 1] == 0) and st["iters"][1] == 0 and st["converged"][1]
+    # iteration cap: not converged, stats still valid
+    X, st, rc = H.solve(B, max_iters=1)
+    assert rc == orc.NOT_CONVERGED
+    assert not st["converged"][0] and st["iters"][0] == 1
+    assert np.all(np.isfinite(st["relres"]))
+    # NaN input rejected
+    Bn = B.copy(); Bn[5, 0] = np.nan
+    _, _, rc = H.solve(Bn)
+    assert rc == orc.EINVAL
+    # given initial guess = solution: converged in 0 iterations
+    Xs, st, rc = H.solve(B, tol=1e-12)
+    X2, st2, rc2 = H.solve(B, X0=Xs, tol=1e-10)
+    assert rc2 == 0 and np.all(st2["iters"] == 0)
+
+
+def test_flexible_beta_matches_fletcher_reeves_in_fp64(orc):
+    p = inputs.poisson7(16)
+    H = orc.Hierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 3, 8)
+    X1, s1, _ = H.solve(B, flexible=False)
+    X2, s2, _ = H.solve(B, flexible=True)
+    assert np.array_equal(s1["iters"], s2["iters"])
+    assert np.allclose(X1, X2, rtol=0, atol=1e-9 * np.abs(X1).max())
+
+
+def _rs_bruteforce(A, theta=0.25):
+    """First-pass Ruge-Stueben split computed from the definition: the
+    weight of an undecided point is |S^T n U| + 2 |S^T n F|, recomputed from
+    scratch before every pick (largest weight, lowest index first)."""
+    n = A.shape[0]
+    S = []
+    for i in range(n):
+        off = [-A[i, j] for j in range(n) if j != i]
+        mx = max(off) if off else 0.0
+        S.append({j for j in range(n) if j != i and mx > 0 and -A[i, j] >= theta * mx})
+    ST = [{j for j in range(n) if i in S[j]} for i in range(n)]
+    state = ["U"] * n
+    while "U" in state:
+        best, bi = -1, -1
+        for i in range(n):
+            if state[i] != "U":
+                continue
+            lam = sum(1 for j in ST[i] if state[j] == "U") + \
+                2 * sum(1 for j in ST[i] if state[j] == "F")
+            if lam > best:
+                best, bi = lam, i
+        state[bi] = "C"
+        for j in ST[bi]:
+            if state[j] == "U":
+                state[j] = "F"
+    return np.array([1 if s == "C" else 2 for s in state], np.int32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_rs_split_bruteforce_irregular(orc, seed):
+    rng = np.random.default_rng(seed)
+    if seed < 2:
+        p = inputs.jump7(6, inputs.jump_kappa(6, rng, block=2))
+        rp, ci, v = p.csr()
+    else:
+        # random weighted graph Laplacian + small diagonal shift (M-matrix)
+        n = 150
+        W = sp.random(n, n, density=0.04, random_state=rng) * 10
+        W = sp.triu(W, 1)
+        W = (W + W.T).tocsr()
+        L = sp.diags(np.asarray(W.sum(axis=1)).ravel() + 0.1) - W
+        L = sp.csr_matrix(L); L.sort_indices()
+        rp, ci, v = (L.indptr.astype(np.int32), L.indices.astype(np.int32),
+                     L.data.astype(np.float64))
+    A = dense(rp, ci, v)
+    st = orc.rs_split(rp, ci, v)
+    assert np.array_equal(st, _rs_bruteforce(A))
+
+
+def _random_mixed_sign(n, seed, pos_frac=0.3):
+    """Symmetric, strictly diagonally dominant, some positive off-diagonals."""
+    rng = np.random.default_rng(seed)
+    W = sp.random(n, n, density=0.06, random_state=rng).tocsr()
+    W.data = W.data * np.where(rng.random(W.nnz) < pos_frac, -0.3, 1.0)
+    W = sp.triu(W, 1)
+    W = (W + W.T).tocsr()
+    d = np.asarray(abs(W).sum(axis=1)).ravel() + 0.5
+    A = sp.csr_matrix(sp.diags(d) - W)
+    A.sort_indices()
+    return (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+            A.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("seed", [10, 11, 12, 13, 14, 15])
+def test_rs_split_bruteforce_mixed(orc, seed):
+    rp, ci, v = _random_mixed_sign(120 + 10 * seed, seed)
+    assert np.array_equal(orc.rs_split(rp, ci, v), _rs_bruteforce(dense(rp, ci, v)))
+
+
+def test_direct_interpolation_positive_offdiagonals(orc):
+    """Rows with positive off-diagonal entries: the interpolatory set holds
+    only negative (strong) couplings, so the positive part of the row is
+    added to the diagonal: w_ik = -alpha a_ik / (a_ii + sum_j a_ij^+)."""
+    rp, ci, v = _random_mixed_sign(300, 42)
+    H = orc.Hierarchy(rp, ci, v, max_coarse=40)
+    A = dense(rp, ci, v)
+    prp, pci, pv, (pr, pc) = H.P(0)
+    P = dense(prp, pci, pv, (pr, pc))
+    cf = H.cf(0)
+    cpts = np.nonzero(cf == 1)[0]
+    npos = 0
+    for i in np.nonzero(cf == 2)[0]:
+        off = A[i].copy(); off[i] = 0
+        nz = np.nonzero(P[i])[0]
+        Ci = cpts[nz]
+        alpha = off[off < 0].sum() / A[i, Ci].sum()
+        d = A[i, i] + off[off > 0].sum()
+        npos += (off > 0).any()
+        assert np.allclose(P[i, nz], -alpha * A[i, Ci] / d, rtol=1e-13, atol=0)
+    assert npos > 20
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_two_grid_error_operator(orc, smoother):
+    """With two levels the cycle's error propagation is the closed form
+    E = S (I - P A_c^{-1} P^T A) S, S the smoother's error operator:
+    Jacobi S = I - w D^-1 A; Chebyshev degree 2 on [lo, hi]:
+    S = T_2((theta I - D^-1 A)/delta) / T_2(theta/delta)."""
+    p = inputs.jump7(6, inputs.jump_kappa(6, np.random.default_rng(3), block=2))
+    H = orc.Hierarchy(*p.csr(), max_coarse=200)
+    assert H.nlev == 2
+    A = dense(*p.csr())
+    P = dense(*H.P(0)[:3], H.P(0)[3])
+    Ac = P.T @ A @ P
+    DA = A / np.diag(A)[:, None]
+    I = np.eye(p.n)
+    if smoother == 0:
+        S = I - (2.0 / 3.0) * DA
+    else:
+        hi = 1.1 * H.lmax(0); lo = 0.3 * hi
+        th, de = (hi + lo) / 2, (hi - lo) / 2
+        Y = (th * I - DA) / de
+        S = (2 * Y @ Y - I) / (2 * (th / de) ** 2 - 1)
+    E = S @ (I - P @ np.linalg.solve(Ac, P.T @ A)) @ S
+    MA = H.vcycle(A, smoother=smoother)
+    assert np.allclose(I - MA, E, rtol=0, atol=1e-11)
+
+
+def _lognormal_graph_laplacian(n, seed, dens=0.05, sigma=2.0):
+    """Graph Laplacian (+0.1 I) with log-normal edge weights: row maxima
+    differ widely, so the strength relation is far from symmetric."""
+    rng = np.random.default_rng(seed)
+    W = sp.random(n, n, density=dens, random_state=rng).tocsr()
+    W.data = np.exp(sigma * rng.standard_normal(W.nnz))
+    W = sp.triu(W, 1)
+    W = (W + W.T).tocsr()
+    A = sp.csr_matrix(sp.diags(np.asarray(W.sum(axis=1)).ravel() + 0.1) - W)
+    A.sort_indices()
+    return (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+            A.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5, 7, 9])
+def test_rs_split_bruteforce_asymmetric_strength(orc, seed):
+    rp, ci, v = _lognormal_graph_laplacian(100, seed)
+    assert np.array_equal(orc.rs_split(rp, ci, v), _rs_bruteforce(dense(rp, ci, v)))
+
+
+@pytest.mark.parametrize("kz,strong", [(0.25, 6), (0.2499, 4), (1.0, 6), (0.01, 4)])
+def test_strength_threshold_inclusive(orc, kz, strong):
+    """-a_ij >= theta max_k(-a_ik): with theta = 0.25 a z-coupling of exactly
+    0.25 is strong, one just below is weak (interior rows)."""
+    N = 5
+    p = inputs.anisotropic7(N, 1.0, 1.0, kz)
+    c = orc.strength_counts(*p.csr(), theta=0.25).reshape(N, N, N)
+    assert np.all(c[1:-1, 1:-1, 1:-1] == strong)
