@@ -1,0 +1,197 @@
+/*
+ * xamg.h -- C ABI of libxamg.so, an MI355X (gfx950) solve phase for sparse
+ * linear systems with multiple right-hand sides, A X = B with X, B of size
+ * n x m (Krasnopolsky and Medvedev, "XAMG: a library for solving linear
+ * systems with multiple right-hand side vectors", Section 1, the equation
+ * A X = B; Sections 2.1-2.2 for the methods and the multi-RHS design).
+ *
+ * The method: classical algebraic multigrid (Ruge-Stueben coarsening,
+ * direct interpolation, Galerkin coarse operators), built once on the host,
+ * used as a V(1,1) preconditioner with Jacobi or Chebyshev smoothing for CG
+ * or BiCGStab (Section 2.1, Table 1); the m columns are independent systems
+ * that share every matrix load (Section 2.2).  Optional reduced-precision
+ * preconditioner and compressed indices follow Section 2.3 ("data
+ * compression": mixed precision, smaller index types in row blocks).
+ *
+ * Conventions for every call:
+ *   - Return value: XAMG_OK (0), XAMG_NOT_CONVERGED (+1, a warning: outputs
+ *     valid) or a negative error code; a detail string for the last error
+ *     of the calling thread is available from xamg_last_error().  No C++
+ *     exception crosses this interface.
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are
+ *     hipMalloc'ed (e.g. PyTorch CUDA/HIP tensors) memory of the current
+ *     device.  The caller owns every pointer it passes; the library copies
+ *     what it keeps.
+ *   - Blocks of m vectors are stored row-major n x m ("interleaved"):
+ *     element (i, j) at [i*m + j], contiguous, float64.
+ *   - CSR matrices: int32 row_ptr (nrows + 1, row_ptr[0] = 0, nondecreasing),
+ *     int32 col (nnz, strictly increasing within a row, 0 <= col < ncols),
+ *     float64 val (nnz).  Square operators must store their diagonal.
+ */
+#ifndef XAMG_H
+#define XAMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes --------------------------------------------------------- */
+#define XAMG_OK 0
+#define XAMG_NOT_CONVERGED 1 /* max_iters reached; X = last iterate, stats valid */
+#define XAMG_EINVAL (-1)     /* bad argument: CSR, sizes, m, NaN/Inf in B, null */
+#define XAMG_ENOMEM (-2)     /* host or device allocation failed */
+#define XAMG_EHIP (-3)       /* HIP runtime error (code in xamg_last_error) */
+#define XAMG_ENODEV (-4)     /* no usable gfx950 device */
+#define XAMG_EBREAKDOWN (-5) /* singular coarse matrix, stalled coarsening, or a
+                                Krylov breakdown that persists after restart */
+
+#define XAMG_MAX_LEVELS 64
+#define XAMG_MAX_M 32 /* columns per solve: 1..32 */
+
+/* ---- enums --------------------------------------------------------------- */
+enum { XAMG_CG = 0, XAMG_BICGSTAB = 1 };
+enum { XAMG_JACOBI = 0, XAMG_CHEBYSHEV = 1 };
+enum { XAMG_FP64 = 0, XAMG_MIXED = 1 };
+enum { XAMG_X0_ZERO = 0, XAMG_X0_GIVEN = 1 };
+enum { XAMG_OP_A = 0, XAMG_OP_P = 1, XAMG_OP_R = 2 };
+
+/* ---- data types ---------------------------------------------------------- */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    const int32_t *row_ptr; /* host */
+    const int32_t *col;     /* host */
+    const double *val;      /* host */
+} xamg_csr_t;
+
+/* A multigrid hierarchy as plain host arrays (level 0 = the system matrix).
+ * P[l] is n_l x n_{l+1} (prolongation), R[l] = P[l]^T is n_{l+1} x n_l,
+ * A[l+1] = R[l] A[l] P[l].  lmax[l] estimates lambda_max(D_l^-1 A_l) and is
+ * used by the Chebyshev smoother only (ignored for the coarsest level). */
+typedef struct {
+    int32_t nlevels;       /* 1..XAMG_MAX_LEVELS */
+    const xamg_csr_t *A;   /* [nlevels] */
+    const xamg_csr_t *P;   /* [nlevels - 1] */
+    const xamg_csr_t *R;   /* [nlevels - 1] */
+    const double *lmax;    /* [nlevels] */
+} xamg_hierarchy_t;
+
+/* Setup parameters of the classical AMG hierarchy (host). */
+typedef struct {
+    double theta;          /* strength threshold, default 0.25 */
+    int32_t max_coarse;    /* stop when a level has <= this many rows, default 64 */
+    int32_t max_levels;    /* error (XAMG_EBREAKDOWN) beyond this, default 40 */
+    int32_t lanczos_steps; /* steps of the lambda_max estimate, default 10 */
+} xamg_setup_params_t;
+
+/* Solver options. */
+typedef struct {
+    int32_t method;        /* XAMG_CG (default) or XAMG_BICGSTAB */
+    int32_t smoother;      /* XAMG_JACOBI (default) or XAMG_CHEBYSHEV */
+    double omega;          /* Jacobi damping, default 2/3 */
+    int32_t cheby_degree;  /* Chebyshev polynomial degree, 1 or 2 (default 2) */
+    double cheby_lo_frac;  /* interval [lo_frac * hi, hi], default 0.3 */
+    double cheby_hi_frac;  /* hi = hi_frac * lmax, default 1.1 */
+    int32_t precision;     /* XAMG_FP64 (default) or XAMG_MIXED: FP32 V-cycle */
+    int32_t index_bits;    /* 32 (default) or 16: compressed preconditioner indices */
+    int32_t max_iters;     /* default 1000 */
+    int32_t x0_mode;       /* XAMG_X0_ZERO (default) or XAMG_X0_GIVEN */
+    int32_t flexible;      /* CG beta: 0 Fletcher-Reeves, 1 flexible; MIXED forces 1 */
+    int32_t check_every;   /* host convergence poll period in iterations, default 1 */
+    void *stream;          /* hipStream_t for all work; NULL = the null stream */
+} xamg_options_t;
+
+/* Per-column solve statistics. */
+typedef struct {
+    int32_t iters;       /* Krylov iterations the column was active */
+    int32_t converged;   /* 1 if ||b - A x|| / ||b|| <= tol */
+    double relres;       /* recurrence residual norm / ||b|| at exit */
+    double true_relres;  /* ||b - A x|| / ||b|| recomputed at exit (FP64) */
+} xamg_stats_t;
+
+typedef struct xamg_host_hierarchy xamg_host_hierarchy_t;
+typedef struct xamg_handle xamg_handle_t;
+
+/* ---- host setup (prerequisite, not part of the timed solve) -------------- */
+
+/* Defaults: theta 0.25, max_coarse 64, max_levels 40, lanczos_steps 10. */
+void xamg_default_setup_params(xamg_setup_params_t *p);
+
+/* Build the classical AMG hierarchy of A on the host (Section 2.3: the
+ * multigrid setup phase, which the paper delegates to hypre's classical
+ * AMG; Section 1).  A is validated (EINVAL on a malformed or non-square CSR
+ * or a missing diagonal).  params may be NULL for the defaults.  On success
+ * *out owns all arrays; release with xamg_hierarchy_free.  EBREAKDOWN if
+ * coarsening stalls (a level keeps > 0.9 of its rows) or needs more than
+ * max_levels levels. */
+int xamg_hierarchy_build(const xamg_csr_t *A, const xamg_setup_params_t *params,
+                         xamg_host_hierarchy_t **out);
+
+/* Fill *view with pointers into h (valid until xamg_hierarchy_free). */
+int xamg_hierarchy_view(const xamg_host_hierarchy_t *h, xamg_hierarchy_t *view);
+
+/* Copy the C/F split of level `level` (1 = C, 2 = F, one byte per row of
+ * A[level]) into cf (host, caller-allocated). */
+int xamg_hierarchy_cf(const xamg_host_hierarchy_t *h, int32_t level, int8_t *cf);
+
+void xamg_hierarchy_free(xamg_host_hierarchy_t *h);
+
+/* ---- device solver ------------------------------------------------------- */
+
+/* Defaults as listed in xamg_options_t. */
+void xamg_default_options(xamg_options_t *o);
+
+/* Upload a hierarchy to the current device and prepare the solver (the
+ * paper's construct_solver_hierarchy, Section 2.4).  H and its arrays are
+ * host memory, deep-copied; the caller may free them on return.  Computes
+ * D^-1 per level, the inverse of the coarsest matrix from its LU
+ * factorisation (EBREAKDOWN if singular), FP32 copies and 16-bit index
+ * encodings when the options ask for them.  opt may be NULL (defaults).
+ * EINVAL on inconsistent sizes or invalid CSR; ENODEV without a gfx950
+ * device; ENOMEM when device memory runs out. */
+int xamg_setup(const xamg_hierarchy_t *H, const xamg_options_t *opt,
+               xamg_handle_t **out);
+
+/* Solve A X = B for m columns (1 <= m <= XAMG_MAX_M) to relative residual
+ * ||b_j - A x_j|| / ||b_j|| <= tol per column (Section 2.4: solver->solve()).
+ * B (n x m, device, read-only) and X (n x m, device, in/out: the initial
+ * guess when x0_mode = GIVEN, overwritten with the solution) are caller
+ * memory valid for the call.  stats (host, m entries) may be NULL.  The
+ * call blocks until the solve ends; all device work runs on opt.stream.
+ * A zero column of B yields a zero column of X, 0 iterations, converged.
+ * Returns OK, NOT_CONVERGED, EINVAL (m out of range, tol <= 0, NaN/Inf in
+ * B, null pointers), EBREAKDOWN (persistent Krylov breakdown), EHIP. */
+int xamg_solve(xamg_handle_t *h, const double *B, double *X, int32_t m, double tol,
+               xamg_stats_t *stats);
+
+/* Apply one V(1,1) cycle from a zero guess, X = M^-1 B (device, n x m
+ * interleaved, float64), with the smoother and precision of the handle.
+ * m in {1, 2, 4, 8, 16, 32}. */
+int xamg_vcycle(xamg_handle_t *h, const double *B, double *X, int32_t m);
+
+/* Y = Op X for Op = A[level] (XAMG_OP_A), P[level] or R[level], in the
+ * handle's FP64 copy (device pointers, row-major interleaved float64;
+ * X has ncols(Op) rows, Y nrows(Op)).  m in {1, 2, 4, 8, 16, 32}. */
+int xamg_spmm(xamg_handle_t *h, int32_t op, int32_t level, int32_t m,
+              const double *X, double *Y);
+
+/* Sizes of the uploaded hierarchy: out[0] = nlevels, then per level l
+ * out[1 + 3l .. 3 + 3l] = n_l, nnz(A_l), nnz(P_l) (0 for the coarsest).
+ * `cap` is the length of out; returns EINVAL if too short. */
+int xamg_info(const xamg_handle_t *h, int64_t *out, int32_t cap);
+
+/* Release every device and host resource of h (NULL is allowed). */
+int xamg_destroy(xamg_handle_t *h);
+
+/* Static description of a return code. */
+const char *xamg_strerror(int code);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *xamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XAMG_H */

@@ -1,0 +1,224 @@
+// kernels.hpp -- gfx950 kernels of the multi-RHS AMG-Krylov solve phase.
+//
+// Every hot operation of the solve is a pass over the rows of one CSR
+// operator with the m right-hand sides interleaved (x[i*M + j]), so that a
+// matrix entry is loaded once and applied to all M columns (the "blas2"
+// multi-RHS SpMV of the paper, Sections 2.2-2.3).  One generic kernel,
+// rows_kernel<M, CPT, Op>, covers them all:
+//
+//   * G = M / CPT lanes of a 64-wide wavefront share a row; each lane owns
+//     CPT consecutive columns and gathers them with one vector load per
+//     nonzero, so a row's M columns are one contiguous, coalesced segment;
+//   * the op supplies the gathered input (x itself, or a value computed on
+//     the fly from b and D^-1 so smoothers from a zero guess need no extra
+//     pass), and the epilogue that turns the row sums into outputs (residual,
+//     Jacobi / Chebyshev updates, prolongation add, ...);
+//   * per-column dot products of the epilogue are reduced in the block in a
+//     fixed tree order and written as one partial per block; a one-block
+//     finalize kernel adds the partials in block order (deterministic) and
+//     updates the Krylov scalars on the device.
+//
+// Rows are split into contiguous chunks, one per block, and blocks are
+// renumbered so that each of the 8 XCDs (which receive blocks round-robin)
+// owns one contiguous eighth of the rows: neighbouring rows share gathered
+// x entries, so this keeps the reuse inside one XCD's L2.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace xamg {
+namespace dev {
+
+constexpr int kBlock = 256;      // threads per block of the row kernels
+constexpr int kMaxDots = 2;      // dots per kernel
+constexpr int kNumXcd = 8;
+
+// ---------------------------------------------------------------------------
+// vector loads/stores of CPT consecutive elements
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+struct alignas(sizeof(T) * N) Pack {
+    T v[N];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ Pack<T, N> load_pack(const T* p)
+{
+    return *reinterpret_cast<const Pack<T, N>*>(p);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void store_pack(T* p, const Pack<T, N>& x)
+{
+    *reinterpret_cast<Pack<T, N>*>(p) = x;
+}
+
+// ---------------------------------------------------------------------------
+// column index decoders
+// ---------------------------------------------------------------------------
+// plain 32-bit CSR columns
+struct Idx32 {
+    const int* ci;
+    __device__ __forceinline__ void row_begin(int) {}
+    __device__ __forceinline__ int col(int k) const { return ci[k]; }
+};
+
+// 16-bit compressed columns: rows are grouped in blocks of kIdxRows; each
+// block stores up to 4 int32 bases (int4: x, y, z, w; w < 0 marks a block
+// kept in 32 bits).  A compressed entry is (window << 14) | offset with
+// column = base[window] + offset, offset < 2^14.
+constexpr int kIdxRows = 64;
+struct Idx16 {
+    const uint16_t* off;
+    const int* ci;          // 32-bit fallback (full array)
+    const int4* base;
+    int b0, b1, b2, b3;
+    bool wide;
+    __device__ __forceinline__ void row_begin(int i)
+    {
+        const int4 b = base[i / kIdxRows];
+        b0 = b.x; b1 = b.y; b2 = b.z; b3 = b.w;
+        wide = b3 < 0;
+    }
+    __device__ __forceinline__ int col(int k) const
+    {
+        if (wide) return ci[k];
+        const unsigned e = off[k];
+        const unsigned w = e >> 14;
+        const int o = int(e & 0x3fffu);
+        const int b = (w == 0) ? b0 : (w == 1) ? b1 : (w == 2) ? b2 : b3;
+        return b + o;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// block-level deterministic reduction of per-column dots
+// ---------------------------------------------------------------------------
+template <int M, int CPT, int ND>
+__device__ __forceinline__ void reduce_dots(double (&d)[ND > 0 ? ND : 1][CPT],
+                                            double* __restrict__ part, int blk)
+{
+    if constexpr (ND > 0) {
+        constexpr int G = M / CPT;
+        constexpr int RPB = kBlock / G;
+        __shared__ double sh[ND * RPB * M];
+        const int g = threadIdx.x % G, rl = threadIdx.x / G;
+#pragma unroll
+        for (int q = 0; q < ND; ++q)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) sh[(q * RPB + rl) * M + g * CPT + c] = d[q][c];
+        __syncthreads();
+#pragma unroll
+        for (int s = RPB / 2; s >= 1; s >>= 1) {
+            if (rl < s) {
+#pragma unroll
+                for (int q = 0; q < ND; ++q)
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c)
+                        sh[(q * RPB + rl) * M + g * CPT + c] +=
+                            sh[(q * RPB + rl + s) * M + g * CPT + c];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x < ND * M) {
+            const int q = threadIdx.x / M, j = threadIdx.x % M;
+            part[size_t(blk) * (ND * M) + threadIdx.x] = sh[(q * RPB) * M + j];
+        }
+    }
+}
+
+// block id -> contiguous chunk, XCD-aware (see header comment)
+__device__ __forceinline__ int logical_block()
+{
+    const int nb = gridDim.x;
+    if (nb % kNumXcd != 0) return blockIdx.x;
+    return (blockIdx.x % kNumXcd) * (nb / kNumXcd) + blockIdx.x / kNumXcd;
+}
+
+// ---------------------------------------------------------------------------
+// the generic row kernel
+// ---------------------------------------------------------------------------
+// Op interface:
+//   using MT (matrix value type), AT (accumulator type), Idx (decoder)
+//   static constexpr bool kMatrix  -- false: pure row-wise vector op
+//   static constexpr int kDots     -- per-column dots produced (0..2)
+//   const int* rp; const MT* val; Idx idx;
+//   void gather(int c, int j0, AT a, AT (&acc)[CPT])   acc += a * in(c, j0..)
+//   void out(int i, int j0, const AT (&acc)[CPT], double (&d)[ND][CPT])
+//   bool active_any()   -- false: whole op is a no-op (every column frozen)
+template <int M, int CPT, class Op>
+__global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* part)
+{
+    constexpr int G = M / CPT;
+    constexpr int RPB = kBlock / G;
+    constexpr int ND = Op::kDots;
+    using AT = typename Op::AT;
+    const int g = threadIdx.x % G;
+    const int rl = threadIdx.x / G;
+    const int j0 = g * CPT;
+    const int blk = logical_block();
+    double dsum[ND > 0 ? ND : 1][CPT];
+#pragma unroll
+    for (int q = 0; q < (ND > 0 ? ND : 1); ++q)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) dsum[q][c] = 0.0;
+
+    if (op.active_any()) {
+        const int ntiles = (nrows + RPB - 1) / RPB;
+        const int per = (ntiles + gridDim.x - 1) / gridDim.x;
+        const int t0 = blk * per;
+        const int t1 = min(ntiles, t0 + per);
+        for (int t = t0; t < t1; ++t) {
+            const int i = t * RPB + rl;
+            if (i >= nrows) continue;
+            AT acc[CPT];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) acc[c] = AT(0);
+            if constexpr (Op::kMatrix) {
+                auto idx = op.idx;
+                idx.row_begin(i);
+                const int kb = op.rp[i], ke = op.rp[i + 1];
+                for (int k = kb; k < ke; ++k) {
+                    const int c = idx.col(k);
+                    const AT a = AT(op.val[k]);
+                    op.gather(c, j0, a, acc);
+                }
+            }
+            op.out(i, j0, acc, dsum);
+        }
+    }
+    reduce_dots<M, CPT, ND>(dsum, part, blk);
+}
+
+// ---------------------------------------------------------------------------
+// finalize: sum block partials in block order, then a per-column functor
+// ---------------------------------------------------------------------------
+constexpr int kFinThreads = 1024;
+
+template <class Fin>
+__global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double* __restrict__ part,
+                                                               int nb, int npair, Fin fin)
+{
+    // thread t: pair p = t % 64, slice s = t / 64 (16 slices)
+    constexpr int kPairs = 64, kSlices = kFinThreads / kPairs;
+    __shared__ double red[kSlices][kPairs];
+    __shared__ double tot[kPairs];
+    const int p = threadIdx.x % kPairs, s = threadIdx.x / kPairs;
+    double acc = 0.0;
+    if (p < npair)
+        for (int b = s; b < nb; b += kSlices) acc += part[size_t(b) * npair + p];
+    red[s][p] = acc;
+    __syncthreads();
+    if (threadIdx.x < kPairs) {
+        double t = 0.0;
+        for (int q = 0; q < kSlices; ++q) t += red[q][threadIdx.x];
+        tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+    fin(tot);
+}
+
+}  // namespace dev
+}  // namespace xamg

@@ -1,0 +1,551 @@
+// ops.hpp -- operations plugged into rows_kernel (see kernels.hpp).
+//
+// Naming: T = vector type of the level (double, or float for a reduced-
+// precision preconditioner), MT = matrix value type, BT = type of the
+// right-hand side read by a smoother (double at the finest level of a
+// mixed-precision cycle, where the cycle's input is the FP64 Krylov
+// residual), OT = output type of the last smoothing pass (double at the
+// finest level: the FP64 preconditioned residual z).
+//
+// Smoothers (on D^-1 A):
+//   Jacobi     x <- x + w D^-1 (b - A x)
+//   Chebyshev  degree 2 on [lo, hi]: with theta = (hi+lo)/2,
+//              delta = (hi-lo)/2, sigma = theta/delta, rho0 = 1/sigma,
+//              rho1 = 1/(2 sigma - rho0), c1 = rho1 rho0, c2 = 2 rho1/delta:
+//                r0 = D^-1 (b - A x), d0 = r0/theta, x1 = x + d0,
+//                r1 = r0 - D^-1 A d0, d1 = c1 d0 + c2 r1, x2 = x1 + d1
+//              (Saad, Iterative Methods for Sparse Linear Systems,
+//              Algorithm 12.1, two steps).
+// From a zero guess the first pass needs no product with x, so the
+// pre-smoother computes the gathered values (w D^-1 b for Jacobi, D^-1 b /
+// theta for Chebyshev) on the fly and fuses the residual (Jacobi) or the
+// second Chebyshev step into the same pass over A.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace xamg {
+namespace dev {
+
+// Per-column Krylov state, resident on the device (one solve at a time).
+struct ColState {
+    double bn2[32];       // ||b_j||^2
+    double rz[32];        // CG: (r, z); BiCGStab: rho
+    double alpha[32], beta[32], omega[32];
+    double rr[32];        // ||r_j||^2 (recurrence)
+    double relres[32];
+    double true_relres[32];
+    double tol;
+    int active[32];       // column still iterating
+    int conv[32];         // recurrence residual passed the test
+    int iters[32];
+    int rst[32];          // restart requested
+    int pz[32];           // next p update is p = z (CG) / p = r (BiCGStab)
+    int cp[32];           // copy t -> r for this column (restart)
+    int brk[32];          // breakdowns in a row (BiCGStab)
+    int skip[32];         // rest of this iteration skipped (BiCGStab)
+    int half[32];         // converged at the half step (BiCGStab)
+    int failed[32];       // stopped by a persistent breakdown
+    int nactive;
+    int nrestart;
+};
+
+template <int CPT>
+struct Cols {
+    int on[CPT];
+    __device__ __forceinline__ void load(const int* flags, int j0)
+    {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) on[c] = flags[j0 + c];
+    }
+};
+
+// ------------------------------------------------------------------------
+// Y = A X  (optionally dot (X_i, Y_i) per column: the Krylov (p, A p))
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, class IdxT, int DOT>
+struct OpAx {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = DOT;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const T* x;
+    T* y;
+    const int* nactive;   // may be null: always active
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&d)[ND][CPT]) const
+    {
+        Pack<T, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) o.v[t] = T(acc[t]);
+        store_pack<T, CPT>(y + size_t(i) * M + j0, o);
+        if constexpr (DOT > 0) {
+            const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[0][t] += double(xi.v[t]) * double(o.v[t]);
+        }
+    }
+};
+
+// ------------------------------------------------------------------------
+// x_fine += P x_coarse
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, class IdxT>
+struct OpProlongAdd {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = 0;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const T* xc;
+    T* xf;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<T, CPT>(xc + size_t(c) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        auto o = load_pack<T, CPT>(xf + size_t(i) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) o.v[t] = T(AT(o.v[t]) + acc[t]);
+        store_pack<T, CPT>(xf + size_t(i) * M + j0, o);
+    }
+};
+
+// ------------------------------------------------------------------------
+// r = b - A x, dots (b, b) and (r, r)  (FP64 Krylov level only)
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, typename BT, class IdxT, int ND_>
+struct OpResid {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = ND_;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const T* x;
+    const BT* b;
+    T* r;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&d)[ND][CPT]) const
+    {
+        const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        Pack<T, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) o.v[t] = T(AT(bi.v[t]) - acc[t]);
+        store_pack<T, CPT>(r + size_t(i) * M + j0, o);
+        if constexpr (ND_ == 2) {
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) {
+                d[0][t] += double(bi.v[t]) * double(bi.v[t]);
+                d[1][t] += double(o.v[t]) * double(o.v[t]);
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------------------------
+// Jacobi pre-smoothing from x = 0, fused with the residual:
+//   x_i = (w d_i) b_i,  r_i = b_i - sum_k a_ik (w d_k) b_k
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, typename BT, class IdxT>
+struct OpJacPre {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = 0;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const MT* dinv;
+    MT omega;
+    const BT* b;
+    T* x;
+    T* r;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
+        const AT wd = omega * dinv[c];
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * (wd * AT(v.v[t]));
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        const AT wd = omega * dinv[i];
+        Pack<T, CPT> xo, ro;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            xo.v[t] = T(wd * AT(bi.v[t]));
+            ro.v[t] = T(AT(bi.v[t]) - acc[t]);
+        }
+        store_pack<T, CPT>(x + size_t(i) * M + j0, xo);
+        store_pack<T, CPT>(r + size_t(i) * M + j0, ro);
+    }
+};
+
+// ------------------------------------------------------------------------
+// Jacobi post-smoothing: xo_i = x_i + (w d_i)(b_i - (A x)_i)
+// DOT >= 1: (b_i, xo_i); DOT == 2: also (q_i, xo_i)  [finest level only]
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, typename BT, typename OT, class IdxT,
+          int DOT>
+struct OpJacPost {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = DOT;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const MT* dinv;
+    MT omega;
+    const T* x;
+    const BT* b;
+    OT* xo;
+    const double* q;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&d)[ND][CPT]) const
+    {
+        const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
+        const AT wd = omega * dinv[i];
+        Pack<OT, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+            o.v[t] = OT(AT(xi.v[t]) + wd * (AT(bi.v[t]) - acc[t]));
+        store_pack<OT, CPT>(xo + size_t(i) * M + j0, o);
+        if constexpr (DOT >= 1) {
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[0][t] += double(bi.v[t]) * double(o.v[t]);
+        }
+        if constexpr (DOT >= 2) {
+            const auto qi = load_pack<double, CPT>(q + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * double(o.v[t]);
+        }
+    }
+};
+
+// ------------------------------------------------------------------------
+// Chebyshev (degree 2) pre-smoothing from x = 0 in one pass:
+//   d0_k = (d_k b_k)/theta gathered on the fly,
+//   x_i = d0_i + (c1 d0_i + c2 (d_i b_i - d_i (A d0)_i))
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, typename BT, class IdxT>
+struct OpChebPre {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = 0;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const MT* dinv;
+    MT theta, c1, c2;
+    const BT* b;
+    T* x;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
+        const AT dc = dinv[c];
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * ((AT(v.v[t]) * dc) / theta);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        const AT di = dinv[i];
+        Pack<T, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            const AT r0 = AT(bi.v[t]) * di;
+            const AT d0 = r0 / theta;
+            const AT r1 = r0 - di * acc[t];
+            const AT d1 = c1 * d0 + c2 * r1;
+            o.v[t] = T(d0 + d1);
+        }
+        store_pack<T, CPT>(x + size_t(i) * M + j0, o);
+    }
+};
+
+// ------------------------------------------------------------------------
+// Chebyshev post-smoothing, pass 1:  r0_i = d_i (b_i - (A x)_i)
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, typename BT, class IdxT>
+struct OpChebPost1 {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = 0;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const MT* dinv;
+    const T* x;
+    const BT* b;
+    T* r0;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        const AT di = dinv[i];
+        Pack<T, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) o.v[t] = T((AT(bi.v[t]) - acc[t]) * di);
+        store_pack<T, CPT>(r0 + size_t(i) * M + j0, o);
+    }
+};
+
+// ------------------------------------------------------------------------
+// Chebyshev post-smoothing, pass 2 (gathers d0 = r0/theta on the fly):
+//   r1 = r0_i - d_i (A d0)_i, d1 = c1 d0_i + c2 r1, xo_i = (x_i + d0_i) + d1
+// DOT as in OpJacPost.
+// ------------------------------------------------------------------------
+template <int M, int CPT, typename MT, typename T, typename BT, typename OT, class IdxT,
+          int DOT>
+struct OpChebPost2 {
+    using AT = MT;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = DOT;
+    const int* rp;
+    const MT* val;
+    IdxT idx;
+    const MT* dinv;
+    MT theta, c1, c2;
+    const T* r0;
+    const T* x;
+    const BT* b;
+    OT* xo;
+    const double* q;
+    const int* nactive;
+    __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    {
+        const auto v = load_pack<T, CPT>(r0 + size_t(c) * M + j0);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] += a * (AT(v.v[t]) / theta);
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&d)[ND][CPT]) const
+    {
+        const auto ri = load_pack<T, CPT>(r0 + size_t(i) * M + j0);
+        const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
+        const AT di = dinv[i];
+        Pack<OT, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            const AT d0 = AT(ri.v[t]) / theta;
+            const AT r1 = AT(ri.v[t]) - di * acc[t];
+            const AT d1 = c1 * d0 + c2 * r1;
+            o.v[t] = OT((AT(xi.v[t]) + d0) + d1);
+        }
+        store_pack<OT, CPT>(xo + size_t(i) * M + j0, o);
+        if constexpr (DOT >= 1) {
+            const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[0][t] += double(bi.v[t]) * double(o.v[t]);
+        }
+        if constexpr (DOT >= 2) {
+            const auto qi = load_pack<double, CPT>(q + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * double(o.v[t]);
+        }
+    }
+};
+
+// ------------------------------------------------------------------------
+// Krylov vector updates (no matrix)
+// ------------------------------------------------------------------------
+// CG: x += alpha p, r -= alpha q on active columns; dot (r, r)
+template <int M, int CPT>
+struct OpUpdXR {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = 1;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const ColState* st;
+    double *x, *r;
+    const double *p, *q;
+    __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
+    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
+                                        double (&d)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        auto xi = load_pack<double, CPT>(x + o);
+        auto ri = load_pack<double, CPT>(r + o);
+        const auto pi = load_pack<double, CPT>(p + o);
+        const auto qi = load_pack<double, CPT>(q + o);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            if (st->active[j0 + t]) {
+                const double a = st->alpha[j0 + t];
+                xi.v[t] += a * pi.v[t];
+                ri.v[t] -= a * qi.v[t];
+            }
+            d[0][t] += ri.v[t] * ri.v[t];
+        }
+        store_pack<double, CPT>(x + o, xi);
+        store_pack<double, CPT>(r + o, ri);
+    }
+};
+
+// CG: p = z + beta p (p = z when pz is set) on active columns
+template <int M, int CPT>
+struct OpUpdP {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = 0;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const ColState* st;
+    double* p;
+    const double* z;
+    __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
+    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        auto pi = load_pack<double, CPT>(p + o);
+        const auto zi = load_pack<double, CPT>(z + o);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            const int j = j0 + t;
+            if (st->active[j]) pi.v[t] = st->pz[j] ? zi.v[t] : zi.v[t] + st->beta[j] * pi.v[t];
+        }
+        store_pack<double, CPT>(p + o, pi);
+    }
+};
+
+// columns flagged in st->cp: dst = src;  columns with b_j = 0: x = 0
+template <int M, int CPT>
+struct OpFixCols {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = 0;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const ColState* st;
+    double* dst;        // r (restart copy)
+    const double* src;  // t
+    double* x;          // zeroed where b_j = 0 (may be null)
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        if (dst) {
+            auto di = load_pack<double, CPT>(dst + o);
+            const auto si = load_pack<double, CPT>(src + o);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t)
+                if (st->cp[j0 + t]) di.v[t] = si.v[t];
+            store_pack<double, CPT>(dst + o, di);
+        }
+        if (x) {
+            auto xi = load_pack<double, CPT>(x + o);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t)
+                if (st->bn2[j0 + t] == 0.0) xi.v[t] = 0.0;
+            store_pack<double, CPT>(x + o, xi);
+        }
+    }
+};
+
+// element-wise fill / cast copy between interleaved blocks with column padding
+template <typename TS, typename TD>
+__global__ void copy_cols_kernel(const TS* __restrict__ src, int ms, TD* __restrict__ dst,
+                                 int md, int n, int mcopy)
+{
+    const size_t total = size_t(n) * md;
+    for (size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+         e += size_t(gridDim.x) * blockDim.x) {
+        const size_t i = e / md;
+        const int j = int(e % md);
+        dst[e] = (src && j < mcopy) ? TD(src[i * ms + j]) : TD(0);
+    }
+}
+
+// ------------------------------------------------------------------------
+// coarsest level: x = A_L^-1 b, the inverse staged in LDS (n_L <= 64)
+// ------------------------------------------------------------------------
+template <int M, typename T>
+__global__ __launch_bounds__(256) void coarse_kernel(const T* __restrict__ inv, int nL,
+                                                     const T* __restrict__ b, T* __restrict__ x,
+                                                     const int* nactive)
+{
+    __shared__ T sa[64 * 64];
+    __shared__ T sb[64 * M];
+    if (nactive && *nactive == 0) return;
+    for (int e = threadIdx.x; e < nL * nL; e += blockDim.x) sa[e] = inv[e];
+    for (int e = threadIdx.x; e < nL * M; e += blockDim.x) sb[e] = b[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nL * M; e += blockDim.x) {
+        const int i = e / M, j = e % M;
+        T s = T(0);
+        for (int k = 0; k < nL; ++k) s += sa[i * nL + k] * sb[k * M + j];
+        x[e] = s;
+    }
+}
+
+}  // namespace dev
+}  // namespace xamg

@@ -1,0 +1,958 @@
+// solver.hip -- device setup, V-cycle, Krylov drivers and the C ABI of
+// libxamg (declared in include/xamg.h).
+//
+// The solve follows the paper's solver structure (Section 2.3: solver
+// objects with setup() and solve(); Section 2.4: construct the hierarchy,
+// then solve for NV right-hand sides at once):
+//   xamg_setup  uploads the hierarchy (A_l, P_l, R_l) in FP64, and in FP32
+//               (optionally with 16-bit indices) for a mixed-precision
+//               preconditioner (Section 2.3, "data compression"), computes
+//               D_l^-1 and the inverse of the coarsest matrix;
+//   xamg_solve  runs preconditioned CG (or BiCGStab, bicgstab.hip) with one
+//               set of scalars per column; every vector operation and dot
+//               is a device kernel, the scalars stay on the device, and the
+//               host only polls the number of still-active columns.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.hpp"
+#include "ops.hpp"
+#include "solver.hpp"
+
+namespace xamg {
+
+using namespace dev;
+
+// ---------------------------------------------------------------------------
+// device memory helpers
+// ---------------------------------------------------------------------------
+void Handle::check(hipError_t e, const char* what)
+{
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory) {
+            set_error("device allocation failed (%s)", what);
+            throw DevFail{XAMG_ENOMEM};
+        }
+        set_error("HIP error %d (%s) in %s", int(e), hipGetErrorString(e), what);
+        throw DevFail{XAMG_EHIP};
+    }
+}
+
+void* Handle::alloc_bytes(size_t bytes)
+{
+    void* p = nullptr;
+    check(hipMalloc(&p, std::max<size_t>(bytes, 256)), "hipMalloc");
+    allocs.push_back(p);
+    return p;
+}
+
+void Handle::release(void* p)
+{
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) {
+        hipFree(p);
+        allocs.erase(it);
+    }
+}
+
+Handle::~Handle()
+{
+    for (void* p : allocs) hipFree(p);
+    if (st_host) hipHostFree(st_host);
+}
+
+template <typename T>
+static T* upload(Handle& h, const T* src, size_t n)
+{
+    T* d = h.alloc<T>(n);
+    if (n) h.check(hipMemcpy(d, src, n * sizeof(T), hipMemcpyHostToDevice), "upload");
+    return d;
+}
+
+static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
+{
+    DCsr d;
+    d.nr = int(c.nrows);
+    d.nc = int(c.ncols);
+    d.nnz = c.nnz;
+    d.rp = upload(h, c.row_ptr, size_t(c.nrows) + 1);
+    d.ci = upload(h, c.col, size_t(c.nnz));
+    if (fp32) {
+        std::vector<float> v(c.val, c.val + c.nnz);
+        d.v = upload(h, v.data(), v.size());
+        d.fp32 = true;
+    } else {
+        d.v = upload(h, c.val, size_t(c.nnz));
+    }
+    return d;
+}
+
+// 16-bit index encoding of a CSR pattern (see Idx16 in kernels.hpp): per
+// block of kIdxRows rows, up to 4 windows with an int32 base each; an entry
+// is (window << 14) | (col - base).  Windows are formed greedily over the
+// block's sorted distinct columns; a block needing more than 4 windows stays
+// in 32 bits (base.w = -1).  Returns the fraction of nonzeros encoded.
+static double encode16(Handle& h, const xamg_csr_t& c, DCsr& d)
+{
+    const int n = int(c.nrows);
+    const int nblk = (n + kIdxRows - 1) / kIdxRows;
+    std::vector<uint16_t> off(size_t(std::max<int64_t>(c.nnz, 1)), 0);
+    std::vector<int4> base(std::max(nblk, 1));
+    int64_t enc = 0;
+    std::vector<int> cols;
+    for (int b = 0; b < nblk; ++b) {
+        const int r0 = b * kIdxRows, r1 = std::min(n, r0 + kIdxRows);
+        cols.assign(c.col + c.row_ptr[r0], c.col + c.row_ptr[r1]);
+        std::sort(cols.begin(), cols.end());
+        int bases[4] = {0, 0, 0, 0};
+        int nw = 0;
+        bool ok = true;
+        for (int col : cols) {
+            if (nw > 0 && col - bases[nw - 1] < (1 << 14)) continue;
+            if (nw == 4) { ok = false; break; }
+            bases[nw++] = col;
+        }
+        if (!ok) {
+            base[b] = make_int4(0, 0, 0, -1);
+            continue;
+        }
+        for (int w = nw; w < 4; ++w) bases[w] = bases[nw > 0 ? nw - 1 : 0];
+        base[b] = make_int4(bases[0], bases[1], bases[2], bases[3]);
+        for (int64_t k = c.row_ptr[r0]; k < c.row_ptr[r1]; ++k) {
+            const int col = c.col[k];
+            int w = nw - 1;
+            while (w > 0 && col < bases[w]) --w;
+            off[k] = uint16_t((w << 14) | (col - bases[w]));
+        }
+        enc += c.row_ptr[r1] - c.row_ptr[r0];
+    }
+    d.off = upload(h, off.data(), off.size());
+    d.base = upload(h, base.data(), base.size());
+    return c.nnz > 0 ? double(enc) / double(c.nnz) : 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// finalize functors (one block; tot[] holds the dot totals)
+// ---------------------------------------------------------------------------
+struct FinInit {   // tot: (b,b)[M], (r,r)[M]
+    ColState* st;
+    double tol;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M) {
+            const double bb = tot[j], rr = tot[M + j];
+            st->bn2[j] = bb;
+            st->rr[j] = rr;
+            const double rel = bb > 0.0 ? sqrt(rr) / sqrt(bb) : 0.0;
+            st->relres[j] = rel;
+            st->true_relres[j] = rel;
+            const int act = (bb > 0.0) && !(rel <= tol);
+            st->active[j] = act;
+            st->conv[j] = !act;
+            st->iters[j] = 0;
+            st->rst[j] = 1;
+            st->pz[j] = 0;
+            st->cp[j] = 0;
+            st->brk[j] = 0;
+            st->skip[j] = 0;
+            st->half[j] = 0;
+            st->failed[j] = 0;
+            st->alpha[j] = st->beta[j] = 0.0;
+            st->omega[j] = 1.0;
+            st->rz[j] = 1.0;
+        }
+        if (j == 0) {
+            st->tol = tol;
+            int bad = 0;
+            for (int q = 0; q < M; ++q) bad |= !isfinite(tot[q]);
+            st->nrestart = bad ? -1 : 0;
+        }
+        recount_active(st, M);
+    }
+};
+
+struct FinAlpha {   // tot: (p, q)[M]
+    ColState* st;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M) {
+            double a = 0.0;
+            if (st->active[j]) {
+                const double pq = tot[j];
+                if (!(pq > 0.0) || !isfinite(pq)) {
+                    st->active[j] = 0;
+                    st->failed[j] = 1;
+                } else {
+                    a = st->rz[j] / pq;
+                }
+            }
+            st->alpha[j] = a;
+        }
+        recount_active(st, M);
+    }
+};
+
+struct FinRR {   // tot: (r, r)[M]
+    ColState* st;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M && st->active[j]) {
+            const double rr = tot[j];
+            st->rr[j] = rr;
+            st->iters[j] += 1;
+            const double rel = sqrt(rr) / sqrt(st->bn2[j]);
+            st->relres[j] = rel;
+            if (rel <= st->tol) {
+                st->active[j] = 0;
+                st->conv[j] = 1;
+            }
+        }
+        recount_active(st, M);
+    }
+};
+
+struct FinBeta {   // tot: (r, z)[M] and, flexible, (z, q)[M]
+    ColState* st;
+    int M;
+    int flexible;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M && st->active[j]) {
+            const double rzn = tot[j];
+            double b = 0.0;
+            if (st->rst[j]) {
+                st->pz[j] = 1;
+                st->rst[j] = 0;
+            } else {
+                st->pz[j] = 0;
+                // flexible: (z_new, r_new - r_old) = -alpha (z_new, q)
+                b = flexible ? -st->alpha[j] * tot[M + j] / st->rz[j] : rzn / st->rz[j];
+            }
+            st->beta[j] = b;
+            st->rz[j] = rzn;
+        }
+    }
+};
+
+struct FinTrue {   // tot: (b, b)[M], (t, t)[M];  t = b - A x
+    ColState* st;
+    int M;
+    int allow_restart;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        __shared__ int nr;
+        if (j == 0) nr = 0;
+        __syncthreads();
+        if (j < M) {
+            const double bb = tot[j], tt = tot[M + j];
+            const double tr = bb > 0.0 ? sqrt(tt) / sqrt(bb) : 0.0;
+            st->true_relres[j] = tr;
+            st->cp[j] = 0;
+            if (allow_restart && st->conv[j] && bb > 0.0 && !(tr <= st->tol) && !st->failed[j]) {
+                st->conv[j] = 0;
+                st->active[j] = 1;
+                st->rst[j] = 1;
+                st->cp[j] = 1;
+                st->relres[j] = tr;
+                atomicAdd(&nr, 1);
+            }
+        }
+        __syncthreads();
+        if (j == 0) st->nrestart = nr;
+        recount_active(st, M);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+struct Cheb {
+    double theta, c1, c2, omega_deg1;
+};
+
+static Cheb cheb_consts(const Handle& h, int l)
+{
+    const double hi = h.opt.cheby_hi_frac * h.lev[l].lmax;
+    const double lo = h.opt.cheby_lo_frac * hi;
+    Cheb c;
+    c.theta = 0.5 * (hi + lo);
+    const double delta = 0.5 * (hi - lo);
+    const double sigma = c.theta / delta;
+    const double rho0 = 1.0 / sigma;
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    c.c1 = rho1 * rho0;
+    c.c2 = (2.0 * rho1) / delta;
+    c.omega_deg1 = 1.0 / c.theta;
+    return c;
+}
+
+template <typename T>
+static const DCsr& matA(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.A64; else return L.A32; }
+template <typename T>
+static const DCsr& matP(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.P64; else return L.P32; }
+template <typename T>
+static const DCsr& matR(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.R64; else return L.R32; }
+template <typename T>
+static const T* dinv_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dinv64; else return L.dinv32; }
+
+// Calls f(idx) with the index decoder of matrix d (16-bit if encoded).
+template <class F>
+static void with_idx(const DCsr& d, F&& f)
+{
+    if (d.off) {
+        Idx16 ix;
+        ix.off = d.off;
+        ix.ci = d.ci;
+        ix.base = d.base;
+        f(ix);
+    } else {
+        f(Idx32{d.ci});
+    }
+}
+
+template <typename T>
+static T* lvbuf(void* p) { return static_cast<T*>(p); }
+
+// One level of V(1,1) from a zero guess.  b: right-hand side of the level
+// (BT), xout: corrected solution (OT).  At the finest level the last pass
+// also accumulates the dots (b, xout) [and (q, xout)].  Returns the block
+// count of the last launch (the one that wrote partial dots).
+template <int M, typename T, typename BT, typename OT>
+static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q)
+{
+    constexpr int CPT = cpt_for<T, M>();
+    const LevelDev& L = h.lev[l];
+    const int* na = &h.st->nactive;
+    const int cap = h.nb_cap;
+    auto& W = h.w.lev[l];
+    int nb = 1;
+    if (l == h.nlev - 1) {
+        // coarsest level: dense inverse in LDS
+        if constexpr (std::is_same<BT, T>::value && std::is_same<OT, T>::value) {
+            const T* inv;
+            if constexpr (sizeof(T) == 8) inv = h.inv64; else inv = h.inv32;
+            hipLaunchKernelGGL((coarse_kernel<M, T>), dim3(1), dim3(256), 0, h.stream, inv,
+                               L.n, b, xout, na);
+        } else {
+            set_error("internal: coarsest level with mixed boundary types");
+            throw DevFail{XAMG_EINVAL};
+        }
+        return 0;
+    }
+    const DCsr& A = matA<T>(L);
+    const T* dinv = dinv_of<T>(L);
+    T* X = lvbuf<T>(W.X);
+    T* R = lvbuf<T>(W.R);
+    T* Tb = lvbuf<T>(W.T);
+    T* Bc = lvbuf<T>(h.w.lev[l + 1].B);
+    T* Xc = lvbuf<T>(h.w.lev[l + 1].X2);
+    const bool cheb2 = h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2;
+    const Cheb ch = cheb_consts(h, l);
+    const T omega = T(h.opt.smoother == XAMG_CHEBYSHEV ? ch.omega_deg1 : h.opt.omega);
+    const int* rp = A.rp;
+    const T* av = static_cast<const T*>(A.v);
+
+    // pre-smoothing from zero (+ residual)
+    with_idx(A, [&](auto ix) {
+        using IX = decltype(ix);
+        if (!cheb2) {
+            OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
+            launch_rows<M, CPT>(h, op, L.n, cap);
+        } else {
+            OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(ch.theta), T(ch.c1),
+                                               T(ch.c2), b, X, na};
+            launch_rows<M, CPT>(h, op, L.n, cap);
+            OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
+            launch_rows<M, CPT>(h, rs, L.n, cap);
+        }
+    });
+    // restriction b_{l+1} = R_l r_l
+    {
+        const DCsr& Rm = matR<T>(L);
+        with_idx(Rm, [&](auto ix) {
+            using IX = decltype(ix);
+            OpAx<M, CPT, T, T, IX, 0> op{Rm.rp, static_cast<const T*>(Rm.v), ix, R, Bc, na};
+            launch_rows<M, CPT>(h, op, Rm.nr, cap);
+        });
+    }
+    vlevel<M, T, T, T>(h, l + 1, Bc, Xc, 0, nullptr);
+    // prolongation x_l += P_l x_{l+1}
+    {
+        const DCsr& Pm = matP<T>(L);
+        with_idx(Pm, [&](auto ix) {
+            using IX = decltype(ix);
+            OpProlongAdd<M, CPT, T, T, IX> op{Pm.rp, static_cast<const T*>(Pm.v), ix, Xc, X, na};
+            launch_rows<M, CPT>(h, op, Pm.nr, cap);
+        });
+    }
+    // post-smoothing (+ finest-level dots)
+    with_idx(A, [&](auto ix) {
+        using IX = decltype(ix);
+        auto post = [&](auto dots_tag) {
+            constexpr int D = decltype(dots_tag)::value;
+            if (!cheb2) {
+                OpJacPost<M, CPT, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
+                                                          q, na};
+                nb = launch_rows<M, CPT>(h, op, L.n, cap);
+            } else {
+                OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
+                launch_rows<M, CPT>(h, p1, L.n, cap);
+                OpChebPost2<M, CPT, T, T, BT, OT, IX, D> p2{
+                    rp, av, ix, dinv, T(ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
+                nb = launch_rows<M, CPT>(h, p2, L.n, cap);
+            }
+        };
+        if (ndots == 2) post(std::integral_constant<int, 2>{});
+        else if (ndots == 1) post(std::integral_constant<int, 1>{});
+        else post(std::integral_constant<int, 0>{});
+    });
+    return nb;
+}
+
+// dots (b, x) [and (q, x)] as a pure vector pass (used when the finest
+// level is also the coarsest and no smoothing pass exists to fuse them into)
+template <int M, int CPT, int D>
+struct OpDotsBX {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = D;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const double *b, *x, *q;
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT], double (&d)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        const auto bi = load_pack<double, CPT>(b + o);
+        const auto xi = load_pack<double, CPT>(x + o);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) d[0][t] += bi.v[t] * xi.v[t];
+        if constexpr (D == 2) {
+            const auto qi = load_pack<double, CPT>(q + o);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * xi.v[t];
+        }
+    }
+};
+
+// z = M^-1 r for the whole hierarchy; returns the block count of the
+// launch that produced the finest-level dots (0 if ndots == 0).
+template <int M>
+int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    if (h.nlev == 1) {
+        hipLaunchKernelGGL((coarse_kernel<M, double>), dim3(1), dim3(256), 0, h.stream,
+                           h.inv64, h.lev[0].n, r, z, &h.st->nactive);
+        if (ndots == 0) return 0;
+        if (ndots == 2) {
+            OpDotsBX<M, CPT, 2> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
+            return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+        }
+        OpDotsBX<M, CPT, 1> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
+        return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+    }
+    if (h.opt.precision == XAMG_MIXED) return vlevel<M, float, double, double>(h, 0, r, z, ndots, q);
+    return vlevel<M, double, double, double>(h, 0, r, z, ndots, q);
+}
+
+// ---------------------------------------------------------------------------
+// work buffers
+// ---------------------------------------------------------------------------
+void ensure_work(Handle& h, int mp, bool bicg)
+{
+    if (h.w.mcap >= mp && (!bicg || h.w.rh)) return;
+    // free old
+    for (auto& W : h.w.lev) {
+        h.release(W.B); h.release(W.X); h.release(W.X2); h.release(W.R); h.release(W.T);
+    }
+    for (double* p : {h.w.r, h.w.z, h.w.p, h.w.q, h.w.t, h.w.rh, h.w.v, h.w.s, h.w.ph, h.w.sh,
+                      h.w.xpad, h.w.bpad})
+        h.release(p);
+    const int mc = std::max(mp, h.w.mcap);
+    h.w = Work{};
+    h.w.mcap = mc;
+    const size_t es = h.opt.precision == XAMG_MIXED ? sizeof(float) : sizeof(double);
+    h.w.lev.resize(h.nlev);
+    for (int l = 0; l < h.nlev; ++l) {
+        const size_t n = size_t(h.lev[l].n) * mc;
+        auto& W = h.w.lev[l];
+        const size_t esl = (h.nlev == 1) ? sizeof(double) : es;
+        if (l > 0) W.B = h.alloc_bytes(n * esl);
+        if (l + 1 < h.nlev) {
+            W.X = h.alloc_bytes(n * esl);
+            W.R = h.alloc_bytes(n * esl);
+            W.T = h.alloc_bytes(n * esl);
+        }
+        if (l > 0) W.X2 = h.alloc_bytes(n * esl);
+    }
+    const size_t n0 = size_t(h.lev[0].n) * mc;
+    h.w.r = h.alloc<double>(n0);
+    h.w.z = h.alloc<double>(n0);
+    h.w.p = h.alloc<double>(n0);
+    h.w.q = h.alloc<double>(n0);
+    h.w.t = h.alloc<double>(n0);
+    if (bicg) {
+        h.w.rh = h.alloc<double>(n0);
+        h.w.v = h.alloc<double>(n0);
+        h.w.s = h.alloc<double>(n0);
+        h.w.ph = h.alloc<double>(n0);
+        h.w.sh = h.alloc<double>(n0);
+    }
+}
+
+void sync_state(Handle& h)
+{
+    h.check(hipMemcpyAsync(h.st_host, h.st, sizeof(ColState), hipMemcpyDeviceToHost, h.stream),
+            "state copy");
+    h.check(hipStreamSynchronize(h.stream), "stream sync");
+}
+
+// ---------------------------------------------------------------------------
+// preconditioned CG, all m columns at once
+// ---------------------------------------------------------------------------
+template <int M>
+int pcg(Handle& h, const double* B, double* X, double tol)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    const int n = h.lev[0].n;
+    const DCsr& A = h.lev[0].A64;
+    const double* av = static_cast<const double*>(A.v);
+    auto& w = h.w;
+    ColState* st = h.st;
+    const int cap = h.nb_cap;
+    const int flex = h.opt.precision == XAMG_MIXED ? 1 : h.opt.flexible;
+    const int nd = flex ? 2 : 1;
+
+    if (h.opt.x0_mode == XAMG_X0_ZERO)
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
+                           nullptr, M, X, M, n, 0);
+    {
+        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, w.r,
+                                                              nullptr};
+        const int nb = launch_rows<M, CPT>(h, op, n, cap);
+        launch_fin(h, nb, 2 * M, FinInit{st, tol, M});
+    }
+    if (h.opt.x0_mode == XAMG_X0_GIVEN) {
+        OpFixCols<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, nullptr, nullptr, X};
+        launch_rows<M, CPT>(h, op, n, cap);
+    }
+    auto precondition = [&]() {
+        const int nb = vcycle<M>(h, w.r, w.z, nd, w.q);
+        launch_fin(h, nb, nd * M, FinBeta{st, M, flex});
+        OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, st, w.p, w.z};
+        launch_rows<M, CPT>(h, up, n, cap);
+    };
+    // q must be finite for the flexible dot of the first cycle
+    if (flex)
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
+                           nullptr, M, w.q, M, n, 0);
+    precondition();
+    sync_state(h);
+    if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
+
+    int it = 0;
+    const int every = std::max(1, h.opt.check_every);
+    for (;;) {
+        if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
+            OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B,
+                                                                  w.t, nullptr};
+            const int nb = launch_rows<M, CPT>(h, op, n, cap);
+            launch_fin(h, nb, 2 * M, FinTrue{st, M, it < h.opt.max_iters ? 1 : 0});
+            sync_state(h);
+            if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
+            OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, st, w.r, w.t, nullptr};
+            launch_rows<M, CPT>(h, cp, n, cap);
+            precondition();
+            sync_state(h);
+            continue;
+        }
+        ++it;
+        {
+            OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, w.p, w.q,
+                                                       &st->nactive};
+            const int nb = launch_rows<M, CPT>(h, op, n, cap);
+            launch_fin(h, nb, M, FinAlpha{st, M});
+        }
+        {
+            OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, w.r, w.p, w.q};
+            const int nb = launch_rows<M, CPT>(h, op, n, cap);
+            launch_fin(h, nb, M, FinRR{st, M});
+        }
+        precondition();
+        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
+    }
+    return XAMG_OK;
+}
+
+template int pcg<1>(Handle&, const double*, double*, double);
+template int pcg<2>(Handle&, const double*, double*, double);
+template int pcg<4>(Handle&, const double*, double*, double);
+template int pcg<8>(Handle&, const double*, double*, double);
+template int pcg<16>(Handle&, const double*, double*, double);
+template int pcg<32>(Handle&, const double*, double*, double);
+template int vcycle<1>(Handle&, const double*, double*, int, const double*);
+template int vcycle<2>(Handle&, const double*, double*, int, const double*);
+template int vcycle<4>(Handle&, const double*, double*, int, const double*);
+template int vcycle<8>(Handle&, const double*, double*, int, const double*);
+template int vcycle<16>(Handle&, const double*, double*, int, const double*);
+template int vcycle<32>(Handle&, const double*, double*, int, const double*);
+
+template <int M>
+void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    OpAx<M, CPT, double, double, Idx32, 0> op{d.rp, static_cast<const double*>(d.v),
+                                              Idx32{d.ci}, X, Y, nullptr};
+    launch_rows<M, CPT>(h, op, d.nr, h.nb_cap);
+}
+
+template <class F>
+static int dispatch_m(int mp, F&& f)
+{
+    switch (mp) {
+    case 1: return f(std::integral_constant<int, 1>{});
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    default: return XAMG_EINVAL;
+    }
+}
+
+static int padded_m(int m)
+{
+    int mp = 1;
+    while (mp < m) mp <<= 1;
+    return mp;
+}
+
+static void fill_stats(const Handle& h, int m, xamg_stats_t* stats)
+{
+    if (!stats) return;
+    const ColState& s = *h.st_host;
+    for (int j = 0; j < m; ++j) {
+        stats[j].iters = s.iters[j];
+        stats[j].converged = (s.conv[j] && !(s.true_relres[j] > s.tol)) ? 1 : 0;
+        stats[j].relres = s.relres[j];
+        stats[j].true_relres = s.true_relres[j];
+    }
+}
+
+int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats)
+{
+    const int mp = padded_m(m);
+    const int n = h.lev[0].n;
+    ensure_work(h, mp, h.opt.method == XAMG_BICGSTAB);
+    const double* Bs = B;
+    double* Xs = X;
+    if (mp != m) {
+        if (!h.w.bpad) {
+            h.w.bpad = h.alloc<double>(size_t(n) * h.w.mcap);
+            h.w.xpad = h.alloc<double>(size_t(n) * h.w.mcap);
+        }
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
+                           B, m, h.w.bpad, mp, n, m);
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
+                           X, m, h.w.xpad, mp, n, m);
+        Bs = h.w.bpad;
+        Xs = h.w.xpad;
+    }
+    int rc = dispatch_m(mp, [&](auto mc) {
+        constexpr int M = decltype(mc)::value;
+        if (h.opt.method == XAMG_BICGSTAB) return bicgstab<M>(h, Bs, Xs, tol);
+        return pcg<M>(h, Bs, Xs, tol);
+    });
+    if (mp != m)
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
+                           h.w.xpad, mp, X, m, n, m);
+    h.check(hipStreamSynchronize(h.stream), "solve sync");
+    if (rc != XAMG_OK) return rc;
+    fill_stats(h, m, stats);
+    const ColState& s = *h.st_host;
+    bool failed = false, notconv = false;
+    for (int j = 0; j < m; ++j) {
+        failed |= s.failed[j] != 0;
+        notconv |= !(s.conv[j] && !(s.true_relres[j] > s.tol));
+    }
+    if (failed) {
+        set_error("Krylov breakdown persisted after restart");
+        return XAMG_EBREAKDOWN;
+    }
+    return notconv ? XAMG_NOT_CONVERGED : XAMG_OK;
+}
+
+}  // namespace xamg
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using xamg::Handle;
+
+extern "C" {
+
+void xamg_default_options(xamg_options_t* o)
+{
+    o->method = XAMG_CG;
+    o->smoother = XAMG_JACOBI;
+    o->omega = 2.0 / 3.0;
+    o->cheby_degree = 2;
+    o->cheby_lo_frac = 0.3;
+    o->cheby_hi_frac = 1.1;
+    o->precision = XAMG_FP64;
+    o->index_bits = 32;
+    o->max_iters = 1000;
+    o->x0_mode = XAMG_X0_ZERO;
+    o->flexible = 0;
+    o->check_every = 1;
+    o->stream = nullptr;
+}
+
+static int device_ok()
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0)
+        return xamg::fail(XAMG_ENODEV, "no HIP device");
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return xamg::fail(XAMG_ENODEV, "cannot query device");
+    if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
+        xamg::set_error("device %d is %s, not gfx950", dev, p.gcnArchName);
+        return XAMG_ENODEV;
+    }
+    return XAMG_OK;
+}
+
+int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle_t** out)
+{
+    xamg::clear_error();
+    if (!H || !out) return xamg::fail(XAMG_EINVAL, "null argument");
+    *out = nullptr;
+    xamg_options_t o;
+    if (opt) o = *opt; else xamg_default_options(&o);
+    if (o.method != XAMG_CG && o.method != XAMG_BICGSTAB) return xamg::fail(XAMG_EINVAL, "method");
+    if (o.smoother != XAMG_JACOBI && o.smoother != XAMG_CHEBYSHEV)
+        return xamg::fail(XAMG_EINVAL, "smoother");
+    if (o.smoother == XAMG_CHEBYSHEV && (o.cheby_degree < 1 || o.cheby_degree > 2))
+        return xamg::fail(XAMG_EINVAL, "cheby_degree must be 1 or 2");
+    if (o.smoother == XAMG_CHEBYSHEV &&
+        !(o.cheby_hi_frac > 0.0 && o.cheby_lo_frac > 0.0 && o.cheby_lo_frac < 1.0))
+        return xamg::fail(XAMG_EINVAL, "Chebyshev interval fractions");
+    if (o.precision != XAMG_FP64 && o.precision != XAMG_MIXED) return xamg::fail(XAMG_EINVAL, "precision");
+    if (o.index_bits != 32 && o.index_bits != 16) return xamg::fail(XAMG_EINVAL, "index_bits");
+    if (o.index_bits == 16 && o.precision != XAMG_MIXED)
+        return xamg::fail(XAMG_EINVAL, "16-bit indices apply to the mixed-precision preconditioner");
+    if (o.max_iters < 0) return xamg::fail(XAMG_EINVAL, "max_iters");
+    if (H->nlevels < 1 || H->nlevels > XAMG_MAX_LEVELS || !H->A)
+        return xamg::fail(XAMG_EINVAL, "nlevels");
+    if (H->nlevels > 1 && (!H->P || !H->R)) return xamg::fail(XAMG_EINVAL, "P/R missing");
+    if (o.smoother == XAMG_CHEBYSHEV && H->nlevels > 1 && !H->lmax)
+        return xamg::fail(XAMG_EINVAL, "lmax missing");
+    for (int l = 0; l < H->nlevels; ++l) {
+        int rc = xamg::validate_csr(&H->A[l], true, "A[l]");
+        if (rc) return rc;
+        if (l + 1 < H->nlevels) {
+            rc = xamg::validate_csr(&H->P[l], false, "P[l]");
+            if (rc) return rc;
+            rc = xamg::validate_csr(&H->R[l], false, "R[l]");
+            if (rc) return rc;
+            if (H->P[l].nrows != H->A[l].nrows || H->P[l].ncols != H->A[l + 1].nrows ||
+                H->R[l].nrows != H->A[l + 1].nrows || H->R[l].ncols != H->A[l].nrows)
+                return xamg::fail(XAMG_EINVAL, "inconsistent level sizes");
+            if (o.smoother == XAMG_CHEBYSHEV && !(H->lmax[l] > 0.0 && std::isfinite(H->lmax[l])))
+                return xamg::fail(XAMG_EINVAL, "lmax must be positive");
+        }
+    }
+    const int nL = int(H->A[H->nlevels - 1].nrows);
+    if (nL > 64) return xamg::fail(XAMG_EINVAL, "coarsest level must have <= 64 rows");
+    int rc = device_ok();
+    if (rc) return rc;
+
+    Handle* h = new (std::nothrow) Handle;
+    if (!h) return xamg::fail(XAMG_ENOMEM, "host allocation");
+    try {
+        h->opt = o;
+        h->stream = static_cast<hipStream_t>(o.stream);
+        h->nlev = H->nlevels;
+        h->lev.resize(h->nlev);
+        const bool mixed = o.precision == XAMG_MIXED;
+        for (int l = 0; l < h->nlev; ++l) {
+            auto& L = h->lev[l];
+            const xamg_csr_t& a = H->A[l];
+            L.n = int(a.nrows);
+            L.lmax = H->lmax ? H->lmax[l] : 0.0;
+            L.A64 = xamg::upload_csr(*h, a, false);
+            std::vector<double> d(L.n);
+            for (int i = 0; i < L.n; ++i)
+                for (int k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k)
+                    if (a.col[k] == i) d[i] = 1.0 / a.val[k];
+            L.dinv64 = xamg::upload(*h, d.data(), d.size());
+            if (l + 1 < h->nlev) {
+                L.P64 = xamg::upload_csr(*h, H->P[l], false);
+                L.R64 = xamg::upload_csr(*h, H->R[l], false);
+            }
+            if (mixed && l + 1 < h->nlev) {
+                L.A32 = xamg::upload_csr(*h, a, true);
+                L.P32 = xamg::upload_csr(*h, H->P[l], true);
+                L.R32 = xamg::upload_csr(*h, H->R[l], true);
+                if (o.index_bits == 16) {
+                    L.frac16[0] = xamg::encode16(*h, a, L.A32);
+                    L.frac16[1] = xamg::encode16(*h, H->P[l], L.P32);
+                    L.frac16[2] = xamg::encode16(*h, H->R[l], L.R32);
+                }
+                std::vector<float> df(d.begin(), d.end());
+                L.dinv32 = xamg::upload(*h, df.data(), df.size());
+            }
+        }
+        // coarsest level inverse (FP64 LU with partial pivoting on the host)
+        {
+            const xamg_csr_t& a = H->A[h->nlev - 1];
+            std::vector<double> dense(size_t(nL) * nL, 0.0), inv(size_t(nL) * nL);
+            for (int i = 0; i < nL; ++i)
+                for (int k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k)
+                    dense[size_t(i) * nL + a.col[k]] = a.val[k];
+            if (xamg::dense_inverse(nL, dense.data(), inv.data()) != XAMG_OK) {
+                delete h;
+                return xamg::fail(XAMG_EBREAKDOWN, "singular coarsest matrix");
+            }
+            h->inv64 = xamg::upload(*h, inv.data(), inv.size());
+            std::vector<float> invf(inv.begin(), inv.end());
+            h->inv32 = xamg::upload(*h, invf.data(), invf.size());
+        }
+        h->st = h->alloc<xamg::dev::ColState>(1);
+        h->check(hipHostMalloc(&h->st_host, sizeof(xamg::dev::ColState), hipHostMallocDefault),
+                 "hipHostMalloc");
+        std::memset(h->st_host, 0, sizeof(xamg::dev::ColState));
+        h->check(hipMemcpy(h->st, h->st_host, sizeof(xamg::dev::ColState), hipMemcpyHostToDevice),
+                 "state init");
+        h->nb_cap = 1024;
+        h->part = h->alloc<double>(size_t(h->nb_cap) * xamg::dev::kMaxDots * XAMG_MAX_M);
+    } catch (const xamg::DevFail& f) {
+        delete h;
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        delete h;
+        return xamg::fail(XAMG_ENOMEM, "host allocation");
+    }
+    *out = static_cast<xamg_handle_t*>(h);
+    return XAMG_OK;
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int xamg_solve(xamg_handle_t* hh, const double* B, double* X, int32_t m, double tol,
+               xamg_stats_t* stats)
+{
+    xamg::clear_error();
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h || !B || !X) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (m < 1 || m > XAMG_MAX_M) return xamg::fail(XAMG_EINVAL, "m must be in 1..32");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return xamg::fail(XAMG_EINVAL, "tol must be positive");
+    if (!aligned16(B) || !aligned16(X)) return xamg::fail(XAMG_EINVAL, "B and X must be 16-byte aligned");
+    try {
+        int rc = xamg::solve_impl(*h, B, X, m, tol, stats);
+        if (rc == XAMG_EINVAL && xamg::last_error()[0] == '\0')
+            xamg::set_error("B contains NaN or Inf");
+        return rc;
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        return xamg::fail(XAMG_ENOMEM, "host allocation");
+    }
+}
+
+int xamg_vcycle(xamg_handle_t* hh, const double* B, double* X, int32_t m)
+{
+    xamg::clear_error();
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h || !B || !X) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
+        return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
+    try {
+        xamg::ensure_work(*h, m, false);
+        // every column counts as active for a stand-alone cycle
+        h->st_host->nactive = m;
+        h->check(hipMemcpyAsync(&h->st->nactive, &h->st_host->nactive, sizeof(int),
+                                hipMemcpyHostToDevice, h->stream), "state");
+        xamg::dispatch_m(m, [&](auto mc) {
+            constexpr int M = decltype(mc)::value;
+            xamg::vcycle<M>(*h, B, X, 0, nullptr);
+            return 0;
+        });
+        h->check(hipStreamSynchronize(h->stream), "vcycle sync");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+int xamg_spmm(xamg_handle_t* hh, int32_t op, int32_t level, int32_t m, const double* X, double* Y)
+{
+    xamg::clear_error();
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h || !X || !Y) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (level < 0 || level >= h->nlev) return xamg::fail(XAMG_EINVAL, "level");
+    if (op != XAMG_OP_A && level == h->nlev - 1) return xamg::fail(XAMG_EINVAL, "no P/R on the coarsest level");
+    if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
+        return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
+    const xamg::DCsr& d = op == XAMG_OP_A ? h->lev[level].A64
+                        : op == XAMG_OP_P ? h->lev[level].P64 : h->lev[level].R64;
+    try {
+        xamg::dispatch_m(m, [&](auto mc) {
+            constexpr int M = decltype(mc)::value;
+            xamg::spmm64<M>(*h, d, X, Y);
+            return 0;
+        });
+        h->check(hipGetLastError(), "spmm launch");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+int xamg_info(const xamg_handle_t* hh, int64_t* out, int32_t cap)
+{
+    const Handle* h = static_cast<const Handle*>(hh);
+    if (!h || !out) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (cap < 1 + 3 * h->nlev) return xamg::fail(XAMG_EINVAL, "output too short");
+    out[0] = h->nlev;
+    for (int l = 0; l < h->nlev; ++l) {
+        out[1 + 3 * l] = h->lev[l].n;
+        out[2 + 3 * l] = h->lev[l].A64.nnz;
+        out[3 + 3 * l] = l + 1 < h->nlev ? h->lev[l].P64.nnz : 0;
+    }
+    return XAMG_OK;
+}
+
+int xamg_destroy(xamg_handle_t* hh)
+{
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h) return XAMG_OK;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    else hipDeviceSynchronize();
+    delete h;
+    return XAMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,133 @@
+// solver.hpp -- device-side handle and launch helpers shared by the solver
+// translation units of libxamg (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.hpp"
+#include "ops.hpp"
+
+struct xamg_handle {};   // opaque ABI tag; the real object is xamg::Handle
+
+namespace xamg {
+
+struct DevFail {
+    int code;
+};
+
+// device CSR (values FP64 or FP32; optional 16-bit index encoding)
+struct DCsr {
+    int nr = 0, nc = 0;
+    int64_t nnz = 0;
+    int* rp = nullptr;
+    int* ci = nullptr;
+    void* v = nullptr;
+    bool fp32 = false;
+    uint16_t* off = nullptr;
+    int4* base = nullptr;
+};
+
+struct LevelDev {
+    int n = 0;
+    double lmax = 0.0;
+    DCsr A64, P64, R64;      // FP64 operators (the Krylov level uses A64 of level 0)
+    DCsr A32, P32, R32;      // FP32 copies for a mixed-precision preconditioner
+    double* dinv64 = nullptr;
+    float* dinv32 = nullptr;
+    double frac16[3] = {0, 0, 0};   // fraction of A/P/R nonzeros in 16-bit form
+};
+
+struct LevelWork {
+    void* B = nullptr;   // right-hand side of the level (l >= 1)
+    void* X = nullptr;   // pre-smoothed + corrected iterate
+    void* X2 = nullptr;  // post-smoothed output (l >= 1)
+    void* R = nullptr;   // residual
+    void* T = nullptr;   // Chebyshev temporary
+};
+
+struct Work {
+    int mcap = 0;
+    std::vector<LevelWork> lev;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
+    double *rh = nullptr, *v = nullptr, *s = nullptr, *ph = nullptr, *sh = nullptr;
+    double *bpad = nullptr, *xpad = nullptr;
+};
+
+struct Handle : xamg_handle {
+    int nlev = 0;
+    std::vector<LevelDev> lev;
+    double* inv64 = nullptr;
+    float* inv32 = nullptr;
+    xamg_options_t opt{};
+    hipStream_t stream = nullptr;
+    Work w;
+    dev::ColState* st = nullptr;
+    dev::ColState* st_host = nullptr;
+    double* part = nullptr;
+    int nb_cap = 1024;
+    std::vector<void*> allocs;
+
+    ~Handle();
+    void check(hipError_t e, const char* what);
+    void* alloc_bytes(size_t bytes);
+    template <typename T>
+    T* alloc(size_t n) { return static_cast<T*>(alloc_bytes(n * sizeof(T))); }
+    void release(void* p);
+};
+
+// ---- launch helpers -------------------------------------------------------
+template <typename T, int M>
+constexpr int cpt_for()
+{
+    if constexpr (sizeof(T) == 8) return M >= 2 ? 2 : 1;
+    else return M >= 4 ? 4 : M;
+}
+
+template <int M, int CPT, class Op>
+int launch_rows(Handle& h, const Op& op, int nrows, int cap)
+{
+    constexpr int G = M / CPT;
+    constexpr int RPB = dev::kBlock / G;
+    const int ntiles = (nrows + RPB - 1) / RPB;
+    int nb = std::max(1, std::min(ntiles, cap));
+    if (nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
+    hipLaunchKernelGGL((dev::rows_kernel<M, CPT, Op>), dim3(nb), dim3(dev::kBlock), 0, h.stream,
+                       op, nrows, h.part);
+    return nb;
+}
+
+template <class Fin>
+void launch_fin(Handle& h, int nb, int npair, const Fin& f)
+{
+    hipLaunchKernelGGL((dev::finalize_kernel<Fin>), dim3(1), dim3(dev::kFinThreads), 0, h.stream,
+                       h.part, nb, npair, f);
+}
+
+__device__ __forceinline__ void recount_active(dev::ColState* st, int M)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int c = 0;
+        for (int j = 0; j < M; ++j) c += st->active[j];
+        st->nactive = c;
+    }
+}
+
+// ---- solver entry points (explicitly instantiated for M = 1..32) ----------
+template <int M>
+int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q);
+template <int M>
+int pcg(Handle& h, const double* B, double* X, double tol);
+template <int M>
+int bicgstab(Handle& h, const double* B, double* X, double tol);
+
+void ensure_work(Handle& h, int mp, bool bicg);
+void sync_state(Handle& h);
+int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats);
+
+}  // namespace xamg

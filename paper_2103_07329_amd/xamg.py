@@ -1,0 +1,300 @@
+"""Thin ctypes binding of libxamg.so (include/xamg.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Device buffers are torch tensors on the current HIP device
+(float64, contiguous, row-major n x m); the stream is torch's current stream
+unless one is given.  If the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxamg.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENODEV, EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
+CG, BICGSTAB = 0, 1
+JACOBI, CHEBYSHEV = 0, 1
+FP64, MIXED = 0, 1
+X0_ZERO, X0_GIVEN = 0, 1
+OP_A, OP_P, OP_R = 0, 1, 2
+
+
+class XamgError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = lib().xamg_strerror(code).decode()
+        detail = lib().xamg_last_error().decode()
+        super().__init__(f"{where}: {msg} ({code}) {detail}")
+
+
+class CsrT(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class HierT(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int32), ("A", ctypes.POINTER(CsrT)),
+                ("P", ctypes.POINTER(CsrT)), ("R", ctypes.POINTER(CsrT)),
+                ("lmax", ctypes.POINTER(ctypes.c_double))]
+
+
+class SetupParamsT(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("max_coarse", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32)]
+
+
+class OptionsT(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("cheby_degree", ctypes.c_int32),
+                ("cheby_lo_frac", ctypes.c_double), ("cheby_hi_frac", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("index_bits", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("x0_mode", ctypes.c_int32),
+                ("flexible", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class StatsT(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double)]
+
+
+_lib = None
+
+EXPORTS = [
+    "xamg_default_setup_params", "xamg_hierarchy_build", "xamg_hierarchy_view",
+    "xamg_hierarchy_cf", "xamg_hierarchy_free", "xamg_default_options", "xamg_setup",
+    "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_destroy",
+    "xamg_strerror", "xamg_last_error",
+]
+
+
+def lib():
+    """Load libxamg.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} not built; run python -m paper_2103_07329_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.xamg_default_setup_params.argtypes = [ctypes.POINTER(SetupParamsT)]
+        L.xamg_default_setup_params.restype = None
+        L.xamg_hierarchy_build.argtypes = [ctypes.POINTER(CsrT), ctypes.POINTER(SetupParamsT),
+                                           ctypes.POINTER(vp)]
+        L.xamg_hierarchy_view.argtypes = [vp, ctypes.POINTER(HierT)]
+        L.xamg_hierarchy_cf.argtypes = [vp, i32, vp]
+        L.xamg_hierarchy_free.argtypes = [vp]
+        L.xamg_hierarchy_free.restype = None
+        L.xamg_default_options.argtypes = [ctypes.POINTER(OptionsT)]
+        L.xamg_default_options.restype = None
+        L.xamg_setup.argtypes = [ctypes.POINTER(HierT), ctypes.POINTER(OptionsT),
+                                 ctypes.POINTER(vp)]
+        L.xamg_solve.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(StatsT)]
+        L.xamg_vcycle.argtypes = [vp, vp, vp, i32]
+        L.xamg_spmm.argtypes = [vp, i32, i32, i32, vp, vp]
+        L.xamg_info.argtypes = [vp, ctypes.POINTER(i64), i32]
+        L.xamg_destroy.argtypes = [vp]
+        L.xamg_strerror.argtypes = [ctypes.c_int]
+        L.xamg_strerror.restype = ctypes.c_char_p
+        L.xamg_last_error.argtypes = []
+        L.xamg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, where, allow=(OK,)):
+    if rc not in allow:
+        raise XamgError(rc, where)
+    return rc
+
+
+def _csr_struct(rp, ci, v, ncols=None, keep=None):
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    v = np.ascontiguousarray(v, np.float64)
+    if keep is not None:
+        keep.extend([rp, ci, v])
+    n = rp.size - 1
+    return CsrT(n, n if ncols is None else int(ncols), int(rp[-1]),
+                rp.ctypes.data, ci.ctypes.data, v.ctypes.data)
+
+
+# ---------------------------------------------------------------------------
+# host hierarchy (the library's own classical AMG setup)
+# ---------------------------------------------------------------------------
+class HostHierarchy:
+    def __init__(self, rp, ci, v, theta=0.25, max_coarse=64, max_levels=40,
+                 lanczos_steps=10):
+        keep = []
+        a = _csr_struct(rp, ci, v, keep=keep)
+        prm = SetupParamsT(theta, max_coarse, max_levels, lanczos_steps)
+        h = ctypes.c_void_p()
+        _check(lib().xamg_hierarchy_build(ctypes.byref(a), ctypes.byref(prm), ctypes.byref(h)),
+               "xamg_hierarchy_build")
+        self._h = h
+        self._view = HierT()
+        _check(lib().xamg_hierarchy_view(h, ctypes.byref(self._view)), "xamg_hierarchy_view")
+        self.nlev = self._view.nlevels
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().xamg_hierarchy_free(self._h)
+            self._h = None
+
+    def view(self):
+        return self._view
+
+    @staticmethod
+    def _arrays(c):
+        n, nnz = c.nrows, c.nnz
+        rp = np.ctypeslib.as_array(ctypes.cast(c.row_ptr, ctypes.POINTER(ctypes.c_int32)),
+                                   (n + 1,)).copy()
+        if nnz:
+            ci = np.ctypeslib.as_array(ctypes.cast(c.col, ctypes.POINTER(ctypes.c_int32)),
+                                       (nnz,)).copy()
+            v = np.ctypeslib.as_array(ctypes.cast(c.val, ctypes.POINTER(ctypes.c_double)),
+                                      (nnz,)).copy()
+        else:
+            ci = np.zeros(0, np.int32)
+            v = np.zeros(0)
+        return rp, ci, v, (n, c.ncols)
+
+    def A(self, l):
+        return self._arrays(self._view.A[l])
+
+    def P(self, l):
+        return self._arrays(self._view.P[l])
+
+    def R(self, l):
+        return self._arrays(self._view.R[l])
+
+    def lmax(self, l):
+        return self._view.lmax[l]
+
+    def cf(self, l):
+        n = self._view.A[l].nrows
+        out = np.empty(n, np.int8)
+        _check(lib().xamg_hierarchy_cf(self._h, l, out.ctypes.data), "xamg_hierarchy_cf")
+        return out
+
+    def sizes(self):
+        return [self._view.A[l].nrows for l in range(self.nlev)]
+
+    def export(self):
+        return {
+            "A": [self.A(l)[:3] for l in range(self.nlev)],
+            "P": [self.P(l)[:3] + (self.P(l)[3][1],) for l in range(self.nlev - 1)],
+            "R": [self.R(l)[:3] for l in range(self.nlev - 1)],
+            "lmax": [self.lmax(l) for l in range(self.nlev)],
+        }
+
+
+def hierarchy_struct(h):
+    """HierT for a HostHierarchy or for an exported dict of arrays; returns
+    (struct, keepalive)."""
+    if isinstance(h, HostHierarchy):
+        return h.view(), [h]
+    keep = []
+    nl = len(h["A"])
+    A = (CsrT * nl)()
+    P = (CsrT * max(nl - 1, 1))()
+    R = (CsrT * max(nl - 1, 1))()
+    for l in range(nl):
+        rp, ci, v = h["A"][l][:3]
+        A[l] = _csr_struct(rp, ci, v, keep=keep)
+    for l in range(nl - 1):
+        rp, ci, v, nc = h["P"][l]
+        P[l] = _csr_struct(rp, ci, v, ncols=nc, keep=keep)
+        rp, ci, v = h["R"][l][:3]
+        R[l] = _csr_struct(rp, ci, v, ncols=len(h["A"][l][0]) - 1, keep=keep)
+    lm = (ctypes.c_double * nl)(*[float(x) for x in h["lmax"]])
+    keep += [A, P, R, lm]
+    s = HierT(nl, A, P, R, lm)
+    return s, keep
+
+
+# ---------------------------------------------------------------------------
+# device solver
+# ---------------------------------------------------------------------------
+def default_options(**kw):
+    o = OptionsT()
+    lib().xamg_default_options(ctypes.byref(o))
+    for k, val in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, val)
+    return o
+
+
+def _ptr(t, dtype="float64"):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if str(t.dtype) != f"torch.{dtype}":
+        raise ValueError(f"tensor must be {dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Device solver over a hierarchy (HostHierarchy or exported arrays)."""
+
+    def __init__(self, hierarchy, stream=None, **options):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        opts = default_options(**options)
+        opts.stream = stream
+        self.options = opts
+        s, keep = hierarchy_struct(hierarchy)
+        h = ctypes.c_void_p()
+        _check(lib().xamg_setup(ctypes.byref(s), ctypes.byref(opts), ctypes.byref(h)),
+               "xamg_setup")
+        del keep
+        self._h = h
+        info = (ctypes.c_int64 * (1 + 3 * 64))()
+        _check(lib().xamg_info(h, info, len(info)), "xamg_info")
+        self.nlev = int(info[0])
+        self.sizes = [int(info[1 + 3 * l]) for l in range(self.nlev)]
+        self.nnzA = [int(info[2 + 3 * l]) for l in range(self.nlev)]
+        self.nnzP = [int(info[3 + 3 * l]) for l in range(self.nlev)]
+        self.n = self.sizes[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xamg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, B, X, tol=1e-8, check=True):
+        """B, X: (n, m) float64 CUDA tensors; X is in/out.  Returns
+        (return code, stats dict)."""
+        m = B.shape[1] if B.dim() == 2 else 1
+        st = (StatsT * m)()
+        rc = lib().xamg_solve(self._h, _ptr(B), _ptr(X), m, tol, st)
+        if check:
+            _check(rc, "xamg_solve", allow=(OK, NOT_CONVERGED))
+        stats = {
+            "iters": np.array([s.iters for s in st], np.int32),
+            "converged": np.array([bool(s.converged) for s in st]),
+            "relres": np.array([s.relres for s in st]),
+            "true_relres": np.array([s.true_relres for s in st]),
+        }
+        return rc, stats
+
+    def vcycle(self, B, X):
+        m = B.shape[1]
+        _check(lib().xamg_vcycle(self._h, _ptr(B), _ptr(X), m), "xamg_vcycle")
+
+    def spmm(self, op, level, X, Y):
+        m = X.shape[1]
+        _check(lib().xamg_spmm(self._h, op, level, m, _ptr(X), _ptr(Y)), "xamg_spmm")

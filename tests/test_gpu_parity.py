@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Both sides take the same seeded inputs and the same hierarchy (the oracle's,
+handed to the device as plain arrays), so FP64 results differ only by the
+rounding of fused multiply-adds and the order of dot-product sums.
+Tolerances (FP64): element-wise relative 1e-12 for single operators and one
+V-cycle; for full solves, equal iteration counts and per-column relative
+error <= 1e-7 against the oracle at the same tolerance (expected ~1e-11),
+and a true relative residual <= tol recomputed on the CPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2103_07329_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MS = [1, 2, 4, 8, 16, 32]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def xm():
+    from paper_2103_07329_amd import xamg
+    xamg.lib()
+    return xamg
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def jump24(orc):
+    rng = np.random.default_rng(77)
+    p = inputs.jump7(24, inputs.jump_kappa(24, rng))
+    return p, orc.Hierarchy(*p.csr())
+
+
+@pytest.fixture(scope="module")
+def poisson32(orc):
+    p = inputs.poisson7(32)
+    return p, orc.Hierarchy(*p.csr())
+
+
+@pytest.mark.parametrize("m", MS)
+def test_spmm_all_levels(orc, torch, xm, jump24, m):
+    p, H = jump24
+    _say(f"[spmm] jump24 m={m}")
+    S = xm.Solver(H.export())
+    rng = np.random.default_rng(m)
+    for l in range(H.nlev):
+        ops = [(xm.OP_A, H.A(l))]
+        if l + 1 < H.nlev:
+            ops += [(xm.OP_P, H.P(l)), (xm.OP_R, H.R(l))]
+        for op, (rp, ci, v, (nr, nc)) in ops:
+            X = rng.uniform(-1, 1, (nc, m))
+            Yref = orc.spmm(rp, ci, v, X, ncols=nc)
+            Xd = _dev(torch, X)
+            Yd = torch.full((nr, m), np.nan, dtype=torch.float64, device="cuda")
+            S.spmm(op, l, Xd, Yd)
+            torch.cuda.synchronize()
+            Y = Yd.cpu().numpy()
+            assert np.isfinite(Y).all()
+            assert _relmax(Y, Yref) <= 1e-13, (l, op)
+    S.close()
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("m", [1, 8, 32])
+def test_vcycle_fp64(orc, torch, xm, jump24, smoother, m):
+    p, H = jump24
+    _say(f"[vcycle] jump24 smoother={smoother} m={m}")
+    S = xm.Solver(H.export(), smoother=smoother)
+    B = inputs.uniform_rhs(p.n, m, 5)
+    Zref = H.vcycle(B, smoother=smoother)
+    Bd = _dev(torch, B)
+    Zd = torch.full_like(Bd, np.nan)
+    S.vcycle(Bd, Zd)
+    torch.cuda.synchronize()
+    assert _relmax(Zd.cpu().numpy(), Zref) <= 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("m", [1, 3, 8])
+def test_pcg_fp64_poisson32(orc, torch, xm, poisson32, smoother, m):
+    p, H = poisson32
+    _say(f"[pcg] poisson32 smoother={smoother} m={m}")
+    B = inputs.uniform_rhs(p.n, 8, 1001)[:, :m].copy()
+    Xo, so, rco = H.solve(B, smoother=smoother, tol=1e-8)
+    assert rco == 0
+    S = xm.Solver(H.export(), smoother=smoother)
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-8)
+    assert rc == xm.OK
+    X = Xd.cpu().numpy()
+    assert np.array_equal(st["iters"], so["iters"])
+    for j in range(m):
+        err = np.linalg.norm(X[:, j] - Xo[:, j]) / np.linalg.norm(Xo[:, j])
+        assert err <= 1e-7, (j, err)
+    # true residual recomputed on the CPU in FP64
+    R = B - orc.spmm(*p.csr(), X)
+    tr = np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.all(tr <= 1e-8)
+    assert np.allclose(st["true_relres"], tr, rtol=1e-6, atol=1e-14)
+    assert st["converged"].all()
+    S.close()
+
+
+def test_pcg_jump_vs_tight_reference(orc, torch, xm, jump24):
+    p, H = jump24
+    _say("[pcg] jump24 m=4 vs tight reference")
+    B = inputs.uniform_rhs(p.n, 4, 3)
+    Xref, _, _ = H.solve(B, tol=1e-12)
+    Xalg, so, _ = H.solve(B, tol=1e-8)
+    S = xm.Solver(H.export())
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-8)
+    assert rc == xm.OK
+    X = Xd.cpu().numpy()
+    assert np.array_equal(st["iters"], so["iters"])
+    e_alg = np.linalg.norm(X - Xalg, axis=0) / np.linalg.norm(Xalg, axis=0)
+    assert e_alg.max() <= 1e-7
+    e_ref = np.linalg.norm(X - Xref, axis=0) / np.linalg.norm(Xref, axis=0)
+    e_ref_oracle = np.linalg.norm(Xalg - Xref, axis=0) / np.linalg.norm(Xref, axis=0)
+    # the device iterate is as close to the exact solution as the oracle's
+    assert np.all(e_ref <= 1.01 * e_ref_oracle + 1e-13)
+    S.close()
+
+
+def test_solve_edge_cases(orc, torch, xm, poisson32):
+    p, H = poisson32
+    _say("[edge] zero column, iteration cap, NaN, x0 given, bad m")
+    S = xm.Solver(H.export())
+    B = inputs.uniform_rhs(p.n, 4, 1)
+    B[:, 2] = 0.0
+    Bd = _dev(torch, B)
+    Xd = torch.full_like(Bd, 3.0)
+    rc, st = S.solve(Bd, Xd)
+    assert rc == xm.OK
+    X = Xd.cpu().numpy()
+    assert np.all(X[:, 2] == 0.0) and st["iters"][2] == 0 and st["converged"][2]
+    # iteration cap
+    S2 = xm.Solver(H.export(), max_iters=1)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S2.solve(Bd, Xd)
+    assert rc == xm.NOT_CONVERGED
+    Xo, so, rco = H.solve(B, max_iters=1)
+    assert rco == 1
+    assert np.array_equal(st["iters"], so["iters"])
+    assert np.allclose(Xd.cpu().numpy(), Xo, rtol=0, atol=1e-12 * np.abs(Xo).max())
+    # NaN in B
+    Bn = B.copy(); Bn[7, 1] = np.nan
+    rc, _ = S.solve(_dev(torch, Bn), torch.zeros_like(Bd), check=False)
+    assert rc == xm.EINVAL
+    # m out of range
+    B33 = _dev(torch, np.ones((p.n, 33)))
+    rc, _ = S.solve(B33, torch.zeros_like(B33), check=False)
+    assert rc == xm.EINVAL
+    # initial guess = solution: 0 iterations
+    Xs, _, _ = H.solve(B, tol=1e-12)
+    S3 = xm.Solver(H.export(), x0_mode=xm.X0_GIVEN)
+    Xd = _dev(torch, Xs)
+    rc, st = S3.solve(Bd, Xd, tol=1e-10)
+    assert rc == xm.OK and np.all(st["iters"] == 0)
+    for s in (S, S2, S3):
+        s.close()
+
+
+def test_one_level_hierarchy(orc, torch, xm):
+    p = inputs.poisson7(4)
+    H = orc.Hierarchy(*p.csr())
+    assert H.nlev == 1
+    _say("[one-level] poisson4")
+    B = inputs.uniform_rhs(p.n, 2, 4)
+    S = xm.Solver(H.export())
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-12)
+    assert rc == xm.OK and np.all(st["iters"] == 1)
+    Xo, so, _ = H.solve(B, tol=1e-12)
+    assert _relmax(Xd.cpu().numpy(), Xo) <= 1e-12
+    S.close()
+
+
+def test_device_setup_matches_host_setup_solution(orc, torch, xm):
+    """The library's own host setup feeds the device solver: the solution
+    must match the oracle (own setup) to the same bar."""
+    p = inputs.poisson7(24)
+    _say("[own-setup] poisson24 m=8 chebyshev")
+    Hp = xm.HostHierarchy(*p.csr())
+    Ho = orc.Hierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 8, 12)
+    Xo, so, _ = Ho.solve(B, smoother=1)
+    S = xm.Solver(Hp, smoother=1)
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd)
+    assert rc == xm.OK
+    assert np.array_equal(st["iters"], so["iters"])
+    e = np.linalg.norm(Xd.cpu().numpy() - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+    assert e.max() <= 1e-7
+    S.close()
