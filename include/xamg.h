@@ -181,6 +181,11 @@ int xamg_spmm(xamg_handle_t *h, int32_t op, int32_t level, int32_t m,
  * `cap` is the length of out; returns EINVAL if too short. */
 int xamg_info(const xamg_handle_t *h, int64_t *out, int32_t cap);
 
+/* Fraction of the nonzeros of A[level], P[level], R[level] (out[0..2],
+ * host) stored with 16-bit column offsets in the reduced-precision copy;
+ * 0 when the handle keeps 32-bit indices.  EINVAL for the coarsest level. */
+int xamg_index16_fraction(const xamg_handle_t *h, int32_t level, double *out);
+
 /* Release every device and host resource of h (NULL is allowed). */
 int xamg_destroy(xamg_handle_t *h);
 

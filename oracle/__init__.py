@@ -81,8 +81,14 @@ def lib():
         L.orc_rs_split.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _i32p]
         L.orc_strength_count.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl,
                                          _i32p]
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = _c_int
         _lib = L
     return _lib
+
+
+def num_threads():
+    return lib().orc_num_threads()
 
 
 def _csr(rp, ci, v):

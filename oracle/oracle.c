@@ -1345,3 +1345,16 @@ int orc_strength_count(int n, const int *rp, const int *ci, const double *v,
     free(srp); free(sci);
     return ORC_OK;
 }
+
+/* threads the OpenMP row loops use (1 without OpenMP) */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

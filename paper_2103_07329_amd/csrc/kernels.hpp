@@ -34,6 +34,7 @@ namespace dev {
 constexpr int kBlock = 256;      // threads per block of the row kernels
 constexpr int kMaxDots = 2;      // dots per kernel
 constexpr int kNumXcd = 8;
+constexpr int kUnroll = 8;      // nonzeros per batch in the row loop
 
 // ---------------------------------------------------------------------------
 // vector loads/stores of CPT consecutive elements
@@ -145,18 +146,24 @@ __device__ __forceinline__ int logical_block()
 //   static constexpr bool kMatrix  -- false: pure row-wise vector op
 //   static constexpr int kDots     -- per-column dots produced (0..2)
 //   const int* rp; const MT* val; Idx idx;
-//   void gather(int c, int j0, AT a, AT (&acc)[CPT])   acc += a * in(c, j0..)
+//   Pack<AT, CPT> fetch(int c, int j0)   the gathered input in(c, j0..j0+CPT)
 //   void out(int i, int j0, const AT (&acc)[CPT], double (&d)[ND][CPT])
 //   bool active_any()   -- false: whole op is a no-op (every column frozen)
-template <int M, int CPT, class Op>
+template <int M, int CPT, int S, class Op>
 __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* part)
 {
+    // G lanes share the columns of a row; S such groups split the row's
+    // nonzeros (long rows of coarse levels) and combine their sums with a
+    // fixed butterfly over the wavefront; U nonzeros per batch and group.
     constexpr int G = M / CPT;
-    constexpr int RPB = kBlock / G;
+    constexpr int RPB = kBlock / (G * S);
+    constexpr int U = S == 1 ? kUnroll : (S == 2 ? kUnroll / 2 : 2);
     constexpr int ND = Op::kDots;
+    static_assert(G * S <= 64, "a row must stay inside one wavefront");
     using AT = typename Op::AT;
     const int g = threadIdx.x % G;
-    const int rl = threadIdx.x / G;
+    const int sg = (threadIdx.x / G) % S;
+    const int rl = threadIdx.x / (G * S);
     const int j0 = g * CPT;
     const int blk = logical_block();
     double dsum[ND > 0 ? ND : 1][CPT];
@@ -172,21 +179,47 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
         const int t1 = min(ntiles, t0 + per);
         for (int t = t0; t < t1; ++t) {
             const int i = t * RPB + rl;
-            if (i >= nrows) continue;
+            const bool live = i < nrows;
             AT acc[CPT];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) acc[c] = AT(0);
             if constexpr (Op::kMatrix) {
-                auto idx = op.idx;
-                idx.row_begin(i);
-                const int kb = op.rp[i], ke = op.rp[i + 1];
-                for (int k = kb; k < ke; ++k) {
-                    const int c = idx.col(k);
-                    const AT a = AT(op.val[k]);
-                    op.gather(c, j0, a, acc);
+                // nonzeros in batches of U: all column indices and values
+                // first, then every gather, then the multiply-adds in
+                // nonzero order (more loads in flight per lane)
+                if (live) {
+                    auto idx = op.idx;
+                    idx.row_begin(i);
+                    const int kb = op.rp[i], ke = op.rp[i + 1];
+                    for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
+                        int cc[U];
+                        AT aa[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int k = k0 + u;
+                            cc[u] = k < ke ? idx.col(k) : -1;
+                            aa[u] = k < ke ? AT(op.val[k]) : AT(0);
+                        }
+                        Pack<AT, CPT> vv[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            if (cc[u] >= 0) vv[u] = op.fetch(cc[u], j0);
+#pragma unroll
+                        for (int u = 0; u < U; ++u)
+                            if (cc[u] >= 0) {
+#pragma unroll
+                                for (int c = 0; c < CPT; ++c) acc[c] += aa[u] * vv[u].v[c];
+                            }
+                    }
+                }
+                if constexpr (S > 1) {
+#pragma unroll
+                    for (int off = G; off < G * S; off <<= 1)
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
                 }
             }
-            op.out(i, j0, acc, dsum);
+            if (live && sg == 0) op.out(i, j0, acc, dsum);
         }
     }
     reduce_dots<M, CPT, ND>(dsum, part, blk);
@@ -197,25 +230,40 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
 // ---------------------------------------------------------------------------
 constexpr int kFinThreads = 1024;
 
+// npair <= 64 partial sums per block; thread t takes pair t % P and slice
+// t / P (P = npair rounded up to a power of two), sums the blocks of its
+// slice in increasing order (8 loads in flight), then the slices are
+// combined by a fixed tree in LDS.
 template <class Fin>
 __global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double* __restrict__ part,
                                                                int nb, int npair, Fin fin)
 {
-    // thread t: pair p = t % 64, slice s = t / 64 (16 slices)
-    constexpr int kPairs = 64, kSlices = kFinThreads / kPairs;
-    __shared__ double red[kSlices][kPairs];
-    __shared__ double tot[kPairs];
-    const int p = threadIdx.x % kPairs, s = threadIdx.x / kPairs;
+    __shared__ double red[kFinThreads];
+    __shared__ double tot[64];
+    int P = 1;
+    while (P < npair) P <<= 1;
+    const int nsl = kFinThreads / P;
+    const int p = threadIdx.x % P, s = threadIdx.x / P;
     double acc = 0.0;
-    if (p < npair)
-        for (int b = s; b < nb; b += kSlices) acc += part[size_t(b) * npair + p];
-    red[s][p] = acc;
-    __syncthreads();
-    if (threadIdx.x < kPairs) {
-        double t = 0.0;
-        for (int q = 0; q < kSlices; ++q) t += red[q][threadIdx.x];
-        tot[threadIdx.x] = t;
+    if (p < npair) {
+        for (int b0 = s; b0 < nb; b0 += 8 * nsl) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u * nsl;
+                v[u] = b < nb ? part[size_t(b) * npair + p] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
     }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = nsl / 2; h >= 1; h >>= 1) {
+        if (s < h) red[threadIdx.x] += red[threadIdx.x + h * P];
+        __syncthreads();
+    }
+    if (threadIdx.x < 64) tot[threadIdx.x] = threadIdx.x < npair ? red[threadIdx.x] : 0.0;
     __syncthreads();
     fin(tot);
 }

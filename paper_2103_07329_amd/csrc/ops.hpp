@@ -50,16 +50,6 @@ struct ColState {
     int nrestart;
 };
 
-template <int CPT>
-struct Cols {
-    int on[CPT];
-    __device__ __forceinline__ void load(const int* flags, int j0)
-    {
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) on[c] = flags[j0 + c];
-    }
-};
-
 // ------------------------------------------------------------------------
 // Y = A X  (optionally dot (X_i, Y_i) per column: the Krylov (p, A p))
 // ------------------------------------------------------------------------
@@ -75,11 +65,13 @@ struct OpAx {
     T* y;
     const int* nactive;   // may be null: always active
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -112,11 +104,13 @@ struct OpProlongAdd {
     T* xf;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(xc + size_t(c) * M + j0);
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -145,11 +139,13 @@ struct OpResid {
     T* r;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -189,12 +185,14 @@ struct OpJacPre {
     T* r;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
         const AT wd = omega * dinv[c];
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * (wd * AT(v.v[t]));
+        for (int t = 0; t < CPT; ++t) r.v[t] = (wd * AT(v.v[t]));
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -234,11 +232,13 @@ struct OpJacPost {
     const double* q;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -283,12 +283,14 @@ struct OpChebPre {
     T* x;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
         const AT dc = dinv[c];
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * ((AT(v.v[t]) * dc) / theta);
+        for (int t = 0; t < CPT; ++t) r.v[t] = ((AT(v.v[t]) * dc) / theta);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -326,11 +328,13 @@ struct OpChebPost1 {
     T* r0;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(x + size_t(c) * M + j0);
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * AT(v.v[t]);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -368,11 +372,13 @@ struct OpChebPost2 {
     const double* q;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ void gather(int c, int j0, AT a, AT (&acc)[CPT]) const
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(r0 + size_t(c) * M + j0);
+        Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) acc[t] += a * (AT(v.v[t]) / theta);
+        for (int t = 0; t < CPT; ++t) r.v[t] = (AT(v.v[t]) / theta);
+        return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
@@ -419,7 +425,7 @@ struct OpUpdXR {
     double *x, *r;
     const double *p, *q;
     __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
-    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
                                         double (&d)[ND][CPT]) const
@@ -456,7 +462,7 @@ struct OpUpdP {
     double* p;
     const double* z;
     __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
-    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
                                         double (&)[ND][CPT]) const
@@ -487,7 +493,7 @@ struct OpFixCols {
     const double* src;  // t
     double* x;          // zeroed where b_j = 0 (may be null)
     __device__ __forceinline__ bool active_any() const { return true; }
-    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
                                         double (&)[ND][CPT]) const

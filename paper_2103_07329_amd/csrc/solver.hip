@@ -82,6 +82,7 @@ static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
     d.nr = int(c.nrows);
     d.nc = int(c.ncols);
     d.nnz = c.nnz;
+    d.split = split_for(c.nnz, int(c.nrows));
     d.rp = upload(h, c.row_ptr, size_t(c.nrows) + 1);
     d.ci = upload(h, c.col, size_t(c.nnz));
     if (fp32) {
@@ -372,13 +373,13 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
         using IX = decltype(ix);
         if (!cheb2) {
             OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
-            launch_rows<M, CPT>(h, op, L.n, cap);
+            launch_mat<M, CPT>(h, op, A.split, L.n, cap);
         } else {
             OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(ch.theta), T(ch.c1),
                                                T(ch.c2), b, X, na};
-            launch_rows<M, CPT>(h, op, L.n, cap);
+            launch_mat<M, CPT>(h, op, A.split, L.n, cap);
             OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
-            launch_rows<M, CPT>(h, rs, L.n, cap);
+            launch_mat<M, CPT>(h, rs, A.split, L.n, cap);
         }
     });
     // restriction b_{l+1} = R_l r_l
@@ -387,7 +388,7 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
         with_idx(Rm, [&](auto ix) {
             using IX = decltype(ix);
             OpAx<M, CPT, T, T, IX, 0> op{Rm.rp, static_cast<const T*>(Rm.v), ix, R, Bc, na};
-            launch_rows<M, CPT>(h, op, Rm.nr, cap);
+            launch_mat<M, CPT>(h, op, Rm.split, Rm.nr, cap);
         });
     }
     vlevel<M, T, T, T>(h, l + 1, Bc, Xc, 0, nullptr);
@@ -397,7 +398,7 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
         with_idx(Pm, [&](auto ix) {
             using IX = decltype(ix);
             OpProlongAdd<M, CPT, T, T, IX> op{Pm.rp, static_cast<const T*>(Pm.v), ix, Xc, X, na};
-            launch_rows<M, CPT>(h, op, Pm.nr, cap);
+            launch_mat<M, CPT>(h, op, Pm.split, Pm.nr, cap);
         });
     }
     // post-smoothing (+ finest-level dots)
@@ -408,13 +409,13 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
             if (!cheb2) {
                 OpJacPost<M, CPT, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
                                                           q, na};
-                nb = launch_rows<M, CPT>(h, op, L.n, cap);
+                nb = launch_mat<M, CPT>(h, op, A.split, L.n, cap);
             } else {
                 OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
-                launch_rows<M, CPT>(h, p1, L.n, cap);
+                launch_mat<M, CPT>(h, p1, A.split, L.n, cap);
                 OpChebPost2<M, CPT, T, T, BT, OT, IX, D> p2{
                     rp, av, ix, dinv, T(ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
-                nb = launch_rows<M, CPT>(h, p2, L.n, cap);
+                nb = launch_mat<M, CPT>(h, p2, A.split, L.n, cap);
             }
         };
         if (ndots == 2) post(std::integral_constant<int, 2>{});
@@ -436,7 +437,7 @@ struct OpDotsBX {
     Idx32 idx{nullptr};
     const double *b, *x, *q;
     __device__ __forceinline__ bool active_any() const { return true; }
-    __device__ __forceinline__ void gather(int, int, AT, AT (&)[CPT]) const {}
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT], double (&d)[ND][CPT]) const
     {
@@ -548,7 +549,7 @@ int pcg(Handle& h, const double* B, double* X, double tol)
     {
         OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, w.r,
                                                               nullptr};
-        const int nb = launch_rows<M, CPT>(h, op, n, cap);
+        const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
         launch_fin(h, nb, 2 * M, FinInit{st, tol, M});
     }
     if (h.opt.x0_mode == XAMG_X0_GIVEN) {
@@ -575,7 +576,7 @@ int pcg(Handle& h, const double* B, double* X, double tol)
         if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
             OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B,
                                                                   w.t, nullptr};
-            const int nb = launch_rows<M, CPT>(h, op, n, cap);
+            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
             launch_fin(h, nb, 2 * M, FinTrue{st, M, it < h.opt.max_iters ? 1 : 0});
             sync_state(h);
             if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
@@ -589,7 +590,7 @@ int pcg(Handle& h, const double* B, double* X, double tol)
         {
             OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, w.p, w.q,
                                                        &st->nactive};
-            const int nb = launch_rows<M, CPT>(h, op, n, cap);
+            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
             launch_fin(h, nb, M, FinAlpha{st, M});
         }
         {
@@ -622,7 +623,7 @@ void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
     constexpr int CPT = cpt_for<double, M>();
     OpAx<M, CPT, double, double, Idx32, 0> op{d.rp, static_cast<const double*>(d.v),
                                               Idx32{d.ci}, X, Y, nullptr};
-    launch_rows<M, CPT>(h, op, d.nr, h.nb_cap);
+    launch_mat<M, CPT>(h, op, d.split, d.nr, h.nb_cap);
 }
 
 template <class F>
@@ -846,7 +847,7 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
         std::memset(h->st_host, 0, sizeof(xamg::dev::ColState));
         h->check(hipMemcpy(h->st, h->st_host, sizeof(xamg::dev::ColState), hipMemcpyHostToDevice),
                  "state init");
-        h->nb_cap = 1024;
+        h->nb_cap = 2048;
         h->part = h->alloc<double>(size_t(h->nb_cap) * xamg::dev::kMaxDots * XAMG_MAX_M);
     } catch (const xamg::DevFail& f) {
         delete h;
@@ -942,6 +943,15 @@ int xamg_info(const xamg_handle_t* hh, int64_t* out, int32_t cap)
         out[2 + 3 * l] = h->lev[l].A64.nnz;
         out[3 + 3 * l] = l + 1 < h->nlev ? h->lev[l].P64.nnz : 0;
     }
+    return XAMG_OK;
+}
+
+int xamg_index16_fraction(const xamg_handle_t* hh, int32_t level, double* out)
+{
+    const Handle* h = static_cast<const Handle*>(hh);
+    if (!h || !out) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (level < 0 || level >= h->nlev - 1) return xamg::fail(XAMG_EINVAL, "level");
+    for (int k = 0; k < 3; ++k) out[k] = h->lev[level].frac16[k];
     return XAMG_OK;
 }
 

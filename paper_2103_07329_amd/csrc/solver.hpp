@@ -30,6 +30,7 @@ struct DCsr {
     bool fp32 = false;
     uint16_t* off = nullptr;
     int4* base = nullptr;
+    int split = 1;   // lane groups per row (1, 2 or 8), from the mean row length
 };
 
 struct LevelDev {
@@ -84,21 +85,50 @@ struct Handle : xamg_handle {
 template <typename T, int M>
 constexpr int cpt_for()
 {
-    if constexpr (sizeof(T) == 8) return M >= 2 ? 2 : 1;
-    else return M >= 4 ? 4 : M;
+    // 32 bytes of the row's columns per lane (16 when fewer columns)
+    if constexpr (sizeof(T) == 8) return M >= 4 ? 4 : M;
+    else return M >= 8 ? 8 : M;
 }
 
-template <int M, int CPT, class Op>
-int launch_rows(Handle& h, const Op& op, int nrows, int cap)
+// groups of lanes that split one row's nonzeros, from the mean row length
+inline int split_for(int64_t nnz, int nrows)
+{
+    const double avg = nrows > 0 ? double(nnz) / nrows : 0.0;
+    return avg > 24.0 ? 8 : (avg > 10.0 ? 2 : 1);
+}
+
+template <int M, int CPT, int S, class Op>
+int launch_rows_s(Handle& h, const Op& op, int nrows, int cap)
 {
     constexpr int G = M / CPT;
-    constexpr int RPB = dev::kBlock / G;
+    constexpr int RPB = dev::kBlock / (G * S);
     const int ntiles = (nrows + RPB - 1) / RPB;
     int nb = std::max(1, std::min(ntiles, cap));
     if (nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
-    hipLaunchKernelGGL((dev::rows_kernel<M, CPT, Op>), dim3(nb), dim3(dev::kBlock), 0, h.stream,
-                       op, nrows, h.part);
+    hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
+                       h.stream, op, nrows, h.part);
     return nb;
+}
+
+// row-wise vector operation (no matrix)
+template <int M, int CPT, class Op>
+int launch_rows(Handle& h, const Op& op, int nrows, int cap)
+{
+    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap);
+}
+
+// operation over the rows of matrix d, with d's row split
+template <int M, int CPT, class Op>
+int launch_mat(Handle& h, const Op& op, int split, int nrows, int cap)
+{
+    constexpr int G = M / CPT;
+    if constexpr (G * 8 <= 64) {
+        if (split >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap);
+    }
+    if constexpr (G * 2 <= 64) {
+        if (split >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap);
+    }
+    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap);
 }
 
 template <class Fin>

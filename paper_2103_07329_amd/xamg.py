@@ -67,7 +67,8 @@ _lib = None
 EXPORTS = [
     "xamg_default_setup_params", "xamg_hierarchy_build", "xamg_hierarchy_view",
     "xamg_hierarchy_cf", "xamg_hierarchy_free", "xamg_default_options", "xamg_setup",
-    "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_destroy",
+    "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_index16_fraction",
+    "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
 ]
 
@@ -96,6 +97,7 @@ def lib():
         L.xamg_vcycle.argtypes = [vp, vp, vp, i32]
         L.xamg_spmm.argtypes = [vp, i32, i32, i32, vp, vp]
         L.xamg_info.argtypes = [vp, ctypes.POINTER(i64), i32]
+        L.xamg_index16_fraction.argtypes = [vp, i32, ctypes.POINTER(dbl)]
         L.xamg_destroy.argtypes = [vp]
         L.xamg_strerror.argtypes = [ctypes.c_int]
         L.xamg_strerror.restype = ctypes.c_char_p
@@ -294,6 +296,11 @@ class Solver:
     def vcycle(self, B, X):
         m = B.shape[1]
         _check(lib().xamg_vcycle(self._h, _ptr(B), _ptr(X), m), "xamg_vcycle")
+
+    def index16_fraction(self, level):
+        out = (ctypes.c_double * 3)()
+        _check(lib().xamg_index16_fraction(self._h, level, out), "xamg_index16_fraction")
+        return tuple(out)
 
     def spmm(self, op, level, X, Y):
         m = X.shape[1]

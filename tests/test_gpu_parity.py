@@ -221,3 +221,184 @@ def test_device_setup_matches_host_setup_solution(orc, torch, xm):
     e = np.linalg.norm(Xd.cpu().numpy() - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
     assert e.max() <= 1e-7
     S.close()
+
+
+# --------------------------------------------------------------------------
+# BiCGStab (FP64)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("m", [1, 8])
+def test_bicgstab_fp64(orc, torch, xm, jump24, smoother, m):
+    p, H = jump24
+    _say(f"[bicgstab] jump24 smoother={smoother} m={m}")
+    B = inputs.uniform_rhs(p.n, m, 31)
+    Xo, so, rco = H.solve(B, method=orc.BICGSTAB, smoother=smoother, tol=1e-8)
+    assert rco == 0
+    S = xm.Solver(H.export(), method=xm.BICGSTAB, smoother=smoother)
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-8)
+    assert rc == xm.OK
+    assert np.array_equal(st["iters"], so["iters"])
+    X = Xd.cpu().numpy()
+    e = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+    assert e.max() <= 1e-7, e
+    tr = np.linalg.norm(B - orc.spmm(*p.csr(), X), axis=0) / np.linalg.norm(B, axis=0)
+    assert np.all(tr <= 1e-8)
+    S.close()
+
+
+def test_bicgstab_edge_cases(orc, torch, xm, poisson32):
+    p, H = poisson32
+    _say("[bicgstab-edge] zero column, cap, one-level")
+    B = inputs.uniform_rhs(p.n, 4, 7)
+    B[:, 1] = 0.0
+    S = xm.Solver(H.export(), method=xm.BICGSTAB)
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd)
+    assert rc == xm.OK and st["iters"][1] == 0 and np.all(Xd.cpu().numpy()[:, 1] == 0)
+    S2 = xm.Solver(H.export(), method=xm.BICGSTAB, max_iters=1)
+    rc, st = S2.solve(Bd, torch.zeros_like(Bd))
+    Xo, so, rco = H.solve(B, method=orc.BICGSTAB, max_iters=1)
+    assert rc == xm.NOT_CONVERGED and rco == orc.NOT_CONVERGED
+    assert np.array_equal(st["iters"], so["iters"])
+    p4 = inputs.poisson7(4)
+    H4 = orc.Hierarchy(*p4.csr())
+    S3 = xm.Solver(H4.export(), method=xm.BICGSTAB)
+    B4 = inputs.uniform_rhs(p4.n, 2, 2)
+    X4 = torch.zeros((p4.n, 2), dtype=torch.float64, device="cuda")
+    rc, st = S3.solve(_dev(torch, B4), X4, tol=1e-12)
+    assert rc == xm.OK and np.all(st["iters"] == 1)
+    for s in (S, S2, S3):
+        s.close()
+
+
+# --------------------------------------------------------------------------
+# mixed precision (FP32 V-cycle, FP64 Krylov) and 16-bit indices
+# --------------------------------------------------------------------------
+# An FP32 V-cycle differs from the FP64 one by the rounding of every stored
+# operand and every operation: unit roundoff 2^-24 ~ 6e-8, amplified by at
+# most a few units per level over ~6-8 levels of smoothing and transfer;
+# 2e-5 relative (max-norm) leaves a margin of ~30 over that estimate.
+MIXED_VCYCLE_TOL = 2e-5
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("m", [1, 16])
+def test_vcycle_mixed_vs_fp64(orc, torch, xm, jump24, smoother, m):
+    p, H = jump24
+    _say(f"[vcycle-mixed] jump24 smoother={smoother} m={m}")
+    B = inputs.uniform_rhs(p.n, m, 6)
+    Zref = H.vcycle(B, smoother=smoother)
+    S = xm.Solver(H.export(), smoother=smoother, precision=xm.MIXED)
+    Bd = _dev(torch, B)
+    Zd = torch.full_like(Bd, np.nan)
+    S.vcycle(Bd, Zd)
+    torch.cuda.synchronize()
+    Z = Zd.cpu().numpy()
+    err = _relmax(Z, Zref)
+    assert err <= MIXED_VCYCLE_TOL, err
+    assert err > 1e-12          # really computed in reduced precision
+    S.close()
+
+
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_index16_bitwise_equal_index32(orc, torch, xm, smoother):
+    """16-bit column offsets decode to the same columns in the same order,
+    so the FP32 V-cycle must be bit-identical to the 32-bit-index one.
+    At 136^3 the z-neighbours lie N^2 = 18496 > 2^14 rows away, so level-0
+    row blocks need three index windows."""
+    p = inputs.anisotropic7(136)
+    _say(f"[index16] aniso136 smoother={smoother}")
+    Hh = xm.HostHierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 2, 9)
+    Bd = _dev(torch, B)
+    outs = []
+    for bits in (32, 16):
+        S = xm.Solver(Hh, smoother=smoother, precision=xm.MIXED, index_bits=bits)
+        if bits == 16:
+            fr = [S.index16_fraction(l) for l in range(S.nlev - 1)]
+            _say("   16-bit fraction per level (A, P, R):", [tuple(round(x, 3) for x in f) for f in fr])
+            assert fr[0][0] == 1.0
+        Zd = torch.full_like(Bd, np.nan)
+        S.vcycle(Bd, Zd)
+        torch.cuda.synchronize()
+        outs.append(Zd.cpu().numpy())
+        S.close()
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("method", [0, 1])
+def test_mixed_solve_accuracy(orc, torch, xm, jump24, method):
+    """FP64 Krylov with an FP32 preconditioner reaches the same tolerance;
+    its error against a tight FP64 reference is no worse than twice the
+    FP64 oracle's own error at the same tolerance (or 1e-7)."""
+    p, H = jump24
+    _say(f"[mixed-solve] jump24 method={method}")
+    B = inputs.uniform_rhs(p.n, 8, 44)
+    Xref, _, _ = H.solve(B, method=method, tol=1e-12)
+    Xalg, so, _ = H.solve(B, method=method, tol=1e-8)
+    S = xm.Solver(H.export(), method=method, precision=xm.MIXED, index_bits=16)
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-8)
+    assert rc == xm.OK
+    X = Xd.cpu().numpy()
+    tr = np.linalg.norm(B - orc.spmm(*p.csr(), X), axis=0) / np.linalg.norm(B, axis=0)
+    assert np.all(tr <= 1e-8)
+    e_mix = np.linalg.norm(X - Xref, axis=0) / np.linalg.norm(Xref, axis=0)
+    e_alg = np.linalg.norm(Xalg - Xref, axis=0) / np.linalg.norm(Xref, axis=0)
+    assert np.all(e_mix <= np.maximum(1e-7, 2 * e_alg)), (e_mix, e_alg)
+    # the FP32 preconditioner costs at most a couple of iterations
+    assert np.all(st["iters"] <= so["iters"] + 2)
+    _say(f"   iters mixed {st['iters'].tolist()} fp64 {so['iters'].tolist()} "
+         f"err {e_mix.max():.2e} (fp64 oracle {e_alg.max():.2e})")
+    S.close()
+
+
+def _poisson_with_far_couplings(N, seed, frac=0.05, w=0.01):
+    """7-point Poisson plus symmetric weak couplings between random distant
+    rows (M-matrix kept: each added -w is matched by +w on both diagonals).
+    Row blocks then touch more than four 2^14-wide column windows, which
+    forces the 32-bit fallback of the 16-bit index encoding."""
+    import scipy.sparse as sp
+    p = inputs.poisson7(N)
+    n = p.n
+    rng = np.random.default_rng(seed)
+    k = int(frac * n)
+    i = rng.integers(0, n, k)
+    j = rng.integers(0, n, k)
+    keep = np.abs(i - j) > 4 * (1 << 14)
+    i, j = i[keep], j[keep]
+    E = sp.coo_matrix((np.full(i.size, -w), (i, j)), shape=(n, n)).tocsr()
+    E = E + E.T
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(n, n)) + E
+    A = A + sp.diags(-np.asarray(E.sum(axis=1)).ravel())
+    A = sp.csr_matrix(A)
+    A.sum_duplicates()
+    A.sort_indices()
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def test_index16_wide_fallback_bitwise(orc, torch, xm):
+    rp, ci, v = _poisson_with_far_couplings(48, 3)
+    _say("[index16-wide] poisson48 + far couplings")
+    Hh = xm.HostHierarchy(rp, ci, v)
+    B = inputs.uniform_rhs(len(rp) - 1, 4, 10)
+    Bd = _dev(torch, B)
+    outs = []
+    for bits in (32, 16):
+        S = xm.Solver(Hh, precision=xm.MIXED, index_bits=bits)
+        if bits == 16:
+            fr = S.index16_fraction(0)
+            _say("   level-0 16-bit fraction (A, P, R):", fr)
+            assert 0.0 < fr[0] < 1.0
+        Zd = torch.full_like(Bd, np.nan)
+        S.vcycle(Bd, Zd)
+        torch.cuda.synchronize()
+        outs.append(Zd.cpu().numpy())
+        S.close()
+    assert np.isfinite(outs[0]).all()
+    assert np.array_equal(outs[0], outs[1])
