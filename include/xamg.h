@@ -186,6 +186,30 @@ int xamg_info(const xamg_handle_t *h, int64_t *out, int32_t cap);
  * 0 when the handle keeps 32-bit indices.  EINVAL for the coarsest level. */
 int xamg_index16_fraction(const xamg_handle_t *h, int32_t level, double *out);
 
+/* Autotuner (Section 2.2's kernels, tuned for this device): for each
+ * operator A_l, P_l, R_l of the copy the V-cycle uses, time the SpMM for
+ * m columns with 1, 2, 4 and 8 lane groups splitting a row's nonzeros, with
+ * HIP events on the solver's stream, and keep the fastest.  Runs by itself
+ * on the first solve for each padded m; this call re-runs it now (enable
+ * = 1) or switches automatic tuning off (enable = 0; the setup-time
+ * row-length heuristic stays in use).  m in {1, 2, 4, 8, 16, 32}. */
+int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
+
+/* Row splits in use for m columns: out[3l .. 3l+2] = split of A_l, P_l,
+ * R_l (0 where the operator does not exist).  cap >= 3 * nlevels. */
+int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
+
+/* Kernel timer: while enabled, every launch of the selected kernel during
+ * xamg_solve is bracketed by HIP events on the solver's stream, and
+ * xamg_timer_read returns the summed event time (ms) and the launch count
+ * since the last enable.  kind: XAMG_TIMER_OFF, XAMG_TIMER_KRYLOV_SPMM (the
+ * finest-level q = A p of CG with its fused (p, q) dot), XAMG_TIMER_PRESMOOTH
+ * (the finest-level pre-smoothing pass from a zero guess).  For measurement
+ * only; it adds two event records per timed launch. */
+enum { XAMG_TIMER_OFF = 0, XAMG_TIMER_KRYLOV_SPMM = 1, XAMG_TIMER_PRESMOOTH = 2 };
+int xamg_timer_enable(xamg_handle_t *h, int32_t kind);
+int xamg_timer_read(xamg_handle_t *h, double *ms, int64_t *count);
+
 /* Release every device and host resource of h (NULL is allowed). */
 int xamg_destroy(xamg_handle_t *h);
 

@@ -16,7 +16,8 @@ INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libxamg.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["common.cpp", "setup.cpp", "solver.hip", "bicgstab.hip", "batched.hip",
+SOURCES = ["common.cpp", "setup.cpp", "solver.hip", "inst_m1.hip", "inst_m2.hip",
+           "inst_m4.hip", "inst_m8.hip", "inst_m16.hip", "inst_m32.hip", "batched.hip",
            "cnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -44,7 +45,7 @@ def _compile(src):
 def build(verbose=True):
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC] + DEV_FLAGS + ["-shared", "-fPIC", "-fopenmp", "-o", tmp] + objs

@@ -1,4 +1,4 @@
-// bicgstab.hip -- right-preconditioned BiCGStab (van der Vorst 1992; the
+// bicgstab.hpp -- right-preconditioned BiCGStab (van der Vorst 1992; the
 // paper's Section 2.1 lists BiCGStab among its Krylov solvers) for m
 // interleaved columns with one set of scalars per column:
 //
@@ -15,13 +15,15 @@
 // breakdowns in a row stop it (reported as XAMG_EBREAKDOWN).  The scalar
 // recurrences run in one-block finalize kernels on the device; every
 // vector operation is a fused row pass (ops.hpp / below).
-#include "solver.hpp"
+#pragma once
+
+#include "cycle.hpp"
 
 namespace xamg {
 
 using namespace dev;
 
-namespace {
+namespace bicg {
 
 // y = A x with dots of y against w (and against y)
 template <int M, int CPT, typename MT, class IdxT, int KIND>
@@ -392,7 +394,9 @@ struct FinTrueB {
     }
 };
 
-}  // namespace
+}  // namespace bicg
+
+using namespace bicg;
 
 template <int M>
 int bicgstab(Handle& h, const double* B, double* X, double tol)
@@ -416,7 +420,7 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
                            nullptr, M, z, M, n, 0);
     {
         OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, r, nullptr};
-        const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
+        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
         launch_fin(h, nb, 2 * M, FinInitB{st, tol, M});
     }
     if (h.opt.x0_mode == XAMG_X0_GIVEN) {
@@ -432,7 +436,7 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
             OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, t,
                                                                   nullptr};
-            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
+            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
             launch_fin(h, nb, 2 * M, FinTrueB{st, M, it < h.opt.max_iters ? 1 : 0});
             sync_state(h);
             if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
@@ -450,7 +454,7 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         vcycle<M>(h, p, ph, 0, nullptr);
         {
             OpAxW<M, CPT, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, ph, v, rh, na};
-            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
+            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
             launch_fin(h, nb, M, FinAlphaB{st, M});
         }
         {
@@ -461,7 +465,7 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         vcycle<M>(h, s, sh, 0, nullptr);
         {
             OpAxW<M, CPT, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, sh, t, s, na};
-            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
+            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
             launch_fin(h, nb, 2 * M, FinOmega{st, M});
         }
         {
@@ -473,12 +477,5 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
     }
     return XAMG_OK;
 }
-
-template int bicgstab<1>(Handle&, const double*, double*, double);
-template int bicgstab<2>(Handle&, const double*, double*, double);
-template int bicgstab<4>(Handle&, const double*, double*, double);
-template int bicgstab<8>(Handle&, const double*, double*, double);
-template int bicgstab<16>(Handle&, const double*, double*, double);
-template int bicgstab<32>(Handle&, const double*, double*, double);
 
 }  // namespace xamg

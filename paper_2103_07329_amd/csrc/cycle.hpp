@@ -1,0 +1,523 @@
+// cycle.hpp -- V-cycle, CG driver and SpMM entry as templates over the
+// number of columns M; instantiated once per M (inst_m*.hip) so the
+// kernels of each column count compile in their own translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "solver.hpp"
+
+namespace xamg {
+
+using namespace dev;
+
+// ---------------------------------------------------------------------------
+// finalize functors (one block; tot[] holds the dot totals)
+// ---------------------------------------------------------------------------
+struct FinInit {   // tot: (b,b)[M], (r,r)[M]
+    ColState* st;
+    double tol;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M) {
+            const double bb = tot[j], rr = tot[M + j];
+            st->bn2[j] = bb;
+            st->rr[j] = rr;
+            const double rel = bb > 0.0 ? sqrt(rr) / sqrt(bb) : 0.0;
+            st->relres[j] = rel;
+            st->true_relres[j] = rel;
+            const int act = (bb > 0.0) && !(rel <= tol);
+            st->active[j] = act;
+            st->conv[j] = !act;
+            st->iters[j] = 0;
+            st->rst[j] = 1;
+            st->pz[j] = 0;
+            st->cp[j] = 0;
+            st->brk[j] = 0;
+            st->skip[j] = 0;
+            st->half[j] = 0;
+            st->failed[j] = 0;
+            st->alpha[j] = st->beta[j] = 0.0;
+            st->omega[j] = 1.0;
+            st->rz[j] = 1.0;
+        }
+        if (j == 0) {
+            st->tol = tol;
+            int bad = 0;
+            for (int q = 0; q < M; ++q) bad |= !isfinite(tot[q]);
+            st->nrestart = bad ? -1 : 0;
+        }
+        recount_active(st, M);
+    }
+};
+
+struct FinAlpha {   // tot: (p, q)[M]
+    ColState* st;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M) {
+            double a = 0.0;
+            if (st->active[j]) {
+                const double pq = tot[j];
+                if (!(pq > 0.0) || !isfinite(pq)) {
+                    st->active[j] = 0;
+                    st->failed[j] = 1;
+                } else {
+                    a = st->rz[j] / pq;
+                }
+            }
+            st->alpha[j] = a;
+        }
+        recount_active(st, M);
+    }
+};
+
+struct FinRR {   // tot: (r, r)[M]
+    ColState* st;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M && st->active[j]) {
+            const double rr = tot[j];
+            st->rr[j] = rr;
+            st->iters[j] += 1;
+            const double rel = sqrt(rr) / sqrt(st->bn2[j]);
+            st->relres[j] = rel;
+            if (rel <= st->tol) {
+                st->active[j] = 0;
+                st->conv[j] = 1;
+            }
+        }
+        recount_active(st, M);
+    }
+};
+
+struct FinBeta {   // tot: (r, z)[M] and, flexible, (z, q)[M]
+    ColState* st;
+    int M;
+    int flexible;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M && st->active[j]) {
+            const double rzn = tot[j];
+            double b = 0.0;
+            if (st->rst[j]) {
+                st->pz[j] = 1;
+                st->rst[j] = 0;
+            } else {
+                st->pz[j] = 0;
+                // flexible: (z_new, r_new - r_old) = -alpha (z_new, q)
+                b = flexible ? -st->alpha[j] * tot[M + j] / st->rz[j] : rzn / st->rz[j];
+            }
+            st->beta[j] = b;
+            st->rz[j] = rzn;
+        }
+    }
+};
+
+struct FinTrue {   // tot: (b, b)[M], (t, t)[M];  t = b - A x
+    ColState* st;
+    int M;
+    int allow_restart;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        __shared__ int nr;
+        if (j == 0) nr = 0;
+        __syncthreads();
+        if (j < M) {
+            const double bb = tot[j], tt = tot[M + j];
+            const double tr = bb > 0.0 ? sqrt(tt) / sqrt(bb) : 0.0;
+            st->true_relres[j] = tr;
+            st->cp[j] = 0;
+            if (allow_restart && st->conv[j] && bb > 0.0 && !(tr <= st->tol) && !st->failed[j]) {
+                st->conv[j] = 0;
+                st->active[j] = 1;
+                st->rst[j] = 1;
+                st->cp[j] = 1;
+                st->relres[j] = tr;
+                atomicAdd(&nr, 1);
+            }
+        }
+        __syncthreads();
+        if (j == 0) st->nrestart = nr;
+        recount_active(st, M);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// V-cycle
+// ---------------------------------------------------------------------------
+struct Cheb {
+    double theta, c1, c2, omega_deg1;
+};
+
+inline Cheb cheb_consts(const Handle& h, int l)
+{
+    const double hi = h.opt.cheby_hi_frac * h.lev[l].lmax;
+    const double lo = h.opt.cheby_lo_frac * hi;
+    Cheb c;
+    c.theta = 0.5 * (hi + lo);
+    const double delta = 0.5 * (hi - lo);
+    const double sigma = c.theta / delta;
+    const double rho0 = 1.0 / sigma;
+    const double rho1 = 1.0 / (2.0 * sigma - rho0);
+    c.c1 = rho1 * rho0;
+    c.c2 = (2.0 * rho1) / delta;
+    c.omega_deg1 = 1.0 / c.theta;
+    return c;
+}
+
+template <typename T>
+static const DCsr& matA(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.A64; else return L.A32; }
+template <typename T>
+static const DCsr& matP(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.P64; else return L.P32; }
+template <typename T>
+static const DCsr& matR(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.R64; else return L.R32; }
+template <typename T>
+static const T* dinv_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dinv64; else return L.dinv32; }
+
+// Calls f(idx) with the index decoder of matrix d (16-bit if encoded).
+template <class F>
+static void with_idx(const DCsr& d, F&& f)
+{
+    if (d.off) {
+        Idx16 ix;
+        ix.off = d.off;
+        ix.ci = d.ci;
+        ix.base = d.base;
+        f(ix);
+    } else {
+        f(Idx32{d.ci});
+    }
+}
+
+template <typename T>
+static T* lvbuf(void* p) { return static_cast<T*>(p); }
+
+// One level of V(1,1) from a zero guess.  b: right-hand side of the level
+// (BT), xout: corrected solution (OT).  At the finest level the last pass
+// also accumulates the dots (b, xout) [and (q, xout)].  Returns the block
+// count of the last launch (the one that wrote partial dots).
+template <int M, typename T, typename BT, typename OT>
+static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q)
+{
+    constexpr int CPT = cpt_for<T, M>();
+    const LevelDev& L = h.lev[l];
+    const int* na = &h.st->nactive;
+    const int cap = h.nb_cap;
+    auto& W = h.w.lev[l];
+    int nb = 1;
+    if (l == h.nlev - 1) {
+        // coarsest level: dense inverse in LDS
+        if constexpr (std::is_same<BT, T>::value && std::is_same<OT, T>::value) {
+            const T* inv;
+            if constexpr (sizeof(T) == 8) inv = h.inv64; else inv = h.inv32;
+            hipLaunchKernelGGL((coarse_kernel<M, T>), dim3(1), dim3(256), 0, h.stream, inv,
+                               L.n, b, xout, na);
+        } else {
+            set_error("internal: coarsest level with mixed boundary types");
+            throw DevFail{XAMG_EINVAL};
+        }
+        return 0;
+    }
+    const DCsr& A = matA<T>(L);
+    const T* dinv = dinv_of<T>(L);
+    T* X = lvbuf<T>(W.X);
+    T* R = lvbuf<T>(W.R);
+    T* Tb = lvbuf<T>(W.T);
+    T* Bc = lvbuf<T>(h.w.lev[l + 1].B);
+    T* Xc = lvbuf<T>(h.w.lev[l + 1].X2);
+    const bool cheb2 = h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2;
+    const Cheb ch = cheb_consts(h, l);
+    const T omega = T(h.opt.smoother == XAMG_CHEBYSHEV ? ch.omega_deg1 : h.opt.omega);
+    const int* rp = A.rp;
+    const T* av = static_cast<const T*>(A.v);
+
+    // pre-smoothing from zero (+ residual)
+    with_idx(A, [&](auto ix) {
+        using IX = decltype(ix);
+        if (l == 0) h.timer_begin(XAMG_TIMER_PRESMOOTH);
+        if (!cheb2) {
+            OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
+            launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
+            if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
+        } else {
+            OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(ch.theta), T(ch.c1),
+                                               T(ch.c2), b, X, na};
+            launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
+            if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
+            OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
+            launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
+        }
+    });
+    // restriction b_{l+1} = R_l r_l
+    {
+        const DCsr& Rm = matR<T>(L);
+        with_idx(Rm, [&](auto ix) {
+            using IX = decltype(ix);
+            OpAx<M, CPT, T, T, IX, 0> op{Rm.rp, static_cast<const T*>(Rm.v), ix, R, Bc, na};
+            launch_mat<M, CPT>(h, op, Rm.template split_of<M>(), Rm.nr, cap);
+        });
+    }
+    vlevel<M, T, T, T>(h, l + 1, Bc, Xc, 0, nullptr);
+    // prolongation x_l += P_l x_{l+1}
+    {
+        const DCsr& Pm = matP<T>(L);
+        with_idx(Pm, [&](auto ix) {
+            using IX = decltype(ix);
+            OpProlongAdd<M, CPT, T, T, IX> op{Pm.rp, static_cast<const T*>(Pm.v), ix, Xc, X, na};
+            launch_mat<M, CPT>(h, op, Pm.template split_of<M>(), Pm.nr, cap);
+        });
+    }
+    // post-smoothing (+ finest-level dots)
+    with_idx(A, [&](auto ix) {
+        using IX = decltype(ix);
+        auto post = [&](auto dots_tag) {
+            constexpr int D = decltype(dots_tag)::value;
+            if (!cheb2) {
+                OpJacPost<M, CPT, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
+                                                          q, na};
+                nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
+            } else {
+                OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
+                launch_mat<M, CPT>(h, p1, A.template split_of<M>(), L.n, cap);
+                OpChebPost2<M, CPT, T, T, BT, OT, IX, D> p2{
+                    rp, av, ix, dinv, T(ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
+                nb = launch_mat<M, CPT>(h, p2, A.template split_of<M>(), L.n, cap);
+            }
+        };
+        if (ndots == 2) post(std::integral_constant<int, 2>{});
+        else if (ndots == 1) post(std::integral_constant<int, 1>{});
+        else post(std::integral_constant<int, 0>{});
+    });
+    return nb;
+}
+
+// dots (b, x) [and (q, x)] as a pure vector pass (used when the finest
+// level is also the coarsest and no smoothing pass exists to fuse them into)
+template <int M, int CPT, int D>
+struct OpDotsBX {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = D;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const double *b, *x, *q;
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT], double (&d)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        const auto bi = load_pack<double, CPT>(b + o);
+        const auto xi = load_pack<double, CPT>(x + o);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) d[0][t] += bi.v[t] * xi.v[t];
+        if constexpr (D == 2) {
+            const auto qi = load_pack<double, CPT>(q + o);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * xi.v[t];
+        }
+    }
+};
+
+// z = M^-1 r for the whole hierarchy; returns the block count of the
+// launch that produced the finest-level dots (0 if ndots == 0).
+template <int M>
+int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    if (h.nlev == 1) {
+        hipLaunchKernelGGL((coarse_kernel<M, double>), dim3(1), dim3(256), 0, h.stream,
+                           h.inv64, h.lev[0].n, r, z, &h.st->nactive);
+        if (ndots == 0) return 0;
+        if (ndots == 2) {
+            OpDotsBX<M, CPT, 2> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
+            return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+        }
+        OpDotsBX<M, CPT, 1> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
+        return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+    }
+    if (h.opt.precision == XAMG_MIXED) return vlevel<M, float, double, double>(h, 0, r, z, ndots, q);
+    return vlevel<M, double, double, double>(h, 0, r, z, ndots, q);
+}
+
+
+// ---------------------------------------------------------------------------
+// preconditioned CG, all m columns at once
+// ---------------------------------------------------------------------------
+template <int M>
+int pcg(Handle& h, const double* B, double* X, double tol)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    const int n = h.lev[0].n;
+    const DCsr& A = h.lev[0].A64;
+    const double* av = static_cast<const double*>(A.v);
+    auto& w = h.w;
+    ColState* st = h.st;
+    const int cap = h.nb_cap;
+    const int flex = h.opt.precision == XAMG_MIXED ? 1 : h.opt.flexible;
+    const int nd = flex ? 2 : 1;
+
+    if (h.opt.x0_mode == XAMG_X0_ZERO)
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
+                           nullptr, M, X, M, n, 0);
+    {
+        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, w.r,
+                                                              nullptr};
+        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+        launch_fin(h, nb, 2 * M, FinInit{st, tol, M});
+    }
+    if (h.opt.x0_mode == XAMG_X0_GIVEN) {
+        OpFixCols<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, nullptr, nullptr, X};
+        launch_rows<M, CPT>(h, op, n, cap);
+    }
+    auto precondition = [&]() {
+        const int nb = vcycle<M>(h, w.r, w.z, nd, w.q);
+        launch_fin(h, nb, nd * M, FinBeta{st, M, flex});
+        OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, st, w.p, w.z};
+        launch_rows<M, CPT>(h, up, n, cap);
+    };
+    // q must be finite for the flexible dot of the first cycle
+    if (flex)
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
+                           nullptr, M, w.q, M, n, 0);
+    precondition();
+    sync_state(h);
+    if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
+
+    int it = 0;
+    const int every = std::max(1, h.opt.check_every);
+    for (;;) {
+        if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
+            OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B,
+                                                                  w.t, nullptr};
+            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+            launch_fin(h, nb, 2 * M, FinTrue{st, M, it < h.opt.max_iters ? 1 : 0});
+            sync_state(h);
+            if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
+            OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, st, w.r, w.t, nullptr};
+            launch_rows<M, CPT>(h, cp, n, cap);
+            precondition();
+            sync_state(h);
+            continue;
+        }
+        ++it;
+        {
+            OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, w.p, w.q,
+                                                       &st->nactive};
+            h.timer_begin(XAMG_TIMER_KRYLOV_SPMM);
+            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+            h.timer_end(XAMG_TIMER_KRYLOV_SPMM);
+            launch_fin(h, nb, M, FinAlpha{st, M});
+        }
+        {
+            OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, w.r, w.p, w.q};
+            const int nb = launch_rows<M, CPT>(h, op, n, cap);
+            launch_fin(h, nb, M, FinRR{st, M});
+        }
+        precondition();
+        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
+    }
+    return XAMG_OK;
+}
+
+
+template <int M>
+void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    OpAx<M, CPT, double, double, Idx32, 0> op{d.rp, static_cast<const double*>(d.v),
+                                              Idx32{d.ci}, X, Y, nullptr};
+    launch_mat<M, CPT>(h, op, d.template split_of<M>(), d.nr, h.nb_cap);
+}
+
+
+// ---------------------------------------------------------------------------
+// autotuner: for every operator of the hierarchy, time the plain SpMM
+// y = Op x with each admissible row split S (lane groups per row) using HIP
+// events, and keep the fastest for this column count.  Runs once per M on
+// the first solve (or on request); setup cost, not solve cost.
+// ---------------------------------------------------------------------------
+template <int M, typename T>
+float time_spmm(Handle& h, const DCsr& d, int S, const T* x, T* y, hipEvent_t e0, hipEvent_t e1)
+{
+    constexpr int CPT = cpt_for<T, M>();
+    float ms = 0.0f;
+    with_idx(d, [&](auto ix) {
+        using IX = decltype(ix);
+        OpAx<M, CPT, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, y, nullptr};
+        launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
+        h.check(hipEventRecord(e0, h.stream), "tune event");
+        for (int r = 0; r < 3; ++r) launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
+        h.check(hipEventRecord(e1, h.stream), "tune event");
+        h.check(hipEventSynchronize(e1), "tune sync");
+        h.check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
+    });
+    return ms;
+}
+
+template <int M, typename T>
+void tune_matrix(Handle& h, DCsr& d, const T* x, T* y, hipEvent_t e0, hipEvent_t e1)
+{
+    constexpr int G = M / cpt_for<T, M>();
+    constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
+    if (!d.rp || d.nr == 0) return;
+    float best = 0.0f;
+    int bestS = 1;
+    for (int S : {1, 2, 4, 8}) {
+        if (G * S > 64) break;
+        const float t = time_spmm<M, T>(h, d, S, x, y, e0, e1);
+        if (S == 1 || t < best) {
+            best = t;
+            bestS = S;
+        }
+    }
+    d.split[k] = bestS;
+}
+
+template <int M>
+void autotune(Handle& h)
+{
+    constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
+    if (h.tuned_mask & (1u << k)) return;
+    const int n0 = h.lev[0].n;
+    // scratch: the Krylov r and z blocks (n0 x mcap doubles), zero-filled
+    hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
+                       nullptr, M, h.w.r, M, n0, 0);
+    hipEvent_t e0, e1;
+    h.check(hipEventCreate(&e0), "hipEventCreate");
+    h.check(hipEventCreate(&e1), "hipEventCreate");
+    const bool mixed = h.opt.precision == XAMG_MIXED;
+    for (int l = 0; l < h.nlev; ++l) {
+        auto& L = h.lev[l];
+        if (l == 0 || !mixed) tune_matrix<M, double>(h, L.A64, h.w.r, h.w.z, e0, e1);
+        if (l + 1 < h.nlev) {
+            if (!mixed) {
+                tune_matrix<M, double>(h, L.P64, h.w.r, h.w.z, e0, e1);
+                tune_matrix<M, double>(h, L.R64, h.w.r, h.w.z, e0, e1);
+            } else {
+                const float* xf = reinterpret_cast<const float*>(h.w.r);
+                float* yf = reinterpret_cast<float*>(h.w.z);
+                tune_matrix<M, float>(h, L.A32, xf, yf, e0, e1);
+                tune_matrix<M, float>(h, L.P32, xf, yf, e0, e1);
+                tune_matrix<M, float>(h, L.R32, xf, yf, e0, e1);
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    h.tuned_mask |= 1u << k;
+}
+
+}  // namespace xamg

@@ -1,0 +1,13 @@
+// inst_m1.hip -- the solver templates instantiated for M = 1 columns.
+#include "bicgstab.hpp"
+#include "cycle.hpp"
+
+namespace xamg {
+
+template int vcycle<1>(Handle&, const double*, double*, int, const double*);
+template int pcg<1>(Handle&, const double*, double*, double);
+template int bicgstab<1>(Handle&, const double*, double*, double);
+template void spmm64<1>(Handle&, const DCsr&, const double*, double*);
+template void autotune<1>(Handle&);
+
+}  // namespace xamg

@@ -1,0 +1,13 @@
+// inst_m32.hip -- the solver templates instantiated for M = 32 columns.
+#include "bicgstab.hpp"
+#include "cycle.hpp"
+
+namespace xamg {
+
+template int vcycle<32>(Handle&, const double*, double*, int, const double*);
+template int pcg<32>(Handle&, const double*, double*, double);
+template int bicgstab<32>(Handle&, const double*, double*, double);
+template void spmm64<32>(Handle&, const DCsr&, const double*, double*);
+template void autotune<32>(Handle&);
+
+}  // namespace xamg

@@ -1,0 +1,13 @@
+// inst_m4.hip -- the solver templates instantiated for M = 4 columns.
+#include "bicgstab.hpp"
+#include "cycle.hpp"
+
+namespace xamg {
+
+template int vcycle<4>(Handle&, const double*, double*, int, const double*);
+template int pcg<4>(Handle&, const double*, double*, double);
+template int bicgstab<4>(Handle&, const double*, double*, double);
+template void spmm64<4>(Handle&, const DCsr&, const double*, double*);
+template void autotune<4>(Handle&);
+
+}  // namespace xamg

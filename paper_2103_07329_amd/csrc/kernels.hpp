@@ -18,10 +18,9 @@
 //     finalize kernel adds the partials in block order (deterministic) and
 //     updates the Krylov scalars on the device.
 //
-// Rows are split into contiguous chunks, one per block, and blocks are
-// renumbered so that each of the 8 XCDs (which receive blocks round-robin)
-// owns one contiguous eighth of the rows: neighbouring rows share gathered
-// x entries, so this keeps the reuse inside one XCD's L2.
+// Each of the 8 XCDs (which receive blocks round-robin) owns one contiguous
+// eighth of the rows and its blocks sweep it together: neighbouring rows
+// share gathered x entries, so this keeps the reuse inside one XCD's L2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -130,14 +129,6 @@ __device__ __forceinline__ void reduce_dots(double (&d)[ND > 0 ? ND : 1][CPT],
     }
 }
 
-// block id -> contiguous chunk, XCD-aware (see header comment)
-__device__ __forceinline__ int logical_block()
-{
-    const int nb = gridDim.x;
-    if (nb % kNumXcd != 0) return blockIdx.x;
-    return (blockIdx.x % kNumXcd) * (nb / kNumXcd) + blockIdx.x / kNumXcd;
-}
-
 // ---------------------------------------------------------------------------
 // the generic row kernel
 // ---------------------------------------------------------------------------
@@ -165,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
     const int sg = (threadIdx.x / G) % S;
     const int rl = threadIdx.x / (G * S);
     const int j0 = g * CPT;
-    const int blk = logical_block();
+    const int blk = blockIdx.x;
     double dsum[ND > 0 ? ND : 1][CPT];
 #pragma unroll
     for (int q = 0; q < (ND > 0 ? ND : 1); ++q)
@@ -173,11 +164,21 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
         for (int c = 0; c < CPT; ++c) dsum[q][c] = 0.0;
 
     if (op.active_any()) {
+        // XCD x (blocks are dealt to the 8 XCDs round-robin) owns a
+        // contiguous slab of tiles; its blocks sweep the slab together, so
+        // rows processed at the same time -- and the x entries they share --
+        // stay inside one XCD's L2.  A launch with one block per tile
+        // reduces to one tile per block in slab order.
         const int ntiles = (nrows + RPB - 1) / RPB;
-        const int per = (ntiles + gridDim.x - 1) / gridDim.x;
-        const int t0 = blk * per;
-        const int t1 = min(ntiles, t0 + per);
-        for (int t = t0; t < t1; ++t) {
+        int tb = 0, te = ntiles, t0 = blockIdx.x, tstep = gridDim.x;
+        if (gridDim.x % kNumXcd == 0) {
+            const int per = (ntiles + kNumXcd - 1) / kNumXcd;
+            tb = (blockIdx.x % kNumXcd) * per;
+            te = min(ntiles, tb + per);
+            t0 = tb + blockIdx.x / kNumXcd;
+            tstep = gridDim.x / kNumXcd;
+        }
+        for (int t = t0; t < te; t += tstep) {
             const int i = t * RPB + rl;
             const bool live = i < nrows;
             AT acc[CPT];

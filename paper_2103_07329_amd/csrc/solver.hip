@@ -66,6 +66,40 @@ Handle::~Handle()
 {
     for (void* p : allocs) hipFree(p);
     if (st_host) hipHostFree(st_host);
+    for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+}
+
+// kernel timer: an event pair around each launch of the selected kind
+void Handle::timer_begin(int kind)
+{
+    if (timer_kind == 0 || kind != timer_kind) return;
+    if (ev_used + 2 > ev_pool.size()) {
+        for (int k = 0; k < 64; ++k) {
+            hipEvent_t e;
+            check(hipEventCreate(&e), "hipEventCreate");
+            ev_pool.push_back(e);
+        }
+    }
+    check(hipEventRecord(ev_pool[ev_used], stream), "hipEventRecord");
+}
+
+void Handle::timer_end(int kind)
+{
+    if (timer_kind == 0 || kind != timer_kind) return;
+    check(hipEventRecord(ev_pool[ev_used + 1], stream), "hipEventRecord");
+    ev_used += 2;
+}
+
+// add up the recorded pairs (after the stream has been synchronised)
+void Handle::timer_collect()
+{
+    for (size_t k = 0; k + 1 < ev_used; k += 2) {
+        float ms = 0.0f;
+        check(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]), "hipEventElapsedTime");
+        timer_ms += ms;
+        timer_count += 1;
+    }
+    ev_used = 0;
 }
 
 template <typename T>
@@ -82,7 +116,7 @@ static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
     d.nr = int(c.nrows);
     d.nc = int(c.ncols);
     d.nnz = c.nnz;
-    d.split = split_for(c.nnz, int(c.nrows));
+    for (int k = 0; k < 6; ++k) d.split[k] = split_for(c.nnz, int(c.nrows));
     d.rp = upload(h, c.row_ptr, size_t(c.nrows) + 1);
     d.ci = upload(h, c.col, size_t(c.nnz));
     if (fp32) {
@@ -140,342 +174,6 @@ static double encode16(Handle& h, const xamg_csr_t& c, DCsr& d)
 }
 
 // ---------------------------------------------------------------------------
-// finalize functors (one block; tot[] holds the dot totals)
-// ---------------------------------------------------------------------------
-struct FinInit {   // tot: (b,b)[M], (r,r)[M]
-    ColState* st;
-    double tol;
-    int M;
-    __device__ void operator()(const double* tot) const
-    {
-        const int j = threadIdx.x;
-        if (j < M) {
-            const double bb = tot[j], rr = tot[M + j];
-            st->bn2[j] = bb;
-            st->rr[j] = rr;
-            const double rel = bb > 0.0 ? sqrt(rr) / sqrt(bb) : 0.0;
-            st->relres[j] = rel;
-            st->true_relres[j] = rel;
-            const int act = (bb > 0.0) && !(rel <= tol);
-            st->active[j] = act;
-            st->conv[j] = !act;
-            st->iters[j] = 0;
-            st->rst[j] = 1;
-            st->pz[j] = 0;
-            st->cp[j] = 0;
-            st->brk[j] = 0;
-            st->skip[j] = 0;
-            st->half[j] = 0;
-            st->failed[j] = 0;
-            st->alpha[j] = st->beta[j] = 0.0;
-            st->omega[j] = 1.0;
-            st->rz[j] = 1.0;
-        }
-        if (j == 0) {
-            st->tol = tol;
-            int bad = 0;
-            for (int q = 0; q < M; ++q) bad |= !isfinite(tot[q]);
-            st->nrestart = bad ? -1 : 0;
-        }
-        recount_active(st, M);
-    }
-};
-
-struct FinAlpha {   // tot: (p, q)[M]
-    ColState* st;
-    int M;
-    __device__ void operator()(const double* tot) const
-    {
-        const int j = threadIdx.x;
-        if (j < M) {
-            double a = 0.0;
-            if (st->active[j]) {
-                const double pq = tot[j];
-                if (!(pq > 0.0) || !isfinite(pq)) {
-                    st->active[j] = 0;
-                    st->failed[j] = 1;
-                } else {
-                    a = st->rz[j] / pq;
-                }
-            }
-            st->alpha[j] = a;
-        }
-        recount_active(st, M);
-    }
-};
-
-struct FinRR {   // tot: (r, r)[M]
-    ColState* st;
-    int M;
-    __device__ void operator()(const double* tot) const
-    {
-        const int j = threadIdx.x;
-        if (j < M && st->active[j]) {
-            const double rr = tot[j];
-            st->rr[j] = rr;
-            st->iters[j] += 1;
-            const double rel = sqrt(rr) / sqrt(st->bn2[j]);
-            st->relres[j] = rel;
-            if (rel <= st->tol) {
-                st->active[j] = 0;
-                st->conv[j] = 1;
-            }
-        }
-        recount_active(st, M);
-    }
-};
-
-struct FinBeta {   // tot: (r, z)[M] and, flexible, (z, q)[M]
-    ColState* st;
-    int M;
-    int flexible;
-    __device__ void operator()(const double* tot) const
-    {
-        const int j = threadIdx.x;
-        if (j < M && st->active[j]) {
-            const double rzn = tot[j];
-            double b = 0.0;
-            if (st->rst[j]) {
-                st->pz[j] = 1;
-                st->rst[j] = 0;
-            } else {
-                st->pz[j] = 0;
-                // flexible: (z_new, r_new - r_old) = -alpha (z_new, q)
-                b = flexible ? -st->alpha[j] * tot[M + j] / st->rz[j] : rzn / st->rz[j];
-            }
-            st->beta[j] = b;
-            st->rz[j] = rzn;
-        }
-    }
-};
-
-struct FinTrue {   // tot: (b, b)[M], (t, t)[M];  t = b - A x
-    ColState* st;
-    int M;
-    int allow_restart;
-    __device__ void operator()(const double* tot) const
-    {
-        const int j = threadIdx.x;
-        __shared__ int nr;
-        if (j == 0) nr = 0;
-        __syncthreads();
-        if (j < M) {
-            const double bb = tot[j], tt = tot[M + j];
-            const double tr = bb > 0.0 ? sqrt(tt) / sqrt(bb) : 0.0;
-            st->true_relres[j] = tr;
-            st->cp[j] = 0;
-            if (allow_restart && st->conv[j] && bb > 0.0 && !(tr <= st->tol) && !st->failed[j]) {
-                st->conv[j] = 0;
-                st->active[j] = 1;
-                st->rst[j] = 1;
-                st->cp[j] = 1;
-                st->relres[j] = tr;
-                atomicAdd(&nr, 1);
-            }
-        }
-        __syncthreads();
-        if (j == 0) st->nrestart = nr;
-        recount_active(st, M);
-    }
-};
-
-// ---------------------------------------------------------------------------
-// V-cycle
-// ---------------------------------------------------------------------------
-struct Cheb {
-    double theta, c1, c2, omega_deg1;
-};
-
-static Cheb cheb_consts(const Handle& h, int l)
-{
-    const double hi = h.opt.cheby_hi_frac * h.lev[l].lmax;
-    const double lo = h.opt.cheby_lo_frac * hi;
-    Cheb c;
-    c.theta = 0.5 * (hi + lo);
-    const double delta = 0.5 * (hi - lo);
-    const double sigma = c.theta / delta;
-    const double rho0 = 1.0 / sigma;
-    const double rho1 = 1.0 / (2.0 * sigma - rho0);
-    c.c1 = rho1 * rho0;
-    c.c2 = (2.0 * rho1) / delta;
-    c.omega_deg1 = 1.0 / c.theta;
-    return c;
-}
-
-template <typename T>
-static const DCsr& matA(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.A64; else return L.A32; }
-template <typename T>
-static const DCsr& matP(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.P64; else return L.P32; }
-template <typename T>
-static const DCsr& matR(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.R64; else return L.R32; }
-template <typename T>
-static const T* dinv_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dinv64; else return L.dinv32; }
-
-// Calls f(idx) with the index decoder of matrix d (16-bit if encoded).
-template <class F>
-static void with_idx(const DCsr& d, F&& f)
-{
-    if (d.off) {
-        Idx16 ix;
-        ix.off = d.off;
-        ix.ci = d.ci;
-        ix.base = d.base;
-        f(ix);
-    } else {
-        f(Idx32{d.ci});
-    }
-}
-
-template <typename T>
-static T* lvbuf(void* p) { return static_cast<T*>(p); }
-
-// One level of V(1,1) from a zero guess.  b: right-hand side of the level
-// (BT), xout: corrected solution (OT).  At the finest level the last pass
-// also accumulates the dots (b, xout) [and (q, xout)].  Returns the block
-// count of the last launch (the one that wrote partial dots).
-template <int M, typename T, typename BT, typename OT>
-static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q)
-{
-    constexpr int CPT = cpt_for<T, M>();
-    const LevelDev& L = h.lev[l];
-    const int* na = &h.st->nactive;
-    const int cap = h.nb_cap;
-    auto& W = h.w.lev[l];
-    int nb = 1;
-    if (l == h.nlev - 1) {
-        // coarsest level: dense inverse in LDS
-        if constexpr (std::is_same<BT, T>::value && std::is_same<OT, T>::value) {
-            const T* inv;
-            if constexpr (sizeof(T) == 8) inv = h.inv64; else inv = h.inv32;
-            hipLaunchKernelGGL((coarse_kernel<M, T>), dim3(1), dim3(256), 0, h.stream, inv,
-                               L.n, b, xout, na);
-        } else {
-            set_error("internal: coarsest level with mixed boundary types");
-            throw DevFail{XAMG_EINVAL};
-        }
-        return 0;
-    }
-    const DCsr& A = matA<T>(L);
-    const T* dinv = dinv_of<T>(L);
-    T* X = lvbuf<T>(W.X);
-    T* R = lvbuf<T>(W.R);
-    T* Tb = lvbuf<T>(W.T);
-    T* Bc = lvbuf<T>(h.w.lev[l + 1].B);
-    T* Xc = lvbuf<T>(h.w.lev[l + 1].X2);
-    const bool cheb2 = h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2;
-    const Cheb ch = cheb_consts(h, l);
-    const T omega = T(h.opt.smoother == XAMG_CHEBYSHEV ? ch.omega_deg1 : h.opt.omega);
-    const int* rp = A.rp;
-    const T* av = static_cast<const T*>(A.v);
-
-    // pre-smoothing from zero (+ residual)
-    with_idx(A, [&](auto ix) {
-        using IX = decltype(ix);
-        if (!cheb2) {
-            OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
-            launch_mat<M, CPT>(h, op, A.split, L.n, cap);
-        } else {
-            OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(ch.theta), T(ch.c1),
-                                               T(ch.c2), b, X, na};
-            launch_mat<M, CPT>(h, op, A.split, L.n, cap);
-            OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
-            launch_mat<M, CPT>(h, rs, A.split, L.n, cap);
-        }
-    });
-    // restriction b_{l+1} = R_l r_l
-    {
-        const DCsr& Rm = matR<T>(L);
-        with_idx(Rm, [&](auto ix) {
-            using IX = decltype(ix);
-            OpAx<M, CPT, T, T, IX, 0> op{Rm.rp, static_cast<const T*>(Rm.v), ix, R, Bc, na};
-            launch_mat<M, CPT>(h, op, Rm.split, Rm.nr, cap);
-        });
-    }
-    vlevel<M, T, T, T>(h, l + 1, Bc, Xc, 0, nullptr);
-    // prolongation x_l += P_l x_{l+1}
-    {
-        const DCsr& Pm = matP<T>(L);
-        with_idx(Pm, [&](auto ix) {
-            using IX = decltype(ix);
-            OpProlongAdd<M, CPT, T, T, IX> op{Pm.rp, static_cast<const T*>(Pm.v), ix, Xc, X, na};
-            launch_mat<M, CPT>(h, op, Pm.split, Pm.nr, cap);
-        });
-    }
-    // post-smoothing (+ finest-level dots)
-    with_idx(A, [&](auto ix) {
-        using IX = decltype(ix);
-        auto post = [&](auto dots_tag) {
-            constexpr int D = decltype(dots_tag)::value;
-            if (!cheb2) {
-                OpJacPost<M, CPT, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
-                                                          q, na};
-                nb = launch_mat<M, CPT>(h, op, A.split, L.n, cap);
-            } else {
-                OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
-                launch_mat<M, CPT>(h, p1, A.split, L.n, cap);
-                OpChebPost2<M, CPT, T, T, BT, OT, IX, D> p2{
-                    rp, av, ix, dinv, T(ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
-                nb = launch_mat<M, CPT>(h, p2, A.split, L.n, cap);
-            }
-        };
-        if (ndots == 2) post(std::integral_constant<int, 2>{});
-        else if (ndots == 1) post(std::integral_constant<int, 1>{});
-        else post(std::integral_constant<int, 0>{});
-    });
-    return nb;
-}
-
-// dots (b, x) [and (q, x)] as a pure vector pass (used when the finest
-// level is also the coarsest and no smoothing pass exists to fuse them into)
-template <int M, int CPT, int D>
-struct OpDotsBX {
-    using AT = double;
-    static constexpr bool kMatrix = false;
-    static constexpr int kDots = D;
-    const int* rp = nullptr;
-    const double* val = nullptr;
-    Idx32 idx{nullptr};
-    const double *b, *x, *q;
-    __device__ __forceinline__ bool active_any() const { return true; }
-    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
-    template <int ND>
-    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT], double (&d)[ND][CPT]) const
-    {
-        const size_t o = size_t(i) * M + j0;
-        const auto bi = load_pack<double, CPT>(b + o);
-        const auto xi = load_pack<double, CPT>(x + o);
-#pragma unroll
-        for (int t = 0; t < CPT; ++t) d[0][t] += bi.v[t] * xi.v[t];
-        if constexpr (D == 2) {
-            const auto qi = load_pack<double, CPT>(q + o);
-#pragma unroll
-            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * xi.v[t];
-        }
-    }
-};
-
-// z = M^-1 r for the whole hierarchy; returns the block count of the
-// launch that produced the finest-level dots (0 if ndots == 0).
-template <int M>
-int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q)
-{
-    constexpr int CPT = cpt_for<double, M>();
-    if (h.nlev == 1) {
-        hipLaunchKernelGGL((coarse_kernel<M, double>), dim3(1), dim3(256), 0, h.stream,
-                           h.inv64, h.lev[0].n, r, z, &h.st->nactive);
-        if (ndots == 0) return 0;
-        if (ndots == 2) {
-            OpDotsBX<M, CPT, 2> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
-            return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
-        }
-        OpDotsBX<M, CPT, 1> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
-        return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
-    }
-    if (h.opt.precision == XAMG_MIXED) return vlevel<M, float, double, double>(h, 0, r, z, ndots, q);
-    return vlevel<M, double, double, double>(h, 0, r, z, ndots, q);
-}
-
-// ---------------------------------------------------------------------------
 // work buffers
 // ---------------------------------------------------------------------------
 void ensure_work(Handle& h, int mp, bool bicg)
@@ -527,105 +225,6 @@ void sync_state(Handle& h)
     h.check(hipStreamSynchronize(h.stream), "stream sync");
 }
 
-// ---------------------------------------------------------------------------
-// preconditioned CG, all m columns at once
-// ---------------------------------------------------------------------------
-template <int M>
-int pcg(Handle& h, const double* B, double* X, double tol)
-{
-    constexpr int CPT = cpt_for<double, M>();
-    const int n = h.lev[0].n;
-    const DCsr& A = h.lev[0].A64;
-    const double* av = static_cast<const double*>(A.v);
-    auto& w = h.w;
-    ColState* st = h.st;
-    const int cap = h.nb_cap;
-    const int flex = h.opt.precision == XAMG_MIXED ? 1 : h.opt.flexible;
-    const int nd = flex ? 2 : 1;
-
-    if (h.opt.x0_mode == XAMG_X0_ZERO)
-        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
-                           nullptr, M, X, M, n, 0);
-    {
-        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, w.r,
-                                                              nullptr};
-        const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
-        launch_fin(h, nb, 2 * M, FinInit{st, tol, M});
-    }
-    if (h.opt.x0_mode == XAMG_X0_GIVEN) {
-        OpFixCols<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, nullptr, nullptr, X};
-        launch_rows<M, CPT>(h, op, n, cap);
-    }
-    auto precondition = [&]() {
-        const int nb = vcycle<M>(h, w.r, w.z, nd, w.q);
-        launch_fin(h, nb, nd * M, FinBeta{st, M, flex});
-        OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, st, w.p, w.z};
-        launch_rows<M, CPT>(h, up, n, cap);
-    };
-    // q must be finite for the flexible dot of the first cycle
-    if (flex)
-        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
-                           nullptr, M, w.q, M, n, 0);
-    precondition();
-    sync_state(h);
-    if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
-
-    int it = 0;
-    const int every = std::max(1, h.opt.check_every);
-    for (;;) {
-        if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
-            OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B,
-                                                                  w.t, nullptr};
-            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
-            launch_fin(h, nb, 2 * M, FinTrue{st, M, it < h.opt.max_iters ? 1 : 0});
-            sync_state(h);
-            if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
-            OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, st, w.r, w.t, nullptr};
-            launch_rows<M, CPT>(h, cp, n, cap);
-            precondition();
-            sync_state(h);
-            continue;
-        }
-        ++it;
-        {
-            OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, w.p, w.q,
-                                                       &st->nactive};
-            const int nb = launch_mat<M, CPT>(h, op, A.split, n, cap);
-            launch_fin(h, nb, M, FinAlpha{st, M});
-        }
-        {
-            OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, w.r, w.p, w.q};
-            const int nb = launch_rows<M, CPT>(h, op, n, cap);
-            launch_fin(h, nb, M, FinRR{st, M});
-        }
-        precondition();
-        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
-    }
-    return XAMG_OK;
-}
-
-template int pcg<1>(Handle&, const double*, double*, double);
-template int pcg<2>(Handle&, const double*, double*, double);
-template int pcg<4>(Handle&, const double*, double*, double);
-template int pcg<8>(Handle&, const double*, double*, double);
-template int pcg<16>(Handle&, const double*, double*, double);
-template int pcg<32>(Handle&, const double*, double*, double);
-template int vcycle<1>(Handle&, const double*, double*, int, const double*);
-template int vcycle<2>(Handle&, const double*, double*, int, const double*);
-template int vcycle<4>(Handle&, const double*, double*, int, const double*);
-template int vcycle<8>(Handle&, const double*, double*, int, const double*);
-template int vcycle<16>(Handle&, const double*, double*, int, const double*);
-template int vcycle<32>(Handle&, const double*, double*, int, const double*);
-
-template <int M>
-void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
-{
-    constexpr int CPT = cpt_for<double, M>();
-    OpAx<M, CPT, double, double, Idx32, 0> op{d.rp, static_cast<const double*>(d.v),
-                                              Idx32{d.ci}, X, Y, nullptr};
-    launch_mat<M, CPT>(h, op, d.split, d.nr, h.nb_cap);
-}
-
 template <class F>
 static int dispatch_m(int mp, F&& f)
 {
@@ -664,6 +263,11 @@ int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_st
     const int mp = padded_m(m);
     const int n = h.lev[0].n;
     ensure_work(h, mp, h.opt.method == XAMG_BICGSTAB);
+    if (h.autotune)
+        dispatch_m(mp, [&](auto mc) {
+            autotune<decltype(mc)::value>(h);
+            return 0;
+        });
     const double* Bs = B;
     double* Xs = X;
     if (mp != m) {
@@ -687,6 +291,7 @@ int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_st
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
                            h.w.xpad, mp, X, m, n, m);
     h.check(hipStreamSynchronize(h.stream), "solve sync");
+    h.timer_collect();
     if (rc != XAMG_OK) return rc;
     fill_stats(h, m, stats);
     const ColState& s = *h.st_host;
@@ -898,10 +503,12 @@ int xamg_vcycle(xamg_handle_t* hh, const double* B, double* X, int32_t m)
                                 hipMemcpyHostToDevice, h->stream), "state");
         xamg::dispatch_m(m, [&](auto mc) {
             constexpr int M = decltype(mc)::value;
+            if (h->autotune) xamg::autotune<M>(*h);
             xamg::vcycle<M>(*h, B, X, 0, nullptr);
             return 0;
         });
         h->check(hipStreamSynchronize(h->stream), "vcycle sync");
+        h->timer_collect();
     } catch (const xamg::DevFail& f) {
         return f.code;
     }
@@ -952,6 +559,72 @@ int xamg_index16_fraction(const xamg_handle_t* hh, int32_t level, double* out)
     if (!h || !out) return xamg::fail(XAMG_EINVAL, "null argument");
     if (level < 0 || level >= h->nlev - 1) return xamg::fail(XAMG_EINVAL, "level");
     for (int k = 0; k < 3; ++k) out[k] = h->lev[level].frac16[k];
+    return XAMG_OK;
+}
+
+int xamg_timer_enable(xamg_handle_t* hh, int32_t kind)
+{
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (kind < XAMG_TIMER_OFF || kind > XAMG_TIMER_PRESMOOTH) return xamg::fail(XAMG_EINVAL, "timer kind");
+    h->timer_kind = kind;
+    h->timer_ms = 0.0;
+    h->timer_count = 0;
+    h->ev_used = 0;
+    return XAMG_OK;
+}
+
+int xamg_timer_read(xamg_handle_t* hh, double* ms, int64_t* count)
+{
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h || !ms || !count) return xamg::fail(XAMG_EINVAL, "null argument");
+    *ms = h->timer_ms;
+    *count = h->timer_count;
+    return XAMG_OK;
+}
+
+int xamg_autotune(xamg_handle_t* hh, int32_t m, int32_t enable)
+{
+    xamg::clear_error();
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
+        return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
+    h->autotune = enable ? 1 : 0;
+    if (!enable) return XAMG_OK;
+    try {
+        xamg::ensure_work(*h, m, h->opt.method == XAMG_BICGSTAB);
+        int k = 0;
+        while ((1 << k) < m) ++k;
+        h->tuned_mask &= ~(1u << k);
+        xamg::dispatch_m(m, [&](auto mc) {
+            xamg::autotune<decltype(mc)::value>(*h);
+            return 0;
+        });
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+int xamg_tuning(const xamg_handle_t* hh, int32_t m, int32_t* out, int32_t cap)
+{
+    const Handle* h = static_cast<const Handle*>(hh);
+    if (!h || !out) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
+        return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
+    if (cap < 3 * h->nlev) return xamg::fail(XAMG_EINVAL, "output too short");
+    int k = 0;
+    while ((1 << k) < m) ++k;
+    const bool mixed = h->opt.precision == XAMG_MIXED;
+    for (int l = 0; l < h->nlev; ++l) {
+        const auto& L = h->lev[l];
+        const bool last = l + 1 == h->nlev;
+        const xamg::DCsr& A = (mixed && !last) ? L.A32 : L.A64;
+        out[3 * l] = A.split[k];
+        out[3 * l + 1] = last ? 0 : (mixed ? L.P32 : L.P64).split[k];
+        out[3 * l + 2] = last ? 0 : (mixed ? L.R32 : L.R64).split[k];
+    }
     return XAMG_OK;
 }
 

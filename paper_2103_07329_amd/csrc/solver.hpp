@@ -30,7 +30,15 @@ struct DCsr {
     bool fp32 = false;
     uint16_t* off = nullptr;
     int4* base = nullptr;
-    int split = 1;   // lane groups per row (1, 2 or 8), from the mean row length
+    // lane groups per row (1, 2, 4 or 8) for each column count M = 2^k,
+    // k = 0..5: a mean-row-length guess at upload, replaced by the
+    // autotuner's measured choice
+    int split[6] = {1, 1, 1, 1, 1, 1};
+    template <int M>
+    int split_of() const
+    {
+        return split[M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5];
+    }
 };
 
 struct LevelDev {
@@ -72,6 +80,17 @@ struct Handle : xamg_handle {
     double* part = nullptr;
     int nb_cap = 1024;
     std::vector<void*> allocs;
+    int autotune = 1;            // tune row splits on the first solve per M
+    unsigned tuned_mask = 0;     // bit k: M = 2^k tuned
+    // kernel timer (measurement only)
+    int timer_kind = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double timer_ms = 0.0;
+    int64_t timer_count = 0;
+    void timer_begin(int kind);
+    void timer_end(int kind);
+    void timer_collect();
 
     ~Handle();
     void check(hipError_t e, const char* what);
@@ -94,7 +113,7 @@ constexpr int cpt_for()
 inline int split_for(int64_t nnz, int nrows)
 {
     const double avg = nrows > 0 ? double(nnz) / nrows : 0.0;
-    return avg > 24.0 ? 8 : (avg > 10.0 ? 2 : 1);
+    return avg > 48.0 ? 8 : (avg > 24.0 ? 4 : 1);
 }
 
 template <int M, int CPT, int S, class Op>
@@ -103,8 +122,10 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap)
     constexpr int G = M / CPT;
     constexpr int RPB = dev::kBlock / (G * S);
     const int ntiles = (nrows + RPB - 1) / RPB;
-    int nb = std::max(1, std::min(ntiles, cap));
-    if (nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
+    // kernels without dot products get one tile per block; kernels with
+    // dots keep at most `cap` blocks so their partial sums stay few
+    int nb = std::max(1, Op::kDots == 0 ? ntiles : std::min(ntiles, cap));
+    if (Op::kDots > 0 && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
                        h.stream, op, nrows, h.part);
     return nb;
@@ -124,6 +145,9 @@ int launch_mat(Handle& h, const Op& op, int split, int nrows, int cap)
     constexpr int G = M / CPT;
     if constexpr (G * 8 <= 64) {
         if (split >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap);
+    }
+    if constexpr (G * 4 <= 64) {
+        if (split >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap);
     }
     if constexpr (G * 2 <= 64) {
         if (split >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap);
@@ -155,6 +179,11 @@ template <int M>
 int pcg(Handle& h, const double* B, double* X, double tol);
 template <int M>
 int bicgstab(Handle& h, const double* B, double* X, double tol);
+template <int M>
+void spmm64(Handle& h, const DCsr& d, const double* X, double* Y);
+// time each operator's SpMM over the row splits and keep the fastest
+template <int M>
+void autotune(Handle& h);
 
 void ensure_work(Handle& h, int mp, bool bicg);
 void sync_state(Handle& h);

@@ -21,6 +21,7 @@ JACOBI, CHEBYSHEV = 0, 1
 FP64, MIXED = 0, 1
 X0_ZERO, X0_GIVEN = 0, 1
 OP_A, OP_P, OP_R = 0, 1, 2
+TIMER_OFF, TIMER_KRYLOV_SPMM, TIMER_PRESMOOTH = 0, 1, 2
 
 
 class XamgError(RuntimeError):
@@ -68,7 +69,7 @@ EXPORTS = [
     "xamg_default_setup_params", "xamg_hierarchy_build", "xamg_hierarchy_view",
     "xamg_hierarchy_cf", "xamg_hierarchy_free", "xamg_default_options", "xamg_setup",
     "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_index16_fraction",
-    "xamg_destroy",
+    "xamg_autotune", "xamg_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
 ]
 
@@ -98,6 +99,10 @@ def lib():
         L.xamg_spmm.argtypes = [vp, i32, i32, i32, vp, vp]
         L.xamg_info.argtypes = [vp, ctypes.POINTER(i64), i32]
         L.xamg_index16_fraction.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+        L.xamg_autotune.argtypes = [vp, i32, i32]
+        L.xamg_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
+        L.xamg_timer_enable.argtypes = [vp, i32]
+        L.xamg_timer_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.xamg_destroy.argtypes = [vp]
         L.xamg_strerror.argtypes = [ctypes.c_int]
         L.xamg_strerror.restype = ctypes.c_char_p
@@ -296,6 +301,23 @@ class Solver:
     def vcycle(self, B, X):
         m = B.shape[1]
         _check(lib().xamg_vcycle(self._h, _ptr(B), _ptr(X), m), "xamg_vcycle")
+
+    def autotune(self, m, enable=True):
+        _check(lib().xamg_autotune(self._h, m, 1 if enable else 0), "xamg_autotune")
+
+    def tuning(self, m):
+        out = (ctypes.c_int32 * (3 * self.nlev))()
+        _check(lib().xamg_tuning(self._h, m, out, len(out)), "xamg_tuning")
+        return [tuple(out[3 * l:3 * l + 3]) for l in range(self.nlev)]
+
+    def timer_enable(self, kind):
+        _check(lib().xamg_timer_enable(self._h, kind), "xamg_timer_enable")
+
+    def timer_read(self):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().xamg_timer_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)), "xamg_timer_read")
+        return ms.value, cnt.value
 
     def index16_fraction(self, level):
         out = (ctypes.c_double * 3)()

@@ -317,6 +317,7 @@ def test_index16_bitwise_equal_index32(orc, torch, xm, smoother):
     outs = []
     for bits in (32, 16):
         S = xm.Solver(Hh, smoother=smoother, precision=xm.MIXED, index_bits=bits)
+        S.autotune(2, enable=False)     # same row splits for both index widths
         if bits == 16:
             fr = [S.index16_fraction(l) for l in range(S.nlev - 1)]
             _say("   16-bit fraction per level (A, P, R):", [tuple(round(x, 3) for x in f) for f in fr])
@@ -358,20 +359,19 @@ def test_mixed_solve_accuracy(orc, torch, xm, jump24, method):
     S.close()
 
 
-def _poisson_with_far_couplings(N, seed, frac=0.05, w=0.01):
-    """7-point Poisson plus symmetric weak couplings between random distant
-    rows (M-matrix kept: each added -w is matched by +w on both diagonals).
-    Row blocks then touch more than four 2^14-wide column windows, which
-    forces the 32-bit fallback of the 16-bit index encoding."""
+def _poisson_with_far_couplings(N, seed, w=0.01):
+    """7-point Poisson plus symmetric weak couplings from every row of the
+    first quarter to a random column in the second half (M-matrix kept: each
+    added -w is matched by +w on both diagonals).  Row blocks of the first
+    quarter then touch at least five 2^14-wide column windows, which forces
+    the 32-bit fallback of the 16-bit index encoding there; the other blocks
+    stay compressed."""
     import scipy.sparse as sp
     p = inputs.poisson7(N)
     n = p.n
     rng = np.random.default_rng(seed)
-    k = int(frac * n)
-    i = rng.integers(0, n, k)
-    j = rng.integers(0, n, k)
-    keep = np.abs(i - j) > 4 * (1 << 14)
-    i, j = i[keep], j[keep]
+    i = np.arange(n // 4)
+    j = rng.integers(n // 2, n, i.size)
     E = sp.coo_matrix((np.full(i.size, -w), (i, j)), shape=(n, n)).tocsr()
     E = E + E.T
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(n, n)) + E
@@ -391,6 +391,7 @@ def test_index16_wide_fallback_bitwise(orc, torch, xm):
     outs = []
     for bits in (32, 16):
         S = xm.Solver(Hh, precision=xm.MIXED, index_bits=bits)
+        S.autotune(4, enable=False)     # same row splits for both index widths
         if bits == 16:
             fr = S.index16_fraction(0)
             _say("   level-0 16-bit fraction (A, P, R):", fr)
@@ -402,3 +403,30 @@ def test_index16_wide_fallback_bitwise(orc, torch, xm):
         S.close()
     assert np.isfinite(outs[0]).all()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_autotune_choices_and_invariance(orc, torch, xm, jump24):
+    """The autotuner only changes how a row's nonzeros are split over lanes
+    (the order of additions inside a row), so solves with and without it
+    agree to rounding and take the same iterations."""
+    p, H = jump24
+    _say("[autotune] jump24 m=16")
+    B = inputs.uniform_rhs(p.n, 16, 71)
+    Bd = _dev(torch, B)
+    S = xm.Solver(H.export(), smoother=xm.CHEBYSHEV)
+    S.autotune(16, enable=False)
+    X0 = torch.zeros_like(Bd)
+    rc0, st0 = S.solve(Bd, X0)
+    S.autotune(16, enable=True)
+    tun = S.tuning(16)
+    _say("   splits (A, P, R) per level:", tun)
+    for l, t in enumerate(tun):
+        assert t[0] in (1, 2, 4, 8)
+        if l + 1 < S.nlev:
+            assert t[1] in (1, 2, 4, 8) and t[2] in (1, 2, 4, 8)
+    X1 = torch.zeros_like(Bd)
+    rc1, st1 = S.solve(Bd, X1)
+    assert rc0 == rc1 == xm.OK
+    assert np.array_equal(st0["iters"], st1["iters"])
+    assert _relmax(X1.cpu().numpy(), X0.cpu().numpy()) <= 1e-11
+    S.close()
