@@ -186,6 +186,29 @@ int xamg_info(const xamg_handle_t *h, int64_t *out, int32_t cap);
  * 0 when the handle keeps 32-bit indices.  EINVAL for the coarsest level. */
 int xamg_index16_fraction(const xamg_handle_t *h, int32_t level, double *out);
 
+/* ---- batched uneven systems -------------------------------------------- */
+typedef struct xamg_batch xamg_batch_t;
+
+/* Group nsys CG handles (each with its own hierarchy, size and options)
+ * for batched solves.  The handles stay owned by the caller and must
+ * outlive the batch; a handle may appear once.  iters_per_launch (0 = 4) is
+ * the number of CG iterations of every system captured into the batch's
+ * HIP graph.  EINVAL for BiCGStab handles or repeated handles. */
+int xamg_batch_create(xamg_handle_t *const *handles, int32_t nsys, int32_t iters_per_launch,
+                      xamg_batch_t **out);
+
+/* Solve all systems of the batch: B[s], X[s] (device, n_s x m[s], as in
+ * xamg_solve), stats[s] (host, m[s] entries, or NULL / stats NULL).  The
+ * iterations of every system run from one captured HIP graph, launched
+ * repeatedly until each system has converged or reached its max_iters;
+ * converged systems' kernels exit immediately.  Per-system results equal
+ * those of xamg_solve on the same handle.  Return: the worst of the
+ * systems' codes (EBREAKDOWN, NOT_CONVERGED, OK); EINVAL as xamg_solve. */
+int xamg_solve_batched(xamg_batch_t *b, const double *const *B, double *const *X,
+                       const int32_t *m, double tol, xamg_stats_t *const *stats);
+
+int xamg_batch_destroy(xamg_batch_t *b);
+
 /* Autotuner (Section 2.2's kernels, tuned for this device): for each
  * operator A_l, P_l, R_l of the copy the V-cycle uses, time the SpMM for
  * m columns with 1, 2, 4 and 8 lane groups splitting a row's nonzeros, with

@@ -240,6 +240,7 @@ struct FinInitB {   // tot: (b,b)[M], (r,r)[M]
         }
         if (j == 0) {
             st->tol = tol;
+            st->max_iters = 1 << 30;   // the host loop enforces the cap
             int bad = 0;
             for (int q = 0; q < M; ++q) bad |= !isfinite(tot[q]);
             st->nrestart = bad ? -1 : 0;

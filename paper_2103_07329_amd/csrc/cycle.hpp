@@ -20,6 +20,7 @@ struct FinInit {   // tot: (b,b)[M], (r,r)[M]
     ColState* st;
     double tol;
     int M;
+    int max_iters;
     __device__ void operator()(const double* tot) const
     {
         const int j = threadIdx.x;
@@ -47,6 +48,7 @@ struct FinInit {   // tot: (b,b)[M], (r,r)[M]
         }
         if (j == 0) {
             st->tol = tol;
+            st->max_iters = max_iters;
             int bad = 0;
             for (int q = 0; q < M; ++q) bad |= !isfinite(tot[q]);
             st->nrestart = bad ? -1 : 0;
@@ -93,6 +95,8 @@ struct FinRR {   // tot: (r, r)[M]
             if (rel <= st->tol) {
                 st->active[j] = 0;
                 st->conv[j] = 1;
+            } else if (st->iters[j] >= st->max_iters) {
+                st->active[j] = 0;   // iteration cap: not converged
             }
         }
         recount_active(st, M);
@@ -138,7 +142,8 @@ struct FinTrue {   // tot: (b, b)[M], (t, t)[M];  t = b - A x
             const double tr = bb > 0.0 ? sqrt(tt) / sqrt(bb) : 0.0;
             st->true_relres[j] = tr;
             st->cp[j] = 0;
-            if (allow_restart && st->conv[j] && bb > 0.0 && !(tr <= st->tol) && !st->failed[j]) {
+            if (allow_restart && st->conv[j] && bb > 0.0 && !(tr <= st->tol) && !st->failed[j] &&
+                st->iters[j] < st->max_iters) {
                 st->conv[j] = 0;
                 st->active[j] = 1;
                 st->rst[j] = 1;
@@ -356,82 +361,125 @@ int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q)
 // ---------------------------------------------------------------------------
 // preconditioned CG, all m columns at once
 // ---------------------------------------------------------------------------
+// The CG driver in enqueue-only pieces (no host synchronisation inside),
+// so the batched solver can capture iterations into a graph.
 template <int M>
-int pcg(Handle& h, const double* B, double* X, double tol)
+int pcg_flex(const Handle& h)
+{
+    return h.opt.precision == XAMG_MIXED ? 1 : h.opt.flexible;
+}
+
+// z = M^-1 r (dots (r, z) [, (z, q)]), beta, p = z + beta p
+template <int M>
+void pcg_precondition(Handle& h)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    const int flex = pcg_flex<M>(h);
+    const int nd = flex ? 2 : 1;
+    const int nb = vcycle<M>(h, h.w.r, h.w.z, nd, h.w.q);
+    launch_fin(h, nb, nd * M, FinBeta{h.st, M, flex});
+    OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.p, h.w.z};
+    launch_rows<M, CPT>(h, up, h.lev[0].n, h.nb_cap);
+}
+
+// r = b - A x, column state, z = M^-1 r, p = z
+template <int M>
+void pcg_start(Handle& h, const double* B, double* X, double tol)
 {
     constexpr int CPT = cpt_for<double, M>();
     const int n = h.lev[0].n;
     const DCsr& A = h.lev[0].A64;
     const double* av = static_cast<const double*>(A.v);
-    auto& w = h.w;
-    ColState* st = h.st;
-    const int cap = h.nb_cap;
-    const int flex = h.opt.precision == XAMG_MIXED ? 1 : h.opt.flexible;
-    const int nd = flex ? 2 : 1;
-
     if (h.opt.x0_mode == XAMG_X0_ZERO)
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                            nullptr, M, X, M, n, 0);
     {
-        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, w.r,
+        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, h.w.r,
                                                               nullptr};
-        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
-        launch_fin(h, nb, 2 * M, FinInit{st, tol, M});
+        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+        launch_fin(h, nb, 2 * M, FinInit{h.st, tol, M, h.opt.max_iters});
     }
     if (h.opt.x0_mode == XAMG_X0_GIVEN) {
-        OpFixCols<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, nullptr, nullptr, X};
-        launch_rows<M, CPT>(h, op, n, cap);
+        OpFixCols<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, h.st, nullptr, nullptr, X};
+        launch_rows<M, CPT>(h, op, n, h.nb_cap);
     }
-    auto precondition = [&]() {
-        const int nb = vcycle<M>(h, w.r, w.z, nd, w.q);
-        launch_fin(h, nb, nd * M, FinBeta{st, M, flex});
-        OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, st, w.p, w.z};
-        launch_rows<M, CPT>(h, up, n, cap);
-    };
     // q must be finite for the flexible dot of the first cycle
-    if (flex)
+    if (pcg_flex<M>(h))
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
-                           nullptr, M, w.q, M, n, 0);
-    precondition();
+                           nullptr, M, h.w.q, M, n, 0);
+    pcg_precondition<M>(h);
+}
+
+// one iteration: q = A p, alpha, x += alpha p, r -= alpha q, test, z, beta, p
+template <int M>
+void pcg_iteration(Handle& h, double* X)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    const int n = h.lev[0].n;
+    const DCsr& A = h.lev[0].A64;
+    const double* av = static_cast<const double*>(A.v);
+    ColState* st = h.st;
+    {
+        OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, h.w.p, h.w.q,
+                                                   &st->nactive};
+        h.timer_begin(XAMG_TIMER_KRYLOV_SPMM);
+        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+        h.timer_end(XAMG_TIMER_KRYLOV_SPMM);
+        launch_fin(h, nb, M, FinAlpha{st, M});
+    }
+    {
+        OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, h.w.r, h.w.p, h.w.q};
+        const int nb = launch_rows<M, CPT>(h, op, n, h.nb_cap);
+        launch_fin(h, nb, M, FinRR{st, M});
+    }
+    pcg_precondition<M>(h);
+}
+
+// true residual of the columns the recurrence froze; columns that fail it
+// restart (r = b - A x, z = M^-1 r, p = z).  Synchronises; returns the
+// number of restarted columns.
+template <int M>
+int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    const int n = h.lev[0].n;
+    const DCsr& A = h.lev[0].A64;
+    const double* av = static_cast<const double*>(A.v);
+    OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, h.w.t,
+                                                          nullptr};
+    const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+    launch_fin(h, nb, 2 * M, FinTrue{h.st, M, allow_restart});
+    sync_state(h);
+    const int nr = h.st_host->nrestart;
+    if (nr > 0) {
+        OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.r, h.w.t, nullptr};
+        launch_rows<M, CPT>(h, cp, n, h.nb_cap);
+        pcg_precondition<M>(h);
+    }
+    return nr;
+}
+
+template <int M>
+int pcg(Handle& h, const double* B, double* X, double tol)
+{
+    pcg_start<M>(h, B, X, tol);
     sync_state(h);
     if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
-
     int it = 0;
     const int every = std::max(1, h.opt.check_every);
     for (;;) {
         if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
-            OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B,
-                                                                  w.t, nullptr};
-            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
-            launch_fin(h, nb, 2 * M, FinTrue{st, M, it < h.opt.max_iters ? 1 : 0});
-            sync_state(h);
-            if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
-            OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, st, w.r, w.t, nullptr};
-            launch_rows<M, CPT>(h, cp, n, cap);
-            precondition();
+            const int nr = pcg_true_check<M>(h, B, X, it < h.opt.max_iters ? 1 : 0);
+            if (nr == 0 || it >= h.opt.max_iters) break;
             sync_state(h);
             continue;
         }
         ++it;
-        {
-            OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, w.p, w.q,
-                                                       &st->nactive};
-            h.timer_begin(XAMG_TIMER_KRYLOV_SPMM);
-            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
-            h.timer_end(XAMG_TIMER_KRYLOV_SPMM);
-            launch_fin(h, nb, M, FinAlpha{st, M});
-        }
-        {
-            OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, w.r, w.p, w.q};
-            const int nb = launch_rows<M, CPT>(h, op, n, cap);
-            launch_fin(h, nb, M, FinRR{st, M});
-        }
-        precondition();
+        pcg_iteration<M>(h, X);
         if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
     }
     return XAMG_OK;
 }
-
 
 template <int M>
 void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
@@ -450,25 +498,43 @@ void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
 // the first solve (or on request); setup cost, not solve cost.
 // ---------------------------------------------------------------------------
 template <int M, typename T>
-float time_spmm(Handle& h, const DCsr& d, int S, const T* x, T* y, hipEvent_t e0, hipEvent_t e1)
+float time_op(Handle& h, const DCsr& d, bool smoothing, int S, const T* x, T* y, T* z,
+              hipEvent_t e0, hipEvent_t e1)
 {
     constexpr int CPT = cpt_for<T, M>();
-    float ms = 0.0f;
+    float best = 0.0f;
     with_idx(d, [&](auto ix) {
         using IX = decltype(ix);
-        OpAx<M, CPT, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, y, nullptr};
-        launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
-        h.check(hipEventRecord(e0, h.stream), "tune event");
-        for (int r = 0; r < 3; ++r) launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
-        h.check(hipEventRecord(e1, h.stream), "tune event");
-        h.check(hipEventSynchronize(e1), "tune sync");
-        h.check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
+        // the square operators are timed on the residual pass r = b - A x
+        // (gathers x, reads b, writes r: the access pattern of the smoothing
+        // passes); transfer operators on the plain product y = Op x
+        auto run = [&]() {
+            if (smoothing) {
+                OpResid<M, CPT, T, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, z, y,
+                                                   nullptr};
+                launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
+            } else {
+                OpAx<M, CPT, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, y, nullptr};
+                launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
+            }
+        };
+        run();
+        for (int r = 0; r < 5; ++r) {
+            float ms = 0.0f;
+            h.check(hipEventRecord(e0, h.stream), "tune event");
+            run();
+            h.check(hipEventRecord(e1, h.stream), "tune event");
+            h.check(hipEventSynchronize(e1), "tune sync");
+            h.check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
+            if (r == 0 || ms < best) best = ms;
+        }
     });
-    return ms;
+    return best;
 }
 
 template <int M, typename T>
-void tune_matrix(Handle& h, DCsr& d, const T* x, T* y, hipEvent_t e0, hipEvent_t e1)
+void tune_matrix(Handle& h, DCsr& d, bool smoothing, const T* x, T* y, T* z, hipEvent_t e0,
+                 hipEvent_t e1)
 {
     constexpr int G = M / cpt_for<T, M>();
     constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
@@ -477,7 +543,7 @@ void tune_matrix(Handle& h, DCsr& d, const T* x, T* y, hipEvent_t e0, hipEvent_t
     int bestS = 1;
     for (int S : {1, 2, 4, 8}) {
         if (G * S > 64) break;
-        const float t = time_spmm<M, T>(h, d, S, x, y, e0, e1);
+        const float t = time_op<M, T>(h, d, smoothing, S, x, y, z, e0, e1);
         if (S == 1 || t < best) {
             best = t;
             bestS = S;
@@ -499,25 +565,32 @@ void autotune(Handle& h)
     h.check(hipEventCreate(&e0), "hipEventCreate");
     h.check(hipEventCreate(&e1), "hipEventCreate");
     const bool mixed = h.opt.precision == XAMG_MIXED;
+    double* x = h.w.r;
+    double* y = h.w.z;
+    double* z = h.w.p;   // right-hand side of the residual pass (finite: zeroed)
+    hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
+                       nullptr, M, z, M, n0, 0);
+    const float* xf = reinterpret_cast<const float*>(x);
+    float* yf = reinterpret_cast<float*>(y);
+    float* zf = reinterpret_cast<float*>(z);
     for (int l = 0; l < h.nlev; ++l) {
         auto& L = h.lev[l];
-        if (l == 0 || !mixed) tune_matrix<M, double>(h, L.A64, h.w.r, h.w.z, e0, e1);
+        if (l == 0 || !mixed) tune_matrix<M, double>(h, L.A64, true, x, y, z, e0, e1);
         if (l + 1 < h.nlev) {
             if (!mixed) {
-                tune_matrix<M, double>(h, L.P64, h.w.r, h.w.z, e0, e1);
-                tune_matrix<M, double>(h, L.R64, h.w.r, h.w.z, e0, e1);
+                tune_matrix<M, double>(h, L.P64, false, x, y, z, e0, e1);
+                tune_matrix<M, double>(h, L.R64, false, x, y, z, e0, e1);
             } else {
-                const float* xf = reinterpret_cast<const float*>(h.w.r);
-                float* yf = reinterpret_cast<float*>(h.w.z);
-                tune_matrix<M, float>(h, L.A32, xf, yf, e0, e1);
-                tune_matrix<M, float>(h, L.P32, xf, yf, e0, e1);
-                tune_matrix<M, float>(h, L.R32, xf, yf, e0, e1);
+                tune_matrix<M, float>(h, L.A32, true, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.P32, false, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.R32, false, xf, yf, zf, e0, e1);
             }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     h.tuned_mask |= 1u << k;
+    h.tune_epoch += 1;
 }
 
 }  // namespace xamg

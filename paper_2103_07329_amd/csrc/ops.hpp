@@ -46,6 +46,7 @@ struct ColState {
     int skip[32];         // rest of this iteration skipped (BiCGStab)
     int half[32];         // converged at the half step (BiCGStab)
     int failed[32];       // stopped by a persistent breakdown
+    int max_iters;        // per-column iteration cap
     int nactive;
     int nrestart;
 };

@@ -82,6 +82,7 @@ struct Handle : xamg_handle {
     std::vector<void*> allocs;
     int autotune = 1;            // tune row splits on the first solve per M
     unsigned tuned_mask = 0;     // bit k: M = 2^k tuned
+    int tune_epoch = 0;          // bumped whenever launch shapes may change
     // kernel timer (measurement only)
     int timer_kind = 0;
     std::vector<hipEvent_t> ev_pool;

@@ -69,6 +69,7 @@ EXPORTS = [
     "xamg_default_setup_params", "xamg_hierarchy_build", "xamg_hierarchy_view",
     "xamg_hierarchy_cf", "xamg_hierarchy_free", "xamg_default_options", "xamg_setup",
     "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_index16_fraction",
+    "xamg_batch_create", "xamg_solve_batched", "xamg_batch_destroy",
     "xamg_autotune", "xamg_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
 ]
@@ -99,6 +100,10 @@ def lib():
         L.xamg_spmm.argtypes = [vp, i32, i32, i32, vp, vp]
         L.xamg_info.argtypes = [vp, ctypes.POINTER(i64), i32]
         L.xamg_index16_fraction.argtypes = [vp, i32, ctypes.POINTER(dbl)]
+        L.xamg_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(vp)]
+        L.xamg_solve_batched.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(i32), dbl, ctypes.POINTER(vp)]
+        L.xamg_batch_destroy.argtypes = [vp]
         L.xamg_autotune.argtypes = [vp, i32, i32]
         L.xamg_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
         L.xamg_timer_enable.argtypes = [vp, i32]
@@ -327,3 +332,47 @@ class Solver:
     def spmm(self, op, level, X, Y):
         m = X.shape[1]
         _check(lib().xamg_spmm(self._h, op, level, m, _ptr(X), _ptr(Y)), "xamg_spmm")
+
+
+class Batch:
+    """Batched solves over several CG Solvers (one captured graph)."""
+
+    def __init__(self, solvers, iters_per_launch=0):
+        self.solvers = list(solvers)
+        hs = (ctypes.c_void_p * len(self.solvers))(*[s._h.value for s in self.solvers])
+        b = ctypes.c_void_p()
+        _check(lib().xamg_batch_create(hs, len(self.solvers), iters_per_launch, ctypes.byref(b)),
+               "xamg_batch_create")
+        self._b = b
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().xamg_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, Bs, Xs, tol=1e-8, check=True):
+        ns = len(self.solvers)
+        Bp = (ctypes.c_void_p * ns)(*[_ptr(b).value for b in Bs])
+        Xp = (ctypes.c_void_p * ns)(*[_ptr(x).value for x in Xs])
+        ms = [b.shape[1] for b in Bs]
+        mm = (ctypes.c_int32 * ns)(*ms)
+        sts = [(StatsT * m)() for m in ms]
+        sp = (ctypes.c_void_p * ns)(*[ctypes.addressof(s) for s in sts])
+        rc = lib().xamg_solve_batched(self._b, Bp, Xp, mm, tol, sp)
+        if check:
+            _check(rc, "xamg_solve_batched", allow=(OK, NOT_CONVERGED))
+        out = []
+        for st in sts:
+            out.append({
+                "iters": np.array([s.iters for s in st], np.int32),
+                "converged": np.array([bool(s.converged) for s in st]),
+                "relres": np.array([s.relres for s in st]),
+                "true_relres": np.array([s.true_relres for s in st]),
+            })
+        return rc, out

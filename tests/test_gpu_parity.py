@@ -430,3 +430,68 @@ def test_autotune_choices_and_invariance(orc, torch, xm, jump24):
     assert np.array_equal(st0["iters"], st1["iters"])
     assert _relmax(X1.cpu().numpy(), X0.cpu().numpy()) <= 1e-11
     S.close()
+
+
+# --------------------------------------------------------------------------
+# batched uneven systems (one captured graph)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_equals_individual(orc, torch, xm, precision):
+    """Every replay of the captured graph (with eager checks between
+    replays) must give exactly the eager per-system result."""
+    _say(f"[batched] 5 jump systems, precision={precision}")
+    systems = inputs.batched_systems(seed=1004, count=5, max_side=24)
+    solvers, Bs = [], []
+    for prob, B in systems:
+        Hh = xm.HostHierarchy(*prob.csr())
+        solvers.append(xm.Solver(Hh, precision=precision))
+        Bs.append(_dev(torch, B))
+    ref = []
+    for S, Bd in zip(solvers, Bs):
+        X = torch.zeros_like(Bd)
+        rc, st = S.solve(Bd, X)
+        assert rc == xm.OK
+        ref.append((X.cpu().numpy(), st["iters"]))
+    batch = xm.Batch(solvers, iters_per_launch=3)
+    for rep in range(2):
+        Xs = [torch.full_like(Bd, 7.0) for Bd in Bs]
+        rc, sts = batch.solve(Bs, Xs)
+        assert rc == xm.OK
+        for (Xr, itr), X, st in zip(ref, Xs, sts):
+            assert np.array_equal(st["iters"], itr)
+            assert np.array_equal(X.cpu().numpy(), Xr)
+            assert st["converged"].all()
+    batch.close()
+    for S in solvers:
+        S.close()
+
+
+def test_batched_vs_oracle_and_cap(orc, torch, xm):
+    _say("[batched] 3 systems vs oracle, iteration cap")
+    systems = inputs.batched_systems(seed=7, count=3, max_side=16)
+    solvers, Bs, orcs = [], [], []
+    for prob, B in systems:
+        Ho = orc.Hierarchy(*prob.csr())
+        solvers.append(xm.Solver(Ho.export()))
+        orcs.append((Ho, B))
+        Bs.append(_dev(torch, B))
+    batch = xm.Batch(solvers)
+    Xs = [torch.zeros_like(b) for b in Bs]
+    rc, sts = batch.solve(Bs, Xs)
+    assert rc == xm.OK
+    for (Ho, B), X, st in zip(orcs, Xs, sts):
+        Xo, so, _ = Ho.solve(B)
+        assert np.array_equal(st["iters"], so["iters"])
+        e = np.linalg.norm(X.cpu().numpy() - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+        assert e.max() <= 1e-7
+    batch.close()
+    capped = [xm.Solver(Ho.export(), max_iters=2) for Ho, _ in orcs]
+    b2 = xm.Batch(capped, iters_per_launch=4)
+    Xs = [torch.zeros_like(b) for b in Bs]
+    rc, sts = b2.solve(Bs, Xs)
+    assert rc == xm.NOT_CONVERGED
+    for st in sts:
+        assert st["iters"].max() <= 2
+    b2.close()
+    for S in solvers + capped:
+        S.close()
