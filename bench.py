@@ -34,7 +34,7 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_2103_07329_amd/csrc/kernels.hpp", "paper_2103_07329_amd/csrc/ops.hpp",
-                  "paper_2103_07329_amd/csrc/solver.hpp"]
+                  "paper_2103_07329_amd/csrc/solver.hpp", "paper_2103_07329_amd/csrc/cycle.hpp"]
 
 
 def log(*a):
@@ -55,10 +55,12 @@ def spmm_bytes(n, nnz, m, vb=8, ib=4, xb=8):
     return nnz * (vb + ib) + 4 * (n + 1) + 2 * n * m * xb
 
 
-def presmooth_bytes(n, nnz, m, vb=8, ib=4, bb=8, xb=8):
-    """Chebyshev pre-smoothing from zero, x = p(D^-1 A) D^-1 b in one pass:
-    matrix and row pointers once, b read once, D^-1 read once, x written."""
-    return nnz * (vb + ib) + 4 * (n + 1) + n * m * bb + n * vb + n * m * xb
+def presmooth_bytes(n, nnz, m, vb=8, ib=4, bb=8, xb=8, jacobi=False):
+    """Pre-smoothing from zero in one pass (Chebyshev: x = p(D^-1 A) D^-1 b;
+    Jacobi: x = w D^-1 b fused with r = b - A x): matrix and row pointers
+    once, b read once, D^-1 read once, x written (Jacobi: r written too)."""
+    return (nnz * (vb + ib) + 4 * (n + 1) + n * m * bb + n * vb + n * m * xb
+            + (n * m * xb if jacobi else 0))
 
 
 def stored_traffic(workload, kernel):
@@ -100,15 +102,23 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="poisson128",
-                    choices=["poisson128", "poisson32", "aniso256"])
+                    choices=["poisson128", "poisson32", "aniso256", "batched"])
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64-vs-mixed and multi-RHS-gain extras")
     ap.add_argument("--cpu-iters", type=int, default=0,
                     help="oracle sample: this many iterations, scaled to the solve")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 512 MiB device copy (PMC byte-counter calibration)")
+    ap.add_argument("--print-source-hash", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="full oracle solve; per-column error of the GPU result against it")
     args = ap.parse_args()
 
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; run with --gpus 1 "
                                    "(sharding across GPUs is a design note only)"}))
@@ -122,6 +132,15 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     wl = args.workload
+    if wl == "batched":
+        return bench_batched(args, torch, inputs, xamg)
+    if args.calibrate_copy:
+        # a plain copy of known size: 512 MiB read + 512 MiB written
+        xc = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        yc = torch.empty_like(xc)
+        yc.copy_(xc)
+        torch.cuda.synchronize()
+        del xc, yc
     if wl == "poisson128":
         N, m = 128, args.m or 16
         prob = inputs.poisson7(N)
@@ -181,7 +200,7 @@ def main():
         avg_ms = tms / cnt
         if kind == xamg.TIMER_PRESMOOTH:
             nbytes = presmooth_bytes(prob.n, prob.nnz, m, vb=vb32, ib=ib32 if mixed else 4,
-                                     bb=8, xb=vb32)
+                                     bb=8, xb=vb32, jacobi=opts["smoother"] == xamg.JACOBI)
             what = "Chebyshev" if opts["smoother"] == xamg.CHEBYSHEV else "Jacobi"
             kdesc = (f"rows_kernel<{m}> {what} pre-smoothing pass from zero, finest level "
                      f"({'FP32 values' if mixed else 'FP64'})")
@@ -206,18 +225,23 @@ def main():
                 "avg_us": K["avg_us"], "launches_timed": K["launches"]}
 
     extras = {}
-    if not args.no_extras and wl != "aniso256":
+    if not args.no_extras:
         # FP64 vs mixed precision (FP32 V-cycle, 16-bit offsets) on the same workload
-        Sm = xamg.Solver(Hh, stream=stream.cuda_stream, precision=xamg.MIXED, index_bits=16,
-                         **opts)
+        oo = dict(opts)
+        if mixed:
+            oo.update(precision=xamg.FP64, index_bits=32)
+        else:
+            oo.update(precision=xamg.MIXED, index_bits=16)
+        Sm = xamg.Solver(Hh, stream=stream.cuda_stream, **oo)
         Xm = torch.zeros_like(Bd)
         Sm.solve(Bd, Xm, tol=1e-8)
         msm, itm, trm, rcm = timed_solves(Sm, Bd, Xm, args.steps, 1e-8, stream, torch)
         dx = (torch.linalg.norm(Xm - Xd, dim=0) / torch.linalg.norm(Xd, dim=0)).max().item()
-        extras["mixed_precision"] = {"ms_per_rhs": msm / m, "iters": int(itm.max()),
-                                     "max_true_relres": trm, "max_rel_diff_vs_fp64": dx}
-        log(f"[bench] mixed: {msm / m:.3f} ms/RHS, iters {int(itm.max())}, "
-            f"rel diff vs fp64 {dx:.2e}")
+        other = "fp64" if mixed else "mixed_precision"
+        extras[other] = {"ms_per_rhs": msm / m, "iters": int(itm.max()),
+                         "max_true_relres": trm, "max_rel_diff": dx}
+        log(f"[bench] {other}: {msm / m:.3f} ms/RHS, iters {int(itm.max())}, "
+            f"rel diff {dx:.2e}")
         Sm.close()
         # multi-RHS gain P_m = m T_1 / T_m
         if wl == "poisson128":
@@ -243,7 +267,9 @@ def main():
         log(f"[bench] oracle setup {time.time() - t0:.1f}s (not timed)")
         kw = dict(smoother=oracle.CHEBYSHEV if opts["smoother"] == xamg.CHEBYSHEV else oracle.JACOBI,
                   method=oracle.BICGSTAB if opts["method"] == xamg.BICGSTAB else oracle.CG)
-        sample_iters = args.cpu_iters if args.cpu_iters > 0 else (2 if wl == "aniso256" else 0)
+        sample_iters = args.cpu_iters if args.cpu_iters > 0 else (
+            2 if wl == "aniso256" and not args.cpu_full else 0)
+        oracle.set_verbose(True)
         t0 = time.perf_counter()
         if sample_iters:
             Xo, so, rco = Ho.solve(B, max_iters=sample_iters, tol=1e-8, **kw)
@@ -260,6 +286,8 @@ def main():
                       f"iterations, setup excluded)")
             err = np.linalg.norm(Xd.cpu().numpy() - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
             log(f"[bench] GPU vs oracle max rel err {err.max():.2e}")
+            extras["per_column_rel_err_vs_oracle"] = [float(e) for e in err]
+            extras["oracle_iters"] = [int(i) for i in so["iters"]]
         cpu = {"value": tcpu * 1e3 / m, "unit": "ms/RHS", "cores": oracle.num_threads(),
                "kind": "oracle", "sample": sample}
         log(f"[bench] oracle {tcpu:.1f}s -> {cpu['value']:.1f} ms/RHS on {cpu['cores']} threads")
@@ -290,6 +318,97 @@ def main():
     out.update(extras)
     print(json.dumps(out), flush=True)
     S.close()
+
+
+def bench_batched(args, torch, inputs, xamg):
+    """12 jump-coefficient systems of uneven size and column count (seed
+    1004), AMG-PCG with an FP32 preconditioner and 16-bit offsets, all
+    iterations from one captured HIP graph; compared with 12 separate FP64
+    solves and 12 separate mixed solves."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    systems = inputs.batched_systems(seed=1004, count=12)
+    t0 = time.time()
+    hier, Bs = [], []
+    for prob, B in systems:
+        hier.append(xamg.HostHierarchy(*prob.csr()))
+        Bs.append(torch.from_numpy(B).to(dev))
+    t_setup = time.time() - t0
+    sides = [p.N for p, _ in systems]
+    ms = [B.shape[1] for _, B in systems]
+    nrhs = sum(ms)
+    log(f"[bench] batched: sides {sides}, m {ms}, host setup {t_setup:.1f}s")
+    mixed = [xamg.Solver(H, stream=stream.cuda_stream, precision=xamg.MIXED, index_bits=16)
+             for H in hier]
+    batch = xamg.Batch(mixed)
+    Xs = [torch.zeros_like(B) for B in Bs]
+    for _ in range(args.warmup):
+        rc, _ = batch.solve(Bs, Xs)
+        assert rc == xamg.OK, rc
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rc, sts = batch.solve(Bs, Xs)
+        assert rc == xamg.OK, rc
+    torch.cuda.synchronize()
+    ms_batched = (time.perf_counter() - t0) * 1e3 / args.steps
+    iters = [int(st["iters"].max()) for st in sts]
+    tr = max(float(st["true_relres"].max()) for st in sts)
+    log(f"[bench] batched graph: {ms_batched:.2f} ms per batch, {ms_batched / nrhs:.4f} ms/RHS, "
+        f"iters {iters}, max true relres {tr:.2e}")
+
+    def separate(solvers):
+        Xl = [torch.zeros_like(B) for B in Bs]
+        for S, B, X in zip(solvers, Bs, Xl):
+            S.solve(B, X)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for S, B, X in zip(solvers, Bs, Xl):
+                rc, _ = S.solve(B, X)
+                assert rc == xamg.OK, rc
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, Xl
+
+    ms_sep_mixed, _ = separate(mixed)
+    fp64 = [xamg.Solver(H, stream=stream.cuda_stream) for H in hier]
+    ms_sep_fp64, X64 = separate(fp64)
+    err = max(float((torch.linalg.norm(X - Y, dim=0) / torch.linalg.norm(Y, dim=0)).max())
+              for X, Y in zip(Xs, X64))
+    log(f"[bench] separate mixed: {ms_sep_mixed:.2f} ms, separate FP64: {ms_sep_fp64:.2f} ms, "
+        f"batched vs FP64 max rel diff {err:.2e}")
+    big = int(np.argmax([p.n for p, _ in systems]))
+    S = mixed[big]
+    S.timer_enable(xamg.TIMER_PRESMOOTH)
+    Xb = torch.zeros_like(Bs[big])
+    S.solve(Bs[big], Xb)
+    tms, cnt = S.timer_read()
+    S.timer_enable(xamg.TIMER_OFF)
+    pb, mb = systems[big][0], ms[big]
+    nbytes = presmooth_bytes(pb.n, pb.nnz, mb, vb=4, ib=2, bb=8, xb=4, jacobi=True)
+    gbs = nbytes / (tms / cnt * 1e-3) / 1e9
+    out = {
+        "metric": "ms per RHS to rel. residual 1e-8 (AMG-PCG), FP64 vs mixed; SpMM HBM GB/s",
+        "value": ms_batched / nrhs, "unit": "ms/RHS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_batched, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
+        "config": {"workload": "batched12_jump_pcg_fp32precond_idx16_graph", "sides": sides,
+                   "m": ms, "total_rhs": nrhs, "tol": 1e-8, "iters": iters,
+                   "host_setup_s": round(t_setup, 1)},
+        "roofline": {"kernel": f"rows_kernel<{mb}> Jacobi pre-smoothing pass, FP32 values, "
+                               f"16-bit offsets, largest system (n={pb.n})",
+                     "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": nbytes,
+                     "avg_us": tms / cnt * 1e3},
+        "separate_solves": {"mixed_ms": ms_sep_mixed, "fp64_ms": ms_sep_fp64,
+                            "fp64_ms_per_rhs": ms_sep_fp64 / nrhs,
+                            "max_rel_diff_batched_vs_fp64": err},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
+    for S in mixed + fp64:
+        S.close()
 
 
 if __name__ == "__main__":

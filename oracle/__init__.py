@@ -81,6 +81,8 @@ def lib():
         L.orc_rs_split.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _i32p]
         L.orc_strength_count.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl,
                                          _i32p]
+        L.orc_set_verbose.argtypes = [_c_int]
+        L.orc_set_verbose.restype = None
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = _c_int
         _lib = L
@@ -89,6 +91,11 @@ def lib():
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_verbose(on=True):
+    """One progress line per Krylov iteration on stderr."""
+    lib().orc_set_verbose(1 if on else 0)
 
 
 def _csr(rp, ci, v):

@@ -30,8 +30,13 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* progress lines on stderr, one per Krylov iteration (off by default) */
+static int g_verbose = 0;
+void orc_set_verbose(int v) { g_verbose = v; }
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -947,6 +952,7 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
         int any = 0;
         for (j = 0; j < m; j++) any |= act[j];
         if (!any) break;
+        if (g_verbose) { fprintf(stderr, "[oracle] CG iteration %d\n", it); fflush(stderr); }
         /* q = A p, alpha = (r, z) / (p, q) */
         spmm(A, m, p, q);
         dots(n, m, p, q, pq);
@@ -1094,6 +1100,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
         int any = 0;
         for (j = 0; j < m; j++) any |= act[j];
         if (!any) break;
+        if (g_verbose) { fprintf(stderr, "[oracle] BiCGStab iteration %d\n", it); fflush(stderr); }
         /* rho' = (rh, r), beta, p = r + beta (p - omega v) */
         for (j = 0; j < m; j++)
             if (act[j] && rst[j]) {
