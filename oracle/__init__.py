@@ -81,6 +81,14 @@ def lib():
         L.orc_rs_split.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _i32p]
         L.orc_strength_count.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl,
                                          _i32p]
+        L.orc_conv3d_fwd.argtypes = [_c_int, _c_int, _c_int, _f64p, _f64p, _f64p]
+        L.orc_conv3d_fwd.restype = None
+        L.orc_conv3d_dgrad.argtypes = [_c_int, _c_int, _c_int, _f64p, _f64p, _f64p]
+        L.orc_conv3d_dgrad.restype = None
+        L.orc_conv3d_wgrad.argtypes = [_c_int, _c_int, _c_int, _f64p, _f64p, _f64p]
+        L.orc_conv3d_wgrad.restype = None
+        L.orc_bf16_round.argtypes = [_c_dbl]
+        L.orc_bf16_round.restype = _c_dbl
         L.orc_set_verbose.argtypes = [_c_int]
         L.orc_set_verbose.restype = None
         L.orc_num_threads.argtypes = []
@@ -274,3 +282,91 @@ class Hierarchy:
         st = {"iters": it, "relres": rr, "true_relres": tr,
               "converged": cv.astype(bool)}
         return (X[:, 0] if vec else X), st, rc
+
+
+# --------------------------------------------------------------------------
+# bias-free 3D CNN (learned warm start)
+# --------------------------------------------------------------------------
+CNN_LAYERS = ((1, 16), (16, 16), (16, 16), (16, 1))   # (cin, cout); ReLU after 1-3
+
+
+def conv3d_fwd(N, W, x):
+    """x: (n, cin) -> (n, cout); W: (cout, cin, 27)."""
+    W = np.ascontiguousarray(W, np.float64)
+    cout, cin = W.shape[:2]
+    x = np.ascontiguousarray(x, np.float64).reshape(N ** 3, cin)
+    y = np.empty((N ** 3, cout))
+    lib().orc_conv3d_fwd(N, cin, cout, x, W, y)
+    return y
+
+
+def conv3d_dgrad(N, W, g):
+    W = np.ascontiguousarray(W, np.float64)
+    cout, cin = W.shape[:2]
+    g = np.ascontiguousarray(g, np.float64).reshape(N ** 3, cout)
+    d = np.empty((N ** 3, cin))
+    lib().orc_conv3d_dgrad(N, cin, cout, g, W, d)
+    return d
+
+
+def conv3d_wgrad(N, g, x, cin, cout):
+    g = np.ascontiguousarray(g, np.float64).reshape(N ** 3, cout)
+    x = np.ascontiguousarray(x, np.float64).reshape(N ** 3, cin)
+    dW = np.empty((cout, cin, 27))
+    lib().orc_conv3d_wgrad(N, cin, cout, g, x, dW)
+    return dW
+
+
+def bf16(a):
+    """Round-to-nearest-even to bfloat16 (element-wise), as float64."""
+    f = np.asarray(a, np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    finite = (u & 0x7F800000) != 0x7F800000
+    u = np.where(finite, u + 0x7FFF + ((u >> 16) & 1), u) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def cnn_forward(N, Ws, x, quantize=False):
+    """Forward of the 4-layer network on one normalised sample x (n,).
+    Returns the list of layer outputs [a1, a2, a3, y] (a1..a3 after ReLU).
+    quantize=True rounds weights and stored activations to BF16 as the
+    device path does (the final output stays in higher precision)."""
+    q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
+    a = q(np.asarray(x, np.float64).reshape(N ** 3, 1))
+    outs = []
+    for l, W in enumerate(Ws):
+        z = conv3d_fwd(N, q(W), a)
+        if l < 3:
+            a = q(np.maximum(z, 0.0))
+            outs.append(a)
+        else:
+            outs.append(z)
+    return outs
+
+
+def cnn_loss_and_grads(N, Ws, xs, ts, quantize=False):
+    """Mean over samples of ||f(x) - t||^2 / ||t||^2 and its gradient
+    with respect to each layer's weights (backpropagation through the
+    oracle's forward, dgrad and wgrad)."""
+    q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
+    grads = [np.zeros_like(np.asarray(W, np.float64)) for W in Ws]
+    loss = 0.0
+    S = len(xs)
+    for x, t in zip(xs, ts):
+        t = np.asarray(t, np.float64).reshape(-1)
+        a0 = q(np.asarray(x, np.float64).reshape(N ** 3, 1))
+        a1, a2, a3, y = cnn_forward(N, Ws, x, quantize)
+        y = y.reshape(-1)
+        tt = float(t @ t)
+        e = y - t
+        loss += float(e @ e) / tt / S
+        g = (2.0 * e / tt / S).reshape(-1, 1)
+        acts = [a0, a1, a2, a3]
+        for l in (3, 2, 1, 0):
+            grads[l] += conv3d_wgrad(N, g, acts[l], Ws[l].shape[1], Ws[l].shape[0])
+            if l > 0:
+                d = conv3d_dgrad(N, q(Ws[l]), g)
+                g = d * (acts[l] > 0)
+                if quantize:
+                    g = q(g)
+    return loss, grads

@@ -1365,3 +1365,94 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* ======================================================================== */
+/* Learned warm start: a bias-free 3D convolutional network (test oracle).  */
+/* Volumes are N^3 grids, voxel r = x + N y + N^2 z, channels last:          */
+/* a[r*C + c].  A layer is a 3x3x3 cross-correlation with zero padding:      */
+/*   out[r, co] = sum_t sum_ci W[co][ci][t] in[r + off(t), ci],              */
+/* tap t = (dz+1)*9 + (dy+1)*3 + (dx+1), off(t) = dx + N dy + N^2 dz, terms  */
+/* with a neighbour outside the grid are zero.  FP64 throughout; callers    */
+/* pass operands already rounded to BF16 when they compare with a BF16 path. */
+/* ======================================================================== */
+static int nbr_of(int N, long r, int t, long *u)
+{
+    int x = (int)(r % N), y = (int)((r / N) % N), z = (int)(r / ((long)N * N));
+    int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    int xx = x + dx, yy = y + dy, zz = z + dz;
+    if (xx < 0 || xx >= N || yy < 0 || yy >= N || zz < 0 || zz >= N) return 0;
+    *u = r + dx + (long)N * dy + (long)N * N * dz;
+    return 1;
+}
+
+/* forward: out (n x cout) from in (n x cin), W [cout][cin][27] */
+void orc_conv3d_fwd(int N, int cin, int cout, const double *in, const double *W, double *out)
+{
+    long n = (long)N * N * N, r;
+#pragma omp parallel for schedule(static)
+    for (r = 0; r < n; r++) {
+        int co, ci, t;
+        for (co = 0; co < cout; co++) {
+            double s = 0.0;
+            for (t = 0; t < 27; t++) {
+                long u;
+                if (!nbr_of(N, r, t, &u)) continue;
+                for (ci = 0; ci < cin; ci++)
+                    s += W[((long)co * cin + ci) * 27 + t] * in[u * cin + ci];
+            }
+            out[r * cout + co] = s;
+        }
+    }
+}
+
+/* input gradient: din[r, ci] = sum_t sum_co W[co][ci][t] g[r - off(t), co]
+ * (the adjoint of the forward map) */
+void orc_conv3d_dgrad(int N, int cin, int cout, const double *g, const double *W, double *din)
+{
+    long n = (long)N * N * N, r;
+#pragma omp parallel for schedule(static)
+    for (r = 0; r < n; r++) {
+        int co, ci, t;
+        for (ci = 0; ci < cin; ci++) din[r * cin + ci] = 0.0;
+        for (t = 0; t < 27; t++) {
+            long u;
+            /* r = u + off(t)  <=>  u is the neighbour of r at the mirrored tap */
+            if (!nbr_of(N, r, 26 - t, &u)) continue;
+            for (ci = 0; ci < cin; ci++) {
+                double s = 0.0;
+                for (co = 0; co < cout; co++)
+                    s += W[((long)co * cin + ci) * 27 + t] * g[u * cout + co];
+                din[r * cin + ci] += s;
+            }
+        }
+    }
+}
+
+/* weight gradient: dW[co][ci][t] = sum_r g[r, co] in[r + off(t), ci] */
+void orc_conv3d_wgrad(int N, int cin, int cout, const double *g, const double *in, double *dW)
+{
+    long n = (long)N * N * N;
+    int co, ci, t;
+    for (co = 0; co < cout; co++)
+        for (ci = 0; ci < cin; ci++)
+            for (t = 0; t < 27; t++) {
+                double s = 0.0;
+                long r, u;
+                for (r = 0; r < n; r++)
+                    if (nbr_of(N, r, t, &u)) s += g[r * cout + co] * in[u * cin + ci];
+                dW[((long)co * cin + ci) * 27 + t] = s;
+            }
+}
+
+/* round-to-nearest-even of a binary32 value to bfloat16, returned as the
+ * double it represents */
+double orc_bf16_round(double v)
+{
+    float f = (float)v;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
