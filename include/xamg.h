@@ -236,6 +236,70 @@ int xamg_timer_read(xamg_handle_t *h, double *ms, int64_t *count);
 /* Release every device and host resource of h (NULL is allowed). */
 int xamg_destroy(xamg_handle_t *h);
 
+/* ---- learned warm start ------------------------------------------------- *
+ * The solve accepts an initial guess (Section 2.4 lists one as an optional
+ * input beside the matrix and the right-hand side; x0_mode = XAMG_X0_GIVEN).
+ * The network that produces one is an extension of this library, not part
+ * of the paper's method.  These calls produce X0 from B with a
+ * small bias-free 3D CNN on an N x N x N grid (row r = x + N y + N^2 z):
+ * four 3x3x3 zero-padded convolutions, channels 1 -> 16 -> 16 -> 16 -> 1,
+ * ReLU after the first three.  Weights and activations BF16 (round to
+ * nearest even), accumulation FP32, master weights FP32.  Weights are one
+ * flat FP32 array of XAMG_CNN_PARAMS values: W1 [16][1][27], W2 [16][16][27],
+ * W3 [16][16][27], W4 [1][16][27] ([out][in][tap], tap t = (dz+1) 9 +
+ * (dy+1) 3 + (dx+1) for neighbour offset (dx, dy, dz)).  Activations are
+ * channels-last, BF16 stored as uint16: a[r * C + c].
+ * All data pointers are device pointers unless stated otherwise. */
+typedef struct xamg_cnn xamg_cnn_t;
+#define XAMG_CNN_PARAMS 14688
+
+/* Create a network for grid side N (a multiple of 16, 16..1024) with initial
+ * weights w_init (host, XAMG_CNN_PARAMS floats).  stream: hipStream_t or
+ * NULL.  Adam moments start at zero.  EINVAL for a bad N; ENOMEM/EHIP. */
+int xamg_cnn_create(int32_t N, const float *w_init, void *stream, xamg_cnn_t **out);
+
+/* Copy the FP32 master weights out / in (host arrays of XAMG_CNN_PARAMS). */
+int xamg_cnn_get_weights(xamg_cnn_t *h, float *w_host);
+int xamg_cnn_set_weights(xamg_cnn_t *h, const float *w_host);
+
+/* Forward over S normalised samples x (S x n FP32, sample-major), writing
+ * y_out (S x n FP32) unless NULL.  With targets t (S x n FP32) it also
+ * back-propagates: the weight gradients of the mean relative squared error
+ * L = (1/S) sum_s ||f(x_s) - t_s||^2 / ||t_s||^2 replace the gradient buffer
+ * and *loss (host, may be NULL) receives L.  Activations and their
+ * gradients are BF16; dL/dy and weight gradients FP32. */
+int xamg_cnn_pass(xamg_cnn_t *h, const float *x, const float *t, int32_t S, float *y_out,
+                  double *loss);
+
+/* Weight gradients of the last pass (host, XAMG_CNN_PARAMS floats). */
+int xamg_cnn_get_grads(xamg_cnn_t *h, float *g_host);
+
+/* One Adam step on the master weights with the last pass's gradients
+ * (bias-corrected moments; lr > 0).  The BF16 copies are refreshed. */
+int xamg_cnn_adam(xamg_cnn_t *h, float lr, float beta1, float beta2, float eps);
+
+/* One layer alone (1..4), for checking against a reference.  mode 0:
+ * forward of `in` (layer 1: n x 1 BF16; 2, 3: n x 16 BF16; 4: n x 16 BF16)
+ * into `out` (layers 1-3: n x 16 BF16 after ReLU; layer 4: n FP32).
+ * mode 1 (layers 2..4): input gradient of the gradient `in` at the layer's
+ * output (layer 4: n FP32; 2, 3: n x 16 BF16), times (mask > 0) with `mask`
+ * the layer's input activation, into `out` (n x 16 BF16).  mode 2: weight
+ * gradient from `in` (gradient at the output, as in mode 1) and `mask` (the
+ * layer's input activation); the result replaces the gradient buffer
+ * (read with xamg_cnn_get_grads; other layers' entries are zero). */
+int xamg_cnn_layer(xamg_cnn_t *h, int32_t layer, int32_t mode, const void *in, const void *mask,
+                   void *out);
+
+/* X0 (n x m, interleaved as in xamg_solve) from B: column j is s_j f(b_j /
+ * s_j) with s_j = ||b_j|| / sqrt(n) (a zero column gives zero).  With a
+ * solver handle of the same n, every column whose initial residual
+ * ||b_j - A x0_j|| is not below ||b_j|| is reset to zero and fallback[j]
+ * (host, m entries, may be NULL) is 1, else 0.  1 <= m <= XAMG_MAX_M. */
+int xamg_warmstart(xamg_cnn_t *h, xamg_handle_t *solver, const double *B, double *X0, int32_t m,
+                   int32_t *fallback);
+
+int xamg_cnn_destroy(xamg_cnn_t *h);
+
 /* Static description of a return code. */
 const char *xamg_strerror(int code);
 

@@ -370,3 +370,14 @@ def cnn_loss_and_grads(N, Ws, xs, ts, quantize=False):
                 if quantize:
                     g = q(g)
     return loss, grads
+
+
+def adam_step(w, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, ICLR 2015, Algorithm 1) in float64:
+    moments m, v updated in place, bias-corrected with step count t >= 1,
+    w <- w - lr * mhat / (sqrt(vhat) + eps).  Returns the new w."""
+    m[...] = beta1 * m + (1.0 - beta1) * g
+    v[...] = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** t)
+    vhat = v / (1.0 - beta2 ** t)
+    return w - lr * mhat / (np.sqrt(vhat) + eps)

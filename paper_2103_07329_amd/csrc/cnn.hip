@@ -1,0 +1,909 @@
+// cnn.hip -- learned warm start: a small bias-free 3D CNN maps a right-hand
+// side b to an initial guess x0 for the solve (an extension of the
+// multi-RHS solver; Section 2.4 lists an initial guess as an optional input).
+//
+// Network: four 3x3x3 convolutions (channels 1 -> 16 -> 16 -> 16 -> 1),
+// zero padding, ReLU after the first three, no bias, so f(c b) = c f(b) for
+// c > 0.  A column is normalised by s = ||b|| / sqrt(n) before the network
+// and the output is multiplied by s.  Weights and activations are BF16
+// (round to nearest even), accumulation FP32, master weights FP32 (Adam).
+//
+// Layout: volumes of N^3 voxels (r = x + N y + N^2 z), channels last:
+// a[r*C + c].  Tap t = (dz+1)*9 + (dy+1)*3 + (dx+1); a layer computes
+// out[r, co] = sum_t sum_ci W[co][ci][t] in[r + off(t), ci] (zero outside).
+//
+// Kernels: the two 16 -> 16 layers (about 94% of the flops) run on the
+// v_mfma_f32_16x16x32_bf16 matrix instruction: a wavefront owns 16
+// consecutive voxels x 16 output channels and takes two taps (32 = 2 x 16
+// input channels) per instruction; the input gradient of these layers is
+// the same kernel with the weights mirrored and transposed, plus the ReLU
+// mask.  The 1 -> 16 and 16 -> 1 layers are VALU kernels.  Weight
+// gradients are LDS-staged FP32 reductions over voxels with per-block
+// partials summed in block order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "solver.hpp"
+
+struct xamg_cnn {};   // opaque ABI tag; the real object is xamg::cnn::Net
+
+namespace xamg {
+namespace cnn {
+
+constexpr int kTaps = 27;
+constexpr int kC = 16;                 // hidden channels
+constexpr int kPairs = 14;             // tap pairs per MFMA layer (27 -> 28)
+constexpr int kChunk = 16;             // voxels per wgrad chunk (N % 16 == 0)
+constexpr int kParams1 = kC * 1 * kTaps;
+constexpr int kParams2 = kC * kC * kTaps;
+constexpr int kParams4 = 1 * kC * kTaps;
+constexpr int kParams = kParams1 + 2 * kParams2 + kParams4;   // 14688
+constexpr int kWgBlocks = 1024;
+constexpr int kColBlocks = 512;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline uint16_t f2bf(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+__host__ __device__ inline float bf2f(uint16_t h)
+{
+    const uint32_t u = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+__device__ inline bool neighbour(int N, int x, int y, int z, int t, long r, long& u)
+{
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const int xx = x + dx, yy = y + dy, zz = z + dz;
+    if (xx < 0 || xx >= N || yy < 0 || yy >= N || zz < 0 || zz >= N) return false;
+    u = r + dx + long(N) * dy + long(N) * N * dz;
+    return true;
+}
+
+// BF16 pairs packed in 32-bit words: element 2k in the low half
+__device__ inline float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ inline uint32_t bf_pack(float lo, float hi)
+{
+    return uint32_t(f2bf(lo)) | (uint32_t(f2bf(hi)) << 16);
+}
+
+// the 16 channels of one voxel as floats
+__device__ inline void load16(const uint16_t* p, float* v)
+{
+    const uint4* q = reinterpret_cast<const uint4*>(p);
+    const uint4 a = q[0], b = q[1];
+    const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[2 * k] = bf_lo(w[k]);
+        v[2 * k + 1] = bf_hi(w[k]);
+    }
+}
+
+// store 16 floats as BF16 channels of one voxel
+__device__ inline void store16(uint16_t* p, const float* v)
+{
+    uint4* q = reinterpret_cast<uint4*>(p);
+    q[0] = make_uint4(bf_pack(v[0], v[1]), bf_pack(v[2], v[3]), bf_pack(v[4], v[5]),
+                      bf_pack(v[6], v[7]));
+    q[1] = make_uint4(bf_pack(v[8], v[9]), bf_pack(v[10], v[11]), bf_pack(v[12], v[13]),
+                      bf_pack(v[14], v[15]));
+}
+
+// ---------------------------------------------------------------------------
+// 16 -> 16 layer on MFMA (forward, or input gradient with mirrored weights)
+// ---------------------------------------------------------------------------
+// wpk[p*64 + lane]: the 8 BF16 values lane `lane` feeds as the B operand for
+// tap pair p: rows k = 8*(lane/16) + j of the 32 x 16 block, i.e. tap
+// 2p + (lane/16)/2, input channel ((lane/16)&1)*8 + j, output channel
+// lane % 16.  out = relu?(acc) * (mask > 0 if mask) in BF16.
+__global__ __launch_bounds__(256) void conv16_mfma(const uint16_t* __restrict__ in,
+                                                   const uint4* __restrict__ wpk,
+                                                   uint16_t* __restrict__ out,
+                                                   const uint16_t* __restrict__ mask, int relu,
+                                                   int N)
+{
+    const long n = long(N) * N * N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long v0 = (long(blockIdx.x) * 4 + wave) * 16;
+    if (v0 >= n) return;
+    const int m = lane & 15, kq = lane >> 4;
+    const long v = v0 + m;
+    const bool vok = v < n;
+    const int x = int(v % N), y = int((v / N) % N), z = int(v / (long(N) * N));
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int ci0 = (kq & 1) * 8;
+#pragma unroll 2
+    for (int p = 0; p < kPairs; ++p) {
+        const int t = 2 * p + (kq >> 1);
+        uint4 a = make_uint4(0, 0, 0, 0);
+        long u;
+        if (vok && t < kTaps && neighbour(N, x, y, z, t, v, u))
+            a = *reinterpret_cast<const uint4*>(in + u * kC + ci0);
+        const uint4 b = wpk[p * 64 + lane];
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                     __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    }
+    // lane holds rows (voxels) 4*kq + j, column (channel) m
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const long vv = v0 + 4 * kq + j;
+        if (vv >= n) continue;
+        float val = acc[j];
+        if (relu) val = fmaxf(val, 0.0f);
+        if (mask && !(bf2f(mask[vv * kC + m]) > 0.0f)) val = 0.0f;
+        out[vv * kC + m] = f2bf(val);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1 -> 16 layer (VALU), ReLU, BF16 out.  w: [co][t] BF16-valued floats.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void conv_in1(const uint16_t* __restrict__ in,
+                                               const float* __restrict__ w,
+                                               uint16_t* __restrict__ out, int N)
+{
+    __shared__ float sw[kC * kTaps];
+    for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    __syncthreads();
+    const long n = long(N) * N * N;
+    const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int x = int(r % N), y = int((r / N) % N), z = int(r / (long(N) * N));
+    float nb[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+        long u;
+        nb[t] = neighbour(N, x, y, z, t, r, u) ? bf2f(in[u]) : 0.0f;
+    }
+    float o[kC];
+#pragma unroll
+    for (int co = 0; co < kC; ++co) {
+        float s = 0.0f;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) s += sw[co * kTaps + t] * nb[t];
+        o[co] = fmaxf(s, 0.0f);
+    }
+    store16(out + r * kC, o);
+}
+
+// ---------------------------------------------------------------------------
+// 16 -> 1 layer (VALU), FP32 out.  w: [ci][t] BF16-valued floats.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void conv_out1(const uint16_t* __restrict__ in,
+                                                const float* __restrict__ w,
+                                                float* __restrict__ out, int N)
+{
+    __shared__ float sw[kC * kTaps];
+    for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    __syncthreads();
+    const long n = long(N) * N * N;
+    const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int x = int(r % N), y = int((r / N) % N), z = int(r / (long(N) * N));
+    float s = 0.0f;
+    for (int t = 0; t < kTaps; ++t) {
+        long u;
+        if (!neighbour(N, x, y, z, t, r, u)) continue;
+        float hv[kC];
+        load16(in + u * kC, hv);
+#pragma unroll
+        for (int ci = 0; ci < kC; ++ci) s += sw[ci * kTaps + t] * hv[ci];
+    }
+    out[r] = s;
+}
+
+// input gradient of the 16 -> 1 layer: g[r, ci] = sum_t w[ci][t] dy[r - off(t)],
+// times (act[r, ci] > 0), BF16 out
+__global__ __launch_bounds__(256) void dgrad_out1(const float* __restrict__ dy,
+                                                 const float* __restrict__ w,
+                                                 const uint16_t* __restrict__ act,
+                                                 uint16_t* __restrict__ g, int N)
+{
+    __shared__ float sw[kC * kTaps];
+    for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    __syncthreads();
+    const long n = long(N) * N * N;
+    const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int x = int(r % N), y = int((r / N) % N), z = int(r / (long(N) * N));
+    float d[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) {
+        long u;
+        d[t] = neighbour(N, x, y, z, 26 - t, r, u) ? dy[u] : 0.0f;   // r - off(t)
+    }
+    float av[kC], o[kC];
+    load16(act + r * kC, av);
+#pragma unroll
+    for (int ci = 0; ci < kC; ++ci) {
+        float s = 0.0f;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) s += sw[ci * kTaps + t] * d[t];
+        o[ci] = av[ci] > 0.0f ? s : 0.0f;
+    }
+    store16(g + r * kC, o);
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: dW[co][ci][t] = sum_r g[r, co] in[r + off(t), ci]
+// ---------------------------------------------------------------------------
+// Chunks of kChunk voxels along x (one row); the chunk's g values and the
+// 3 x 3 rows (x - 1 .. x + kChunk) of inputs are staged in LDS as floats.
+// G: gradient channels (COUT), I: input channels (CIN); thread (o, i) with
+// o < COUT, i < CIN accumulates the 27 taps.  gsrc_f32: g given as FP32.
+template <int COUT, int CIN>
+__global__ __launch_bounds__(256) void wgrad_lds(const uint16_t* __restrict__ g16,
+                                                const float* __restrict__ g32,
+                                                const uint16_t* __restrict__ in, int N,
+                                                float* __restrict__ part)
+{
+    constexpr int W = kChunk + 2;
+    __shared__ float sg[kChunk * COUT];
+    __shared__ float si[9 * W * CIN];
+    const long n = long(N) * N * N;
+    const long nchunks = n / kChunk;
+    const int tid = threadIdx.x;
+    const int o = tid / CIN, i = tid % CIN;
+    const bool own = tid < COUT * CIN;
+    float acc[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc[t] = 0.0f;
+    for (long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long r0 = c * kChunk;
+        const int x0 = int(r0 % N), y = int((r0 / N) % N), z = int(r0 / (long(N) * N));
+        __syncthreads();
+        for (int e = tid; e < kChunk * COUT; e += blockDim.x) {
+            const long idx = r0 * COUT + e;
+            sg[e] = g32 ? g32[idx] : bf2f(g16[idx]);
+        }
+        for (int e = tid; e < 9 * W * CIN; e += blockDim.x) {
+            const int ch = e % CIN, xw = (e / CIN) % W, seg = e / (CIN * W);
+            const int yy = y + seg % 3 - 1, zz = z + seg / 3 - 1, xx = x0 + xw - 1;
+            float val = 0.0f;
+            if (xx >= 0 && xx < N && yy >= 0 && yy < N && zz >= 0 && zz < N)
+                val = bf2f(in[(xx + long(N) * yy + long(N) * N * zz) * CIN + ch]);
+            si[e] = val;
+        }
+        __syncthreads();
+        if (own) {
+            for (int k = 0; k < kChunk; ++k) {
+                const float gv = sg[k * COUT + o];
+#pragma unroll
+                for (int t = 0; t < kTaps; ++t) {
+                    const int dx = t % 3, seg = t / 3;   // seg = (dz+1)*3 + (dy+1)
+                    acc[t] += gv * si[(seg * W + k + dx) * CIN + i];
+                }
+            }
+        }
+    }
+    if (own) {
+        float* dst = part + size_t(blockIdx.x) * (COUT * CIN * kTaps);
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) dst[(o * CIN + i) * kTaps + t] = acc[t];
+    }
+}
+
+// sum the partials of nb blocks in block order, add into dst (FP32)
+__global__ void reduce_parts(const float* __restrict__ part, int nb, int len,
+                             float* __restrict__ dst)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s += part[size_t(b) * len + e];
+    dst[e] += s;
+}
+
+// ---------------------------------------------------------------------------
+// loss: per sample e2 = sum (y - t)^2, tt = sum t^2 (block partials)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void loss_parts(const float* __restrict__ y,
+                                                 const float* __restrict__ t, long n,
+                                                 double* __restrict__ part)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += long(gridDim.x) * blockDim.x) {
+        const double e = double(y[r]) - double(t[r]);
+        a += e * e;
+        b += double(t[r]) * double(t[r]);
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) {
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+            s2[threadIdx.x] += s2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+// out[0] += e2 / tt / S (the sample's loss); out[1] = 2 / (tt S) (gradient scale)
+__global__ void loss_finish(const double* __restrict__ part, int nb, int S, double* out)
+{
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        a += part[2 * k];
+        b += part[2 * k + 1];
+    }
+    out[0] += a / b / S;
+    out[1] = 2.0 / (b * S);
+}
+
+__global__ void loss_grad(const float* __restrict__ y, const float* __restrict__ t, long n,
+                          const double* __restrict__ sc, float* __restrict__ dy)
+{
+    const float s = float(sc[1]);
+    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += long(gridDim.x) * blockDim.x)
+        dy[r] = s * (y[r] - t[r]);
+}
+
+// ---------------------------------------------------------------------------
+// weights: Adam on FP32 masters, then BF16 copies in each kernel's layout
+// ---------------------------------------------------------------------------
+__global__ void adam_step(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                          float* __restrict__ v, int len, float lr, float b1, float b2, float eps,
+                          float c1, float c2)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    const float gg = g[e];
+    const float mm = b1 * m[e] + (1.0f - b1) * gg;
+    const float vv = b2 * v[e] + (1.0f - b2) * gg * gg;
+    m[e] = mm;
+    v[e] = vv;
+    const float mh = mm / c1, vh = vv / c2;
+    w[e] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// Layer offsets in the flat master array: W1 [16][1][27], W2, W3 [16][16][27],
+// W4 [1][16][27].
+__global__ void pack_weights(const float* __restrict__ w, float* __restrict__ w1b,
+                             float* __restrict__ w4b, uint16_t* __restrict__ pk)
+{
+    // pk: 4 packs of kPairs*64*8 BF16: [W2 fwd, W2 dgrad, W3 fwd, W3 dgrad]
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kParams1) w1b[e] = bf2f(f2bf(w[e]));   // [co][t]
+    if (e < kParams4) {
+        // W4 [0][ci][t] -> [ci][t]
+        w4b[e] = bf2f(f2bf(w[kParams1 + 2 * kParams2 + e]));
+    }
+    constexpr int per = kPairs * 64 * 8;
+    if (e >= 4 * per) return;
+    const int which = e / per, rem = e % per;
+    const int p = rem / (64 * 8), lane = (rem / 8) % 64, j = rem % 8;
+    const int kq = lane >> 4, col = lane & 15;
+    const int t = 2 * p + (kq >> 1);
+    const int row = (kq & 1) * 8 + j;   // input channel of this pass
+    const float* W = w + kParams1 + (which / 2) * kParams2;   // [co][ci][t]
+    float val = 0.0f;
+    if (t < kTaps) {
+        if ((which & 1) == 0)
+            val = W[(col * kC + row) * kTaps + t];            // fwd: B[ci][co]
+        else
+            val = W[(row * kC + col) * kTaps + (26 - t)];     // dgrad: B[co][ci], mirrored
+    }
+    pk[e] = f2bf(val);
+}
+
+// ---------------------------------------------------------------------------
+// data preparation / warm start
+// ---------------------------------------------------------------------------
+// column j of an interleaved n x m FP64 block -> BF16 volume scaled by 1/s
+// (a zero column gives a zero volume)
+__global__ void col_to_bf16(const double* __restrict__ B, int m, int j, long n,
+                            const double* __restrict__ s, uint16_t* __restrict__ out)
+{
+    const float inv = s[j] > 0.0 ? float(1.0 / s[j]) : 0.0f;
+    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += long(gridDim.x) * blockDim.x)
+        out[r] = f2bf(float(B[r * m + j]) * inv);
+}
+
+__global__ void f32_to_bf16(const float* __restrict__ x, long n, uint16_t* __restrict__ out)
+{
+    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += long(gridDim.x) * blockDim.x)
+        out[r] = f2bf(x[r]);
+}
+
+// X0[:, j] = s_j * y
+__global__ void y_to_col(const float* __restrict__ y, int m, int j, long n,
+                         const double* __restrict__ s, double* __restrict__ X0)
+{
+    const double sc = s[j];
+    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += long(gridDim.x) * blockDim.x)
+        X0[r * m + j] = sc > 0.0 ? sc * double(y[r]) : 0.0;
+}
+
+// Per-column sums of squares over a contiguous row range per block:
+// part[(block * m + j) * 2] = sum b_rj^2 and, with a matrix, part[... + 1] =
+// sum (b - A x)_rj^2.  Thread t < g m (g = 256 / m) takes column t % m and
+// rows q, q + g, ... of the range (q = t / m), so loads stay contiguous.
+__global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
+                                             const double* __restrict__ X,
+                                             const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const double* __restrict__ v, int m, long n,
+                                             double* __restrict__ part)
+{
+    __shared__ double s0[256], s1[256];
+    const int t = threadIdx.x, g = 256 / m;
+    const int j = t % m, q = t / m;
+    const long per = (n + gridDim.x - 1) / gridDim.x;
+    const long r0 = long(blockIdx.x) * per, r1 = std::min(n, r0 + per);
+    double bb = 0.0, rr = 0.0;
+    if (q < g) {
+        for (long r = r0 + q; r < r1; r += g) {
+            const double b = B[r * m + j];
+            bb += b * b;
+            if (rp) {
+                double s = b;
+                for (int k = rp[r]; k < rp[r + 1]; ++k) s -= v[k] * X[long(ci[k]) * m + j];
+                rr += s * s;
+            }
+        }
+    }
+    s0[t] = bb;
+    s1[t] = rr;
+    __syncthreads();
+    if (t < m) {
+        double a = 0.0, c = 0.0;
+        for (int k = 0; k < g; ++k) {
+            a += s0[k * m + t];
+            c += s1[k * m + t];
+        }
+        part[(size_t(blockIdx.x) * m + t) * 2] = a;
+        part[(size_t(blockIdx.x) * m + t) * 2 + 1] = c;
+    }
+}
+
+// sums[2j + k] = sum over blocks (in block order) of part[(b m + j) 2 + k];
+// with scales, s_j = sqrt(sums[2j] / n)
+__global__ void col_sq_finish(const double* __restrict__ part, int nb, int m, long n,
+                              double* __restrict__ sums, double* __restrict__ scales)
+{
+    const int j = threadIdx.x;
+    if (j >= m) return;
+    double a = 0.0, c = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        a += part[(size_t(b) * m + j) * 2];
+        c += part[(size_t(b) * m + j) * 2 + 1];
+    }
+    sums[2 * j] = a;
+    sums[2 * j + 1] = c;
+    if (scales) scales[j] = sqrt(a / double(n));
+}
+
+__global__ void zero_col(double* __restrict__ X0, int m, int j, long n)
+{
+    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
+         r += long(gridDim.x) * blockDim.x)
+        X0[r * m + j] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// host object
+// ---------------------------------------------------------------------------
+struct Net : xamg_cnn {
+    int N = 0;
+    long n = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    float *w = nullptr, *g = nullptr, *mo = nullptr, *ve = nullptr;   // masters, grads, Adam
+    float *w1b = nullptr, *w4b = nullptr;
+    uint16_t* pk = nullptr;
+    uint16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
+    uint16_t *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
+    float *y = nullptr, *dy = nullptr, *wpart = nullptr;
+    double *lpart = nullptr, *lacc = nullptr, *scales = nullptr, *sums = nullptr;
+    double* cpart = nullptr;   // col_sq partials
+    int64_t adam_t = 0;
+
+    ~Net()
+    {
+        for (void* p : allocs) hipFree(p);
+    }
+    void chk(hipError_t e, const char* what)
+    {
+        if (e != hipSuccess) {
+            set_error("HIP error %d (%s) in %s", int(e), hipGetErrorString(e), what);
+            throw DevFail{e == hipErrorOutOfMemory ? XAMG_ENOMEM : XAMG_EHIP};
+        }
+    }
+    template <typename T>
+    T* alloc(size_t count)
+    {
+        void* p = nullptr;
+        chk(hipMalloc(&p, std::max<size_t>(count * sizeof(T), 256)), "hipMalloc");
+        allocs.push_back(p);
+        return static_cast<T*>(p);
+    }
+    const uint4* pack(int which) const
+    {
+        return reinterpret_cast<const uint4*>(pk + size_t(which) * kPairs * 64 * 8);
+    }
+    int grid(long count, int per = 256) const { return int((count + per - 1) / per); }
+
+    void repack()
+    {
+        const int total = std::max(4 * kPairs * 64 * 8, kParams1);
+        hipLaunchKernelGGL(pack_weights, dim3(grid(total)), dim3(256), 0, stream, w, w1b, w4b, pk);
+    }
+
+    // forward of one normalised sample already in a0; y = f(a0)
+    void forward()
+    {
+        hipLaunchKernelGGL(conv_in1, dim3(grid(n)), dim3(256), 0, stream, a0, w1b, a1, N);
+        const int nb16 = int((n + 63) / 64);
+        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, a1, pack(0), a2,
+                           static_cast<const uint16_t*>(nullptr), 1, N);
+        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, a2, pack(2), a3,
+                           static_cast<const uint16_t*>(nullptr), 1, N);
+        hipLaunchKernelGGL(conv_out1, dim3(grid(n)), dim3(256), 0, stream, a3, w4b, y, N);
+    }
+
+    // backward of one sample (dy set); weight gradients accumulate into g
+    void backward()
+    {
+        const int nb16 = int((n + 63) / 64);
+        const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
+        // layer 4: dW4 and g3 = W4^T dy masked by a3 > 0
+        hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, stream,
+                           static_cast<const uint16_t*>(nullptr), dy, a3, N, wpart);
+        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams4)), dim3(256), 0, stream, wpart, nbw,
+                           kParams4, g + kParams1 + 2 * kParams2);
+        hipLaunchKernelGGL(dgrad_out1, dim3(grid(n)), dim3(256), 0, stream, dy, w4b, a3, g3, N);
+        // layer 3: dW3 from (g3, a2); g2 = dgrad masked by a2 > 0
+        hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g3,
+                           static_cast<const float*>(nullptr), a2, N, wpart);
+        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
+                           kParams2, g + kParams1 + kParams2);
+        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
+        // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
+        hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g2,
+                           static_cast<const float*>(nullptr), a1, N, wpart);
+        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
+                           kParams2, g + kParams1);
+        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
+        // layer 1: dW1 from (g1, a0)
+        hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, stream, g1,
+                           static_cast<const float*>(nullptr), a0, N, wpart);
+        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams1)), dim3(256), 0, stream, wpart, nbw,
+                           kParams1, g);
+    }
+};
+
+}  // namespace cnn
+}  // namespace xamg
+
+using xamg::cnn::Net;
+
+extern "C" {
+
+int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** out)
+{
+    xamg::clear_error();
+    if (!w_init || !out) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (N < 16 || N % 16 != 0 || N > 1024) return xamg::fail(XAMG_EINVAL, "N must be a multiple of 16");
+    *out = nullptr;
+    Net* net = new (std::nothrow) Net;
+    if (!net) return xamg::fail(XAMG_ENOMEM, "host allocation");
+    using namespace xamg::cnn;
+    try {
+        net->N = N;
+        net->n = long(N) * N * N;
+        net->stream = static_cast<hipStream_t>(stream);
+        const long n = net->n;
+        net->w = net->alloc<float>(kParams);
+        net->g = net->alloc<float>(kParams);
+        net->mo = net->alloc<float>(kParams);
+        net->ve = net->alloc<float>(kParams);
+        net->w1b = net->alloc<float>(kParams1);
+        net->w4b = net->alloc<float>(kParams4);
+        net->pk = net->alloc<uint16_t>(4 * kPairs * 64 * 8);
+        net->a0 = net->alloc<uint16_t>(n);
+        net->a1 = net->alloc<uint16_t>(n * kC);
+        net->a2 = net->alloc<uint16_t>(n * kC);
+        net->a3 = net->alloc<uint16_t>(n * kC);
+        net->g1 = net->alloc<uint16_t>(n * kC);
+        net->g2 = net->alloc<uint16_t>(n * kC);
+        net->g3 = net->alloc<uint16_t>(n * kC);
+        net->y = net->alloc<float>(n);
+        net->dy = net->alloc<float>(n);
+        net->wpart = net->alloc<float>(size_t(kWgBlocks) * kParams2);
+        net->lpart = net->alloc<double>(2 * 1024);
+        net->lacc = net->alloc<double>(2);
+        net->scales = net->alloc<double>(64);
+        net->sums = net->alloc<double>(2 * 64);
+        net->cpart = net->alloc<double>(size_t(kColBlocks) * 2 * 64);
+        net->chk(hipMemcpy(net->w, w_init, kParams * sizeof(float), hipMemcpyHostToDevice), "weights");
+        std::vector<float> zero(kParams, 0.0f);
+        net->chk(hipMemcpy(net->mo, zero.data(), kParams * sizeof(float), hipMemcpyHostToDevice), "adam");
+        net->chk(hipMemcpy(net->ve, zero.data(), kParams * sizeof(float), hipMemcpyHostToDevice), "adam");
+        net->repack();
+        net->chk(hipStreamSynchronize(net->stream), "create sync");
+    } catch (const xamg::DevFail& f) {
+        delete net;
+        return f.code;
+    }
+    *out = static_cast<xamg_cnn_t*>(net);
+    return XAMG_OK;
+}
+
+int xamg_cnn_get_weights(xamg_cnn_t* h, float* w_host)
+{
+    Net* net = static_cast<Net*>(h);
+    if (!net || !w_host) return xamg::fail(XAMG_EINVAL, "null argument");
+    try {
+        net->chk(hipStreamSynchronize(net->stream), "sync");
+        net->chk(hipMemcpy(w_host, net->w, xamg::cnn::kParams * sizeof(float), hipMemcpyDeviceToHost),
+                 "weights");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+int xamg_cnn_set_weights(xamg_cnn_t* h, const float* w_host)
+{
+    Net* net = static_cast<Net*>(h);
+    if (!net || !w_host) return xamg::fail(XAMG_EINVAL, "null argument");
+    try {
+        net->chk(hipMemcpy(net->w, w_host, xamg::cnn::kParams * sizeof(float), hipMemcpyHostToDevice),
+                 "weights");
+        net->repack();
+        net->chk(hipStreamSynchronize(net->stream), "sync");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+// One forward (and, with targets, backward) pass over S normalised samples.
+// x: S x n FP32 inputs, t: S x n FP32 targets or NULL, y_out: S x n FP32
+// (device) or NULL.  With targets the weight gradients are summed over the
+// samples into the gradient buffer and *loss = mean relative squared error.
+int xamg_cnn_pass(xamg_cnn_t* h, const float* x, const float* t, int32_t S, float* y_out,
+                  double* loss)
+{
+    using namespace xamg::cnn;
+    Net* net = static_cast<Net*>(h);
+    if (!net || !x || S < 1) return xamg::fail(XAMG_EINVAL, "bad arguments");
+    try {
+        const long n = net->n;
+        if (t) {
+            net->chk(hipMemsetAsync(net->g, 0, kParams * sizeof(float), net->stream), "grad zero");
+            net->chk(hipMemsetAsync(net->lacc, 0, 2 * sizeof(double), net->stream), "loss zero");
+        }
+        for (int s = 0; s < S; ++s) {
+            hipLaunchKernelGGL(f32_to_bf16, dim3(1024), dim3(256), 0, net->stream, x + size_t(s) * n,
+                               n, net->a0);
+            net->forward();
+            if (y_out)
+                net->chk(hipMemcpyAsync(y_out + size_t(s) * n, net->y, n * sizeof(float),
+                                        hipMemcpyDeviceToDevice, net->stream), "y copy");
+            if (t) {
+                const float* ts = t + size_t(s) * n;
+                hipLaunchKernelGGL(loss_parts, dim3(1024), dim3(256), 0, net->stream, net->y, ts, n,
+                                   net->lpart);
+                hipLaunchKernelGGL(loss_finish, dim3(1), dim3(64), 0, net->stream, net->lpart, 1024, S,
+                                   net->lacc);
+                hipLaunchKernelGGL(loss_grad, dim3(1024), dim3(256), 0, net->stream, net->y, ts, n,
+                                   net->lacc, net->dy);
+                net->backward();
+            }
+        }
+        if (t && loss) {
+            double l[2];
+            net->chk(hipMemcpyAsync(l, net->lacc, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                    net->stream), "loss copy");
+            net->chk(hipStreamSynchronize(net->stream), "sync");
+            *loss = l[0];
+        }
+        net->chk(hipGetLastError(), "cnn pass");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+// Copy the summed weight gradients of the last pass (host, 14688 floats).
+int xamg_cnn_get_grads(xamg_cnn_t* h, float* g_host)
+{
+    Net* net = static_cast<Net*>(h);
+    if (!net || !g_host) return xamg::fail(XAMG_EINVAL, "null argument");
+    try {
+        net->chk(hipStreamSynchronize(net->stream), "sync");
+        net->chk(hipMemcpy(g_host, net->g, xamg::cnn::kParams * sizeof(float), hipMemcpyDeviceToHost),
+                 "grads");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+// Adam step with the gradients of the last pass.
+int xamg_cnn_adam(xamg_cnn_t* h, float lr, float beta1, float beta2, float eps)
+{
+    using namespace xamg::cnn;
+    Net* net = static_cast<Net*>(h);
+    if (!net || !(lr > 0.0f)) return xamg::fail(XAMG_EINVAL, "bad arguments");
+    try {
+        net->adam_t += 1;
+        const float c1 = 1.0f - std::pow(beta1, float(net->adam_t));
+        const float c2 = 1.0f - std::pow(beta2, float(net->adam_t));
+        hipLaunchKernelGGL(adam_step, dim3(net->grid(kParams)), dim3(256), 0, net->stream, net->w,
+                           net->g, net->mo, net->ve, kParams, lr, beta1, beta2, eps, c1, c2);
+        net->repack();
+        net->chk(hipGetLastError(), "adam");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+// Single-layer kernels for tests (device pointers, BF16 as uint16).
+// layer 1..4; in: n x cin, out: n x cout (layer 4: FP32 out).  mode 0 =
+// forward, mode 1 = input gradient (layers 2..4; `mask` = activation whose
+// sign gates the result), mode 2 = weight gradient (out = FP32 [cout][cin][27]
+// added to the net's gradient buffer, read with xamg_cnn_get_grads).
+int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, const void* mask,
+                   void* out)
+{
+    using namespace xamg::cnn;
+    Net* net = static_cast<Net*>(h);
+    if (!net || !in || !out || layer < 1 || layer > 4 || mode < 0 || mode > 2)
+        return xamg::fail(XAMG_EINVAL, "bad arguments");
+    try {
+        const long n = net->n;
+        const int N = net->N;
+        const int nb16 = int((n + 63) / 64);
+        const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
+        const uint16_t* i16 = static_cast<const uint16_t*>(in);
+        const uint16_t* m16 = static_cast<const uint16_t*>(mask);
+        if (mode == 0) {
+            if (layer == 1)
+                hipLaunchKernelGGL(conv_in1, dim3(net->grid(n)), dim3(256), 0, net->stream, i16,
+                                   net->w1b, static_cast<uint16_t*>(out), N);
+            else if (layer == 4)
+                hipLaunchKernelGGL(conv_out1, dim3(net->grid(n)), dim3(256), 0, net->stream, i16,
+                                   net->w4b, static_cast<float*>(out), N);
+            else
+                hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, net->stream, i16,
+                                   net->pack(layer == 2 ? 0 : 2), static_cast<uint16_t*>(out),
+                                   static_cast<const uint16_t*>(nullptr), 1, N);
+        } else if (mode == 1) {
+            if (layer == 1) return xamg::fail(XAMG_EINVAL, "no input gradient for layer 1");
+            if (!mask) return xamg::fail(XAMG_EINVAL, "mask required");
+            if (layer == 4)
+                hipLaunchKernelGGL(dgrad_out1, dim3(net->grid(n)), dim3(256), 0, net->stream,
+                                   static_cast<const float*>(in), net->w4b, m16,
+                                   static_cast<uint16_t*>(out), N);
+            else
+                hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, net->stream, i16,
+                                   net->pack(layer == 2 ? 1 : 3), static_cast<uint16_t*>(out), m16,
+                                   0, N);
+        } else {
+            // in = gradient at the layer's output, mask = the layer's input
+            if (!mask) return xamg::fail(XAMG_EINVAL, "layer input required");
+            net->chk(hipMemsetAsync(net->g, 0, kParams * sizeof(float), net->stream), "grad zero");
+            if (layer == 1) {
+                hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, net->stream, i16,
+                                   static_cast<const float*>(nullptr), m16, N, net->wpart);
+                hipLaunchKernelGGL(reduce_parts, dim3(net->grid(kParams1)), dim3(256), 0,
+                                   net->stream, net->wpart, nbw, kParams1, net->g);
+            } else if (layer == 4) {
+                hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, net->stream,
+                                   static_cast<const uint16_t*>(nullptr),
+                                   static_cast<const float*>(in), m16, N, net->wpart);
+                hipLaunchKernelGGL(reduce_parts, dim3(net->grid(kParams4)), dim3(256), 0,
+                                   net->stream, net->wpart, nbw, kParams4,
+                                   net->g + kParams1 + 2 * kParams2);
+            } else {
+                hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, net->stream, i16,
+                                   static_cast<const float*>(nullptr), m16, N, net->wpart);
+                hipLaunchKernelGGL(reduce_parts, dim3(net->grid(kParams2)), dim3(256), 0,
+                                   net->stream, net->wpart, nbw, kParams2,
+                                   net->g + kParams1 + (layer - 2) * kParams2);
+            }
+        }
+        net->chk(hipGetLastError(), "layer");
+        net->chk(hipStreamSynchronize(net->stream), "layer sync");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+// Warm start: X0[:, j] = s_j f(B[:, j] / s_j), s_j = ||b_j|| / sqrt(n); then,
+// with a solver handle, every column whose initial residual is not smaller
+// than ||b_j|| is reset to zero (fallback[j] = 1, host, may be NULL).
+int xamg_warmstart(xamg_cnn_t* h, xamg_handle_t* solver, const double* B, double* X0, int32_t m,
+                   int32_t* fallback)
+{
+    using namespace xamg::cnn;
+    xamg::clear_error();
+    Net* net = static_cast<Net*>(h);
+    if (!net || !B || !X0 || m < 1 || m > XAMG_MAX_M) return xamg::fail(XAMG_EINVAL, "bad arguments");
+    if (solver && static_cast<xamg::Handle*>(solver)->lev[0].n != net->n)
+        return xamg::fail(XAMG_EINVAL, "solver size differs from the network grid");
+    try {
+        const long n = net->n;
+        const int nbc = int(std::min<long>(kColBlocks, std::max<long>(1, n / 64)));
+        hipLaunchKernelGGL(col_sq, dim3(nbc), dim3(256), 0, net->stream, B,
+                           static_cast<const double*>(nullptr), static_cast<const int*>(nullptr),
+                           static_cast<const int*>(nullptr), static_cast<const double*>(nullptr),
+                           m, n, net->cpart);
+        hipLaunchKernelGGL(col_sq_finish, dim3(1), dim3(64), 0, net->stream, net->cpart, nbc, m, n,
+                           net->sums, net->scales);
+        for (int j = 0; j < m; ++j) {
+            hipLaunchKernelGGL(col_to_bf16, dim3(1024), dim3(256), 0, net->stream, B, m, j, n,
+                               net->scales, net->a0);
+            net->forward();
+            hipLaunchKernelGGL(y_to_col, dim3(1024), dim3(256), 0, net->stream, net->y, m, j, n,
+                               net->scales, X0);
+        }
+        net->chk(hipGetLastError(), "warm start");
+        if (solver) {
+            // fallback: ||b_j - A x0_j|| >= ||b_j||  =>  x0_j = 0
+            const xamg::DCsr& A = static_cast<xamg::Handle*>(solver)->lev[0].A64;
+            hipLaunchKernelGGL(col_sq, dim3(nbc), dim3(256), 0, net->stream, B, X0, A.rp, A.ci,
+                               static_cast<const double*>(A.v), m, n, net->cpart);
+            hipLaunchKernelGGL(col_sq_finish, dim3(1), dim3(64), 0, net->stream, net->cpart, nbc, m,
+                               n, net->sums, static_cast<double*>(nullptr));
+            double sums[2 * 64];
+            net->chk(hipMemcpyAsync(sums, net->sums, 2 * m * sizeof(double), hipMemcpyDeviceToHost,
+                                    net->stream), "norm copy");
+            net->chk(hipStreamSynchronize(net->stream), "sync");
+            for (int j = 0; j < m; ++j) {
+                const bool fb = !(sums[2 * j + 1] < sums[2 * j]);
+                if (fb)
+                    hipLaunchKernelGGL(zero_col, dim3(1024), dim3(256), 0, net->stream, X0, m, j, n);
+                if (fallback) fallback[j] = fb ? 1 : 0;
+            }
+            net->chk(hipGetLastError(), "fallback");
+        } else if (fallback) {
+            for (int j = 0; j < m; ++j) fallback[j] = 0;
+        }
+        net->chk(hipStreamSynchronize(net->stream), "sync");
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+int xamg_cnn_destroy(xamg_cnn_t* h)
+{
+    Net* net = static_cast<Net*>(h);
+    if (!net) return XAMG_OK;
+    hipStreamSynchronize(net->stream);
+    delete net;
+    return XAMG_OK;
+}
+
+}  // extern "C"

@@ -72,7 +72,13 @@ EXPORTS = [
     "xamg_batch_create", "xamg_solve_batched", "xamg_batch_destroy",
     "xamg_autotune", "xamg_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
+    "xamg_cnn_create", "xamg_cnn_get_weights", "xamg_cnn_set_weights", "xamg_cnn_pass",
+    "xamg_cnn_get_grads", "xamg_cnn_adam", "xamg_cnn_layer", "xamg_warmstart",
+    "xamg_cnn_destroy",
 ]
+
+CNN_PARAMS = 14688
+CNN_LAYERS = ((1, 16), (16, 16), (16, 16), (16, 1))   # (cin, cout) per layer
 
 
 def lib():
@@ -113,6 +119,17 @@ def lib():
         L.xamg_strerror.restype = ctypes.c_char_p
         L.xamg_last_error.argtypes = []
         L.xamg_last_error.restype = ctypes.c_char_p
+        f32p = ctypes.POINTER(ctypes.c_float)
+        L.xamg_cnn_create.argtypes = [i32, f32p, vp, ctypes.POINTER(vp)]
+        L.xamg_cnn_get_weights.argtypes = [vp, f32p]
+        L.xamg_cnn_set_weights.argtypes = [vp, f32p]
+        L.xamg_cnn_pass.argtypes = [vp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
+        L.xamg_cnn_get_grads.argtypes = [vp, f32p]
+        L.xamg_cnn_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float]
+        L.xamg_cnn_layer.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.xamg_warmstart.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(i32)]
+        L.xamg_cnn_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -376,3 +393,112 @@ class Batch:
                 "true_relres": np.array([s.true_relres for s in st]),
             })
         return rc, out
+
+
+def _f32_host(a, count):
+    a = np.ascontiguousarray(a, np.float32).reshape(-1)
+    if a.size != count:
+        raise ValueError(f"expected {count} values, got {a.size}")
+    return a
+
+
+def split_weights(flat):
+    """Flat XAMG_CNN_PARAMS array -> [W1, W2, W3, W4], W_l of shape (cout, cin, 27)."""
+    flat = np.asarray(flat).reshape(-1)
+    out, k = [], 0
+    for cin, cout in CNN_LAYERS:
+        size = cout * cin * 27
+        out.append(flat[k:k + size].reshape(cout, cin, 27))
+        k += size
+    return out
+
+
+def join_weights(Ws):
+    return np.concatenate([np.asarray(W, np.float32).reshape(-1) for W in Ws])
+
+
+class Cnn:
+    """Warm-start network on an N^3 grid (device weights, Adam state)."""
+
+    def __init__(self, N, weights, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        w = _f32_host(weights, CNN_PARAMS)
+        h = ctypes.c_void_p()
+        _check(lib().xamg_cnn_create(N, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream,
+                                     ctypes.byref(h)), "xamg_cnn_create")
+        self._h = h
+        self.N = N
+        self.n = N ** 3
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().xamg_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        w = np.empty(CNN_PARAMS, np.float32)
+        _check(lib().xamg_cnn_get_weights(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "xamg_cnn_get_weights")
+        return w
+
+    def set_weights(self, weights):
+        w = _f32_host(weights, CNN_PARAMS)
+        _check(lib().xamg_cnn_set_weights(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "xamg_cnn_set_weights")
+
+    def grads(self):
+        g = np.empty(CNN_PARAMS, np.float32)
+        _check(lib().xamg_cnn_get_grads(self._h, g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "xamg_cnn_get_grads")
+        return g
+
+    def forward(self, x, y=None):
+        """x: (S, n) float32 device tensor of normalised samples -> y (S, n)."""
+        import torch
+        S = x.shape[0]
+        if y is None:
+            y = torch.empty_like(x)
+        _check(lib().xamg_cnn_pass(self._h, _ptr(x, "float32"), None, S, _ptr(y, "float32"), None),
+               "xamg_cnn_pass")
+        return y
+
+    def loss_and_grads(self, x, t):
+        """One forward + backward over the samples; returns the loss (the
+        gradients stay on the device for adam(); grads() copies them)."""
+        S = x.shape[0]
+        loss = ctypes.c_double()
+        _check(lib().xamg_cnn_pass(self._h, _ptr(x, "float32"), _ptr(t, "float32"), S, None,
+                                   ctypes.byref(loss)), "xamg_cnn_pass")
+        return loss.value
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _check(lib().xamg_cnn_adam(self._h, lr, beta1, beta2, eps), "xamg_cnn_adam")
+
+    def layer(self, layer, mode, inp, mask, out):
+        """Single-layer kernel (see xamg_cnn_layer); BF16 tensors are
+        torch.bfloat16, FP32 tensors torch.float32."""
+        def p(t):
+            if t is None:
+                return None
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("tensor must be a contiguous GPU tensor")
+            return ctypes.c_void_p(t.data_ptr())
+        _check(lib().xamg_cnn_layer(self._h, layer, mode, p(inp), p(mask), p(out)), "xamg_cnn_layer")
+
+    def warmstart(self, B, X0, solver=None):
+        """X0 (n, m) from B (n, m), float64 device tensors.  With a solver,
+        columns whose initial residual is not below ||b|| are reset to zero;
+        returns the per-column fallback flags."""
+        m = B.shape[1]
+        fb = (ctypes.c_int32 * m)()
+        _check(lib().xamg_warmstart(self._h, solver._h if solver is not None else None, _ptr(B),
+                                    _ptr(X0), m, fb), "xamg_warmstart")
+        return np.array(list(fb), np.int32)

@@ -195,3 +195,26 @@ def test_bf16_matches_torch():
     assert np.array_equal(got, ref)
     got_c = np.array([oracle.lib().orc_bf16_round(float(v)) for v in a[:2000]])
     assert np.array_equal(got_c, ref[:2000])
+
+
+def test_adam_first_step_closed_form():
+    # after one step the bias-corrected moments are g and g^2 exactly:
+    # w1 = w0 - lr g / (|g| + eps)
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.integers(-3, 3, 50)
+    m = np.zeros(50)
+    v = np.zeros(50)
+    w1 = oracle.adam_step(w, g, m, v, 1, lr=1e-3)
+    assert np.allclose(w1, w - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=1e-15)
+
+
+def test_adam_constant_gradient_limit():
+    # with a constant gradient the corrected moments stay g and g^2 at every step
+    g = np.array([2.0, -0.5, 1e-3])
+    w = np.zeros(3)
+    m = np.zeros(3)
+    v = np.zeros(3)
+    for t in range(1, 51):
+        w = oracle.adam_step(w, g, m, v, t, lr=0.01)
+    assert np.allclose(w, -50 * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-10)
