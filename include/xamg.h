@@ -298,6 +298,16 @@ int xamg_cnn_layer(xamg_cnn_t *h, int32_t layer, int32_t mode, const void *in, c
 int xamg_warmstart(xamg_cnn_t *h, xamg_handle_t *solver, const double *B, double *X0, int32_t m,
                    int32_t *fallback);
 
+/* Kernel timer of the network (measurement only): while enabled, every
+ * launch of the selected kernel is bracketed by HIP events on the network's
+ * stream; xamg_cnn_timer_read returns the summed time (ms) and the launch
+ * count since the last enable.  kind: XAMG_CNN_TIMER_OFF,
+ * XAMG_CNN_TIMER_CONV16 (the MFMA 16 -> 16 forward convolutions),
+ * XAMG_CNN_TIMER_WGRAD16 (the 16 x 16 weight-gradient reductions). */
+enum { XAMG_CNN_TIMER_OFF = 0, XAMG_CNN_TIMER_CONV16 = 1, XAMG_CNN_TIMER_WGRAD16 = 2 };
+int xamg_cnn_timer_enable(xamg_cnn_t *h, int32_t kind);
+int xamg_cnn_timer_read(xamg_cnn_t *h, double *ms, int64_t *count);
+
 int xamg_cnn_destroy(xamg_cnn_t *h);
 
 /* Static description of a return code. */

@@ -523,10 +523,46 @@ struct Net : xamg_cnn {
     double *lpart = nullptr, *lacc = nullptr, *scales = nullptr, *sums = nullptr;
     double* cpart = nullptr;   // col_sq partials
     int64_t adam_t = 0;
+    // kernel timer (measurement only): event pairs around the selected launches
+    int timer_kind = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double timer_ms = 0.0;
+    int64_t timer_count = 0;
 
     ~Net()
     {
+        for (hipEvent_t e : ev_pool) hipEventDestroy(e);
         for (void* p : allocs) hipFree(p);
+    }
+    void tbegin(int kind)
+    {
+        if (timer_kind != kind) return;
+        if (ev_used + 2 > ev_pool.size()) {
+            for (int k = 0; k < 64; ++k) {
+                hipEvent_t e;
+                chk(hipEventCreate(&e), "hipEventCreate");
+                ev_pool.push_back(e);
+            }
+        }
+        chk(hipEventRecord(ev_pool[ev_used], stream), "hipEventRecord");
+    }
+    void tend(int kind)
+    {
+        if (timer_kind != kind) return;
+        chk(hipEventRecord(ev_pool[ev_used + 1], stream), "hipEventRecord");
+        ev_used += 2;
+    }
+    // after a stream synchronisation
+    void tcollect()
+    {
+        for (size_t k = 0; k + 1 < ev_used; k += 2) {
+            float ms = 0.0f;
+            chk(hipEventElapsedTime(&ms, ev_pool[k], ev_pool[k + 1]), "hipEventElapsedTime");
+            timer_ms += ms;
+            timer_count += 1;
+        }
+        ev_used = 0;
     }
     void chk(hipError_t e, const char* what)
     {
@@ -560,10 +596,14 @@ struct Net : xamg_cnn {
     {
         hipLaunchKernelGGL(conv_in1, dim3(grid(n)), dim3(256), 0, stream, a0, w1b, a1, N);
         const int nb16 = int((n + 63) / 64);
+        tbegin(XAMG_CNN_TIMER_CONV16);
         hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, a1, pack(0), a2,
                            static_cast<const uint16_t*>(nullptr), 1, N);
+        tend(XAMG_CNN_TIMER_CONV16);
+        tbegin(XAMG_CNN_TIMER_CONV16);
         hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, a2, pack(2), a3,
                            static_cast<const uint16_t*>(nullptr), 1, N);
+        tend(XAMG_CNN_TIMER_CONV16);
         hipLaunchKernelGGL(conv_out1, dim3(grid(n)), dim3(256), 0, stream, a3, w4b, y, N);
     }
 
@@ -579,14 +619,18 @@ struct Net : xamg_cnn {
                            kParams4, g + kParams1 + 2 * kParams2);
         hipLaunchKernelGGL(dgrad_out1, dim3(grid(n)), dim3(256), 0, stream, dy, w4b, a3, g3, N);
         // layer 3: dW3 from (g3, a2); g2 = dgrad masked by a2 > 0
+        tbegin(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g3,
                            static_cast<const float*>(nullptr), a2, N, wpart);
+        tend(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
                            kParams2, g + kParams1 + kParams2);
         hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
         // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
+        tbegin(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g2,
                            static_cast<const float*>(nullptr), a1, N, wpart);
+        tend(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
                            kParams2, g + kParams1);
         hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
@@ -726,6 +770,10 @@ int xamg_cnn_pass(xamg_cnn_t* h, const float* x, const float* t, int32_t S, floa
             *loss = l[0];
         }
         net->chk(hipGetLastError(), "cnn pass");
+        if (net->ev_used) {
+            net->chk(hipStreamSynchronize(net->stream), "sync");
+            net->tcollect();
+        }
     } catch (const xamg::DevFail& f) {
         return f.code;
     }
@@ -891,9 +939,43 @@ int xamg_warmstart(xamg_cnn_t* h, xamg_handle_t* solver, const double* B, double
             for (int j = 0; j < m; ++j) fallback[j] = 0;
         }
         net->chk(hipStreamSynchronize(net->stream), "sync");
+        net->tcollect();
     } catch (const xamg::DevFail& f) {
         return f.code;
     }
+    return XAMG_OK;
+}
+
+int xamg_cnn_timer_enable(xamg_cnn_t* h, int32_t kind)
+{
+    Net* net = static_cast<Net*>(h);
+    if (!net) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (kind < XAMG_CNN_TIMER_OFF || kind > XAMG_CNN_TIMER_WGRAD16)
+        return xamg::fail(XAMG_EINVAL, "timer kind");
+    try {
+        net->chk(hipStreamSynchronize(net->stream), "sync");
+        net->tcollect();
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    net->timer_kind = kind;
+    net->timer_ms = 0.0;
+    net->timer_count = 0;
+    return XAMG_OK;
+}
+
+int xamg_cnn_timer_read(xamg_cnn_t* h, double* ms, int64_t* count)
+{
+    Net* net = static_cast<Net*>(h);
+    if (!net || !ms || !count) return xamg::fail(XAMG_EINVAL, "null argument");
+    try {
+        net->chk(hipStreamSynchronize(net->stream), "sync");
+        net->tcollect();
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    *ms = net->timer_ms;
+    *count = net->timer_count;
     return XAMG_OK;
 }
 

@@ -160,27 +160,59 @@ def uniform_rhs(n, m, seed):
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, m))
 
 
+def gaussian_params(N, m, seed, nsrc=8, wlo=2.0, whi=8.0):
+    """Source parameters of ``gaussian_rhs``: centres (m, nsrc, 3) uniform in
+    [0, N)^3, widths (m, nsrc) uniform in [wlo, whi] cells, amplitudes
+    (m, nsrc) uniform in [-1, 1], drawn from numpy's default_rng(seed) column
+    by column in the order centres, widths, amplitudes."""
+    rng = np.random.default_rng(seed)
+    c = np.empty((m, nsrc, 3))
+    s = np.empty((m, nsrc))
+    a = np.empty((m, nsrc))
+    for j in range(m):
+        c[j] = rng.uniform(0.0, N, size=(nsrc, 3))
+        s[j] = rng.uniform(wlo, whi, size=nsrc)
+        a[j] = rng.uniform(-1.0, 1.0, size=nsrc)
+    return c, s, a
+
+
 def gaussian_rhs(N, m, seed, nsrc=8, wlo=2.0, whi=8.0):
     """Each column is a sum of ``nsrc`` Gaussian sources
-    a * exp(-|x - c|^2 / (2 s^2)) with centres c uniform in [0, N)^3,
-    widths s uniform in [wlo, whi] cells and amplitudes a uniform in [-1, 1].
-    Draw order per column: centres (nsrc x 3), widths, amplitudes."""
-    rng = np.random.default_rng(seed)
+    a * exp(-|x - c|^2 / (2 s^2)) at the cell indices x (lexicographic, x
+    fastest), with the parameters of ``gaussian_params``."""
+    c, s, a = gaussian_params(N, m, seed, nsrc, wlo, whi)
     n = N ** 3
     ax = np.arange(N, dtype=np.float64)
     B = np.empty((n, m))
     for j in range(m):
-        c = rng.uniform(0.0, N, size=(nsrc, 3))
-        s = rng.uniform(wlo, whi, size=nsrc)
-        a = rng.uniform(-1.0, 1.0, size=nsrc)
         col = np.zeros((N, N, N))
         for t in range(nsrc):
-            gx = np.exp(-(ax - c[t, 0]) ** 2 / (2 * s[t] ** 2))
-            gy = np.exp(-(ax - c[t, 1]) ** 2 / (2 * s[t] ** 2))
-            gz = np.exp(-(ax - c[t, 2]) ** 2 / (2 * s[t] ** 2))
-            col += a[t] * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+            gx = np.exp(-(ax - c[j, t, 0]) ** 2 / (2 * s[j, t] ** 2))
+            gy = np.exp(-(ax - c[j, t, 1]) ** 2 / (2 * s[j, t] ** 2))
+            gz = np.exp(-(ax - c[j, t, 2]) ** 2 / (2 * s[j, t] ** 2))
+            col += a[j, t] * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
         B[:, j] = col.ravel()
     return B
+
+
+def gaussian_rhs_torch(N, params, cols, torch, device):
+    """Columns ``cols`` of a Gaussian-source block with parameters from
+    ``gaussian_params``, evaluated with torch (float64) on ``device``:
+    an (n, len(cols)) contiguous tensor.  Same formula as ``gaussian_rhs``
+    (values agree to rounding); used to make large training sets in place."""
+    c, s, a = (torch.as_tensor(v, dtype=torch.float64, device=device) for v in params)
+    ax = torch.arange(N, dtype=torch.float64, device=device)
+    out = torch.empty((N ** 3, len(cols)), dtype=torch.float64, device=device)
+    for k, j in enumerate(cols):
+        col = torch.zeros((N, N, N), dtype=torch.float64, device=device)
+        for t in range(c.shape[1]):
+            den = 2 * s[j, t] ** 2
+            gx = torch.exp(-(ax - c[j, t, 0]) ** 2 / den)
+            gy = torch.exp(-(ax - c[j, t, 1]) ** 2 / den)
+            gz = torch.exp(-(ax - c[j, t, 2]) ** 2 / den)
+            col += a[j, t] * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+        out[:, k] = col.reshape(-1)
+    return out
 
 
 def batched_systems(seed=1004, count=12, sides=BATCH_SIDES, ms=BATCH_MS,

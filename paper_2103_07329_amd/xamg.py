@@ -22,6 +22,7 @@ FP64, MIXED = 0, 1
 X0_ZERO, X0_GIVEN = 0, 1
 OP_A, OP_P, OP_R = 0, 1, 2
 TIMER_OFF, TIMER_KRYLOV_SPMM, TIMER_PRESMOOTH = 0, 1, 2
+CNN_TIMER_OFF, CNN_TIMER_CONV16, CNN_TIMER_WGRAD16 = 0, 1, 2
 
 
 class XamgError(RuntimeError):
@@ -74,7 +75,7 @@ EXPORTS = [
     "xamg_strerror", "xamg_last_error",
     "xamg_cnn_create", "xamg_cnn_get_weights", "xamg_cnn_set_weights", "xamg_cnn_pass",
     "xamg_cnn_get_grads", "xamg_cnn_adam", "xamg_cnn_layer", "xamg_warmstart",
-    "xamg_cnn_destroy",
+    "xamg_cnn_timer_enable", "xamg_cnn_timer_read", "xamg_cnn_destroy",
 ]
 
 CNN_PARAMS = 14688
@@ -129,6 +130,8 @@ def lib():
                                     ctypes.c_float]
         L.xamg_cnn_layer.argtypes = [vp, i32, i32, vp, vp, vp]
         L.xamg_warmstart.argtypes = [vp, vp, vp, vp, i32, ctypes.POINTER(i32)]
+        L.xamg_cnn_timer_enable.argtypes = [vp, i32]
+        L.xamg_cnn_timer_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.xamg_cnn_destroy.argtypes = [vp]
         _lib = L
     return _lib
@@ -168,10 +171,16 @@ class HostHierarchy:
         _check(lib().xamg_hierarchy_view(h, ctypes.byref(self._view)), "xamg_hierarchy_view")
         self.nlev = self._view.nlevels
 
-    def __del__(self):
+    def close(self):
         if getattr(self, "_h", None):
             lib().xamg_hierarchy_free(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def view(self):
         return self._view
@@ -492,6 +501,16 @@ class Cnn:
                 raise ValueError("tensor must be a contiguous GPU tensor")
             return ctypes.c_void_p(t.data_ptr())
         _check(lib().xamg_cnn_layer(self._h, layer, mode, p(inp), p(mask), p(out)), "xamg_cnn_layer")
+
+    def timer_enable(self, kind):
+        _check(lib().xamg_cnn_timer_enable(self._h, kind), "xamg_cnn_timer_enable")
+
+    def timer_read(self):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().xamg_cnn_timer_read(self._h, ctypes.byref(ms), ctypes.byref(cnt)),
+               "xamg_cnn_timer_read")
+        return ms.value, cnt.value
 
     def warmstart(self, B, X0, solver=None):
         """X0 (n, m) from B (n, m), float64 device tensors.  With a solver,
