@@ -256,7 +256,7 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
             launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
         } else {
-            OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(ch.theta), T(ch.c1),
+            OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1),
                                                T(ch.c2), b, X, na};
             launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
@@ -296,7 +296,7 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
                 OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
                 launch_mat<M, CPT>(h, p1, A.template split_of<M>(), L.n, cap);
                 OpChebPost2<M, CPT, T, T, BT, OT, IX, D> p2{
-                    rp, av, ix, dinv, T(ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
+                    rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
                 nb = launch_mat<M, CPT>(h, p2, A.template split_of<M>(), L.n, cap);
             }
         };

@@ -267,7 +267,7 @@ struct OpJacPost {
 
 // ------------------------------------------------------------------------
 // Chebyshev (degree 2) pre-smoothing from x = 0 in one pass:
-//   d0_k = (d_k b_k)/theta gathered on the fly,
+//   d0_k = (d_k b_k) / theta (times a precomputed 1 / theta) gathered on the fly,
 //   x_i = d0_i + (c1 d0_i + c2 (d_i b_i - d_i (A d0)_i))
 // ------------------------------------------------------------------------
 template <int M, int CPT, typename MT, typename T, typename BT, class IdxT>
@@ -279,7 +279,7 @@ struct OpChebPre {
     const MT* val;
     IdxT idx;
     const MT* dinv;
-    MT theta, c1, c2;
+    MT inv_theta, c1, c2;   // 1 / theta, precomputed on the host
     const BT* b;
     T* x;
     const int* nactive;
@@ -287,10 +287,10 @@ struct OpChebPre {
     __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
-        const AT dc = dinv[c];
+        const AT dc = dinv[c] * inv_theta;
         Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) r.v[t] = ((AT(v.v[t]) * dc) / theta);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]) * dc;
         return r;
     }
     template <int ND>
@@ -303,7 +303,7 @@ struct OpChebPre {
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
             const AT r0 = AT(bi.v[t]) * di;
-            const AT d0 = r0 / theta;
+            const AT d0 = r0 * inv_theta;
             const AT r1 = r0 - di * acc[t];
             const AT d1 = c1 * d0 + c2 * r1;
             o.v[t] = T(d0 + d1);
@@ -365,7 +365,7 @@ struct OpChebPost2 {
     const MT* val;
     IdxT idx;
     const MT* dinv;
-    MT theta, c1, c2;
+    MT inv_theta, c1, c2;   // 1 / theta, precomputed on the host
     const T* r0;
     const T* x;
     const BT* b;
@@ -378,7 +378,7 @@ struct OpChebPost2 {
         const auto v = load_pack<T, CPT>(r0 + size_t(c) * M + j0);
         Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) r.v[t] = (AT(v.v[t]) / theta);
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]) * inv_theta;
         return r;
     }
     template <int ND>
@@ -391,7 +391,7 @@ struct OpChebPost2 {
         Pack<OT, CPT> o;
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
-            const AT d0 = AT(ri.v[t]) / theta;
+            const AT d0 = AT(ri.v[t]) * inv_theta;
             const AT r1 = AT(ri.v[t]) - di * acc[t];
             const AT d1 = c1 * d0 + c2 * r1;
             o.v[t] = OT((AT(xi.v[t]) + d0) + d1);
