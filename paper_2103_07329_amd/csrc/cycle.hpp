@@ -493,12 +493,12 @@ void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
 
 // ---------------------------------------------------------------------------
 // autotuner: for every operator of the hierarchy, time the plain SpMM
-// y = Op x with each admissible row split S (lane groups per row) using HIP
+// y = Op x with a row split (lane groups per row, optionally sweeping) using HIP
 // events, and keep the fastest for this column count.  Runs once per M on
 // the first solve (or on request); setup cost, not solve cost.
 // ---------------------------------------------------------------------------
 template <int M, typename T>
-float time_op(Handle& h, const DCsr& d, bool smoothing, int S, const T* x, T* y, T* z,
+float time_op(Handle& h, const DCsr& d, bool smoothing, int split, T* x, T* y, T* z,
               hipEvent_t e0, hipEvent_t e1)
 {
     constexpr int CPT = cpt_for<T, M>();
@@ -512,15 +512,32 @@ float time_op(Handle& h, const DCsr& d, bool smoothing, int S, const T* x, T* y,
             if (smoothing) {
                 OpResid<M, CPT, T, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, z, y,
                                                    nullptr};
-                launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
+                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             } else {
                 OpAx<M, CPT, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, y, nullptr};
-                launch_mat<M, CPT>(h, op, S, d.nr, h.nb_cap);
+                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             }
+        };
+        // Before each timed run: stream through two other work blocks
+        // (Krylov q -> t, n0 x mcap each), so the operator is no longer in
+        // L2 or the memory-side cache, then rewrite the run's input blocks
+        // (zeros), so they are -- as in the V-cycle, where a pass reads the
+        // vectors the previous pass of the level has just written while the
+        // matrix streams from HBM.
+        auto prepare = [&]() {
+            const int mc = h.w.mcap;
+            hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(4096), dim3(256), 0,
+                               h.stream, h.w.q, mc, h.w.t, mc, h.lev[0].n, mc);
+            hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
+                               static_cast<const T*>(nullptr), M, x, M, d.nc, 0);
+            if (smoothing)
+                hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
+                                   static_cast<const T*>(nullptr), M, z, M, d.nr, 0);
         };
         run();
         for (int r = 0; r < 5; ++r) {
             float ms = 0.0f;
+            prepare();
             h.check(hipEventRecord(e0, h.stream), "tune event");
             run();
             h.check(hipEventRecord(e1, h.stream), "tune event");
@@ -533,7 +550,7 @@ float time_op(Handle& h, const DCsr& d, bool smoothing, int S, const T* x, T* y,
 }
 
 template <int M, typename T>
-void tune_matrix(Handle& h, DCsr& d, bool smoothing, const T* x, T* y, T* z, hipEvent_t e0,
+void tune_matrix(Handle& h, DCsr& d, bool smoothing, T* x, T* y, T* z, hipEvent_t e0,
                  hipEvent_t e1)
 {
     constexpr int G = M / cpt_for<T, M>();
@@ -543,10 +560,12 @@ void tune_matrix(Handle& h, DCsr& d, bool smoothing, const T* x, T* y, T* z, hip
     int bestS = 1;
     for (int S : {1, 2, 4, 8}) {
         if (G * S > 64) break;
-        const float t = time_op<M, T>(h, d, smoothing, S, x, y, z, e0, e1);
-        if (S == 1 || t < best) {
-            best = t;
-            bestS = S;
+        for (int sw : {0, kSweep}) {
+            const float t = time_op<M, T>(h, d, smoothing, S | sw, x, y, z, e0, e1);
+            if ((S == 1 && sw == 0) || t < best) {
+                best = t;
+                bestS = S | sw;
+            }
         }
     }
     d.split[k] = bestS;
@@ -570,7 +589,7 @@ void autotune(Handle& h)
     double* z = h.w.p;   // right-hand side of the residual pass (finite: zeroed)
     hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                        nullptr, M, z, M, n0, 0);
-    const float* xf = reinterpret_cast<const float*>(x);
+    float* xf = reinterpret_cast<float*>(x);
     float* yf = reinterpret_cast<float*>(y);
     float* zf = reinterpret_cast<float*>(z);
     for (int l = 0; l < h.nlev; ++l) {

@@ -30,9 +30,9 @@ struct DCsr {
     bool fp32 = false;
     uint16_t* off = nullptr;
     int4* base = nullptr;
-    // lane groups per row (1, 2, 4 or 8) for each column count M = 2^k,
-    // k = 0..5: a mean-row-length guess at upload, replaced by the
-    // autotuner's measured choice
+    // lane groups per row (1, 2, 4 or 8, plus kSweep for a sweeping launch)
+    // for each column count M = 2^k, k = 0..5: a mean-row-length guess at
+    // upload, replaced by the autotuner's measured choice
     int split[6] = {1, 1, 1, 1, 1, 1};
     template <int M>
     int split_of() const
@@ -117,16 +117,23 @@ inline int split_for(int64_t nnz, int nrows)
     return avg > 48.0 ? 8 : (avg > 24.0 ? 4 : 1);
 }
 
+// A row split value is S (1, 2, 4 or 8 lane groups per row) plus kSweep
+// when the launch uses at most `cap` blocks that sweep their XCD's slab of
+// tiles instead of one block per tile (better L2 reuse of the gathered
+// vector on some operators; the autotuner decides per operator).
+constexpr int kSweep = 16;
+
 template <int M, int CPT, int S, class Op>
-int launch_rows_s(Handle& h, const Op& op, int nrows, int cap)
+int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = false)
 {
     constexpr int G = M / CPT;
     constexpr int RPB = dev::kBlock / (G * S);
     const int ntiles = (nrows + RPB - 1) / RPB;
-    // kernels without dot products get one tile per block; kernels with
-    // dots keep at most `cap` blocks so their partial sums stay few
-    int nb = std::max(1, Op::kDots == 0 ? ntiles : std::min(ntiles, cap));
-    if (Op::kDots > 0 && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
+    // one tile per block, unless the kernel has dot products (at most `cap`
+    // blocks so their partial sums stay few) or the operator sweeps
+    const bool capped = Op::kDots > 0 || sweep;
+    int nb = std::max(1, capped ? std::min(ntiles, cap) : ntiles);
+    if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
                        h.stream, op, nrows, h.part);
     return nb;
@@ -139,21 +146,23 @@ int launch_rows(Handle& h, const Op& op, int nrows, int cap)
     return launch_rows_s<M, CPT, 1>(h, op, nrows, cap);
 }
 
-// operation over the rows of matrix d, with d's row split
+// operation over the rows of matrix d, with d's row split (see kSweep)
 template <int M, int CPT, class Op>
 int launch_mat(Handle& h, const Op& op, int split, int nrows, int cap)
 {
     constexpr int G = M / CPT;
+    const bool sweep = (split & kSweep) != 0;
+    const int s = split & (kSweep - 1);
     if constexpr (G * 8 <= 64) {
-        if (split >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap);
+        if (s >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap, sweep);
     }
     if constexpr (G * 4 <= 64) {
-        if (split >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap);
+        if (s >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap, sweep);
     }
     if constexpr (G * 2 <= 64) {
-        if (split >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap);
+        if (s >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap, sweep);
     }
-    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap);
+    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap, sweep);
 }
 
 template <class Fin>
