@@ -210,20 +210,22 @@ int xamg_solve_batched(xamg_batch_t *b, const double *const *B, double *const *X
 int xamg_batch_destroy(xamg_batch_t *b);
 
 /* Autotuner (Section 2.2's kernels, tuned for this device): for each
- * operator A_l, P_l, R_l of the copy the V-cycle uses, time the SpMM for
- * m columns with 1, 2, 4 and 8 lane groups splitting a row's nonzeros, each
- * with one block per tile of rows or with a sweeping launch (at most 2048
- * blocks, each XCD's blocks walking its slab of tiles together), with HIP
- * events on the solver's stream, and keep the fastest.  Runs by itself
+ * operator A_l, P_l, R_l of the copy the V-cycle uses (A_l twice: on the
+ * residual pass and on the pre-smoothing pass, which gathers b and D^-1),
+ * time the SpMM for m columns with 1, 2, 4 and 8 lane groups splitting a
+ * row's nonzeros, each with one block per tile of rows or with a sweeping
+ * launch (at most 2048 blocks, each XCD's blocks walking its slab of tiles
+ * together), with HIP events on the solver's stream, and keep the fastest.  Runs by itself
  * on the first solve for each padded m; this call re-runs it now (enable
  * = 1) or switches automatic tuning off (enable = 0; the setup-time
  * row-length heuristic stays in use).  m in {1, 2, 4, 8, 16, 32}. */
 int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
 
-/* Row splits in use for m columns: out[3l .. 3l+2] = split of A_l, P_l,
- * R_l (0 where the operator does not exist): the lane groups per row (1,
- * 2, 4, 8) plus 16 when the operator uses the sweeping launch.
- * cap >= 3 * nlevels. */
+/* Row splits in use for m columns: out[4l .. 4l+3] = split of A_l (the
+ * residual and post-smoothing passes), of A_l's pre-smoothing pass, of P_l
+ * and of R_l (0 where the operator or pass does not exist): the lane groups
+ * per row (1, 2, 4, 8) plus 16 when the pass uses the sweeping launch.
+ * cap >= 4 * nlevels. */
 int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
 
 /* Kernel timer: while enabled, every launch of the selected kernel during

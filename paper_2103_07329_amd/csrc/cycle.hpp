@@ -253,12 +253,12 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
         if (l == 0) h.timer_begin(XAMG_TIMER_PRESMOOTH);
         if (!cheb2) {
             OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
-            launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
+            launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
         } else {
             OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1),
                                                T(ch.c2), b, X, na};
-            launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
+            launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
             OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
             launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
@@ -497,24 +497,31 @@ void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
 // events, and keep the fastest for this column count.  Runs once per M on
 // the first solve (or on request); setup cost, not solve cost.
 // ---------------------------------------------------------------------------
+// kind: 0 = residual pass r = b - A x (the post-smoothing and residual
+// passes gather x), 1 = plain product y = Op x (transfer operators),
+// 2 = pre-smoothing pass from zero (gathers b and D^-1)
 template <int M, typename T>
-float time_op(Handle& h, const DCsr& d, bool smoothing, int split, T* x, T* y, T* z,
+float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x, T* y, T* z,
               hipEvent_t e0, hipEvent_t e1)
 {
     constexpr int CPT = cpt_for<T, M>();
     float best = 0.0f;
     with_idx(d, [&](auto ix) {
         using IX = decltype(ix);
-        // the square operators are timed on the residual pass r = b - A x
-        // (gathers x, reads b, writes r: the access pattern of the smoothing
-        // passes); transfer operators on the plain product y = Op x
         auto run = [&]() {
-            if (smoothing) {
-                OpResid<M, CPT, T, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, z, y,
-                                                   nullptr};
+            const T* av = static_cast<const T*>(d.v);
+            if (kind == 0) {
+                OpResid<M, CPT, T, T, T, IX, 0> op{d.rp, av, ix, x, z, y, nullptr};
+                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
+            } else if (kind == 1) {
+                OpAx<M, CPT, T, T, IX, 0> op{d.rp, av, ix, x, y, nullptr};
+                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
+            } else if (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) {
+                OpChebPre<M, CPT, T, T, T, IX> op{d.rp, av, ix, dinv, T(1), T(0), T(0), x, y,
+                                                  nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             } else {
-                OpAx<M, CPT, T, T, IX, 0> op{d.rp, static_cast<const T*>(d.v), ix, x, y, nullptr};
+                OpJacPre<M, CPT, T, T, T, IX> op{d.rp, av, ix, dinv, T(0.5), x, y, z, nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             }
         };
@@ -530,7 +537,7 @@ float time_op(Handle& h, const DCsr& d, bool smoothing, int split, T* x, T* y, T
                                h.stream, h.w.q, mc, h.w.t, mc, h.lev[0].n, mc);
             hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
                                static_cast<const T*>(nullptr), M, x, M, d.nc, 0);
-            if (smoothing)
+            if (kind == 0)
                 hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
                                    static_cast<const T*>(nullptr), M, z, M, d.nr, 0);
         };
@@ -550,7 +557,7 @@ float time_op(Handle& h, const DCsr& d, bool smoothing, int split, T* x, T* y, T
 }
 
 template <int M, typename T>
-void tune_matrix(Handle& h, DCsr& d, bool smoothing, T* x, T* y, T* z, hipEvent_t e0,
+void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, hipEvent_t e0,
                  hipEvent_t e1)
 {
     constexpr int G = M / cpt_for<T, M>();
@@ -561,14 +568,14 @@ void tune_matrix(Handle& h, DCsr& d, bool smoothing, T* x, T* y, T* z, hipEvent_
     for (int S : {1, 2, 4, 8}) {
         if (G * S > 64) break;
         for (int sw : {0, kSweep}) {
-            const float t = time_op<M, T>(h, d, smoothing, S | sw, x, y, z, e0, e1);
+            const float t = time_op<M, T>(h, d, kind, dinv, S | sw, x, y, z, e0, e1);
             if ((S == 1 && sw == 0) || t < best) {
                 best = t;
                 bestS = S | sw;
             }
         }
     }
-    d.split[k] = bestS;
+    (kind == 2 ? d.split_pre : d.split)[k] = bestS;
 }
 
 template <int M>
@@ -594,15 +601,20 @@ void autotune(Handle& h)
     float* zf = reinterpret_cast<float*>(z);
     for (int l = 0; l < h.nlev; ++l) {
         auto& L = h.lev[l];
-        if (l == 0 || !mixed) tune_matrix<M, double>(h, L.A64, true, x, y, z, e0, e1);
-        if (l + 1 < h.nlev) {
+        const bool last = l + 1 == h.nlev;
+        if (l == 0 || !mixed) {
+            tune_matrix<M, double>(h, L.A64, 0, L.dinv64, x, y, z, e0, e1);
+            if (!last && !mixed) tune_matrix<M, double>(h, L.A64, 2, L.dinv64, x, y, z, e0, e1);
+        }
+        if (!last) {
             if (!mixed) {
-                tune_matrix<M, double>(h, L.P64, false, x, y, z, e0, e1);
-                tune_matrix<M, double>(h, L.R64, false, x, y, z, e0, e1);
+                tune_matrix<M, double>(h, L.P64, 1, L.dinv64, x, y, z, e0, e1);
+                tune_matrix<M, double>(h, L.R64, 1, L.dinv64, x, y, z, e0, e1);
             } else {
-                tune_matrix<M, float>(h, L.A32, true, xf, yf, zf, e0, e1);
-                tune_matrix<M, float>(h, L.P32, false, xf, yf, zf, e0, e1);
-                tune_matrix<M, float>(h, L.R32, false, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.A32, 0, L.dinv32, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.A32, 2, L.dinv32, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.P32, 1, L.dinv32, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.R32, 1, L.dinv32, xf, yf, zf, e0, e1);
             }
         }
     }

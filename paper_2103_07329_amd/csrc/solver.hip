@@ -116,7 +116,7 @@ static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
     d.nr = int(c.nrows);
     d.nc = int(c.ncols);
     d.nnz = c.nnz;
-    for (int k = 0; k < 6; ++k) d.split[k] = split_for(c.nnz, int(c.nrows));
+    for (int k = 0; k < 6; ++k) d.split[k] = d.split_pre[k] = split_for(c.nnz, int(c.nrows));
     d.rp = upload(h, c.row_ptr, size_t(c.nrows) + 1);
     d.ci = upload(h, c.col, size_t(c.nnz));
     if (fp32) {
@@ -613,7 +613,7 @@ int xamg_tuning(const xamg_handle_t* hh, int32_t m, int32_t* out, int32_t cap)
     if (!h || !out) return xamg::fail(XAMG_EINVAL, "null argument");
     if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
         return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
-    if (cap < 3 * h->nlev) return xamg::fail(XAMG_EINVAL, "output too short");
+    if (cap < 4 * h->nlev) return xamg::fail(XAMG_EINVAL, "output too short");
     int k = 0;
     while ((1 << k) < m) ++k;
     const bool mixed = h->opt.precision == XAMG_MIXED;
@@ -621,9 +621,10 @@ int xamg_tuning(const xamg_handle_t* hh, int32_t m, int32_t* out, int32_t cap)
         const auto& L = h->lev[l];
         const bool last = l + 1 == h->nlev;
         const xamg::DCsr& A = (mixed && !last) ? L.A32 : L.A64;
-        out[3 * l] = A.split[k];
-        out[3 * l + 1] = last ? 0 : (mixed ? L.P32 : L.P64).split[k];
-        out[3 * l + 2] = last ? 0 : (mixed ? L.R32 : L.R64).split[k];
+        out[4 * l] = A.split[k];
+        out[4 * l + 1] = last ? 0 : A.split_pre[k];
+        out[4 * l + 2] = last ? 0 : (mixed ? L.P32 : L.P64).split[k];
+        out[4 * l + 3] = last ? 0 : (mixed ? L.R32 : L.R64).split[k];
     }
     return XAMG_OK;
 }

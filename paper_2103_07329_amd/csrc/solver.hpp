@@ -34,10 +34,18 @@ struct DCsr {
     // for each column count M = 2^k, k = 0..5: a mean-row-length guess at
     // upload, replaced by the autotuner's measured choice
     int split[6] = {1, 1, 1, 1, 1, 1};
+    // the same for the pre-smoothing pass of a square operator, which
+    // gathers b and D^-1 instead of x and is tuned on its own
+    int split_pre[6] = {1, 1, 1, 1, 1, 1};
     template <int M>
     int split_of() const
     {
         return split[M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5];
+    }
+    template <int M>
+    int split_pre_of() const
+    {
+        return split_pre[M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5];
     }
 };
 

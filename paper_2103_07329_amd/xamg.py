@@ -337,9 +337,10 @@ class Solver:
         _check(lib().xamg_autotune(self._h, m, 1 if enable else 0), "xamg_autotune")
 
     def tuning(self, m):
-        out = (ctypes.c_int32 * (3 * self.nlev))()
+        """Per level (A, A pre-smoothing, P, R) row splits (see xamg_tuning)."""
+        out = (ctypes.c_int32 * (4 * self.nlev))()
         _check(lib().xamg_tuning(self._h, m, out, len(out)), "xamg_tuning")
-        return [tuple(out[3 * l:3 * l + 3]) for l in range(self.nlev)]
+        return [tuple(out[4 * l:4 * l + 4]) for l in range(self.nlev)]
 
     def timer_enable(self, kind):
         _check(lib().xamg_timer_enable(self._h, kind), "xamg_timer_enable")
