@@ -382,7 +382,7 @@ void pcg_precondition(Handle& h)
     launch_rows<M, CPT>(h, up, h.lev[0].n, h.nb_cap);
 }
 
-// r = b - A x, column state, z = M^-1 r, p = z
+// r = b - A x, column state (the first iteration computes z = M^-1 r, p = z)
 template <int M>
 void pcg_start(Handle& h, const double* B, double* X, double tol)
 {
@@ -407,10 +407,12 @@ void pcg_start(Handle& h, const double* B, double* X, double tol)
     if (pcg_flex<M>(h))
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                            nullptr, M, h.w.q, M, n, 0);
-    pcg_precondition<M>(h);
 }
 
-// one iteration: q = A p, alpha, x += alpha p, r -= alpha q, test, z, beta, p
+// one iteration: z = M^-1 r, beta, p = z + beta p (beta = 0 on a column's
+// first or restarted iteration), q = A p, alpha, x += alpha p,
+// r -= alpha q, convergence test.  The test comes last, so no
+// preconditioner runs after the last column has converged.
 template <int M>
 void pcg_iteration(Handle& h, double* X)
 {
@@ -419,6 +421,7 @@ void pcg_iteration(Handle& h, double* X)
     const DCsr& A = h.lev[0].A64;
     const double* av = static_cast<const double*>(A.v);
     ColState* st = h.st;
+    pcg_precondition<M>(h);
     {
         OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, h.w.p, h.w.q,
                                                    &st->nactive};
@@ -432,12 +435,11 @@ void pcg_iteration(Handle& h, double* X)
         const int nb = launch_rows<M, CPT>(h, op, n, h.nb_cap);
         launch_fin(h, nb, M, FinRR{st, M});
     }
-    pcg_precondition<M>(h);
 }
 
 // true residual of the columns the recurrence froze; columns that fail it
-// restart (r = b - A x, z = M^-1 r, p = z).  Synchronises; returns the
-// number of restarted columns.
+// restart (r = b - A x; their next iteration takes z = M^-1 r, p = z).
+// Synchronises; returns the number of restarted columns.
 template <int M>
 int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
 {
@@ -454,7 +456,6 @@ int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
     if (nr > 0) {
         OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.r, h.w.t, nullptr};
         launch_rows<M, CPT>(h, cp, n, h.nb_cap);
-        pcg_precondition<M>(h);
     }
     return nr;
 }
