@@ -24,7 +24,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EBREAKDOWN = 0, 1, -1, -2, -5
 CG, BICGSTAB = 0, 1
-JACOBI, CHEBYSHEV = 0, 1
+JACOBI, CHEBYSHEV, GAUSS_SEIDEL = 0, 1, 2
 A_, P_, R_ = 0, 1, 2
 
 
@@ -62,10 +62,14 @@ def lib():
         L.orc_hier_lmax.argtypes = [_vp, _c_int]
         L.orc_hier_lmax.restype = _c_dbl
         L.orc_vcycle.argtypes = [_vp, _c_int, _c_dbl, _c_int, _c_dbl, _c_dbl,
-                                 _c_int, _f64p, _f64p]
+                                 _c_int, _c_int, _f64p, _f64p]
         L.orc_solve.argtypes = [_vp, _c_int, _c_int, _c_dbl, _c_int, _c_dbl,
-                                _c_dbl, _c_int, _c_int, _c_int, _c_dbl, _c_int,
-                                _c_int, _f64p, _f64p, _i32p, _f64p, _f64p, _i32p]
+                                _c_dbl, _c_int, _c_int, _c_int, _c_int, _c_dbl,
+                                _c_int, _c_int, _f64p, _f64p, _i32p, _f64p, _f64p,
+                                _i32p]
+        L.orc_hgs_sweep.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_int, _c_int,
+                                    _c_int, _f64p, _f64p, _f64p]
+        L.orc_hgs_sweep.restype = None
         L.orc_spmm.argtypes = [_c_int, _c_int, _i32p, _i32p, _f64p, _c_int,
                                _f64p, _f64p]
         L.orc_jacobi.argtypes = [_c_int, _i32p, _i32p, _f64p, _f64p, _c_dbl,
@@ -247,19 +251,19 @@ class Hierarchy:
         }
 
     def vcycle(self, B, smoother=JACOBI, omega=2.0 / 3.0, degree=2,
-               lo_frac=0.3, hi_frac=1.1):
+               lo_frac=0.3, hi_frac=1.1, gs_block=8):
         B = np.ascontiguousarray(B, np.float64)
         vec = B.ndim == 1
         if vec:
             B = B[:, None].copy()
         X = np.zeros_like(B)
         lib().orc_vcycle(self._h, smoother, omega, degree, lo_frac, hi_frac,
-                         B.shape[1], B, X)
+                         gs_block, B.shape[1], B, X)
         return X[:, 0] if vec else X
 
     def solve(self, B, X0=None, method=CG, smoother=JACOBI, omega=2.0 / 3.0,
               degree=2, lo_frac=0.3, hi_frac=1.1, flexible=False, precond=True,
-              max_iters=1000, tol=1e-8):
+              max_iters=1000, tol=1e-8, gs_block=8):
         """Returns (X, stats dict, return code)."""
         B = np.ascontiguousarray(B, np.float64)
         vec = B.ndim == 1
@@ -277,7 +281,7 @@ class Hierarchy:
         tr = np.zeros(m)
         cv = np.zeros(m, np.int32)
         rc = lib().orc_solve(self._h, method, smoother, omega, degree, lo_frac,
-                             hi_frac, int(flexible), int(precond), max_iters,
+                             hi_frac, gs_block, int(flexible), int(precond), max_iters,
                              tol, given, m, B, X, it, rr, tr, cv)
         st = {"iters": it, "relres": rr, "true_relres": tr,
               "converged": cv.astype(bool)}
@@ -288,6 +292,19 @@ class Hierarchy:
 # bias-free 3D CNN (learned warm start)
 # --------------------------------------------------------------------------
 CNN_LAYERS = ((1, 16), (16, 16), (16, 16), (16, 1))   # (cin, cout); ReLU after 1-3
+
+
+def hgs_sweep(rp, ci, v, B, backward, b, xo):
+    """One l1-hybrid Gauss-Seidel sweep (blocks of B rows) from xo: returns xn."""
+    rp, ci, v = _csr(rp, ci, v)
+    b = np.ascontiguousarray(b, np.float64)
+    vec = b.ndim == 1
+    b2 = b[:, None] if vec else b
+    xo2 = np.ascontiguousarray(np.asarray(xo, np.float64).reshape(b2.shape))
+    xn = np.empty_like(b2)
+    lib().orc_hgs_sweep(rp.size - 1, rp, ci, v, int(B), int(backward), b2.shape[1],
+                        np.ascontiguousarray(b2), xo2, xn)
+    return xn[:, 0] if vec else xn
 
 
 def conv3d_fwd(N, W, x):

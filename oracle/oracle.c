@@ -18,6 +18,11 @@
  *    a dense LU (the paper's "direct" method, Section 2.1, Table 1).
  *  - Jacobi and Chebyshev smoothers (Section 2.1, Table 1); Chebyshev with
  *    polynomial order 2 as in the configuration example of Section 2.4.
+ *  - Symmetric Gauss-Seidel (Section 2.1, Table 1; the smoother of the runs
+ *    of Section 3.1, "hybrid symmetric Gauss-Seidel") in its l1-hybrid form:
+ *    Gauss-Seidel inside blocks of consecutive rows, Jacobi across blocks,
+ *    with the l1 diagonal of Baker, Falgout, Kolev and Yang, "Multigrid
+ *    smoothers for ultraparallel computing", SISC 33 (2011).
  *  - V(1,1) cycle as the preconditioner of CG (Hestenes-Stiefel) or of
  *    right-preconditioned BiCGStab (van der Vorst), both cited in Section 2.1.
  *
@@ -723,11 +728,12 @@ double orc_hier_lmax(const ohier *h, int l) { return h->lmax[l]; }
 /* Smoothers (on D^-1 A)                                                     */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    int smoother;      /* 0 = Jacobi, 1 = Chebyshev */
+    int smoother;      /* 0 = Jacobi, 1 = Chebyshev, 2 = l1-hybrid symmetric GS */
     double omega;      /* Jacobi damping */
     int degree;        /* Chebyshev degree */
     double lo_frac;    /* Chebyshev interval [lo_frac*hi, hi] */
     double hi_frac;    /* hi = hi_frac * lambda_max estimate */
+    int gs_block;      /* Gauss-Seidel block size (rows) */
 } smopt;
 
 /* damped Jacobi: x <- x + omega D^-1 (b - A x); t is an n x m temporary */
@@ -791,6 +797,55 @@ static void chebyshev(const ocsr *a, const double *dinv, double lo, double hi,
     }
 }
 
+/*
+ * l1-hybrid Gauss-Seidel sweep (Baker, Falgout, Kolev, Yang 2011).  The rows
+ * are cut into blocks of B consecutive rows; block k holds rows
+ * [kB, min(n, kB + B)).  With d_i = a_ii + sum over j outside i's block of
+ * |a_ij|, one forward sweep computes, row by row in increasing order inside
+ * each block (the blocks are independent of each other),
+ *   xn_i = xo_i + (b_i - sum_{j in block, j < i} a_ij xn_j
+ *                      - sum_{all other j} a_ij xo_j) / d_i,
+ * i.e. Gauss-Seidel inside a block and Jacobi (old values) across blocks;
+ * the backward sweep runs each block's rows in decreasing order and uses the
+ * new values of the rows j > i of the block.  xo and xn are n x m and must
+ * not overlap.  With B >= n this is plain Gauss-Seidel; with B = 1 it is
+ * l1-Jacobi.
+ */
+static void hgs_sweep(const ocsr *a, int B, int backward, int m, const double *b,
+                      const double *xo, double *xn)
+{
+    int n = a->nr, nblk = (n + B - 1) / B, blk;
+#pragma omp parallel for schedule(static)
+    for (blk = 0; blk < nblk; blk++) {
+        int lo = blk * B, hi = lo + B < n ? lo + B : n, s, j;
+        for (s = 0; s < hi - lo; s++) {
+            int i = backward ? hi - 1 - s : lo + s, k;
+            double d = 0.0;
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int c = a->ci[k];
+                if (c == i) d += a->v[k];
+                else if (c < lo || c >= hi) d += fabs(a->v[k]);
+            }
+            for (j = 0; j < m; j++) {
+                double acc = 0.0;
+                for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                    int c = a->ci[k];
+                    int fresh = c >= lo && c < hi && (backward ? c > i : c < i);
+                    acc += a->v[k] * (fresh ? xn[(size_t)c * m + j] : xo[(size_t)c * m + j]);
+                }
+                xn[(size_t)i * m + j] = xo[(size_t)i * m + j] + (b[(size_t)i * m + j] - acc) / d;
+            }
+        }
+    }
+}
+
+/* symmetric sweep: forward from x into t, then backward from t into x */
+static void hgs_symmetric(const ocsr *a, int B, int m, const double *b, double *x, double *t)
+{
+    hgs_sweep(a, B, 0, m, b, x, t);
+    hgs_sweep(a, B, 1, m, b, t, x);
+}
+
 /* ------------------------------------------------------------------------ */
 /* V(1,1) cycle from a zero initial guess:                                   */
 /*   pre-smooth, r = b - A x, b_c = R r, recurse (coarsest: direct LU),      */
@@ -835,6 +890,8 @@ static void smooth(const ohier *h, int l, const smopt *so, int m, const double *
 {
     if (so->smoother == 0)
         jacobi(&h->A[l], h->dinv[l], so->omega, m, b, x, w->t[l]);
+    else if (so->smoother == 2)
+        hgs_symmetric(&h->A[l], so->gs_block, m, b, x, w->t[l]);
     else
         chebyshev(&h->A[l], h->dinv[l], so->lo_frac * so->hi_frac * h->lmax[l],
                   so->hi_frac * h->lmax[l], so->degree, m, b, x, w->r[l], w->d[l],
@@ -871,10 +928,11 @@ static void vcycle_level(const ohier *h, int l, const smopt *so, int m,
 }
 
 int orc_vcycle(const ohier *h, int smoother, double omega, int degree,
-               double lo_frac, double hi_frac, int m, const double *b, double *x)
+               double lo_frac, double hi_frac, int gs_block, int m, const double *b, double *x)
 {
     vws w;
-    smopt so = {smoother, omega, degree, lo_frac, hi_frac};
+    smopt so = {smoother, omega, degree, lo_frac, hi_frac, gs_block};
+    if (smoother == 2 && gs_block < 1) return ORC_EINVAL;
     if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
     vcycle_level(h, 0, &so, m, b, x, &w);
     vws_free(&w, h->nlev);
@@ -1228,17 +1286,17 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
  * relative residual, true relative residual, converged flag.
  */
 int orc_solve(const ohier *h, int method, int smoother, double omega, int degree,
-              double lo_frac, double hi_frac, int flexible, int precond,
+              double lo_frac, double hi_frac, int gs_block, int flexible, int precond,
               int max_iters, double tol, int x0_given, int m, const double *B,
               double *X, int *iters, double *relres, double *true_relres, int *conv)
 {
     vws w;
     kopt ko = {method, flexible, max_iters, tol, x0_given, precond};
-    smopt so = {smoother, omega, degree, lo_frac, hi_frac};
+    smopt so = {smoother, omega, degree, lo_frac, hi_frac, gs_block};
     int rc, j, n = h->A[0].nr;
     size_t q, nm = (size_t)n * m;
     double *t;
-    if (m < 1) return ORC_EINVAL;
+    if (m < 1 || (smoother == 2 && gs_block < 1)) return ORC_EINVAL;
     for (q = 0; q < nm; q++) if (!isfinite(B[q])) return ORC_EINVAL;
     if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
     if (method == 0) rc = pcg(h, &ko, &so, m, B, X, iters, relres, conv, &w);
@@ -1293,6 +1351,14 @@ void orc_chebyshev(int n, const int *rp, const int *ci, const double *v,
     a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
     chebyshev(&a, dinv, lo, hi, degree, m, b, x, r, d, t);
     free(r); free(d); free(t);
+}
+
+void orc_hgs_sweep(int n, const int *rp, const int *ci, const double *v, int B,
+                   int backward, int m, const double *b, const double *xo, double *xn)
+{
+    ocsr a;
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    hgs_sweep(&a, B, backward, m, b, xo, xn);
 }
 
 double orc_lanczos(int n, const int *rp, const int *ci, const double *v, int steps,

@@ -310,7 +310,7 @@ def test_lanczos_estimate(orc, N):
 # --------------------------------------------------------------------------
 # V-cycle
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
 @pytest.mark.parametrize("k", [0, 2])
 def test_vcycle_symmetric_positive(orc, smoother, k):
     p = _problems_small()[k]
@@ -330,7 +330,7 @@ def test_vcycle_is_contraction(orc):
     p = inputs.poisson7(10)
     A = dense(*p.csr())
     H = orc.Hierarchy(*p.csr(), max_coarse=20)
-    for smoother in (0, 1):
+    for smoother in (0, 1, 2):
         MA = H.vcycle(A, smoother=smoother)        # columns: M A e_i
         E = np.eye(p.n) - MA
         L = np.linalg.cholesky(A)
@@ -355,7 +355,7 @@ def test_one_level_pcg_one_iteration(orc):
 
 
 @pytest.mark.parametrize("method", [0, 1])
-@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
 @pytest.mark.parametrize("k", [0, 1, 2])
 def test_krylov_dense_bruteforce(orc, method, smoother, k):
     p = _problems_small()[k]
@@ -402,7 +402,7 @@ def test_cg_eigenvector_one_iteration(orc):
         assert np.allclose(x, v / lam, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("method,smoother", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("method,smoother", [(0, 0), (0, 1), (1, 0), (1, 1), (0, 2), (1, 2)])
 def test_column_independence_bitwise(orc, method, smoother):
     p = inputs.poisson7(12)
     H = orc.Hierarchy(*p.csr())
@@ -539,12 +539,15 @@ def test_direct_interpolation_positive_offdiagonals(orc):
     assert npos > 20
 
 
-@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
 def test_two_grid_error_operator(orc, smoother):
     """With two levels the cycle's error propagation is the closed form
     E = S (I - P A_c^{-1} P^T A) S, S the smoother's error operator:
     Jacobi S = I - w D^-1 A; Chebyshev degree 2 on [lo, hi]:
-    S = T_2((theta I - D^-1 A)/delta) / T_2(theta/delta)."""
+    S = T_2((theta I - D^-1 A)/delta) / T_2(theta/delta); symmetric
+    l1-hybrid Gauss-Seidel (blocks of 8 rows): S = (I - Mb^-1 A)(I - Mf^-1 A)
+    with Mf = D_l1 + (in-block strictly lower part), Mb = D_l1 + (in-block
+    strictly upper part)."""
     p = inputs.jump7(6, inputs.jump_kappa(6, np.random.default_rng(3), block=2))
     H = orc.Hierarchy(*p.csr(), max_coarse=200)
     assert H.nlev == 2
@@ -555,6 +558,9 @@ def test_two_grid_error_operator(orc, smoother):
     I = np.eye(p.n)
     if smoother == 0:
         S = I - (2.0 / 3.0) * DA
+    elif smoother == 2:
+        Mf, Mb = _hgs_splitting(A, 8)
+        S = (I - np.linalg.solve(Mb, A)) @ (I - np.linalg.solve(Mf, A))
     else:
         hi = 1.1 * H.lmax(0); lo = 0.3 * hi
         th, de = (hi + lo) / 2, (hi - lo) / 2
@@ -563,6 +569,21 @@ def test_two_grid_error_operator(orc, smoother):
     E = S @ (I - P @ np.linalg.solve(Ac, P.T @ A)) @ S
     MA = H.vcycle(A, smoother=smoother)
     assert np.allclose(I - MA, E, rtol=0, atol=1e-11)
+
+
+def _hgs_splitting(A, B):
+    """Forward / backward matrices of the l1-hybrid Gauss-Seidel sweep with
+    blocks of B consecutive rows, from their definition: D_l1 = diag(a_ii +
+    sum_{j outside the block} |a_ij|), plus the in-block strictly lower
+    (forward) or upper (backward) entries of A."""
+    n = A.shape[0]
+    blk = np.arange(n) // B
+    same = blk[:, None] == blk[None, :]
+    off = np.where(same, 0.0, np.abs(A)).sum(axis=1)
+    D = np.diag(np.diag(A) + off)
+    L = np.tril(np.where(same, A, 0.0), -1)
+    U = np.triu(np.where(same, A, 0.0), 1)
+    return D + L, D + U
 
 
 def _lognormal_graph_laplacian(n, seed, dens=0.05, sigma=2.0):
