@@ -52,7 +52,7 @@ extern "C" {
 
 /* ---- enums --------------------------------------------------------------- */
 enum { XAMG_CG = 0, XAMG_BICGSTAB = 1 };
-enum { XAMG_JACOBI = 0, XAMG_CHEBYSHEV = 1 };
+enum { XAMG_JACOBI = 0, XAMG_CHEBYSHEV = 1, XAMG_GAUSS_SEIDEL = 2 };
 enum { XAMG_FP64 = 0, XAMG_MIXED = 1 };
 enum { XAMG_X0_ZERO = 0, XAMG_X0_GIVEN = 1 };
 enum { XAMG_OP_A = 0, XAMG_OP_P = 1, XAMG_OP_R = 2 };
@@ -88,7 +88,14 @@ typedef struct {
 /* Solver options. */
 typedef struct {
     int32_t method;        /* XAMG_CG (default) or XAMG_BICGSTAB */
-    int32_t smoother;      /* XAMG_JACOBI (default) or XAMG_CHEBYSHEV */
+    int32_t smoother;      /* XAMG_JACOBI (default), XAMG_CHEBYSHEV or XAMG_GAUSS_SEIDEL:
+                              symmetric Gauss-Seidel (Section 2.1, Table 1; the
+                              smoother of Section 3.1) in its l1-hybrid form --
+                              Gauss-Seidel inside blocks of gs_block consecutive
+                              rows, Jacobi across blocks, diagonal a_ii plus the
+                              absolute couplings to other blocks (Baker et al.,
+                              SISC 2011); one forward and one backward sweep per
+                              smoothing step */
     double omega;          /* Jacobi damping, default 2/3 */
     int32_t cheby_degree;  /* Chebyshev polynomial degree, 1 or 2 (default 2) */
     double cheby_lo_frac;  /* interval [lo_frac * hi, hi], default 0.3 */
@@ -99,6 +106,7 @@ typedef struct {
     int32_t x0_mode;       /* XAMG_X0_ZERO (default) or XAMG_X0_GIVEN */
     int32_t flexible;      /* CG beta: 0 Fletcher-Reeves, 1 flexible; MIXED forces 1 */
     int32_t check_every;   /* host convergence poll period in iterations, default 1 */
+    int32_t gs_block;      /* Gauss-Seidel block size in rows: 4, 8 (default) or 16 */
     void *stream;          /* hipStream_t for all work; NULL = the null stream */
 } xamg_options_t;
 

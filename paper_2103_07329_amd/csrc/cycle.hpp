@@ -208,6 +208,62 @@ static void with_idx(const DCsr& d, F&& f)
 template <typename T>
 static T* lvbuf(void* p) { return static_cast<T*>(p); }
 
+template <typename T>
+static const T* dl1_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dl1inv64; else return L.dl1inv32; }
+
+// one l1-hybrid Gauss-Seidel sweep over the rows of A (block size from the
+// options: 4, 8 or 16 rows)
+template <int M, bool BWD, bool ZERO, typename MT, typename XT, typename BT, typename OT>
+static void launch_hgs(Handle& h, const DCsr& A, const MT* dl1, const BT* b, const XT* xo, OT* xn,
+                       const int* na)
+{
+    constexpr int CPT = cpt_for<MT, M>();
+    constexpr int NG = kGsThreads / (M / CPT);
+    const int n = A.nr;
+    const MT* av = static_cast<const MT*>(A.v);
+    auto go = [&](auto blk) {
+        constexpr int BLK = decltype(blk)::value;
+        const int nblk = (n + BLK - 1) / BLK;
+        const int grid = std::max(1, (nblk + NG - 1) / NG);
+        hipLaunchKernelGGL((hgs_kernel<M, CPT, BLK, BWD, ZERO, MT, XT, BT, OT>), dim3(grid),
+                           dim3(kGsThreads), 0, h.stream, A.rp, A.ci, av, dl1, b, xo, xn, n, na);
+    };
+    if (h.opt.gs_block == 4) go(std::integral_constant<int, 4>{});
+    else if (h.opt.gs_block == 16) go(std::integral_constant<int, 16>{});
+    else go(std::integral_constant<int, 8>{});
+}
+
+// dots (b, x) [and (q, x)] as a pure vector pass (used when the finest
+// level is also the coarsest and no smoothing pass exists to fuse them into)
+template <int M, int CPT, int D>
+struct OpDotsBX {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = D;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const double *b, *x, *q;
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT], double (&d)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        const auto bi = load_pack<double, CPT>(b + o);
+        const auto xi = load_pack<double, CPT>(x + o);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) d[0][t] += bi.v[t] * xi.v[t];
+        if constexpr (D == 2) {
+            const auto qi = load_pack<double, CPT>(q + o);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * xi.v[t];
+        }
+    }
+};
+
+
+
 // One level of V(1,1) from a zero guess.  b: right-hand side of the level
 // (BT), xout: corrected solution (OT).  At the finest level the last pass
 // also accumulates the dots (b, xout) [and (q, xout)].  Returns the block
@@ -247,11 +303,20 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
     const int* rp = A.rp;
     const T* av = static_cast<const T*>(A.v);
 
+    const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
     // pre-smoothing from zero (+ residual)
     with_idx(A, [&](auto ix) {
         using IX = decltype(ix);
         if (l == 0) h.timer_begin(XAMG_TIMER_PRESMOOTH);
-        if (!cheb2) {
+        if (gs) {
+            // symmetric sweep from zero: forward into T, backward into X
+            const T* dl1 = dl1_of<T>(L);
+            launch_hgs<M, false, true>(h, A, dl1, b, static_cast<const T*>(nullptr), Tb, na);
+            if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
+            launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), X, na);
+            OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
+            launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
+        } else if (!cheb2) {
             OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
             launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
@@ -288,7 +353,23 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
         using IX = decltype(ix);
         auto post = [&](auto dots_tag) {
             constexpr int D = decltype(dots_tag)::value;
-            if (!cheb2) {
+            if (gs) {
+                // symmetric sweep: forward X -> T, backward T -> xout; the
+                // finest level's dots in a pass of their own
+                const T* dl1 = dl1_of<T>(L);
+                launch_hgs<M, false, false>(h, A, dl1, b, static_cast<const T*>(X), Tb, na);
+                launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), xout, na);
+                if constexpr (D > 0) {
+                    if constexpr (std::is_same<BT, double>::value && std::is_same<OT, double>::value) {
+                        constexpr int CPD = cpt_for<double, M>();
+                        OpDotsBX<M, CPD, D> op;
+                        op.b = b;
+                        op.x = xout;
+                        op.q = q;
+                        nb = launch_rows<M, CPD>(h, op, L.n, cap);
+                    }
+                }
+            } else if (!cheb2) {
                 OpJacPost<M, CPT, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
                                                           q, na};
                 nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
@@ -306,35 +387,6 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
     });
     return nb;
 }
-
-// dots (b, x) [and (q, x)] as a pure vector pass (used when the finest
-// level is also the coarsest and no smoothing pass exists to fuse them into)
-template <int M, int CPT, int D>
-struct OpDotsBX {
-    using AT = double;
-    static constexpr bool kMatrix = false;
-    static constexpr int kDots = D;
-    const int* rp = nullptr;
-    const double* val = nullptr;
-    Idx32 idx{nullptr};
-    const double *b, *x, *q;
-    __device__ __forceinline__ bool active_any() const { return true; }
-    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
-    template <int ND>
-    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT], double (&d)[ND][CPT]) const
-    {
-        const size_t o = size_t(i) * M + j0;
-        const auto bi = load_pack<double, CPT>(b + o);
-        const auto xi = load_pack<double, CPT>(x + o);
-#pragma unroll
-        for (int t = 0; t < CPT; ++t) d[0][t] += bi.v[t] * xi.v[t];
-        if constexpr (D == 2) {
-            const auto qi = load_pack<double, CPT>(q + o);
-#pragma unroll
-            for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * xi.v[t];
-        }
-    }
-};
 
 // z = M^-1 r for the whole hierarchy; returns the block count of the
 // launch that produced the finest-level dots (0 if ndots == 0).

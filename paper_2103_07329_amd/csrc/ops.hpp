@@ -533,6 +533,101 @@ __global__ void copy_cols_kernel(const TS* __restrict__ src, int ms, TD* __restr
 }
 
 // ------------------------------------------------------------------------
+// l1-hybrid Gauss-Seidel sweep (Baker, Falgout, Kolev, Yang 2011): rows in
+// blocks of BLK consecutive rows; inside a block Gauss-Seidel in row order
+// (backward: reverse order), across blocks the previous iterate xo (Jacobi),
+// with the l1 diagonal d_i = a_ii + sum_{j outside the block} |a_ij|:
+//   xn_i = xo_i + (b_i - sum_j a_ij v_j) / d_i,
+//   v_j = xn_j for the block's rows already updated in this sweep, xo_j else.
+// ZERO: xo = 0 (the pre-smoothing sweep from a zero guess; no gathers).
+// One lane group (M / CPT lanes) per block, the block's rows one after the
+// other; the rows already updated are kept in LDS, where each lane reads
+// back only the columns it wrote itself (no barrier needed).  xo and xn must
+// not overlap.  Launch: kGsThreads threads per workgroup.
+// ------------------------------------------------------------------------
+constexpr int kGsThreads = 64;
+
+template <int M, int CPT, int BLK, bool BWD, bool ZERO, typename MT, typename XT, typename BT,
+          typename OT>
+__global__ __launch_bounds__(kGsThreads) void hgs_kernel(
+    const int* __restrict__ rp, const int* __restrict__ ci, const MT* __restrict__ val,
+    const MT* __restrict__ dl1inv, const BT* __restrict__ b, const XT* __restrict__ xo,
+    OT* __restrict__ xn, int nrows, const int* nactive)
+{
+    constexpr int G = M / CPT;
+    constexpr int NG = kGsThreads / G;   // blocks of rows per workgroup
+    constexpr int U = 8;
+    using AT = MT;
+    __shared__ AT fresh[NG][BLK][M];
+    if (nactive && *nactive == 0) return;
+    const int g = threadIdx.x % G, q = threadIdx.x / G;
+    const int j0 = g * CPT;
+    const int lo = (blockIdx.x * NG + q) * BLK;
+    if (lo >= nrows) return;
+    const int hi = min(nrows, lo + BLK);
+    for (int s = 0; s < hi - lo; ++s) {
+        const int r = BWD ? hi - lo - 1 - s : s;
+        const int i = lo + r;
+        AT acc[CPT];
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) acc[t] = AT(0);
+        const int kb = rp[i], ke = rp[i + 1];
+        for (int k0 = kb; k0 < ke; k0 += U) {
+            int cc[U];
+            AT aa[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + u;
+                cc[u] = k < ke ? ci[k] : -1;
+                aa[u] = k < ke ? AT(val[k]) : AT(0);
+            }
+            Pack<AT, CPT> vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = cc[u];
+                const int rc = c - lo;
+                const bool upd = c >= 0 && rc >= 0 && rc < hi - lo && (BWD ? rc > r : rc < r);
+                if (upd) {
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t) vv[u].v[t] = fresh[q][rc][j0 + t];
+                } else if (!ZERO && c >= 0) {
+                    const auto x = load_pack<XT, CPT>(xo + size_t(c) * M + j0);
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t) vv[u].v[t] = AT(x.v[t]);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < CPT; ++t) vv[u].v[t] = AT(0);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int t = 0; t < CPT; ++t) acc[t] += aa[u] * vv[u].v[t];
+        }
+        const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        const AT di = dl1inv[i];
+        Pack<OT, CPT> o;
+        if constexpr (ZERO) {
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) {
+                const AT v = di * (AT(bi.v[t]) - acc[t]);
+                fresh[q][r][j0 + t] = v;
+                o.v[t] = OT(v);
+            }
+        } else {
+            const auto xi = load_pack<XT, CPT>(xo + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) {
+                const AT v = AT(xi.v[t]) + di * (AT(bi.v[t]) - acc[t]);
+                fresh[q][r][j0 + t] = v;
+                o.v[t] = OT(v);
+            }
+        }
+        store_pack<OT, CPT>(xn + size_t(i) * M + j0, o);
+    }
+}
+
+// ------------------------------------------------------------------------
 // coarsest level: x = A_L^-1 b, the inverse staged in LDS (n_L <= 64)
 // ------------------------------------------------------------------------
 template <int M, typename T>

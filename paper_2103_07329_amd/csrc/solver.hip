@@ -330,6 +330,7 @@ void xamg_default_options(xamg_options_t* o)
     o->x0_mode = XAMG_X0_ZERO;
     o->flexible = 0;
     o->check_every = 1;
+    o->gs_block = 8;
     o->stream = nullptr;
 }
 
@@ -358,8 +359,11 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     xamg_options_t o;
     if (opt) o = *opt; else xamg_default_options(&o);
     if (o.method != XAMG_CG && o.method != XAMG_BICGSTAB) return xamg::fail(XAMG_EINVAL, "method");
-    if (o.smoother != XAMG_JACOBI && o.smoother != XAMG_CHEBYSHEV)
+    if (o.smoother != XAMG_JACOBI && o.smoother != XAMG_CHEBYSHEV &&
+        o.smoother != XAMG_GAUSS_SEIDEL)
         return xamg::fail(XAMG_EINVAL, "smoother");
+    if (o.smoother == XAMG_GAUSS_SEIDEL && o.gs_block != 4 && o.gs_block != 8 && o.gs_block != 16)
+        return xamg::fail(XAMG_EINVAL, "gs_block must be 4, 8 or 16");
     if (o.smoother == XAMG_CHEBYSHEV && (o.cheby_degree < 1 || o.cheby_degree > 2))
         return xamg::fail(XAMG_EINVAL, "cheby_degree must be 1 or 2");
     if (o.smoother == XAMG_CHEBYSHEV &&
@@ -429,6 +433,27 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
                 }
                 std::vector<float> df(d.begin(), d.end());
                 L.dinv32 = xamg::upload(*h, df.data(), df.size());
+            }
+            if (o.smoother == XAMG_GAUSS_SEIDEL && l + 1 < h->nlev) {
+                // l1 diagonal of the Gauss-Seidel blocks: a_ii plus the
+                // absolute couplings to rows outside the row's block
+                std::vector<double> e(L.n, 0.0);
+                const int B = o.gs_block;
+                for (int i = 0; i < L.n; ++i) {
+                    const int lo = (i / B) * B, hi = lo + B;
+                    double di = 0.0;
+                    for (int k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k) {
+                        const int c = a.col[k];
+                        if (c == i) di += a.val[k];
+                        else if (c < lo || c >= hi) di += std::fabs(a.val[k]);
+                    }
+                    e[i] = 1.0 / di;
+                }
+                L.dl1inv64 = xamg::upload(*h, e.data(), e.size());
+                if (mixed) {
+                    std::vector<float> ef(e.begin(), e.end());
+                    L.dl1inv32 = xamg::upload(*h, ef.data(), ef.size());
+                }
             }
         }
         // coarsest level inverse (FP64 LU with partial pivoting on the host)

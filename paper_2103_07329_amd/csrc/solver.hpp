@@ -56,6 +56,8 @@ struct LevelDev {
     DCsr A32, P32, R32;      // FP32 copies for a mixed-precision preconditioner
     double* dinv64 = nullptr;
     float* dinv32 = nullptr;
+    double* dl1inv64 = nullptr;   // 1 / l1 diagonal of the Gauss-Seidel blocks
+    float* dl1inv32 = nullptr;
     double frac16[3] = {0, 0, 0};   // fraction of A/P/R nonzeros in 16-bit form
 };
 

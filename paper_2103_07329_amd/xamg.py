@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libxamg.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENODEV, EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 CG, BICGSTAB = 0, 1
-JACOBI, CHEBYSHEV = 0, 1
+JACOBI, CHEBYSHEV, GAUSS_SEIDEL = 0, 1, 2
 FP64, MIXED = 0, 1
 X0_ZERO, X0_GIVEN = 0, 1
 OP_A, OP_P, OP_R = 0, 1, 2
@@ -56,7 +56,7 @@ class OptionsT(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("index_bits", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("x0_mode", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("gs_block", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class StatsT(ctypes.Structure):

@@ -36,6 +36,7 @@ def test_error_strings_and_defaults():
     o = xamg.default_options()
     assert o.method == xamg.CG and o.smoother == xamg.JACOBI
     assert abs(o.omega - 2.0 / 3.0) < 1e-15 and o.cheby_degree == 2 and o.max_iters == 1000
+    assert o.gs_block == 8
     p = xamg.SetupParamsT()
     L.xamg_default_setup_params(ctypes.byref(p))
     assert p.theta == 0.25 and p.max_coarse == 64
@@ -56,6 +57,11 @@ def test_setup_argument_errors_without_device():
     bad = xamg.default_options(method=7)
     assert L.xamg_setup(ctypes.byref(H), ctypes.byref(bad), ctypes.byref(h)) == xamg.EINVAL
     bad = xamg.default_options(index_bits=16)      # 16-bit needs MIXED
+    assert L.xamg_setup(ctypes.byref(H), ctypes.byref(bad), ctypes.byref(h)) == xamg.EINVAL
+    for blk in (0, 5, 32):                          # Gauss-Seidel blocks: 4, 8 or 16 rows
+        bad = xamg.default_options(smoother=xamg.GAUSS_SEIDEL, gs_block=blk)
+        assert L.xamg_setup(ctypes.byref(H), ctypes.byref(bad), ctypes.byref(h)) == xamg.EINVAL
+    bad = xamg.default_options(smoother=3)
     assert L.xamg_setup(ctypes.byref(H), ctypes.byref(bad), ctypes.byref(h)) == xamg.EINVAL
     big = inputs.poisson7(5)                        # 125 rows > 64 on the coarsest level
     b = xamg._csr_struct(*big.csr(), keep=keep)
