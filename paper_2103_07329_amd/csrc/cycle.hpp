@@ -212,25 +212,40 @@ template <typename T>
 static const T* dl1_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dl1inv64; else return L.dl1inv32; }
 
 // one l1-hybrid Gauss-Seidel sweep over the rows of A (block size from the
-// options: 4, 8 or 16 rows)
+// options: 4, 8 or 16 rows; lane groups per block from A's row split)
 template <int M, bool BWD, bool ZERO, typename MT, typename XT, typename BT, typename OT>
 static void launch_hgs(Handle& h, const DCsr& A, const MT* dl1, const BT* b, const XT* xo, OT* xn,
                        const int* na)
 {
     constexpr int CPT = cpt_for<MT, M>();
-    constexpr int NG = kGsThreads / (M / CPT);
+    constexpr int G = M / CPT;
     const int n = A.nr;
     const MT* av = static_cast<const MT*>(A.v);
-    auto go = [&](auto blk) {
+    auto go = [&](auto blk, auto sgr) {
         constexpr int BLK = decltype(blk)::value;
+        constexpr int S = decltype(sgr)::value;
+        constexpr int NG = kGsThreads / (G * S);
         const int nblk = (n + BLK - 1) / BLK;
         const int grid = std::max(1, (nblk + NG - 1) / NG);
-        hipLaunchKernelGGL((hgs_kernel<M, CPT, BLK, BWD, ZERO, MT, XT, BT, OT>), dim3(grid),
+        hipLaunchKernelGGL((hgs_kernel<M, CPT, S, BLK, BWD, ZERO, MT, XT, BT, OT>), dim3(grid),
                            dim3(kGsThreads), 0, h.stream, A.rp, A.ci, av, dl1, b, xo, xn, n, na);
     };
-    if (h.opt.gs_block == 4) go(std::integral_constant<int, 4>{});
-    else if (h.opt.gs_block == 16) go(std::integral_constant<int, 16>{});
-    else go(std::integral_constant<int, 8>{});
+    auto with_s = [&](auto blk) {
+        const int s = A.template split_of<M>() & (kSweep - 1);
+        if constexpr (G * 8 <= kGsThreads) {
+            if (s >= 8) return go(blk, std::integral_constant<int, 8>{});
+        }
+        if constexpr (G * 4 <= kGsThreads) {
+            if (s >= 4) return go(blk, std::integral_constant<int, 4>{});
+        }
+        if constexpr (G * 2 <= kGsThreads) {
+            if (s >= 2) return go(blk, std::integral_constant<int, 2>{});
+        }
+        go(blk, std::integral_constant<int, 1>{});
+    };
+    if (h.opt.gs_block == 4) with_s(std::integral_constant<int, 4>{});
+    else if (h.opt.gs_block == 16) with_s(std::integral_constant<int, 16>{});
+    else with_s(std::integral_constant<int, 8>{});
 }
 
 // dots (b, x) [and (q, x)] as a pure vector pass (used when the finest

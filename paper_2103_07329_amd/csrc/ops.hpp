@@ -540,27 +540,33 @@ __global__ void copy_cols_kernel(const TS* __restrict__ src, int ms, TD* __restr
 //   xn_i = xo_i + (b_i - sum_j a_ij v_j) / d_i,
 //   v_j = xn_j for the block's rows already updated in this sweep, xo_j else.
 // ZERO: xo = 0 (the pre-smoothing sweep from a zero guess; no gathers).
-// One lane group (M / CPT lanes) per block, the block's rows one after the
-// other; the rows already updated are kept in LDS, where each lane reads
-// back only the columns it wrote itself (no barrier needed).  xo and xn must
-// not overlap.  Launch: kGsThreads threads per workgroup.
+// S lane groups (M / CPT lanes each) per block share out each row's
+// nonzeros (batches of U per group, as in rows_kernel) and combine their sums
+// with a fixed xor butterfly; the block's rows are processed one after the
+// other.  The rows already updated are kept in LDS: every group computes the
+// new values of its columns, so each lane reads back slots it has written
+// itself (with the same values the other groups wrote; no barrier needed).
+// xo and xn must not overlap.  Launch: kGsThreads threads per workgroup.
 // ------------------------------------------------------------------------
 constexpr int kGsThreads = 64;
 
-template <int M, int CPT, int BLK, bool BWD, bool ZERO, typename MT, typename XT, typename BT,
-          typename OT>
+template <int M, int CPT, int S, int BLK, bool BWD, bool ZERO, typename MT, typename XT,
+          typename BT, typename OT>
 __global__ __launch_bounds__(kGsThreads) void hgs_kernel(
     const int* __restrict__ rp, const int* __restrict__ ci, const MT* __restrict__ val,
     const MT* __restrict__ dl1inv, const BT* __restrict__ b, const XT* __restrict__ xo,
     OT* __restrict__ xn, int nrows, const int* nactive)
 {
     constexpr int G = M / CPT;
-    constexpr int NG = kGsThreads / G;   // blocks of rows per workgroup
-    constexpr int U = 8;
+    static_assert(G * S <= kGsThreads, "a block's lanes must fit in the workgroup");
+    constexpr int NG = kGsThreads / (G * S);   // blocks of rows per workgroup
+    constexpr int U = S == 1 ? 8 : (S == 2 ? 4 : 2);
     using AT = MT;
     __shared__ AT fresh[NG][BLK][M];
     if (nactive && *nactive == 0) return;
-    const int g = threadIdx.x % G, q = threadIdx.x / G;
+    const int g = threadIdx.x % G;
+    const int sg = (threadIdx.x / G) % S;
+    const int q = threadIdx.x / (G * S);
     const int j0 = g * CPT;
     const int lo = (blockIdx.x * NG + q) * BLK;
     if (lo >= nrows) return;
@@ -572,7 +578,7 @@ __global__ __launch_bounds__(kGsThreads) void hgs_kernel(
 #pragma unroll
         for (int t = 0; t < CPT; ++t) acc[t] = AT(0);
         const int kb = rp[i], ke = rp[i + 1];
-        for (int k0 = kb; k0 < ke; k0 += U) {
+        for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
             int cc[U];
             AT aa[U];
 #pragma unroll
@@ -604,6 +610,12 @@ __global__ __launch_bounds__(kGsThreads) void hgs_kernel(
 #pragma unroll
                 for (int t = 0; t < CPT; ++t) acc[t] += aa[u] * vv[u].v[t];
         }
+        if constexpr (S > 1) {
+#pragma unroll
+            for (int off = G; off < G * S; off <<= 1)
+#pragma unroll
+                for (int t = 0; t < CPT; ++t) acc[t] += __shfl_xor(acc[t], off, 64);
+        }
         const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
         const AT di = dl1inv[i];
         Pack<OT, CPT> o;
@@ -623,7 +635,7 @@ __global__ __launch_bounds__(kGsThreads) void hgs_kernel(
                 o.v[t] = OT(v);
             }
         }
-        store_pack<OT, CPT>(xn + size_t(i) * M + j0, o);
+        if (sg == 0) store_pack<OT, CPT>(xn + size_t(i) * M + j0, o);
     }
 }
 
