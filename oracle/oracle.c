@@ -24,7 +24,8 @@
  *    with the l1 diagonal of Baker, Falgout, Kolev and Yang, "Multigrid
  *    smoothers for ultraparallel computing", SISC 33 (2011).
  *  - V(1,1) cycle as the preconditioner of CG (Hestenes-Stiefel) or of
- *    right-preconditioned BiCGStab (van der Vorst), both cited in Section 2.1.
+ *    right-preconditioned BiCGStab (van der Vorst), both cited in Section 2.1,
+ *    or as a solver on its own (the stationary multigrid iteration).
  *
  * The paper gives no formulas for these methods; each routine below says
  * which textbook definition it follows.  Everything is sequential FP64
@@ -1281,6 +1282,65 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
 }
 
 /*
+ * Multigrid as a standalone solver (Section 2.1, Table 1 lists MultiGrid as
+ * a solver as well as a preconditioner): the stationary iteration
+ *   x <- x + V(b - A x),
+ * V the V(1,1) cycle, per column until ||b - A x|| / ||b|| <= tol.  The
+ * residual is recomputed from x every iteration (it is the true residual);
+ * converged columns stay frozen.
+ */
+static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
+                   const double *B, double *X, int *iters, double *relres, int *conv,
+                   vws *w)
+{
+    const ocsr *A = &h->A[0];
+    int n = A->nr, j, it, i;
+    size_t nm = (size_t)n * m;
+    double *r = (double *)malloc(nm * sizeof(double) + 8);
+    double *z = (double *)malloc(nm * sizeof(double) + 8);
+    double *bn = (double *)malloc((size_t)m * sizeof(double));
+    double *rr = (double *)malloc((size_t)m * sizeof(double));
+    int *act = (int *)malloc((size_t)m * sizeof(int));
+    if (!r || !z || !bn || !rr || !act) return ORC_ENOMEM;
+
+    if (!ko->x0_given) memset(X, 0, nm * sizeof(double));
+    residual(A, m, B, X, r);
+    dots(n, m, B, B, bn);
+    dots(n, m, r, r, rr);
+    for (j = 0; j < m; j++) {
+        bn[j] = sqrt(bn[j]);
+        iters[j] = 0; conv[j] = 0; act[j] = 1;
+        if (bn[j] == 0.0) {
+            for (i = 0; i < n; i++) X[(size_t)i * m + j] = 0.0;
+            relres[j] = 0.0; conv[j] = 1; act[j] = 0;
+            continue;
+        }
+        relres[j] = sqrt(rr[j]) / bn[j];
+        if (relres[j] <= ko->tol) { conv[j] = 1; act[j] = 0; }
+    }
+    for (it = 1; it <= ko->max_iters; it++) {
+        int any = 0;
+        for (j = 0; j < m; j++) any |= act[j];
+        if (!any) break;
+        if (g_verbose) { fprintf(stderr, "[oracle] MG iteration %d\n", it); fflush(stderr); }
+        apply_prec(h, ko, so, m, r, z, w);
+        for (i = 0; i < n; i++)
+            for (j = 0; j < m; j++)
+                if (act[j]) X[(size_t)i * m + j] += z[(size_t)i * m + j];
+        residual(A, m, B, X, r);
+        dots(n, m, r, r, rr);
+        for (j = 0; j < m; j++) {
+            if (!act[j]) continue;
+            iters[j] = it;
+            relres[j] = sqrt(rr[j]) / bn[j];
+            if (relres[j] <= ko->tol) { conv[j] = 1; act[j] = 0; }
+        }
+    }
+    free(r); free(z); free(bn); free(rr); free(act);
+    return ORC_OK;
+}
+
+/*
  * Solve A X = B (A = level 0 of h).  X is the initial guess when x0_given,
  * the solution on return.  Per-column outputs: iterations, recurrence
  * relative residual, true relative residual, converged flag.
@@ -1300,6 +1360,7 @@ int orc_solve(const ohier *h, int method, int smoother, double omega, int degree
     for (q = 0; q < nm; q++) if (!isfinite(B[q])) return ORC_EINVAL;
     if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
     if (method == 0) rc = pcg(h, &ko, &so, m, B, X, iters, relres, conv, &w);
+    else if (method == 2) rc = mgsolve(h, &ko, &so, m, B, X, iters, relres, conv, &w);
     else rc = bicgstab(h, &ko, &so, m, B, X, iters, relres, conv, &w);
     vws_free(&w, h->nlev);
     t = (double *)malloc(nm * sizeof(double));

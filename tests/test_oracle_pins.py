@@ -402,7 +402,7 @@ def test_cg_eigenvector_one_iteration(orc):
         assert np.allclose(x, v / lam, rtol=0, atol=1e-13)
 
 
-@pytest.mark.parametrize("method,smoother", [(0, 0), (0, 1), (1, 0), (1, 1), (0, 2), (1, 2)])
+@pytest.mark.parametrize("method,smoother", [(0, 0), (0, 1), (1, 0), (1, 1), (0, 2), (1, 2), (2, 0), (2, 2)])
 def test_column_independence_bitwise(orc, method, smoother):
     p = inputs.poisson7(12)
     H = orc.Hierarchy(*p.csr())
@@ -614,3 +614,70 @@ def test_strength_threshold_inclusive(orc, kz, strong):
     p = inputs.anisotropic7(N, 1.0, 1.0, kz)
     c = orc.strength_counts(*p.csr(), theta=0.25).reshape(N, N, N)
     assert np.all(c[1:-1, 1:-1, 1:-1] == strong)
+
+
+# --------------------------------------------------------------------------
+# multigrid as a standalone solver
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("smoother", [0, 1, 2])
+def test_mg_solver_is_the_stationary_iteration(orc, smoother):
+    """k iterations of the MG solver equal x_{i+1} = x_i + M (b - A x_i)
+    with M the V-cycle as a dense matrix (its columns are V(e_i))."""
+    p = _problems_small()[2]
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    A = dense(*p.csr())
+    Mv = H.vcycle(np.eye(p.n), smoother=smoother)
+    B = inputs.uniform_rhs(p.n, 3, 17)
+    X = np.zeros_like(B)
+    for k in range(1, 5):
+        X = X + Mv @ (B - A @ X)
+        Xk, st, rc = H.solve(B, method=orc.MG, smoother=smoother, max_iters=k, tol=1e-30)
+        assert np.all(st["iters"] == k)
+        assert np.allclose(Xk, X, rtol=0, atol=1e-11 * np.abs(X).max())
+
+
+@pytest.mark.parametrize("smoother", [0, 1, 2])
+def test_mg_solver_converges_to_dense_solution(orc, smoother):
+    p = _problems_small()[1]
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    B = inputs.uniform_rhs(p.n, 4, 19)
+    X, st, rc = H.solve(B, method=orc.MG, smoother=smoother, tol=1e-10)
+    assert rc == 0 and np.all(st["converged"])
+    Xd = np.linalg.solve(dense(*p.csr()), B)
+    assert np.allclose(X, Xd, rtol=0, atol=1e-8 * np.abs(Xd).max())
+    # the stopping residual is the true one
+    assert np.allclose(st["relres"], st["true_relres"], rtol=1e-12, atol=0)
+    assert np.all(st["true_relres"] <= 1e-10)
+
+
+def test_mg_solver_one_level_is_exact(orc):
+    p = inputs.poisson7(4)
+    H = orc.Hierarchy(*p.csr())
+    assert H.nlev == 1
+    B = inputs.uniform_rhs(p.n, 2, 3)
+    X, st, rc = H.solve(B, method=orc.MG, tol=1e-12)
+    assert rc == 0 and np.all(st["iters"] == 1)
+
+
+def test_mg_solver_stops_at_first_iterate_within_tol(orc):
+    """Per column, the MG solver stops at the first k with
+    ||b - A x_k|| / ||b|| <= tol, x_k from the dense stationary iteration."""
+    p = _problems_small()[2]
+    H = orc.Hierarchy(*p.csr(), max_coarse=20)
+    A = dense(*p.csr())
+    Mv = H.vcycle(np.eye(p.n), smoother=1)
+    B = inputs.uniform_rhs(p.n, 5, 23)
+    B[:, 2] *= 1e-3                     # scale does not matter (relative test)
+    tol = 1e-6
+    X = np.zeros_like(B)
+    first = np.full(5, -1)
+    for k in range(1, 60):
+        X = X + Mv @ (B - A @ X)
+        rel = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+        for j in range(5):
+            if first[j] < 0 and rel[j] <= tol:
+                first[j] = k
+        if np.all(first > 0):
+            break
+    Xs, st, rc = H.solve(B, method=orc.MG, smoother=1, tol=tol)
+    assert np.array_equal(st["iters"], first)
