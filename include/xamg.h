@@ -51,7 +51,7 @@ extern "C" {
 #define XAMG_MAX_M 32 /* columns per solve: 1..32 */
 
 /* ---- enums --------------------------------------------------------------- */
-enum { XAMG_CG = 0, XAMG_BICGSTAB = 1 };
+enum { XAMG_CG = 0, XAMG_BICGSTAB = 1, XAMG_MG = 2 };
 enum { XAMG_JACOBI = 0, XAMG_CHEBYSHEV = 1, XAMG_GAUSS_SEIDEL = 2 };
 enum { XAMG_FP64 = 0, XAMG_MIXED = 1 };
 enum { XAMG_X0_ZERO = 0, XAMG_X0_GIVEN = 1 };
@@ -87,7 +87,9 @@ typedef struct {
 
 /* Solver options. */
 typedef struct {
-    int32_t method;        /* XAMG_CG (default) or XAMG_BICGSTAB */
+    int32_t method;        /* XAMG_CG (default), XAMG_BICGSTAB, or XAMG_MG: multigrid as
+                              the solver (Table 1), x <- x + V(b - A x) per column
+                              until the true relative residual is <= tol */
     int32_t smoother;      /* XAMG_JACOBI (default), XAMG_CHEBYSHEV or XAMG_GAUSS_SEIDEL:
                               symmetric Gauss-Seidel (Section 2.1, Table 1; the
                               smoother of Section 3.1) in its l1-hybrid form --
@@ -201,7 +203,8 @@ typedef struct xamg_batch xamg_batch_t;
  * for batched solves.  The handles stay owned by the caller and must
  * outlive the batch; a handle may appear once.  iters_per_launch (0 = 4) is
  * the number of CG iterations of every system captured into the batch's
- * HIP graph.  EINVAL for BiCGStab handles or repeated handles. */
+ * HIP graph.  EINVAL for handles whose method is not CG, or repeated
+ * handles. */
 int xamg_batch_create(xamg_handle_t *const *handles, int32_t nsys, int32_t iters_per_launch,
                       xamg_batch_t **out);
 

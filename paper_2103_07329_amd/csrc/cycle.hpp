@@ -103,6 +103,30 @@ struct FinRR {   // tot: (r, r)[M]
     }
 };
 
+struct FinMG {   // tot: (b, b)[M], (r, r)[M] of the recomputed residual r = b - A x
+    ColState* st;
+    int M;
+    __device__ void operator()(const double* tot) const
+    {
+        const int j = threadIdx.x;
+        if (j < M && st->active[j]) {
+            const double rr = tot[M + j];
+            st->rr[j] = rr;
+            st->iters[j] += 1;
+            const double rel = sqrt(rr) / sqrt(st->bn2[j]);
+            st->relres[j] = rel;
+            st->true_relres[j] = rel;
+            if (rel <= st->tol) {
+                st->active[j] = 0;
+                st->conv[j] = 1;
+            } else if (st->iters[j] >= st->max_iters) {
+                st->active[j] = 0;   // iteration cap: not converged
+            }
+        }
+        recount_active(st, M);
+    }
+};
+
 struct FinBeta {   // tot: (r, z)[M] and, flexible, (z, q)[M]
     ColState* st;
     int M;
@@ -525,6 +549,34 @@ int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
         launch_rows<M, CPT>(h, cp, n, h.nb_cap);
     }
     return nr;
+}
+
+// Multigrid as a standalone solver (Section 2.1, Table 1): per column
+// x <- x + V(b - A x) until ||b - A x|| / ||b|| <= tol; the residual is
+// recomputed from x each iteration, so it is the true residual.
+template <int M>
+int mg_solve(Handle& h, const double* B, double* X, double tol)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    const int n = h.lev[0].n;
+    const DCsr& A = h.lev[0].A64;
+    const double* av = static_cast<const double*>(A.v);
+    pcg_start<M>(h, B, X, tol);   // r = b - A x, column state
+    sync_state(h);
+    if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
+    const int every = std::max(1, h.opt.check_every);
+    for (int it = 0; h.st_host->nactive > 0 && it < h.opt.max_iters;) {
+        ++it;
+        vcycle<M>(h, h.w.r, h.w.z, 0, nullptr);
+        OpAddActive<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, X, h.w.z};
+        launch_rows<M, CPT>(h, up, n, h.nb_cap);
+        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, h.w.r,
+                                                              nullptr};
+        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+        launch_fin(h, nb, 2 * M, FinMG{h.st, M});
+        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
+    }
+    return XAMG_OK;
 }
 
 template <int M>

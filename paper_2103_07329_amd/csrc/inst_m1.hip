@@ -6,6 +6,7 @@ namespace xamg {
 
 template int vcycle<1>(Handle&, const double*, double*, int, const double*);
 template int pcg<1>(Handle&, const double*, double*, double);
+template int mg_solve<1>(Handle&, const double*, double*, double);
 template int bicgstab<1>(Handle&, const double*, double*, double);
 template void spmm64<1>(Handle&, const DCsr&, const double*, double*);
 template void autotune<1>(Handle&);

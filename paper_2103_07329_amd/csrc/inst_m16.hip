@@ -6,6 +6,7 @@ namespace xamg {
 
 template int vcycle<16>(Handle&, const double*, double*, int, const double*);
 template int pcg<16>(Handle&, const double*, double*, double);
+template int mg_solve<16>(Handle&, const double*, double*, double);
 template int bicgstab<16>(Handle&, const double*, double*, double);
 template void spmm64<16>(Handle&, const DCsr&, const double*, double*);
 template void autotune<16>(Handle&);

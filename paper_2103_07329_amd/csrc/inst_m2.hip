@@ -6,6 +6,7 @@ namespace xamg {
 
 template int vcycle<2>(Handle&, const double*, double*, int, const double*);
 template int pcg<2>(Handle&, const double*, double*, double);
+template int mg_solve<2>(Handle&, const double*, double*, double);
 template int bicgstab<2>(Handle&, const double*, double*, double);
 template void spmm64<2>(Handle&, const DCsr&, const double*, double*);
 template void autotune<2>(Handle&);

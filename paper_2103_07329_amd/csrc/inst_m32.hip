@@ -6,6 +6,7 @@ namespace xamg {
 
 template int vcycle<32>(Handle&, const double*, double*, int, const double*);
 template int pcg<32>(Handle&, const double*, double*, double);
+template int mg_solve<32>(Handle&, const double*, double*, double);
 template int bicgstab<32>(Handle&, const double*, double*, double);
 template void spmm64<32>(Handle&, const DCsr&, const double*, double*);
 template void autotune<32>(Handle&);

@@ -6,6 +6,7 @@ namespace xamg {
 
 template int vcycle<4>(Handle&, const double*, double*, int, const double*);
 template int pcg<4>(Handle&, const double*, double*, double);
+template int mg_solve<4>(Handle&, const double*, double*, double);
 template int bicgstab<4>(Handle&, const double*, double*, double);
 template void spmm64<4>(Handle&, const DCsr&, const double*, double*);
 template void autotune<4>(Handle&);

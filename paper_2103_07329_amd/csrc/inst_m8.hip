@@ -6,6 +6,7 @@ namespace xamg {
 
 template int vcycle<8>(Handle&, const double*, double*, int, const double*);
 template int pcg<8>(Handle&, const double*, double*, double);
+template int mg_solve<8>(Handle&, const double*, double*, double);
 template int bicgstab<8>(Handle&, const double*, double*, double);
 template void spmm64<8>(Handle&, const DCsr&, const double*, double*);
 template void autotune<8>(Handle&);

@@ -480,6 +480,34 @@ struct OpUpdP {
     }
 };
 
+// multigrid iteration: x += z on the active columns
+template <int M, int CPT>
+struct OpAddActive {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = 0;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const ColState* st;
+    double* x;
+    const double* z;
+    __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        auto xi = load_pack<double, CPT>(x + o);
+        const auto zi = load_pack<double, CPT>(z + o);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+            if (st->active[j0 + t]) xi.v[t] += zi.v[t];
+        store_pack<double, CPT>(x + o, xi);
+    }
+};
+
 // columns flagged in st->cp: dst = src;  columns with b_j = 0: x = 0
 template <int M, int CPT>
 struct OpFixCols {

@@ -285,6 +285,7 @@ int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_st
     int rc = dispatch_m(mp, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         if (h.opt.method == XAMG_BICGSTAB) return bicgstab<M>(h, Bs, Xs, tol);
+        if (h.opt.method == XAMG_MG) return mg_solve<M>(h, Bs, Xs, tol);
         return pcg<M>(h, Bs, Xs, tol);
     });
     if (mp != m)
@@ -358,7 +359,8 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     *out = nullptr;
     xamg_options_t o;
     if (opt) o = *opt; else xamg_default_options(&o);
-    if (o.method != XAMG_CG && o.method != XAMG_BICGSTAB) return xamg::fail(XAMG_EINVAL, "method");
+    if (o.method != XAMG_CG && o.method != XAMG_BICGSTAB && o.method != XAMG_MG)
+        return xamg::fail(XAMG_EINVAL, "method");
     if (o.smoother != XAMG_JACOBI && o.smoother != XAMG_CHEBYSHEV &&
         o.smoother != XAMG_GAUSS_SEIDEL)
         return xamg::fail(XAMG_EINVAL, "smoother");

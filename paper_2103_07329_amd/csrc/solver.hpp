@@ -200,6 +200,8 @@ int pcg(Handle& h, const double* B, double* X, double tol);
 template <int M>
 int bicgstab(Handle& h, const double* B, double* X, double tol);
 template <int M>
+int mg_solve(Handle& h, const double* B, double* X, double tol);
+template <int M>
 void spmm64(Handle& h, const DCsr& d, const double* X, double* Y);
 // time each operator's SpMM over the row splits and keep the fastest
 template <int M>
