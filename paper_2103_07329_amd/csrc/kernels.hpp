@@ -195,11 +195,34 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                     for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
                         int cc[U];
                         AT aa[U];
+                        if constexpr (G > 1) {
+                            // the G lanes of the row load every G-th entry of
+                            // the batch and exchange them (fewer load
+                            // instructions through the address units)
+                            constexpr int PL = (U + G - 1) / G;
+                            int cown[PL];
+                            AT aown[PL];
 #pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const int k = k0 + u;
-                            cc[u] = k < ke ? idx.col(k) : -1;
-                            aa[u] = k < ke ? AT(op.val[k]) : AT(0);
+                            for (int q = 0; q < PL; ++q) {
+                                const int u = g + G * q;
+                                const int k = k0 + u;
+                                const bool ok = u < U && k < ke;
+                                cown[q] = ok ? idx.col(k) : -1;
+                                aown[q] = ok ? AT(op.val[k]) : AT(0);
+                            }
+                            const int base = (threadIdx.x & 63) - g;
+#pragma unroll
+                            for (int u = 0; u < U; ++u) {
+                                cc[u] = __shfl(cown[u / G], base + u % G, 64);
+                                aa[u] = __shfl(aown[u / G], base + u % G, 64);
+                            }
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < U; ++u) {
+                                const int k = k0 + u;
+                                cc[u] = k < ke ? idx.col(k) : -1;
+                                aa[u] = k < ke ? AT(op.val[k]) : AT(0);
+                            }
                         }
                         Pack<AT, CPT> vv[U];
 #pragma unroll
