@@ -94,6 +94,52 @@ struct Idx16 {
 };
 
 // ---------------------------------------------------------------------------
+// value of lane K of the caller's group of G consecutive lanes (groups
+// aligned to G): DPP quad permutes for G = 2, 4 (vector ALU moves), a
+// shuffle for larger groups
+// ---------------------------------------------------------------------------
+template <int G, int K>
+__device__ __forceinline__ int grp_bcast(int v)
+{
+    if constexpr (G == 4)
+        return __builtin_amdgcn_mov_dpp(v, K | (K << 2) | (K << 4) | (K << 6), 0xF, 0xF, false);
+    else if constexpr (G == 2)
+        return __builtin_amdgcn_mov_dpp(v, K | (K << 2) | ((K + 2) << 4) | ((K + 2) << 6), 0xF,
+                                        0xF, false);
+    else
+        return __shfl(v, ((threadIdx.x & 63) & ~(G - 1)) + K, 64);
+}
+
+template <int G, int K>
+__device__ __forceinline__ float grp_bcast(float v)
+{
+    return __int_as_float(grp_bcast<G, K>(__float_as_int(v)));
+}
+
+template <int G, int K>
+__device__ __forceinline__ double grp_bcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = grp_bcast<G, K>(int(b & 0xffffffffLL));
+    const int hi = grp_bcast<G, K>(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) |
+                                static_cast<long long>(static_cast<unsigned>(lo)));
+}
+
+// cc[u] = column index of batch entry u, aa[u] its value, from the entries
+// each lane of the group loaded (lane g holds entries g, g + G, ...)
+template <int G, int U, int PL, typename AT, int u = 0>
+__device__ __forceinline__ void grp_share(const int (&cown)[PL], const AT (&aown)[PL],
+                                          int (&cc)[U], AT (&aa)[U])
+{
+    if constexpr (u < U) {
+        cc[u] = grp_bcast<G, u % G>(cown[u / G]);
+        aa[u] = grp_bcast<G, u % G>(aown[u / G]);
+        grp_share<G, U, PL, AT, u + 1>(cown, aown, cc, aa);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // block-level deterministic reduction of per-column dots
 // ---------------------------------------------------------------------------
 template <int M, int CPT, int ND>
@@ -210,12 +256,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                                 cown[q] = ok ? idx.col(k) : -1;
                                 aown[q] = ok ? AT(op.val[k]) : AT(0);
                             }
-                            const int base = (threadIdx.x & 63) - g;
-#pragma unroll
-                            for (int u = 0; u < U; ++u) {
-                                cc[u] = __shfl(cown[u / G], base + u % G, 64);
-                                aa[u] = __shfl(aown[u / G], base + u % G, 64);
-                            }
+                            grp_share<G, U, PL, AT>(cown, aown, cc, aa);
                         } else {
 #pragma unroll
                             for (int u = 0; u < U; ++u) {
