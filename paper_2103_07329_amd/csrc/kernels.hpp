@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace xamg {
 namespace dev {
@@ -126,18 +127,23 @@ __device__ __forceinline__ double grp_bcast(double v)
                                 static_cast<long long>(static_cast<unsigned>(lo)));
 }
 
-// cc[u] = column index of batch entry u, aa[u] its value, from the entries
-// each lane of the group loaded (lane g holds entries g, g + G, ...)
-template <int G, int U, int PL, typename AT, int u = 0>
-__device__ __forceinline__ void grp_share(const int (&cown)[PL], const AT (&aown)[PL],
-                                          int (&cc)[U], AT (&aa)[U])
+// out[u] = entry u of a batch, from the entries each lane of the group
+// loaded (lane g holds entries g, g + G, ...)
+template <int G, int U, int PL, typename V, int u = 0>
+__device__ __forceinline__ void grp_share(const V (&own)[PL], V (&out)[U])
 {
     if constexpr (u < U) {
-        cc[u] = grp_bcast<G, u % G>(cown[u / G]);
-        aa[u] = grp_bcast<G, u % G>(aown[u / G]);
-        grp_share<G, U, PL, AT, u + 1>(cown, aown, cc, aa);
+        out[u] = grp_bcast<G, u % G>(own[u / G]);
+        grp_share<G, U, PL, V, u + 1>(own, out);
     }
 }
+
+// ops whose gathered value carries a per-column factor (a smoother's
+// D^-1 on the fly) expose it as scale(c) and take it in fetch_scaled
+template <class T, class = void>
+struct op_has_scale : std::false_type {};
+template <class T>
+struct op_has_scale<T, std::void_t<decltype(&T::scale)>> : std::true_type {};
 
 // ---------------------------------------------------------------------------
 // block-level deterministic reduction of per-column dots
@@ -184,6 +190,8 @@ __device__ __forceinline__ void reduce_dots(double (&d)[ND > 0 ? ND : 1][CPT],
 //   static constexpr int kDots     -- per-column dots produced (0..2)
 //   const int* rp; const MT* val; Idx idx;
 //   Pack<AT, CPT> fetch(int c, int j0)   the gathered input in(c, j0..j0+CPT)
+//     or, for a gathered input with a per-column factor: AT scale(int c) and
+//     Pack<AT, CPT> fetch_scaled(int c, int j0, AT scale(c))
 //   void out(int i, int j0, const AT (&acc)[CPT], double (&d)[ND][CPT])
 //   bool active_any()   -- false: whole op is a no-op (every column frozen)
 template <int M, int CPT, int S, class Op>
@@ -241,6 +249,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                     for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
                         int cc[U];
                         AT aa[U];
+                        AT ss[U];   // per-column factors (scaled gathers only)
                         if constexpr (G > 1) {
                             // the G lanes of the row load every G-th entry of
                             // the batch and exchange them (fewer load
@@ -256,7 +265,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                                 cown[q] = ok ? idx.col(k) : -1;
                                 aown[q] = ok ? AT(op.val[k]) : AT(0);
                             }
-                            grp_share<G, U, PL, AT>(cown, aown, cc, aa);
+                            grp_share<G, U, PL, int>(cown, cc);
+                            grp_share<G, U, PL, AT>(aown, aa);
                         } else {
 #pragma unroll
                             for (int u = 0; u < U; ++u) {
@@ -268,7 +278,32 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                         Pack<AT, CPT> vv[U];
 #pragma unroll
                         for (int u = 0; u < U; ++u)
-                            if (cc[u] >= 0) vv[u] = op.fetch(cc[u], j0);
+                            if (cc[u] >= 0) {
+                                if constexpr (op_has_scale<Op>::value)
+                                    vv[u] = op.fetch_raw(cc[u], j0);
+                                else
+                                    vv[u] = op.fetch(cc[u], j0);
+                            }
+                        if constexpr (op_has_scale<Op>::value) {
+                            // per-column factors of the gathered values, folded
+                            // into the matrix coefficients
+                            if constexpr (G > 1) {
+                                constexpr int PL = (U + G - 1) / G;
+                                AT sown[PL];
+#pragma unroll
+                                for (int q = 0; q < PL; ++q) {
+                                    const int u = g + G * q;
+                                    const int c = u < U ? cc[u < U ? u : 0] : -1;
+                                    sown[q] = c >= 0 ? op.scale(c) : AT(0);
+                                }
+                                grp_share<G, U, PL, AT>(sown, ss);
+                            } else {
+#pragma unroll
+                                for (int u = 0; u < U; ++u) ss[u] = cc[u] >= 0 ? op.scale(cc[u]) : AT(0);
+                            }
+#pragma unroll
+                            for (int u = 0; u < U; ++u) aa[u] *= ss[u];
+                        }
 #pragma unroll
                         for (int u = 0; u < U; ++u)
                             if (cc[u] >= 0) {

@@ -186,13 +186,16 @@ struct OpJacPre {
     T* r;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
+    // the gathered value is (w d_c) b_c: rows_kernel gathers b_c, loads the
+    // factor w d_c once per nonzero for the row's lanes and folds it into
+    // the matrix coefficient
+    __device__ __forceinline__ AT scale(int c) const { return omega * dinv[c]; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch_raw(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
-        const AT wd = omega * dinv[c];
         Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) r.v[t] = (wd * AT(v.v[t]));
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
         return r;
     }
     template <int ND>
@@ -284,13 +287,15 @@ struct OpChebPre {
     T* x;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
+    // gathered value (d_c / theta) b_c; the factor is folded into the matrix
+    // coefficient by rows_kernel
+    __device__ __forceinline__ AT scale(int c) const { return dinv[c] * inv_theta; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch_raw(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
-        const AT dc = dinv[c] * inv_theta;
         Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]) * dc;
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
         return r;
     }
     template <int ND>
