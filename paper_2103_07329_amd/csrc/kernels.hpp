@@ -138,6 +138,13 @@ __device__ __forceinline__ void grp_share(const V (&own)[PL], V (&out)[U])
     }
 }
 
+// ops whose epilogue needs the row's own gathered input (the diagonal
+// entry's value) define out_self(i, j0, acc, have, self, d)
+template <class T, class = void>
+struct op_wants_self : std::false_type {};
+template <class T>
+struct op_wants_self<T, std::void_t<decltype(T::kWantSelf)>> : std::bool_constant<T::kWantSelf> {};
+
 // ops whose gathered value carries a per-column factor (a smoother's
 // D^-1 on the fly) expose it as scale(c) and take it in fetch_scaled
 template <class T, class = void>
@@ -238,6 +245,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
             AT acc[CPT];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) acc[c] = AT(0);
+            Pack<AT, CPT> self{};   // the row's own gathered input (S == 1)
+            bool have_self = false;
             if constexpr (Op::kMatrix) {
                 // nonzeros in batches of U: all column indices and values
                 // first, then every gather, then the multiply-adds in
@@ -284,6 +293,14 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                                 else
                                     vv[u] = op.fetch(cc[u], j0);
                             }
+                        if constexpr (op_wants_self<Op>::value && S == 1) {
+#pragma unroll
+                            for (int u = 0; u < U; ++u)
+                                if (cc[u] == i) {
+                                    self = vv[u];
+                                    have_self = true;
+                                }
+                        }
                         if constexpr (op_has_scale<Op>::value) {
                             // per-column factors of the gathered values, folded
                             // into the matrix coefficients
@@ -319,7 +336,12 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
                         for (int c = 0; c < CPT; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
                 }
             }
-            if (live && sg == 0) op.out(i, j0, acc, dsum);
+            if (live && sg == 0) {
+                if constexpr (op_wants_self<Op>::value)
+                    op.out_self(i, j0, acc, have_self, self, dsum);
+                else
+                    op.out(i, j0, acc, dsum);
+            }
         }
     }
     reduce_dots<M, CPT, ND>(dsum, part, blk);

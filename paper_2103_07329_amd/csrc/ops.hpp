@@ -78,12 +78,28 @@ struct OpAx {
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
                                         double (&d)[ND][CPT]) const
     {
+        out_self(i, j0, acc, false, Pack<AT, CPT>{}, d);
+    }
+    // with the dot, x_i is the diagonal entry's gathered value when the row
+    // kernel has it (no second load of the row's own input)
+    static constexpr bool kWantSelf = DOT > 0;
+    template <int ND>
+    __device__ __forceinline__ void out_self(int i, int j0, const AT (&acc)[CPT], bool have,
+                                             const Pack<AT, CPT>& xs, double (&d)[ND][CPT]) const
+    {
         Pack<T, CPT> o;
 #pragma unroll
         for (int t = 0; t < CPT; ++t) o.v[t] = T(acc[t]);
         store_pack<T, CPT>(y + size_t(i) * M + j0, o);
         if constexpr (DOT > 0) {
-            const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
+            Pack<AT, CPT> xi;
+            if (have) {
+                xi = xs;
+            } else {
+                const auto xl = load_pack<T, CPT>(x + size_t(i) * M + j0);
+#pragma unroll
+                for (int t = 0; t < CPT; ++t) xi.v[t] = AT(xl.v[t]);
+            }
 #pragma unroll
             for (int t = 0; t < CPT; ++t) d[0][t] += double(xi.v[t]) * double(o.v[t]);
         }
