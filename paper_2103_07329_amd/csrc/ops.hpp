@@ -264,13 +264,28 @@ struct OpJacPost {
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
                                         double (&d)[ND][CPT]) const
     {
+        out_self(i, j0, acc, false, Pack<AT, CPT>{}, d);
+    }
+    // x_i from the gathered diagonal entry when the row kernel has it
+    static constexpr bool kWantSelf = true;
+    template <int ND>
+    __device__ __forceinline__ void out_self(int i, int j0, const AT (&acc)[CPT], bool have,
+                                             const Pack<AT, CPT>& xs, double (&d)[ND][CPT]) const
+    {
         const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
-        const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
+        Pack<AT, CPT> xi;
+        if (have) {
+            xi = xs;
+        } else {
+            const auto xl = load_pack<T, CPT>(x + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) xi.v[t] = AT(xl.v[t]);
+        }
         const AT wd = omega * dinv[i];
         Pack<OT, CPT> o;
 #pragma unroll
         for (int t = 0; t < CPT; ++t)
-            o.v[t] = OT(AT(xi.v[t]) + wd * (AT(bi.v[t]) - acc[t]));
+            o.v[t] = OT(xi.v[t] + wd * (AT(bi.v[t]) - acc[t]));
         store_pack<OT, CPT>(xo + size_t(i) * M + j0, o);
         if constexpr (DOT >= 1) {
 #pragma unroll
@@ -394,26 +409,42 @@ struct OpChebPost2 {
     const double* q;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
+    // gathers r0 itself; the 1/theta of d0 = r0/theta is applied to the sum
     __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<T, CPT>(r0 + size_t(c) * M + j0);
         Pack<AT, CPT> r;
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]) * inv_theta;
+        for (int t = 0; t < CPT; ++t) r.v[t] = AT(v.v[t]);
         return r;
     }
     template <int ND>
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
                                         double (&d)[ND][CPT]) const
     {
-        const auto ri = load_pack<T, CPT>(r0 + size_t(i) * M + j0);
+        out_self(i, j0, acc, false, Pack<AT, CPT>{}, d);
+    }
+    // r0_i from the gathered diagonal entry when the row kernel has it
+    static constexpr bool kWantSelf = true;
+    template <int ND>
+    __device__ __forceinline__ void out_self(int i, int j0, const AT (&acc)[CPT], bool have,
+                                             const Pack<AT, CPT>& rs, double (&d)[ND][CPT]) const
+    {
+        Pack<AT, CPT> ri;
+        if (have) {
+            ri = rs;
+        } else {
+            const auto rl = load_pack<T, CPT>(r0 + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) ri.v[t] = AT(rl.v[t]);
+        }
         const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
         const AT di = dinv[i];
         Pack<OT, CPT> o;
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
-            const AT d0 = AT(ri.v[t]) * inv_theta;
-            const AT r1 = AT(ri.v[t]) - di * acc[t];
+            const AT d0 = ri.v[t] * inv_theta;
+            const AT r1 = ri.v[t] - di * (acc[t] * inv_theta);
             const AT d1 = c1 * d0 + c2 * r1;
             o.v[t] = OT((AT(xi.v[t]) + d0) + d1);
         }
