@@ -661,11 +661,28 @@ __global__ __launch_bounds__(kGsThreads) void hgs_kernel(
         for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
             int cc[U];
             AT aa[U];
+            if constexpr (G > 1) {
+                // the G lanes of a group load every G-th entry and exchange them
+                constexpr int PL = (U + G - 1) / G;
+                int cown[PL];
+                AT aown[PL];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int k = k0 + u;
-                cc[u] = k < ke ? ci[k] : -1;
-                aa[u] = k < ke ? AT(val[k]) : AT(0);
+                for (int p = 0; p < PL; ++p) {
+                    const int u = g + G * p;
+                    const int k = k0 + u;
+                    const bool ok = u < U && k < ke;
+                    cown[p] = ok ? ci[k] : -1;
+                    aown[p] = ok ? AT(val[k]) : AT(0);
+                }
+                grp_share<G, U, PL, int>(cown, cc);
+                grp_share<G, U, PL, AT>(aown, aa);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int k = k0 + u;
+                    cc[u] = k < ke ? ci[k] : -1;
+                    aa[u] = k < ke ? AT(val[k]) : AT(0);
+                }
             }
             Pack<AT, CPT> vv[U];
 #pragma unroll
