@@ -89,21 +89,34 @@ struct OpBicgP {
         bool reset = false;
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
-            const int j = j0 + t;
-            if (!st->active[j]) continue;
-            if (st->pz[j]) {
+            if (!ac_[t]) continue;
+            if (pz_[t]) {
                 hi.v[t] = ri.v[t];
                 pi.v[t] = ri.v[t];
                 vi.v[t] = 0.0;
                 reset = true;
             } else {
-                pi.v[t] = ri.v[t] + st->beta[j] * (pi.v[t] - st->omega[j] * vi.v[t]);
+                pi.v[t] = ri.v[t] + be_[t] * (pi.v[t] - om_[t] * vi.v[t]);
             }
         }
         store_pack<double, CPT>(p + o, pi);
         if (reset) {
             store_pack<double, CPT>(v + o, vi);
             store_pack<double, CPT>(rh + o, hi);
+        }
+    }
+    // the lane's columns' coefficients and flags, loaded once per thread
+    static constexpr bool kBegin = true;
+    double be_[CPT] = {}, om_[CPT] = {};
+    int ac_[CPT] = {}, pz_[CPT] = {};
+    __device__ __forceinline__ void begin(int j0)
+    {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            ac_[t] = st->active[j0 + t];
+            pz_[t] = st->pz[j0 + t];
+            be_[t] = st->beta[j0 + t];
+            om_[t] = st->omega[j0 + t];
         }
     }
 };
@@ -131,10 +144,17 @@ struct OpBicgS {
         Pack<double, CPT> so;
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
-            so.v[t] = ri.v[t] - st->alpha[j0 + t] * vi.v[t];
+            so.v[t] = ri.v[t] - al_[t] * vi.v[t];
             d[0][t] += so.v[t] * so.v[t];
         }
         store_pack<double, CPT>(s + o, so);
+    }
+    static constexpr bool kBegin = true;
+    double al_[CPT] = {};
+    __device__ __forceinline__ void begin(int j0)
+    {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) al_[t] = st->alpha[j0 + t];
     }
 };
 
@@ -166,17 +186,28 @@ struct OpBicgXR {
         const auto hi = load_pack<double, CPT>(rh + o);
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int j = j0 + c;
-            if (st->active[j] && !st->skip[j]) {
-                const double a = st->alpha[j], w = st->omega[j];
-                xi.v[c] += a * pi.v[c] + w * qi.v[c];
-                ri.v[c] = si.v[c] - w * ti.v[c];
+            if (go_[c]) {
+                xi.v[c] += al_[c] * pi.v[c] + om_[c] * qi.v[c];
+                ri.v[c] = si.v[c] - om_[c] * ti.v[c];
             }
             d[0][c] += hi.v[c] * ri.v[c];
             d[1][c] += ri.v[c] * ri.v[c];
         }
         store_pack<double, CPT>(x + o, xi);
         store_pack<double, CPT>(r + o, ri);
+    }
+    static constexpr bool kBegin = true;
+    double al_[CPT] = {}, om_[CPT] = {};
+    int go_[CPT] = {};
+    __device__ __forceinline__ void begin(int j0)
+    {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int j = j0 + c;
+            go_[c] = st->active[j] && !st->skip[j];
+            al_[c] = st->alpha[j];
+            om_[c] = st->omega[j];
+        }
     }
 };
 

@@ -201,9 +201,17 @@ __device__ __forceinline__ void reduce_dots(double (&d)[ND > 0 ? ND : 1][CPT],
 //     Pack<AT, CPT> fetch_scaled(int c, int j0, AT scale(c))
 //   void out(int i, int j0, const AT (&acc)[CPT], double (&d)[ND][CPT])
 //   bool active_any()   -- false: whole op is a no-op (every column frozen)
+// ops that read per-column coefficients (Krylov alpha, beta, flags) load
+// them once per thread in begin(j0) instead of once per row
+template <class T, class = void>
+struct op_has_begin : std::false_type {};
+template <class T>
+struct op_has_begin<T, std::void_t<decltype(T::kBegin)>> : std::bool_constant<T::kBegin> {};
+
 template <int M, int CPT, int S, class Op>
-__global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* part)
+__global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, double* part)
 {
+    Op op = op_in;
     // G lanes share the columns of a row; S such groups split the row's
     // nonzeros (long rows of coarse levels) and combine their sums with a
     // fixed butterfly over the wavefront; U nonzeros per batch and group.
@@ -218,6 +226,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op, int nrows, double* 
     const int rl = threadIdx.x / (G * S);
     const int j0 = g * CPT;
     const int blk = blockIdx.x;
+    if constexpr (op_has_begin<Op>::value) op.begin(j0);
     double dsum[ND > 0 ? ND : 1][CPT];
 #pragma unroll
     for (int q = 0; q < (ND > 0 ? ND : 1); ++q)

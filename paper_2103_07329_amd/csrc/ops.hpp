@@ -490,15 +490,26 @@ struct OpUpdXR {
         const auto qi = load_pack<double, CPT>(q + o);
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
-            if (st->active[j0 + t]) {
-                const double a = st->alpha[j0 + t];
-                xi.v[t] += a * pi.v[t];
-                ri.v[t] -= a * qi.v[t];
+            if (ac_[t]) {
+                xi.v[t] += al_[t] * pi.v[t];
+                ri.v[t] -= al_[t] * qi.v[t];
             }
             d[0][t] += ri.v[t] * ri.v[t];
         }
         store_pack<double, CPT>(x + o, xi);
         store_pack<double, CPT>(r + o, ri);
+    }
+    // the lane's columns' alpha and active flag, loaded once per thread
+    static constexpr bool kBegin = true;
+    double al_[CPT] = {};
+    int ac_[CPT] = {};
+    __device__ __forceinline__ void begin(int j0)
+    {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            ac_[t] = st->active[j0 + t];
+            al_[t] = st->alpha[j0 + t];
+        }
     }
 };
 
@@ -524,11 +535,21 @@ struct OpUpdP {
         auto pi = load_pack<double, CPT>(p + o);
         const auto zi = load_pack<double, CPT>(z + o);
 #pragma unroll
-        for (int t = 0; t < CPT; ++t) {
-            const int j = j0 + t;
-            if (st->active[j]) pi.v[t] = st->pz[j] ? zi.v[t] : zi.v[t] + st->beta[j] * pi.v[t];
-        }
+        for (int t = 0; t < CPT; ++t)
+            if (ac_[t]) pi.v[t] = pz_[t] ? zi.v[t] : zi.v[t] + be_[t] * pi.v[t];
         store_pack<double, CPT>(p + o, pi);
+    }
+    static constexpr bool kBegin = true;
+    double be_[CPT] = {};
+    int ac_[CPT] = {}, pz_[CPT] = {};
+    __device__ __forceinline__ void begin(int j0)
+    {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            ac_[t] = st->active[j0 + t];
+            pz_[t] = st->pz[j0 + t];
+            be_[t] = st->beta[j0 + t];
+        }
     }
 };
 
@@ -555,8 +576,15 @@ struct OpAddActive {
         const auto zi = load_pack<double, CPT>(z + o);
 #pragma unroll
         for (int t = 0; t < CPT; ++t)
-            if (st->active[j0 + t]) xi.v[t] += zi.v[t];
+            if (ac_[t]) xi.v[t] += zi.v[t];
         store_pack<double, CPT>(x + o, xi);
+    }
+    static constexpr bool kBegin = true;
+    int ac_[CPT] = {};
+    __device__ __forceinline__ void begin(int j0)
+    {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) ac_[t] = st->active[j0 + t];
     }
 };
 
