@@ -35,6 +35,13 @@ constexpr int kBlock = 256;      // threads per block of the row kernels
 constexpr int kMaxDots = 2;      // dots per kernel
 constexpr int kNumXcd = 8;
 constexpr int kUnroll = 8;      // nonzeros per batch in the row loop
+// per-column smoother factors folded into each lane's own coefficients
+// before the exchange (instead of exchanging the factors)
+constexpr bool kFoldOwnScale = true;
+// ops that need the row's own input may take it from the gathered diagonal
+// entry instead of loading it again; with 16-byte lanes the extra registers
+// cost more than the load saves (whole-solve timing), so it is off
+constexpr bool kSelfCapture = false;
 
 // ---------------------------------------------------------------------------
 // vector loads/stores of CPT consecutive elements
@@ -234,14 +241,15 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
         for (int c = 0; c < CPT; ++c) dsum[q][c] = 0.0;
 
     if (op.active_any()) {
-        // XCD x (blocks are dealt to the 8 XCDs round-robin) owns a
-        // contiguous slab of tiles; its blocks sweep the slab together, so
-        // rows processed at the same time -- and the x entries they share --
-        // stay inside one XCD's L2.  A launch with one block per tile
-        // reduces to one tile per block in slab order.
+        // A sweeping launch (fewer blocks than tiles): XCD x (blocks are
+        // dealt to the 8 XCDs round-robin) owns a contiguous slab of tiles
+        // and its blocks sweep the slab together, so rows processed at the
+        // same time -- and the x entries they share -- stay inside one XCD's
+        // L2.  A launch with one block per tile takes tiles in block order
+        // (measured faster for that shape than slab order).
         const int ntiles = (nrows + RPB - 1) / RPB;
         int tb = 0, te = ntiles, t0 = blockIdx.x, tstep = gridDim.x;
-        if (gridDim.x % kNumXcd == 0) {
+        if (gridDim.x % kNumXcd == 0 && int(gridDim.x) < ntiles) {
             const int per = (ntiles + kNumXcd - 1) / kNumXcd;
             tb = (blockIdx.x % kNumXcd) * per;
             te = min(ntiles, tb + per);
@@ -267,14 +275,17 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                     for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
                         int cc[U];
                         AT aa[U];
-                        AT ss[U];   // per-column factors (scaled gathers only)
+                        // the G lanes of the row load every G-th entry of the
+                        // batch and exchange them (fewer load instructions
+                        // through the address units); with a per-column
+                        // factor, each lane folds it into its own entries'
+                        // coefficients after the gathers are issued and only
+                        // the products are exchanged
+                        constexpr bool fold_own = kFoldOwnScale && G > 1 && op_has_scale<Op>::value;
+                        constexpr int PL = (U + G - 1) / G;
+                        int cown[PL];
+                        AT aown[PL];
                         if constexpr (G > 1) {
-                            // the G lanes of the row load every G-th entry of
-                            // the batch and exchange them (fewer load
-                            // instructions through the address units)
-                            constexpr int PL = (U + G - 1) / G;
-                            int cown[PL];
-                            AT aown[PL];
 #pragma unroll
                             for (int q = 0; q < PL; ++q) {
                                 const int u = g + G * q;
@@ -284,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                                 aown[q] = ok ? AT(op.val[k]) : AT(0);
                             }
                             grp_share<G, U, PL, int>(cown, cc);
-                            grp_share<G, U, PL, AT>(aown, aa);
+                            if constexpr (!fold_own) grp_share<G, U, PL, AT>(aown, aa);
                         } else {
 #pragma unroll
                             for (int u = 0; u < U; ++u) {
@@ -293,16 +304,22 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                                 aa[u] = k < ke ? AT(op.val[k]) : AT(0);
                             }
                         }
+                        // padding entries (past the row's end) keep a zero
+                        // gathered value and a zero coefficient, so the
+                        // multiply-adds below need no per-entry condition
+                        // (a conditional update costs selects and registers)
                         Pack<AT, CPT> vv[U];
 #pragma unroll
-                        for (int u = 0; u < U; ++u)
+                        for (int u = 0; u < U; ++u) {
+                            vv[u] = Pack<AT, CPT>{};
                             if (cc[u] >= 0) {
                                 if constexpr (op_has_scale<Op>::value)
                                     vv[u] = op.fetch_raw(cc[u], j0);
                                 else
                                     vv[u] = op.fetch(cc[u], j0);
                             }
-                        if constexpr (op_wants_self<Op>::value && S == 1) {
+                        }
+                        if constexpr (kSelfCapture && op_wants_self<Op>::value && S == 1) {
 #pragma unroll
                             for (int u = 0; u < U; ++u)
                                 if (cc[u] == i) {
@@ -310,11 +327,16 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                                     have_self = true;
                                 }
                         }
-                        if constexpr (op_has_scale<Op>::value) {
+                        if constexpr (fold_own) {
                             // per-column factors of the gathered values, folded
                             // into the matrix coefficients
+#pragma unroll
+                            for (int q = 0; q < PL; ++q)
+                                aown[q] *= cown[q] >= 0 ? op.scale(cown[q]) : AT(0);
+                            grp_share<G, U, PL, AT>(aown, aa);
+                        } else if constexpr (op_has_scale<Op>::value) {
+                            AT ss[U];
                             if constexpr (G > 1) {
-                                constexpr int PL = (U + G - 1) / G;
                                 AT sown[PL];
 #pragma unroll
                                 for (int q = 0; q < PL; ++q) {
@@ -332,10 +354,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                         }
 #pragma unroll
                         for (int u = 0; u < U; ++u)
-                            if (cc[u] >= 0) {
 #pragma unroll
-                                for (int c = 0; c < CPT; ++c) acc[c] += aa[u] * vv[u].v[c];
-                            }
+                            for (int c = 0; c < CPT; ++c) acc[c] += aa[u] * vv[u].v[c];
                     }
                 }
                 if constexpr (S > 1) {
@@ -346,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                 }
             }
             if (live && sg == 0) {
-                if constexpr (op_wants_self<Op>::value)
+                if constexpr (kSelfCapture && op_wants_self<Op>::value)
                     op.out_self(i, j0, acc, have_self, self, dsum);
                 else
                     op.out(i, j0, acc, dsum);

@@ -406,6 +406,14 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     try {
         h->opt = o;
         h->stream = static_cast<hipStream_t>(o.stream);
+        {
+            int dev = 0, ncu = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) ==
+                    hipSuccess &&
+                ncu > 0)
+                h->num_cu = ncu;
+        }
         h->nlev = H->nlevels;
         h->lev.resize(h->nlev);
         const bool mixed = o.precision == XAMG_MIXED;

@@ -89,6 +89,7 @@ struct Handle : xamg_handle {
     dev::ColState* st_host = nullptr;
     double* part = nullptr;
     int nb_cap = 1024;
+    int num_cu = 256;            // compute units of the device (sizes sweeping launches)
     std::vector<void*> allocs;
     int autotune = 1;            // tune row splits on the first solve per M
     unsigned tuned_mask = 0;     // bit k: M = 2^k tuned
@@ -115,9 +116,12 @@ struct Handle : xamg_handle {
 template <typename T, int M>
 constexpr int cpt_for()
 {
-    // 32 bytes of the row's columns per lane (16 when fewer columns)
-    if constexpr (sizeof(T) == 8) return M >= 4 ? 4 : M;
-    else return M >= 8 ? 8 : M;
+    // 16 bytes of the row's columns per lane (one dwordx4 load per gathered
+    // nonzero): the lanes of a row then read each 64-byte piece of it with
+    // a single load instruction, which measured faster than 32 bytes per
+    // lane in two loads (fewer cache lines per instruction)
+    if constexpr (sizeof(T) == 8) return M >= 2 ? 2 : M;
+    else return M >= 4 ? 4 : M;
 }
 
 // groups of lanes that split one row's nonzeros, from the mean row length
@@ -133,6 +137,21 @@ inline int split_for(int64_t nnz, int nrows)
 // vector on some operators; the autotuner decides per operator).
 constexpr int kSweep = 16;
 
+// blocks of rows_kernel<M, CPT, S, Op> that the device holds at once (its
+// occupancy, from the kernel's registers and LDS, times the CU count)
+template <int M, int CPT, int S, class Op>
+int resident_blocks(const Handle& h)
+{
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, dev::rows_kernel<M, CPT, S, Op>,
+                                                         dev::kBlock, 0) != hipSuccess)
+            b = 1;
+        return std::max(1, b);
+    }();
+    return per_cu * h.num_cu;
+}
+
 template <int M, int CPT, int S, class Op>
 int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = false)
 {
@@ -140,9 +159,13 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     constexpr int RPB = dev::kBlock / (G * S);
     const int ntiles = (nrows + RPB - 1) / RPB;
     // one tile per block, unless the kernel has dot products (at most `cap`
-    // blocks so their partial sums stay few) or the operator sweeps
+    // blocks so their partial sums stay few) or the operator sweeps; a
+    // sweeping grid is no larger than what the device holds at once, so
+    // every block starts in the first round and none waits for a free slot
     const bool capped = Op::kDots > 0 || sweep;
-    int nb = std::max(1, capped ? std::min(ntiles, cap) : ntiles);
+    int nb = ntiles;
+    if (capped) nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h)});
+    nb = std::max(1, nb);
     if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
                        h.stream, op, nrows, h.part);
