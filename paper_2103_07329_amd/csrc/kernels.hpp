@@ -18,9 +18,9 @@
 //     finalize kernel adds the partials in block order (deterministic) and
 //     updates the Krylov scalars on the device.
 //
-// Each of the 8 XCDs (which receive blocks round-robin) owns one contiguous
-// eighth of the rows and its blocks sweep it together: neighbouring rows
-// share gathered x entries, so this keeps the reuse inside one XCD's L2.
+// Tiles of rows are taken in block order, so the device works on one
+// contiguous window of rows at a time and the x rows that neighbouring rows
+// share are reused from L2 or the memory-side cache.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -241,21 +241,14 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
         for (int c = 0; c < CPT; ++c) dsum[q][c] = 0.0;
 
     if (op.active_any()) {
-        // A sweeping launch (fewer blocks than tiles): XCD x (blocks are
-        // dealt to the 8 XCDs round-robin) owns a contiguous slab of tiles
-        // and its blocks sweep the slab together, so rows processed at the
-        // same time -- and the x entries they share -- stay inside one XCD's
-        // L2.  A launch with one block per tile takes tiles in block order
-        // (measured faster for that shape than slab order).
+        // tiles in block order: a launch with one block per tile, or a
+        // sweep by as many blocks as the device holds at once, each taking
+        // every gridDim-th tile, so the chip works on one contiguous window
+        // of rows at a time and the x rows they share stay in L2 or the
+        // memory-side cache between their uses (measured faster than giving
+        // each XCD a contiguous slab of its own)
         const int ntiles = (nrows + RPB - 1) / RPB;
-        int tb = 0, te = ntiles, t0 = blockIdx.x, tstep = gridDim.x;
-        if (gridDim.x % kNumXcd == 0 && int(gridDim.x) < ntiles) {
-            const int per = (ntiles + kNumXcd - 1) / kNumXcd;
-            tb = (blockIdx.x % kNumXcd) * per;
-            te = min(ntiles, tb + per);
-            t0 = tb + blockIdx.x / kNumXcd;
-            tstep = gridDim.x / kNumXcd;
-        }
+        const int t0 = blockIdx.x, te = ntiles, tstep = gridDim.x;
         for (int t = t0; t < te; t += tstep) {
             const int i = t * RPB + rl;
             const bool live = i < nrows;

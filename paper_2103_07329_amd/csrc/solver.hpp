@@ -132,9 +132,10 @@ inline int split_for(int64_t nnz, int nrows)
 }
 
 // A row split value is S (1, 2, 4 or 8 lane groups per row) plus kSweep
-// when the launch uses at most `cap` blocks that sweep their XCD's slab of
-// tiles instead of one block per tile (better L2 reuse of the gathered
-// vector on some operators; the autotuner decides per operator).
+// when the launch uses at most `cap` blocks (no more than the device holds
+// at once) that sweep the tiles instead of one block per tile (better
+// reuse of the gathered vector on most operators; the autotuner decides per
+// operator).
 constexpr int kSweep = 16;
 
 // blocks of rows_kernel<M, CPT, S, Op> that the device holds at once (its
@@ -166,7 +167,7 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     int nb = ntiles;
     if (capped) nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h)});
     nb = std::max(1, nb);
-    if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;
+    if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;   // even over the 8 XCDs
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
                        h.stream, op, nrows, h.part);
     return nb;
