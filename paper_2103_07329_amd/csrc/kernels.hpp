@@ -241,14 +241,24 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
         for (int c = 0; c < CPT; ++c) dsum[q][c] = 0.0;
 
     if (op.active_any()) {
-        // tiles in block order: a launch with one block per tile, or a
-        // sweep by as many blocks as the device holds at once, each taking
-        // every gridDim-th tile, so the chip works on one contiguous window
-        // of rows at a time and the x rows they share stay in L2 or the
-        // memory-side cache between their uses (measured faster than giving
-        // each XCD a contiguous slab of its own)
+        // Matrix passes take tiles in block order: a launch with one block
+        // per tile, or a sweep by as many blocks as the device holds at
+        // once, each taking every gridDim-th tile, so the chip works on one
+        // contiguous window of rows at a time and the x rows they share stay
+        // in L2 or the memory-side cache between their uses (measured faster
+        // than per-XCD slabs).  A sweeping row-wise vector op (pure
+        // streaming) gives each XCD (blocks are dealt to the 8 XCDs
+        // round-robin) a contiguous slab of tiles instead, which streams
+        // faster.
         const int ntiles = (nrows + RPB - 1) / RPB;
-        const int t0 = blockIdx.x, te = ntiles, tstep = gridDim.x;
+        int tb = 0, te = ntiles, t0 = blockIdx.x, tstep = gridDim.x;
+        if (!Op::kMatrix && gridDim.x % kNumXcd == 0 && int(gridDim.x) < ntiles) {
+            const int per = (ntiles + kNumXcd - 1) / kNumXcd;
+            tb = (blockIdx.x % kNumXcd) * per;
+            te = min(ntiles, tb + per);
+            t0 = tb + blockIdx.x / kNumXcd;
+            tstep = gridDim.x / kNumXcd;
+        }
         for (int t = t0; t < te; t += tstep) {
             const int i = t * RPB + rl;
             const bool live = i < nrows;
