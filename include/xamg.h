@@ -225,8 +225,9 @@ int xamg_batch_destroy(xamg_batch_t *b);
  * residual pass and on the pre-smoothing pass, which gathers b and D^-1),
  * time the SpMM for m columns with 1, 2, 4 and 8 lane groups splitting a
  * row's nonzeros, each with one block per tile of rows or with a sweeping
- * launch (at most 2048 blocks, each XCD's blocks walking its slab of tiles
- * together), with HIP events on the solver's stream, and keep the fastest.  Runs by itself
+ * launch (at most 2048 blocks and no more than the device holds at once,
+ * taking the tiles in block order), with HIP events on the solver's
+ * stream, and keep the fastest.  Runs by itself
  * on the first solve for each padded m; this call re-runs it now (enable
  * = 1) or switches automatic tuning off (enable = 0; the setup-time
  * row-length heuristic stays in use).  m in {1, 2, 4, 8, 16, 32}. */
@@ -238,6 +239,18 @@ int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
  * per row (1, 2, 4, 8) plus 16 when the pass uses the sweeping launch.
  * cap >= 4 * nlevels. */
 int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
+
+/* Set the row splits for m columns: the inverse of xamg_tuning, same layout
+ * (in[4l .. 4l+3] for A_l, A_l's pre-smoothing pass, P_l and R_l; entries
+ * 1..3 of the coarsest level are ignored), applied to the FP64 and the FP32
+ * copies.  Each value is 1, 2, 4 or 8 lane groups per row, plus 16 for the
+ * sweeping launch; a split wider than a wavefront allows for m (lanes per
+ * row x groups > 64) runs with the widest that fits.  Marks m as tuned, so
+ * the values stay until xamg_autotune(h, m, 1).  For callers that tune
+ * offline, and for tests that force every launch shape.  count >= 4 *
+ * nlevels.  Returns OK or EINVAL (null pointer, m, count or a value out of
+ * range); the handle is unchanged on error. */
+int xamg_set_tuning(xamg_handle_t *h, int32_t m, const int32_t *in, int32_t count);
 
 /* Kernel timer: while enabled, every launch of the selected kernel during
  * xamg_solve is bracketed by HIP events on the solver's stream, and

@@ -664,6 +664,45 @@ int xamg_tuning(const xamg_handle_t* hh, int32_t m, int32_t* out, int32_t cap)
     return XAMG_OK;
 }
 
+int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t count)
+{
+    xamg::clear_error();
+    Handle* h = static_cast<Handle*>(hh);
+    if (!h || !in) return xamg::fail(XAMG_EINVAL, "null argument");
+    if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
+        return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
+    if (count < 4 * h->nlev) return xamg::fail(XAMG_EINVAL, "input too short");
+    const auto valid = [](int v) {
+        const int s = v & ~xamg::kSweep;
+        return (v & ~(xamg::kSweep | 15)) == 0 && (s == 1 || s == 2 || s == 4 || s == 8);
+    };
+    for (int l = 0; l < h->nlev; ++l) {
+        const bool last = l + 1 == h->nlev;
+        for (int e = 0; e < (last ? 1 : 4); ++e)
+            if (!valid(in[4 * l + e])) {
+                xamg::set_error("split %d (level %d, entry %d) is not 1, 2, 4 or 8 (+16)",
+                                in[4 * l + e], l, e);
+                return XAMG_EINVAL;
+            }
+    }
+    int k = 0;
+    while ((1 << k) < m) ++k;
+    for (int l = 0; l < h->nlev; ++l) {
+        auto& L = h->lev[l];
+        const bool last = l + 1 == h->nlev;
+        for (xamg::DCsr* A : {&L.A64, &L.A32}) {
+            A->split[k] = in[4 * l];
+            if (!last) A->split_pre[k] = in[4 * l + 1];
+        }
+        if (last) continue;
+        L.P64.split[k] = L.P32.split[k] = in[4 * l + 2];
+        L.R64.split[k] = L.R32.split[k] = in[4 * l + 3];
+    }
+    h->tuned_mask |= 1u << k;
+    h->tune_epoch += 1;
+    return XAMG_OK;
+}
+
 int xamg_destroy(xamg_handle_t* hh)
 {
     Handle* h = static_cast<Handle*>(hh);

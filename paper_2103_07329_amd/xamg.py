@@ -71,7 +71,7 @@ EXPORTS = [
     "xamg_hierarchy_cf", "xamg_hierarchy_free", "xamg_default_options", "xamg_setup",
     "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_index16_fraction",
     "xamg_batch_create", "xamg_solve_batched", "xamg_batch_destroy",
-    "xamg_autotune", "xamg_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
+    "xamg_autotune", "xamg_tuning", "xamg_set_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
     "xamg_cnn_create", "xamg_cnn_get_weights", "xamg_cnn_set_weights", "xamg_cnn_pass",
     "xamg_cnn_get_grads", "xamg_cnn_adam", "xamg_cnn_layer", "xamg_warmstart",
@@ -113,6 +113,7 @@ def lib():
         L.xamg_batch_destroy.argtypes = [vp]
         L.xamg_autotune.argtypes = [vp, i32, i32]
         L.xamg_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
+        L.xamg_set_tuning.argtypes = [vp, i32, ctypes.POINTER(i32), i32]
         L.xamg_timer_enable.argtypes = [vp, i32]
         L.xamg_timer_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.xamg_destroy.argtypes = [vp]
@@ -341,6 +342,13 @@ class Solver:
         out = (ctypes.c_int32 * (4 * self.nlev))()
         _check(lib().xamg_tuning(self._h, m, out, len(out)), "xamg_tuning")
         return [tuple(out[4 * l:4 * l + 4]) for l in range(self.nlev)]
+
+    def set_tuning(self, m, splits):
+        """Force the row splits for m columns: one (A, A pre-smoothing, P, R)
+        tuple per level, as tuning() returns (see xamg_set_tuning)."""
+        flat = [int(v) for t in splits for v in t]
+        arr = (ctypes.c_int32 * len(flat))(*flat)
+        _check(lib().xamg_set_tuning(self._h, m, arr, len(flat)), "xamg_set_tuning")
 
     def timer_enable(self, kind):
         _check(lib().xamg_timer_enable(self._h, kind), "xamg_timer_enable")

@@ -1,0 +1,125 @@
+"""Every launch shape the autotuner can choose, forced through
+xamg_set_tuning: 1, 2, 4 or 8 lane groups per row, each with one block per
+tile or with the sweeping launch, on a jump-coefficient problem of 23^3 =
+12167 rows, which leaves a ragged last tile on every level.  For each shape:
+one V-cycle (Jacobi, Chebyshev, symmetric Gauss-Seidel) against the
+oracle's, element-wise within 1e-12 (FP64: only the rounding of fused
+multiply-adds and the order of the lane groups' partial sums differ), and
+PCG solves with the oracle's iteration counts (FP64) and a true residual
+within tolerance (mixed precision).  At m = 32 the 8-group split is wider
+than a wavefront allows and runs as 4 groups."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2103_07329_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [s | sw for s in (1, 2, 4, 8) for sw in (0, 16)]
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def xm():
+    from paper_2103_07329_amd import xamg
+    xamg.lib()
+    return xamg
+
+
+@pytest.fixture(scope="module")
+def jump23(orc):
+    rng = np.random.default_rng(2323)
+    p = inputs.jump7(23, inputs.jump_kappa(23, rng))
+    return p, orc.Hierarchy(*p.csr())
+
+
+def _relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _force(S, m, v):
+    S.set_tuning(m, [(v, v, v, v)] * S.nlev)
+    got = S.tuning(m)
+    assert got[0][0] == v and got[-1][0] == v
+    if S.nlev > 1:
+        assert got[0][1:] == (v, v, v)
+
+
+@pytest.mark.parametrize("m", [1, 16, 32])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
+def test_forced_shapes_vcycle(orc, torch, xm, jump23, smoother, m):
+    p, H = jump23
+    _say(f"[shapes vcycle] jump23 n={p.n} smoother={smoother} m={m}")
+    B = inputs.uniform_rhs(p.n, m, 230 + m)
+    Zref = H.vcycle(B, smoother=smoother, gs_block=8)
+    S = xm.Solver(H.export(), smoother=smoother, gs_block=8)
+    Bd = torch.from_numpy(B).cuda()
+    for v in SHAPES:
+        _force(S, m, v)
+        Zd = torch.full_like(Bd, float("nan"))
+        S.vcycle(Bd, Zd)
+        torch.cuda.synchronize()
+        Z = Zd.cpu().numpy()
+        assert np.isfinite(Z).all(), v
+        err = _relmax(Z, Zref)
+        _say(f"   split {v:2d}: rel err {err:.2e}")
+        assert err <= 1e-12, v
+    S.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_forced_shapes_pcg(orc, torch, xm, jump23, precision):
+    p, H = jump23
+    m = 8
+    _say(f"[shapes pcg] jump23 m={m} precision={precision}")
+    B = inputs.uniform_rhs(p.n, m, 239)
+    Xo, so, rco = H.solve(B, smoother=1, tol=1e-8)
+    assert rco == 0
+    import scipy.sparse as sp
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
+    S = xm.Solver(H.export(), smoother=1, precision=precision)
+    Bd = torch.from_numpy(B).cuda()
+    for v in SHAPES:
+        _force(S, m, v)
+        Xd = torch.zeros_like(Bd)
+        rc, st = S.solve(Bd, Xd, tol=1e-8)
+        assert rc == xm.OK, v
+        X = Xd.cpu().numpy()
+        tr = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+        _say(f"   split {v:2d}: iters {st['iters'].tolist()}, true relres {tr.max():.2e}")
+        assert np.all(tr <= 1e-8), v
+        if precision == 0:
+            assert np.array_equal(st["iters"], so["iters"]), v
+            err = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+            assert err.max() <= 1e-7, v
+    S.close()
+
+
+def test_set_tuning_rejects_bad_values(orc, torch, xm, jump23):
+    p, H = jump23
+    _say("[shapes] bad split values")
+    S = xm.Solver(H.export())
+    S.set_tuning(16, [(2, 4, 1, 8 | 16)] * S.nlev)
+    before = S.tuning(16)
+    for bad in (0, 3, 5, 32, 16, -1, 8 | 32):
+        with pytest.raises(xm.XamgError):
+            S.set_tuning(16, [(bad, 1, 1, 1)] + [(1, 1, 1, 1)] * (S.nlev - 1))
+        assert S.tuning(16) == before
+    with pytest.raises(xm.XamgError):
+        S.set_tuning(16, [(1, 1, 1, 1)] * (S.nlev - 1))   # too short
+    with pytest.raises(xm.XamgError):
+        S.set_tuning(12, [(1, 1, 1, 1)] * S.nlev)          # m not a power of two
+    S.close()
