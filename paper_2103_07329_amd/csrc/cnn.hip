@@ -13,9 +13,9 @@
 // out[r, co] = sum_t sum_ci W[co][ci][t] in[r + off(t), ci] (zero outside).
 //
 // Kernels: the two 16 -> 16 layers (about 94% of the flops) run on the
-// v_mfma_f32_16x16x32_bf16 matrix instruction: a wavefront owns 16
-// consecutive voxels x 16 output channels and takes two taps (32 = 2 x 16
-// input channels) per instruction; the input gradient of these layers is
+// v_mfma_f32_16x16x32_bf16 matrix instruction from an LDS-staged tile of the
+// input: a wavefront computes rows of 16 consecutive voxels x 16 output
+// channels and takes two taps (32 = 2 x 16 input channels) per instruction; the input gradient of these layers is
 // the same kernel with the weights mirrored and transposed, plus the ReLU
 // mask.  The 1 -> 16 and 16 -> 1 layers are VALU kernels.  Weight
 // gradients are LDS-staged FP32 reductions over voxels with per-block
@@ -111,44 +111,78 @@ __device__ inline void store16(uint16_t* p, const float* v)
 // tap pair p: rows k = 8*(lane/16) + j of the 32 x 16 block, i.e. tap
 // 2p + (lane/16)/2, input channel ((lane/16)&1)*8 + j, output channel
 // lane % 16.  out = relu?(acc) * (mask > 0 if mask) in BF16.
-__global__ __launch_bounds__(256) void conv16_mfma(const uint16_t* __restrict__ in,
-                                                   const uint4* __restrict__ wpk,
-                                                   uint16_t* __restrict__ out,
-                                                   const uint16_t* __restrict__ mask, int relu,
-                                                   int N)
+//
+// A block computes a tile of 16 (x) x 4 (y) x 4 (z) output voxels.  It first
+// stages the 18 x 6 x 6 input voxels around the tile (one-voxel halo, zero
+// outside the volume; 16 BF16 channels = 32 bytes each, 20.7 KB) in LDS, so
+// an input voxel is read from memory about 2.5 times per layer instead of
+// once per tap.  Wave w takes z-slice w of the tile: for each tap pair p it
+// reads the A fragments of its 4 rows (16 voxels each) from LDS and issues
+// 4 independent MFMAs, with the 14 packed B fragments held in registers.
+constexpr int kTX = 16, kTY = 4, kTZ = 4;            // output tile
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;               // 648 staged voxels
+
+__global__ __launch_bounds__(256) void conv16_lds(const uint16_t* __restrict__ in,
+                                                  const uint4* __restrict__ wpk,
+                                                  uint16_t* __restrict__ out,
+                                                  const uint16_t* __restrict__ mask, int relu,
+                                                  int N)
 {
-    const long n = long(N) * N * N;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long v0 = (long(blockIdx.x) * 4 + wave) * 16;
-    if (v0 >= n) return;
-    const int m = lane & 15, kq = lane >> 4;
-    const long v = v0 + m;
-    const bool vok = v < n;
-    const int x = int(v % N), y = int((v / N) % N), z = int(v / (long(N) * N));
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int ci0 = (kq & 1) * 8;
-#pragma unroll 2
-    for (int p = 0; p < kPairs; ++p) {
-        const int t = 2 * p + (kq >> 1);
-        uint4 a = make_uint4(0, 0, 0, 0);
-        long u;
-        if (vok && t < kTaps && neighbour(N, x, y, z, t, v, u))
-            a = *reinterpret_cast<const uint4*>(in + u * kC + ci0);
-        const uint4 b = wpk[p * 64 + lane];
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                     __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+    __shared__ uint4 tile[kHalo * 2];   // voxel h: tile[2h] channels 0-7, tile[2h+1] 8-15
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
+    for (int e = threadIdx.x; e < kHalo * 2; e += blockDim.x) {
+        const int h = e >> 1;
+        const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
+            v = *reinterpret_cast<const uint4*>(in + ((long(gz) * N + gy) * N + gx) * kC +
+                                                (e & 1) * 8);
+        tile[e] = v;
     }
-    // lane holds rows (voxels) 4*kq + j, column (channel) m
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int half = kq & 1, tsel = kq >> 1;
+    uint4 b[kPairs];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const long vv = v0 + 4 * kq + j;
-        if (vv >= n) continue;
-        float val = acc[j];
-        if (relu) val = fmaxf(val, 0.0f);
-        if (mask && !(bf2f(mask[vv * kC + m]) > 0.0f)) val = 0.0f;
-        out[vv * kC + m] = f2bf(val);
+    for (int p = 0; p < kPairs; ++p) b[p] = wpk[p * 64 + lane];
+    __syncthreads();
+    f32x4 acc[kTY];
+#pragma unroll
+    for (int r = 0; r < kTY; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) {
+        const int t = 2 * p + tsel;
+        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+        // voxel (m, row r, slice wave) shifted by the tap, in halo coordinates
+        const int h0 = ((wave + 1 + dz) * kHY + (1 + dy)) * kHX + (m + 1 + dx);
+#pragma unroll
+        for (int r = 0; r < kTY; ++r) {
+            uint4 a = make_uint4(0, 0, 0, 0);
+            if (t < kTaps) a = tile[(h0 + r * kHX) * 2 + half];
+            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                            __builtin_bit_cast(bf16x8, b[p]),
+                                                            acc[r], 0, 0, 0);
+        }
+    }
+    // lane holds rows (voxels) 4*kq + j of each 16-voxel row, column (channel) m
+#pragma unroll
+    for (int r = 0; r < kTY; ++r) {
+        const long v0 = (long(z0 + wave) * N + (y0 + r)) * N + x0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long vv = v0 + 4 * kq + j;
+            float val = acc[r][j];
+            if (relu) val = fmaxf(val, 0.0f);
+            if (mask && !(bf2f(mask[vv * kC + m]) > 0.0f)) val = 0.0f;
+            out[vv * kC + m] = f2bf(val);
+        }
     }
 }
+
+// one block per output tile (N is a multiple of 16, so tiles are whole)
+inline dim3 conv16_grid(int N) { return dim3(N / kTX, N / kTY, N / kTZ); }
 
 // ---------------------------------------------------------------------------
 // 1 -> 16 layer (VALU), ReLU, BF16 out.  w: [co][t] BF16-valued floats.
@@ -595,13 +629,13 @@ struct Net : xamg_cnn {
     void forward()
     {
         hipLaunchKernelGGL(conv_in1, dim3(grid(n)), dim3(256), 0, stream, a0, w1b, a1, N);
-        const int nb16 = int((n + 63) / 64);
+        const dim3 g16 = conv16_grid(N);
         tbegin(XAMG_CNN_TIMER_CONV16);
-        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, a1, pack(0), a2,
+        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, a1, pack(0), a2,
                            static_cast<const uint16_t*>(nullptr), 1, N);
         tend(XAMG_CNN_TIMER_CONV16);
         tbegin(XAMG_CNN_TIMER_CONV16);
-        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, a2, pack(2), a3,
+        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, a2, pack(2), a3,
                            static_cast<const uint16_t*>(nullptr), 1, N);
         tend(XAMG_CNN_TIMER_CONV16);
         hipLaunchKernelGGL(conv_out1, dim3(grid(n)), dim3(256), 0, stream, a3, w4b, y, N);
@@ -610,7 +644,7 @@ struct Net : xamg_cnn {
     // backward of one sample (dy set); weight gradients accumulate into g
     void backward()
     {
-        const int nb16 = int((n + 63) / 64);
+        const dim3 g16 = conv16_grid(N);
         const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         // layer 4: dW4 and g3 = W4^T dy masked by a3 > 0
         hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, stream,
@@ -625,7 +659,7 @@ struct Net : xamg_cnn {
         tend(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
                            kParams2, g + kParams1 + kParams2);
-        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
+        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
         // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g2,
@@ -633,7 +667,7 @@ struct Net : xamg_cnn {
         tend(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
                            kParams2, g + kParams1);
-        hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
+        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
         // layer 1: dW1 from (g1, a0)
         hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, stream, g1,
                            static_cast<const float*>(nullptr), a0, N, wpart);
@@ -830,7 +864,7 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
     try {
         const long n = net->n;
         const int N = net->N;
-        const int nb16 = int((n + 63) / 64);
+        const dim3 g16 = conv16_grid(N);
         const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         const uint16_t* i16 = static_cast<const uint16_t*>(in);
         const uint16_t* m16 = static_cast<const uint16_t*>(mask);
@@ -842,7 +876,7 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
                 hipLaunchKernelGGL(conv_out1, dim3(net->grid(n)), dim3(256), 0, net->stream, i16,
                                    net->w4b, static_cast<float*>(out), N);
             else
-                hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, net->stream, i16,
+                hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, net->stream, i16,
                                    net->pack(layer == 2 ? 0 : 2), static_cast<uint16_t*>(out),
                                    static_cast<const uint16_t*>(nullptr), 1, N);
         } else if (mode == 1) {
@@ -853,7 +887,7 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
                                    static_cast<const float*>(in), net->w4b, m16,
                                    static_cast<uint16_t*>(out), N);
             else
-                hipLaunchKernelGGL(conv16_mfma, dim3(nb16), dim3(256), 0, net->stream, i16,
+                hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, net->stream, i16,
                                    net->pack(layer == 2 ? 1 : 3), static_cast<uint16_t*>(out), m16,
                                    0, N);
         } else {
