@@ -104,7 +104,9 @@ struct Idx16 {
 // ---------------------------------------------------------------------------
 // value of lane K of the caller's group of G consecutive lanes (groups
 // aligned to G): DPP quad permutes for G = 2, 4 (vector ALU moves), a
-// shuffle for larger groups
+// bit-mode swizzle for G = 8, 16 (the source lane (l & ~(G-1)) | K within
+// each 32-lane half is encoded in the instruction, so no address register
+// is held per broadcast), a shuffle for G = 32, 64
 // ---------------------------------------------------------------------------
 template <int G, int K>
 __device__ __forceinline__ int grp_bcast(int v)
@@ -114,6 +116,8 @@ __device__ __forceinline__ int grp_bcast(int v)
     else if constexpr (G == 2)
         return __builtin_amdgcn_mov_dpp(v, K | (K << 2) | ((K + 2) << 4) | ((K + 2) << 6), 0xF,
                                         0xF, false);
+    else if constexpr (G == 8 || G == 16)
+        return __builtin_amdgcn_ds_swizzle(v, (0x1f & ~(G - 1)) | (K << 5));
     else
         return __shfl(v, ((threadIdx.x & 63) & ~(G - 1)) + K, 64);
 }

@@ -137,6 +137,7 @@ inline int split_for(int64_t nnz, int nrows)
 // reuse of the gathered vector on most operators; the autotuner decides per
 // operator).
 constexpr int kSweep = 16;
+constexpr int kSweepPerCu = 5;
 
 // blocks of rows_kernel<M, CPT, S, Op> that the device holds at once (its
 // occupancy, from the kernel's registers and LDS, times the CU count)
@@ -162,10 +163,14 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     // one tile per block, unless the kernel has dot products (at most `cap`
     // blocks so their partial sums stay few) or the operator sweeps; a
     // sweeping grid is no larger than what the device holds at once, so
-    // every block starts in the first round and none waits for a free slot
+    // every block starts in the first round and none waits for a free slot,
+    // and has at most kSweepPerCu blocks per CU (the window of rows the
+    // sweep works on at a time; measured best on 7- and 19-point rows
+    // whatever the occupancy)
     const bool capped = Op::kDots > 0 || sweep;
     int nb = ntiles;
-    if (capped) nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h)});
+    if (capped)
+        nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h), kSweepPerCu * h.num_cu});
     nb = std::max(1, nb);
     if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;   // even over the 8 XCDs
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
