@@ -618,8 +618,9 @@ void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
 // the first solve (or on request); setup cost, not solve cost.
 // ---------------------------------------------------------------------------
 // kind: 0 = residual pass r = b - A x (the post-smoothing and residual
-// passes gather x), 1 = plain product y = Op x (transfer operators),
-// 2 = pre-smoothing pass from zero (gathers b and D^-1)
+// passes gather x), 1 = plain product y = Op x (restriction),
+// 2 = pre-smoothing pass from zero (gathers b and D^-1), 3 = prolongation
+// y += Op x (reads and writes the fine vector)
 template <int M, typename T>
 float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x, T* y, T* z,
               hipEvent_t e0, hipEvent_t e1)
@@ -635,6 +636,9 @@ float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             } else if (kind == 1) {
                 OpAx<M, CPT, T, T, IX, 0> op{d.rp, av, ix, x, y, nullptr};
+                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
+            } else if (kind == 3) {
+                OpProlongAdd<M, CPT, T, T, IX> op{d.rp, av, ix, x, y, nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             } else if (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) {
                 OpChebPre<M, CPT, T, T, T, IX> op{d.rp, av, ix, dinv, T(1), T(0), T(0), x, y,
@@ -731,12 +735,12 @@ void autotune(Handle& h)
         }
         if (!last) {
             if (!mixed) {
-                tune_matrix<M, double>(h, L.P64, 1, L.dinv64, x, y, z, e0, e1);
+                tune_matrix<M, double>(h, L.P64, 3, L.dinv64, x, y, z, e0, e1);
                 tune_matrix<M, double>(h, L.R64, 1, L.dinv64, x, y, z, e0, e1);
             } else {
                 tune_matrix<M, float>(h, L.A32, 0, L.dinv32, xf, yf, zf, e0, e1);
                 tune_matrix<M, float>(h, L.A32, 2, L.dinv32, xf, yf, zf, e0, e1);
-                tune_matrix<M, float>(h, L.P32, 1, L.dinv32, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.P32, 3, L.dinv32, xf, yf, zf, e0, e1);
                 tune_matrix<M, float>(h, L.R32, 1, L.dinv32, xf, yf, zf, e0, e1);
             }
         }

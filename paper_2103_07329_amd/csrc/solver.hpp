@@ -164,13 +164,14 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     // blocks so their partial sums stay few) or the operator sweeps; a
     // sweeping grid is no larger than what the device holds at once, so
     // every block starts in the first round and none waits for a free slot,
-    // and has at most kSweepPerCu blocks per CU (the window of rows the
-    // sweep works on at a time; measured best on 7- and 19-point rows
-    // whatever the occupancy)
+    // and a matrix pass has at most kSweepPerCu blocks per CU (the window of
+    // rows the sweep works on at a time; measured best on 7- and 19-point
+    // rows whatever the occupancy; streaming vector ops use every slot)
     const bool capped = Op::kDots > 0 || sweep;
     int nb = ntiles;
     if (capped)
-        nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h), kSweepPerCu * h.num_cu});
+        nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h),
+                       Op::kMatrix ? kSweepPerCu * h.num_cu : ntiles});
     nb = std::max(1, nb);
     if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;   // even over the 8 XCDs
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
