@@ -343,6 +343,10 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
     const T* av = static_cast<const T*>(A.v);
 
     const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
+    if (!gs && !A.vd) {
+        set_error("internal: level %d has no column-scaled matrix for pre-smoothing", l);
+        throw DevFail{XAMG_EINVAL};
+    }
     // pre-smoothing from zero (+ residual)
     with_idx(A, [&](auto ix) {
         using IX = decltype(ix);
@@ -356,11 +360,13 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
             OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
             launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
         } else if (!cheb2) {
-            OpJacPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, omega, b, X, R, na};
+            const T* avd = static_cast<const T*>(A.vd);
+            OpJacPre<M, CPT, T, T, BT, IX> op{rp, avd, ix, dinv, omega, b, X, R, na};
             launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
         } else {
-            OpChebPre<M, CPT, T, T, BT, IX> op{rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1),
+            const T* avd = static_cast<const T*>(A.vd);
+            OpChebPre<M, CPT, T, T, BT, IX> op{rp, avd, ix, dinv, T(1.0 / ch.theta), T(ch.c1),
                                                T(ch.c2), b, X, na};
             launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
@@ -641,11 +647,12 @@ float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x
                 OpProlongAdd<M, CPT, T, T, IX> op{d.rp, av, ix, x, y, nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             } else if (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) {
-                OpChebPre<M, CPT, T, T, T, IX> op{d.rp, av, ix, dinv, T(1), T(0), T(0), x, y,
-                                                  nullptr};
+                OpChebPre<M, CPT, T, T, T, IX> op{d.rp, static_cast<const T*>(d.vd), ix, dinv, T(1),
+                                                  T(0), T(0), x, y, nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             } else {
-                OpJacPre<M, CPT, T, T, T, IX> op{d.rp, av, ix, dinv, T(0.5), x, y, z, nullptr};
+                OpJacPre<M, CPT, T, T, T, IX> op{d.rp, static_cast<const T*>(d.vd), ix, dinv, T(0.5),
+                                                 x, y, z, nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
             }
         };
@@ -687,6 +694,7 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
     constexpr int G = M / cpt_for<T, M>();
     constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
     if (!d.rp || d.nr == 0) return;
+    if (kind == 2 && !d.vd) return;   // no pre-smoothing pass (Gauss-Seidel smoother)
     // candidates from the simplest launch up; a later one replaces the
     // current choice only when it is more than 3% faster, so that near-ties
     // (within the timing noise) resolve the same way from run to run

@@ -35,9 +35,6 @@ constexpr int kBlock = 256;      // threads per block of the row kernels
 constexpr int kMaxDots = 2;      // dots per kernel
 constexpr int kNumXcd = 8;
 constexpr int kUnroll = 8;      // nonzeros per batch in the row loop
-// per-column smoother factors folded into each lane's own coefficients
-// before the exchange (instead of exchanging the factors)
-constexpr bool kFoldOwnScale = true;
 // ops that need the row's own input may take it from the gathered diagonal
 // entry instead of loading it again; with 16-byte lanes the extra registers
 // cost more than the load saves (whole-solve timing), so it is off
@@ -156,12 +153,6 @@ struct op_wants_self : std::false_type {};
 template <class T>
 struct op_wants_self<T, std::void_t<decltype(T::kWantSelf)>> : std::bool_constant<T::kWantSelf> {};
 
-// ops whose gathered value carries a per-column factor (a smoother's
-// D^-1 on the fly) expose it as scale(c) and take it in fetch_scaled
-template <class T, class = void>
-struct op_has_scale : std::false_type {};
-template <class T>
-struct op_has_scale<T, std::void_t<decltype(&T::scale)>> : std::true_type {};
 
 // ---------------------------------------------------------------------------
 // block-level deterministic reduction of per-column dots
@@ -208,8 +199,6 @@ __device__ __forceinline__ void reduce_dots(double (&d)[ND > 0 ? ND : 1][CPT],
 //   static constexpr int kDots     -- per-column dots produced (0..2)
 //   const int* rp; const MT* val; Idx idx;
 //   Pack<AT, CPT> fetch(int c, int j0)   the gathered input in(c, j0..j0+CPT)
-//     or, for a gathered input with a per-column factor: AT scale(int c) and
-//     Pack<AT, CPT> fetch_scaled(int c, int j0, AT scale(c))
 //   void out(int i, int j0, const AT (&acc)[CPT], double (&d)[ND][CPT])
 //   bool active_any()   -- false: whole op is a no-op (every column frozen)
 // ops that read per-column coefficients (Krylov alpha, beta, flags) load
@@ -282,17 +271,13 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                     for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
                         int cc[U];
                         AT aa[U];
-                        // the G lanes of the row load every G-th entry of the
-                        // batch and exchange them (fewer load instructions
-                        // through the address units); with a per-column
-                        // factor, each lane folds it into its own entries'
-                        // coefficients after the gathers are issued and only
-                        // the products are exchanged
-                        constexpr bool fold_own = kFoldOwnScale && G > 1 && op_has_scale<Op>::value;
-                        constexpr int PL = (U + G - 1) / G;
-                        int cown[PL];
-                        AT aown[PL];
                         if constexpr (G > 1) {
+                            // the G lanes of the row load every G-th entry of
+                            // the batch and exchange them (fewer load
+                            // instructions through the address units)
+                            constexpr int PL = (U + G - 1) / G;
+                            int cown[PL];
+                            AT aown[PL];
 #pragma unroll
                             for (int q = 0; q < PL; ++q) {
                                 const int u = g + G * q;
@@ -302,7 +287,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                                 aown[q] = ok ? AT(op.val[k]) : AT(0);
                             }
                             grp_share<G, U, PL, int>(cown, cc);
-                            if constexpr (!fold_own) grp_share<G, U, PL, AT>(aown, aa);
+                            grp_share<G, U, PL, AT>(aown, aa);
                         } else {
 #pragma unroll
                             for (int u = 0; u < U; ++u) {
@@ -319,12 +304,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             vv[u] = Pack<AT, CPT>{};
-                            if (cc[u] >= 0) {
-                                if constexpr (op_has_scale<Op>::value)
-                                    vv[u] = op.fetch_raw(cc[u], j0);
-                                else
-                                    vv[u] = op.fetch(cc[u], j0);
-                            }
+                            if (cc[u] >= 0) vv[u] = op.fetch(cc[u], j0);
                         }
                         if constexpr (kSelfCapture && op_wants_self<Op>::value && S == 1) {
 #pragma unroll
@@ -333,31 +313,6 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, doubl
                                     self = vv[u];
                                     have_self = true;
                                 }
-                        }
-                        if constexpr (fold_own) {
-                            // per-column factors of the gathered values, folded
-                            // into the matrix coefficients
-#pragma unroll
-                            for (int q = 0; q < PL; ++q)
-                                aown[q] *= cown[q] >= 0 ? op.scale(cown[q]) : AT(0);
-                            grp_share<G, U, PL, AT>(aown, aa);
-                        } else if constexpr (op_has_scale<Op>::value) {
-                            AT ss[U];
-                            if constexpr (G > 1) {
-                                AT sown[PL];
-#pragma unroll
-                                for (int q = 0; q < PL; ++q) {
-                                    const int u = g + G * q;
-                                    const int c = u < U ? cc[u < U ? u : 0] : -1;
-                                    sown[q] = c >= 0 ? op.scale(c) : AT(0);
-                                }
-                                grp_share<G, U, PL, AT>(sown, ss);
-                            } else {
-#pragma unroll
-                                for (int u = 0; u < U; ++u) ss[u] = cc[u] >= 0 ? op.scale(cc[u]) : AT(0);
-                            }
-#pragma unroll
-                            for (int u = 0; u < U; ++u) aa[u] *= ss[u];
                         }
 #pragma unroll
                         for (int u = 0; u < U; ++u)

@@ -16,10 +16,11 @@
 //                r1 = r0 - D^-1 A d0, d1 = c1 d0 + c2 r1, x2 = x1 + d1
 //              (Saad, Iterative Methods for Sparse Linear Systems,
 //              Algorithm 12.1, two steps).
-// From a zero guess the first pass needs no product with x, so the
-// pre-smoother computes the gathered values (w D^-1 b for Jacobi, D^-1 b /
-// theta for Chebyshev) on the fly and fuses the residual (Jacobi) or the
-// second Chebyshev step into the same pass over A.
+// From a zero guess the first pass needs no product with x: the
+// pre-smoother gathers b itself against the column-scaled matrix A D^-1
+// (stored once at setup), scales the row sum by w (Jacobi) or 1/theta
+// (Chebyshev), and fuses the residual (Jacobi) or the second Chebyshev step
+// into the same pass over A.
 #pragma once
 
 #include "kernels.hpp"
@@ -193,7 +194,7 @@ struct OpJacPre {
     static constexpr bool kMatrix = true;
     static constexpr int kDots = 0;
     const int* rp;
-    const MT* val;
+    const MT* val;       // column-scaled values a_ij d_j (A D^-1)
     IdxT idx;
     const MT* dinv;
     MT omega;
@@ -202,11 +203,9 @@ struct OpJacPre {
     T* r;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    // the gathered value is (w d_c) b_c: rows_kernel gathers b_c, loads the
-    // factor w d_c once per nonzero for the row's lanes and folds it into
-    // the matrix coefficient
-    __device__ __forceinline__ AT scale(int c) const { return omega * dinv[c]; }
-    __device__ __forceinline__ Pack<AT, CPT> fetch_raw(int c, int j0) const
+    // gathers b_c; the row sum is (A D^-1 b)_i, and x = w D^-1 b gives
+    // (A x)_i = w (A D^-1 b)_i
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
         Pack<AT, CPT> r;
@@ -224,7 +223,7 @@ struct OpJacPre {
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
             xo.v[t] = T(wd * AT(bi.v[t]));
-            ro.v[t] = T(AT(bi.v[t]) - acc[t]);
+            ro.v[t] = T(AT(bi.v[t]) - omega * acc[t]);
         }
         store_pack<T, CPT>(x + size_t(i) * M + j0, xo);
         store_pack<T, CPT>(r + size_t(i) * M + j0, ro);
@@ -310,7 +309,7 @@ struct OpChebPre {
     static constexpr bool kMatrix = true;
     static constexpr int kDots = 0;
     const int* rp;
-    const MT* val;
+    const MT* val;       // column-scaled values a_ij d_j (A D^-1)
     IdxT idx;
     const MT* dinv;
     MT inv_theta, c1, c2;   // 1 / theta, precomputed on the host
@@ -318,10 +317,9 @@ struct OpChebPre {
     T* x;
     const int* nactive;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
-    // gathered value (d_c / theta) b_c; the factor is folded into the matrix
-    // coefficient by rows_kernel
-    __device__ __forceinline__ AT scale(int c) const { return dinv[c] * inv_theta; }
-    __device__ __forceinline__ Pack<AT, CPT> fetch_raw(int c, int j0) const
+    // gathers b_c; the row sum is (A D^-1 b)_i = theta (A d0)_i with
+    // d0 = D^-1 b / theta
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
         const auto v = load_pack<BT, CPT>(b + size_t(c) * M + j0);
         Pack<AT, CPT> r;
@@ -340,7 +338,7 @@ struct OpChebPre {
         for (int t = 0; t < CPT; ++t) {
             const AT r0 = AT(bi.v[t]) * di;
             const AT d0 = r0 * inv_theta;
-            const AT r1 = r0 - di * acc[t];
+            const AT r1 = r0 - di * (acc[t] * inv_theta);
             const AT d1 = c1 * d0 + c2 * r1;
             o.v[t] = T(d0 + d1);
         }

@@ -444,6 +444,18 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
                 std::vector<float> df(d.begin(), d.end());
                 L.dinv32 = xamg::upload(*h, df.data(), df.size());
             }
+            if (o.smoother != XAMG_GAUSS_SEIDEL && l + 1 < h->nlev) {
+                // A D^-1 for the pre-smoothing pass from zero (which gathers
+                // b_j d_j), in the precision the V-cycle runs in
+                std::vector<double> vd(size_t(a.nnz));
+                for (int64_t k = 0; k < a.nnz; ++k) vd[k] = a.val[k] * d[a.col[k]];
+                if (mixed) {
+                    std::vector<float> vf(vd.begin(), vd.end());
+                    L.A32.vd = xamg::upload(*h, vf.data(), vf.size());
+                } else {
+                    L.A64.vd = xamg::upload(*h, vd.data(), vd.size());
+                }
+            }
             if (o.smoother == XAMG_GAUSS_SEIDEL && l + 1 < h->nlev) {
                 // l1 diagonal of the Gauss-Seidel blocks: a_ii plus the
                 // absolute couplings to rows outside the row's block

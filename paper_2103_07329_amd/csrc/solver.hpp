@@ -27,6 +27,10 @@ struct DCsr {
     int* rp = nullptr;
     int* ci = nullptr;
     void* v = nullptr;
+    // values scaled by the inverse diagonal of their column (a_ij / a_jj,
+    // i.e. A D^-1) for the Jacobi / Chebyshev pre-smoothing pass from zero;
+    // same type as v; null where no such pass runs
+    void* vd = nullptr;
     bool fp32 = false;
     uint16_t* off = nullptr;
     int4* base = nullptr;
