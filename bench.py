@@ -65,6 +65,48 @@ def presmooth_bytes(n, nnz, m, vb=8, ib=4, bb=8, xb=8, jacobi=False):
             + (n * m * xb if jacobi else 0))
 
 
+def pcg_iteration_bytes(S, m, chebyshev, mixed, flexible, idx16=None):
+    """Algorithmic bytes of one PCG iteration: every array each kernel of
+    the iteration reads or writes, counted once per kernel.  The V-cycle is
+    Jacobi or Chebyshev-2 V(1,1) (FP32 vectors and values when mixed; its
+    level-0 input r and output z are FP64), then the Krylov SpMM q = A p
+    with its dot, x += a p and r -= a q with (r, r), and p = z + b p.
+    idx16[l] = fraction of 16-bit column indices of (A_l, P_l, R_l)."""
+    n, nnzA, nnzP, L = S.sizes, S.nnzA, S.nnzP, S.nlev
+    vb = 4 if mixed else 8
+    tot = 0.0
+    for l in range(L):
+        V = n[l] * m * vb
+        if l == L - 1:
+            tot += n[l] * n[l] * vb + 2 * V        # dense inverse, b in, x out
+            continue
+        ibA, ibP, ibR = ((2 * f + 4 * (1 - f)) for f in idx16[l]) if idx16 else (4, 4, 4)
+        MA = nnzA[l] * (vb + ibA) + 4 * (n[l] + 1)
+        MP = nnzP[l] * (vb + ibP) + 4 * (n[l] + 1)
+        MR = nnzP[l] * (vb + ibR) + 4 * (n[l + 1] + 1)
+        Vc = n[l + 1] * m * vb
+        d = n[l] * vb                              # D^-1
+        io = n[l] * m * 8 if l == 0 else V         # level-0 input r / output z (FP64)
+        if chebyshev:
+            tot += MA + io + d + V                 # pre: gather b (A D^-1), D^-1, write x
+            tot += MA + V + io + V                 # residual
+        else:
+            tot += MA + io + d + 2 * V             # pre: gather b, D^-1, write x and r
+        tot += MR + V + Vc                         # restriction
+        tot += MP + Vc + 2 * V                     # prolongation add
+        if chebyshev:
+            tot += MA + V + io + d + V             # post 1: gather x, b, D^-1, write r0
+            tot += MA + V + V + d + io             # post 2: gather r0, x, D^-1, write z
+        else:
+            tot += MA + V + io + d + io            # post: gather x, b, D^-1, write z
+        if l == 0:
+            tot += n[0] * m * 8 * (1 if flexible else 0) + (0 if not chebyshev else n[0] * m * 8)
+    V0 = n[0] * m * 8
+    tot += nnzA[0] * 12 + 4 * (n[0] + 1) + 2 * V0  # q = A p (FP64)
+    tot += 6 * V0 + 3 * V0                         # x, r update; p update
+    return tot
+
+
 def stored_traffic(workload, kernel):
     """HBM bytes per launch from the committed PMC summary of this
     workload/kernel, if it was taken on the current kernel sources."""
@@ -262,6 +304,27 @@ def main():
     log(f"[bench] {args.steps} solves: {ms_step:.3f} ms/solve, {ms_step / m:.3f} ms/RHS, "
         f"iters {iters0.tolist()}, max true relres {tr0:.2e}")
 
+    iteration = None
+    smo = opts["smoother"]
+    if opts["method"] == xamg.CG and smo in (xamg.JACOBI, xamg.CHEBYSHEV):
+        idx16 = None
+        if mixed and opts.get("index_bits", 32) == 16:
+            import ctypes
+            idx16 = []
+            for l in range(S.nlev - 1):
+                fr = (ctypes.c_double * 3)()
+                xamg.lib().xamg_index16_fraction(S._h, l, fr)
+                idx16.append(tuple(fr))
+        ib = pcg_iteration_bytes(S, m, smo == xamg.CHEBYSHEV, mixed,
+                                 flexible=mixed, idx16=idx16)
+        it = int(iters0.max())
+        gbs_it = ib * it / (ms_step * 1e-3) / 1e9
+        iteration = {"bytes": ib, "iters": it, "ms_per_iteration": ms_step / it,
+                     "achieved_gbs": gbs_it, "frac": gbs_it / HBM_PEAK_GBS}
+        log(f"[bench] whole PCG iteration: {ib / 1e6:.0f} MB algorithmic, "
+            f"{ms_step / it:.3f} ms -> {gbs_it:.0f} GB/s ({gbs_it / HBM_PEAK_GBS:.1%} of peak; "
+            f"start and final residual check included in the time)")
+
     dom = max(kernels, key=lambda k: kernels[k]["total_ms_per_step"])
     K = kernels[dom]
     traffic = stored_traffic(wl, dom)
@@ -370,10 +433,12 @@ def main():
             "workload": desc, "n": prob.n, "nnz": prob.nnz, "m": m, "tol": 1e-8,
             "iters": int(iters0.max()), "levels": S.nlev,
             "operator_complexity": round(sum(nnzA) / nnzA[0], 3),
+            "grid_complexity": round(sum(S.sizes) / S.sizes[0], 3),
             "host_setup_s": round(t_setup, 2),
         },
         "roofline": roofline,
         "kernels": kernels,
+        "iteration": iteration,
         "cpu_baseline": cpu,
     }
     out.update(extras)
