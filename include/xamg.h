@@ -234,10 +234,11 @@ int xamg_batch_destroy(xamg_batch_t *b);
 int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
 
 /* Row splits in use for m columns: out[4l .. 4l+3] = split of A_l (the
- * residual and post-smoothing passes), of A_l's pre-smoothing pass, of P_l
- * and of R_l (0 where the operator or pass does not exist): the lane groups
- * per row (1, 2, 4, 8) plus 16 when the pass uses the sweeping launch.
- * cap >= 4 * nlevels. */
+ * residual and post-smoothing passes), of A_l's pre-smoothing pass (with
+ * the Gauss-Seidel smoother: of its sweeps, lane groups per block of rows),
+ * of P_l and of R_l (0 where the operator or pass does not exist): the lane
+ * groups per row (1, 2, 4, 8) plus 16 when the pass uses the sweeping
+ * launch.  cap >= 4 * nlevels. */
 int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
 
 /* Set the row splits for m columns: the inverse of xamg_tuning, same layout

@@ -236,10 +236,12 @@ template <typename T>
 static const T* dl1_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dl1inv64; else return L.dl1inv32; }
 
 // one l1-hybrid Gauss-Seidel sweep over the rows of A (block size from the
-// options: 4, 8 or 16 rows; lane groups per block from A's row split)
+// options: 4, 8 or 16 rows; `split` lane groups per block, normally A's
+// Gauss-Seidel split, tuned on its own and kept in the pre-smoothing slot,
+// since this smoother has no separate pre-smoothing pass)
 template <int M, bool BWD, bool ZERO, typename MT, typename XT, typename BT, typename OT>
 static void launch_hgs(Handle& h, const DCsr& A, const MT* dl1, const BT* b, const XT* xo, OT* xn,
-                       const int* na)
+                       const int* na, int split)
 {
     constexpr int CPT = cpt_for<MT, M>();
     constexpr int G = M / CPT;
@@ -255,7 +257,7 @@ static void launch_hgs(Handle& h, const DCsr& A, const MT* dl1, const BT* b, con
                            dim3(kGsThreads), 0, h.stream, A.rp, A.ci, av, dl1, b, xo, xn, n, na);
     };
     auto with_s = [&](auto blk) {
-        const int s = A.template split_of<M>() & (kSweep - 1);
+        const int s = split & (kSweep - 1);
         if constexpr (G * 8 <= kGsThreads) {
             if (s >= 8) return go(blk, std::integral_constant<int, 8>{});
         }
@@ -354,9 +356,11 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
         if (gs) {
             // symmetric sweep from zero: forward into T, backward into X
             const T* dl1 = dl1_of<T>(L);
-            launch_hgs<M, false, true>(h, A, dl1, b, static_cast<const T*>(nullptr), Tb, na);
+            launch_hgs<M, false, true>(h, A, dl1, b, static_cast<const T*>(nullptr), Tb, na,
+                                       A.template split_pre_of<M>());
             if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
-            launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), X, na);
+            launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), X, na,
+                                       A.template split_pre_of<M>());
             OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
             launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
         } else if (!cheb2) {
@@ -402,8 +406,10 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
                 // symmetric sweep: forward X -> T, backward T -> xout; the
                 // finest level's dots in a pass of their own
                 const T* dl1 = dl1_of<T>(L);
-                launch_hgs<M, false, false>(h, A, dl1, b, static_cast<const T*>(X), Tb, na);
-                launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), xout, na);
+                launch_hgs<M, false, false>(h, A, dl1, b, static_cast<const T*>(X), Tb, na,
+                                            A.template split_pre_of<M>());
+                launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), xout, na,
+                                           A.template split_pre_of<M>());
                 if constexpr (D > 0) {
                     if constexpr (std::is_same<BT, double>::value && std::is_same<OT, double>::value) {
                         constexpr int CPD = cpt_for<double, M>();
@@ -625,8 +631,9 @@ void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
 // ---------------------------------------------------------------------------
 // kind: 0 = residual pass r = b - A x (the post-smoothing and residual
 // passes gather x), 1 = plain product y = Op x (restriction),
-// 2 = pre-smoothing pass from zero (gathers b and D^-1), 3 = prolongation
-// y += Op x (reads and writes the fine vector)
+// 2 = pre-smoothing pass from zero (gathers b against A D^-1), or with the
+// Gauss-Seidel smoother a forward sweep (dinv = its l1 diagonal), 3 =
+// prolongation y += Op x (reads and writes the fine vector)
 template <int M, typename T>
 float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x, T* y, T* z,
               hipEvent_t e0, hipEvent_t e1)
@@ -646,6 +653,9 @@ float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x
             } else if (kind == 3) {
                 OpProlongAdd<M, CPT, T, T, IX> op{d.rp, av, ix, x, y, nullptr};
                 launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
+            } else if (h.opt.smoother == XAMG_GAUSS_SEIDEL) {
+                launch_hgs<M, false, false>(h, d, dinv, static_cast<const T*>(z),
+                                            static_cast<const T*>(x), y, nullptr, split);
             } else if (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) {
                 OpChebPre<M, CPT, T, T, T, IX> op{d.rp, static_cast<const T*>(d.vd), ix, dinv, T(1),
                                                   T(0), T(0), x, y, nullptr};
@@ -694,7 +704,8 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
     constexpr int G = M / cpt_for<T, M>();
     constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
     if (!d.rp || d.nr == 0) return;
-    if (kind == 2 && !d.vd) return;   // no pre-smoothing pass (Gauss-Seidel smoother)
+    const bool gs_sweep = kind == 2 && h.opt.smoother == XAMG_GAUSS_SEIDEL;
+    if (kind == 2 && !gs_sweep && !d.vd) return;
     // candidates from the simplest launch up; a later one replaces the
     // current choice only when it is more than 3% faster, so that near-ties
     // (within the timing noise) resolve the same way from run to run
@@ -703,6 +714,7 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
     for (int S : {1, 2, 4, 8}) {
         if (G * S > 64) break;
         for (int sw : {0, kSweep}) {
+            if (gs_sweep && sw) continue;   // the sweep kernel has one launch shape
             const float t = time_op<M, T>(h, d, kind, dinv, S | sw, x, y, z, e0, e1);
             if ((S == 1 && sw == 0) || t < 0.97f * best) {
                 best = t;
@@ -726,6 +738,7 @@ void autotune(Handle& h)
     h.check(hipEventCreate(&e0), "hipEventCreate");
     h.check(hipEventCreate(&e1), "hipEventCreate");
     const bool mixed = h.opt.precision == XAMG_MIXED;
+    const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
     double* x = h.w.r;
     double* y = h.w.z;
     double* z = h.w.p;   // right-hand side of the residual pass (finite: zeroed)
@@ -739,7 +752,8 @@ void autotune(Handle& h)
         const bool last = l + 1 == h.nlev;
         if (l == 0 || !mixed) {
             tune_matrix<M, double>(h, L.A64, 0, L.dinv64, x, y, z, e0, e1);
-            if (!last && !mixed) tune_matrix<M, double>(h, L.A64, 2, L.dinv64, x, y, z, e0, e1);
+            if (!last && !mixed)
+                tune_matrix<M, double>(h, L.A64, 2, gs ? L.dl1inv64 : L.dinv64, x, y, z, e0, e1);
         }
         if (!last) {
             if (!mixed) {
@@ -747,7 +761,8 @@ void autotune(Handle& h)
                 tune_matrix<M, double>(h, L.R64, 1, L.dinv64, x, y, z, e0, e1);
             } else {
                 tune_matrix<M, float>(h, L.A32, 0, L.dinv32, xf, yf, zf, e0, e1);
-                tune_matrix<M, float>(h, L.A32, 2, L.dinv32, xf, yf, zf, e0, e1);
+                tune_matrix<M, float>(h, L.A32, 2, gs ? L.dl1inv32 : L.dinv32, xf, yf, zf, e0,
+                                      e1);
                 tune_matrix<M, float>(h, L.P32, 3, L.dinv32, xf, yf, zf, e0, e1);
                 tune_matrix<M, float>(h, L.R32, 1, L.dinv32, xf, yf, zf, e0, e1);
             }
