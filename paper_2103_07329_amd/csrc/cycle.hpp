@@ -397,7 +397,12 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
             launch_mat<M, CPT>(h, op, Pm.template split_of<M>(), Pm.nr, cap);
         });
     }
-    // post-smoothing (+ finest-level dots)
+    // post-smoothing (+ finest-level dots).  The last pass of the finest
+    // level of a mixed cycle writes the FP64 z and reads the FP64 b (and q)
+    // of its dots: it takes the FP64 lane layout (16 bytes of those rows per
+    // lane; measured 3% faster on the mixed solve than the FP32 layout's
+    // two loads per lane)
+    constexpr int CPO = sizeof(OT) > sizeof(T) ? cpt_for<OT, M>() : CPT;
     with_idx(A, [&](auto ix) {
         using IX = decltype(ix);
         auto post = [&](auto dots_tag) {
@@ -421,15 +426,15 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
                     }
                 }
             } else if (!cheb2) {
-                OpJacPost<M, CPT, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
+                OpJacPost<M, CPO, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
                                                           q, na};
-                nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), L.n, cap);
+                nb = launch_mat<M, CPO>(h, op, A.template split_of<M>(), L.n, cap);
             } else {
                 OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
                 launch_mat<M, CPT>(h, p1, A.template split_of<M>(), L.n, cap);
-                OpChebPost2<M, CPT, T, T, BT, OT, IX, D> p2{
+                OpChebPost2<M, CPO, T, T, BT, OT, IX, D> p2{
                     rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
-                nb = launch_mat<M, CPT>(h, p2, A.template split_of<M>(), L.n, cap);
+                nb = launch_mat<M, CPO>(h, p2, A.template split_of<M>(), L.n, cap);
             }
         };
         if (ndots == 2) post(std::integral_constant<int, 2>{});
