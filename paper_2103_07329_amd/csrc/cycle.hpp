@@ -310,7 +310,8 @@ struct OpDotsBX {
 // also accumulates the dots (b, xout) [and (q, xout)].  Returns the block
 // count of the last launch (the one that wrote partial dots).
 template <int M, typename T, typename BT, typename OT>
-static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q)
+static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q,
+                  const double* bd = nullptr)
 {
     constexpr int CPT = cpt_for<T, M>();
     const LevelDev& L = h.lev[l];
@@ -427,13 +428,14 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
                 }
             } else if (!cheb2) {
                 OpJacPost<M, CPO, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
-                                                          q, na};
+                                                          q, na, bd};
                 nb = launch_mat<M, CPO>(h, op, A.template split_of<M>(), L.n, cap);
             } else {
                 OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
                 launch_mat<M, CPT>(h, p1, A.template split_of<M>(), L.n, cap);
                 OpChebPost2<M, CPO, T, T, BT, OT, IX, D> p2{
-                    rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na};
+                    rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na,
+                    bd};
                 nb = launch_mat<M, CPO>(h, p2, A.template split_of<M>(), L.n, cap);
             }
         };
@@ -447,7 +449,8 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
 // z = M^-1 r for the whole hierarchy; returns the block count of the
 // launch that produced the finest-level dots (0 if ndots == 0).
 template <int M>
-int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q)
+int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q,
+           const float* r32)
 {
     constexpr int CPT = cpt_for<double, M>();
     if (h.nlev == 1) {
@@ -461,7 +464,12 @@ int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q)
         OpDotsBX<M, CPT, 1> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
         return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
     }
-    if (h.opt.precision == XAMG_MIXED) return vlevel<M, float, double, double>(h, 0, r, z, ndots, q);
+    if (h.opt.precision == XAMG_MIXED) {
+        // with an FP32 copy of r the finest level gathers and reads that copy,
+        // and only the dots of its last pass read the FP64 r
+        if (r32) return vlevel<M, float, float, double>(h, 0, r32, z, ndots, q, r);
+        return vlevel<M, float, double, double>(h, 0, r, z, ndots, q);
+    }
     return vlevel<M, double, double, double>(h, 0, r, z, ndots, q);
 }
 
@@ -484,10 +492,19 @@ void pcg_precondition(Handle& h)
     constexpr int CPT = cpt_for<double, M>();
     const int flex = pcg_flex<M>(h);
     const int nd = flex ? 2 : 1;
-    const int nb = vcycle<M>(h, h.w.r, h.w.z, nd, h.w.q);
+    const int nb = vcycle<M>(h, h.w.r, h.w.z, nd, h.w.q, h.w.r32);
     launch_fin(h, nb, nd * M, FinBeta{h.st, M, flex});
     OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.p, h.w.z};
     launch_rows<M, CPT>(h, up, h.lev[0].n, h.nb_cap);
+}
+
+// r32 = float(r), where a pass other than OpUpdXR has rewritten r
+template <int M>
+void sync_r32(Handle& h)
+{
+    if (!h.w.r32) return;
+    hipLaunchKernelGGL((copy_cols_kernel<double, float>), dim3(2048), dim3(256), 0, h.stream,
+                       h.w.r, M, h.w.r32, M, h.lev[0].n, M);
 }
 
 // r = b - A x, column state (the first iteration computes z = M^-1 r, p = z)
@@ -515,6 +532,7 @@ void pcg_start(Handle& h, const double* B, double* X, double tol)
     if (pcg_flex<M>(h))
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                            nullptr, M, h.w.q, M, n, 0);
+    sync_r32<M>(h);
 }
 
 // one iteration: z = M^-1 r, beta, p = z + beta p (beta = 0 on a column's
@@ -539,7 +557,7 @@ void pcg_iteration(Handle& h, double* X)
         launch_fin(h, nb, M, FinAlpha{st, M});
     }
     {
-        OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, h.w.r, h.w.p, h.w.q};
+        OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, h.w.r, h.w.p, h.w.q, h.w.r32};
         const int nb = launch_rows<M, CPT>(h, op, n, h.nb_cap);
         launch_fin(h, nb, M, FinRR{st, M});
     }
@@ -564,6 +582,7 @@ int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
     if (nr > 0) {
         OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.r, h.w.t, nullptr};
         launch_rows<M, CPT>(h, cp, n, h.nb_cap);
+        sync_r32<M>(h);
     }
     return nr;
 }

@@ -4,7 +4,7 @@
 
 namespace xamg {
 
-template int vcycle<32>(Handle&, const double*, double*, int, const double*);
+template int vcycle<32>(Handle&, const double*, double*, int, const double*, const float*);
 template int pcg<32>(Handle&, const double*, double*, double);
 template int mg_solve<32>(Handle&, const double*, double*, double);
 template int bicgstab<32>(Handle&, const double*, double*, double);

@@ -4,7 +4,7 @@
 
 namespace xamg {
 
-template int vcycle<8>(Handle&, const double*, double*, int, const double*);
+template int vcycle<8>(Handle&, const double*, double*, int, const double*, const float*);
 template int pcg<8>(Handle&, const double*, double*, double);
 template int mg_solve<8>(Handle&, const double*, double*, double);
 template int bicgstab<8>(Handle&, const double*, double*, double);

@@ -250,6 +250,8 @@ struct OpJacPost {
     OT* xo;
     const double* q;
     const int* nactive;
+    // FP64 right-hand side for the dot (b, xo) when b itself is an FP32 copy
+    const double* bd = nullptr;
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
     __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
     {
@@ -287,8 +289,14 @@ struct OpJacPost {
             o.v[t] = OT(xi.v[t] + wd * (AT(bi.v[t]) - acc[t]));
         store_pack<OT, CPT>(xo + size_t(i) * M + j0, o);
         if constexpr (DOT >= 1) {
+            if (bd) {
+                const auto bv = load_pack<double, CPT>(bd + size_t(i) * M + j0);
 #pragma unroll
-            for (int t = 0; t < CPT; ++t) d[0][t] += double(bi.v[t]) * double(o.v[t]);
+                for (int t = 0; t < CPT; ++t) d[0][t] += bv.v[t] * double(o.v[t]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < CPT; ++t) d[0][t] += double(bi.v[t]) * double(o.v[t]);
+            }
         }
         if constexpr (DOT >= 2) {
             const auto qi = load_pack<double, CPT>(q + size_t(i) * M + j0);
@@ -406,6 +414,20 @@ struct OpChebPost2 {
     OT* xo;
     const double* q;
     const int* nactive;
+    // FP64 right-hand side for the dot (b, xo) when b itself is an FP32 copy
+    const double* bd = nullptr;
+    __device__ __forceinline__ Pack<double, CPT> dot_b(int i, int j0) const
+    {
+        Pack<double, CPT> v;
+        if (bd) {
+            v = load_pack<double, CPT>(bd + size_t(i) * M + j0);
+        } else {
+            const auto bl = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) v.v[t] = double(bl.v[t]);
+        }
+        return v;
+    }
     __device__ __forceinline__ bool active_any() const { return !nactive || *nactive > 0; }
     // gathers r0 itself; the 1/theta of d0 = r0/theta is applied to the sum
     __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
@@ -448,9 +470,9 @@ struct OpChebPost2 {
         }
         store_pack<OT, CPT>(xo + size_t(i) * M + j0, o);
         if constexpr (DOT >= 1) {
-            const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+            const auto bi = dot_b(i, j0);
 #pragma unroll
-            for (int t = 0; t < CPT; ++t) d[0][t] += double(bi.v[t]) * double(o.v[t]);
+            for (int t = 0; t < CPT; ++t) d[0][t] += bi.v[t] * double(o.v[t]);
         }
         if constexpr (DOT >= 2) {
             const auto qi = load_pack<double, CPT>(q + size_t(i) * M + j0);
@@ -475,6 +497,7 @@ struct OpUpdXR {
     const ColState* st;
     double *x, *r;
     const double *p, *q;
+    float* r32 = nullptr;   // optional FP32 copy of r (input of a mixed V-cycle)
     __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
     __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
@@ -496,6 +519,12 @@ struct OpUpdXR {
         }
         store_pack<double, CPT>(x + o, xi);
         store_pack<double, CPT>(r + o, ri);
+        if (r32) {
+            Pack<float, CPT> rf;
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) rf.v[t] = float(ri.v[t]);
+            store_pack<float, CPT>(r32 + o, rf);
+        }
     }
     // the lane's columns' alpha and active flag, loaded once per thread
     static constexpr bool kBegin = true;

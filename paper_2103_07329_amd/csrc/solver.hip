@@ -186,6 +186,7 @@ void ensure_work(Handle& h, int mp, bool bicg)
     for (double* p : {h.w.r, h.w.z, h.w.p, h.w.q, h.w.t, h.w.rh, h.w.v, h.w.s, h.w.ph, h.w.sh,
                       h.w.xpad, h.w.bpad})
         h.release(p);
+    h.release(h.w.r32);
     const int mc = std::max(mp, h.w.mcap);
     h.w = Work{};
     h.w.mcap = mc;
@@ -209,6 +210,9 @@ void ensure_work(Handle& h, int mp, bool bicg)
     h.w.p = h.alloc<double>(n0);
     h.w.q = h.alloc<double>(n0);
     h.w.t = h.alloc<double>(n0);
+    if (h.opt.precision == XAMG_MIXED && h.opt.method == XAMG_CG &&
+        h.opt.smoother != XAMG_GAUSS_SEIDEL && h.nlev > 1)
+        h.w.r32 = h.alloc<float>(n0);
     if (bicg) {
         h.w.rh = h.alloc<double>(n0);
         h.w.v = h.alloc<double>(n0);

@@ -79,6 +79,9 @@ struct Work {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
     double *rh = nullptr, *v = nullptr, *s = nullptr, *ph = nullptr, *sh = nullptr;
     double *bpad = nullptr, *xpad = nullptr;
+    // FP32 copy of r for the finest level of a mixed CG V-cycle (Jacobi or
+    // Chebyshev smoother), kept equal to float(r) wherever r changes
+    float* r32 = nullptr;
 };
 
 struct Handle : xamg_handle {
@@ -228,7 +231,8 @@ __device__ __forceinline__ void recount_active(dev::ColState* st, int M)
 
 // ---- solver entry points (explicitly instantiated for M = 1..32) ----------
 template <int M>
-int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q);
+int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q,
+           const float* r32 = nullptr);
 template <int M>
 int pcg(Handle& h, const double* B, double* X, double tol);
 template <int M>
