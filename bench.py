@@ -283,11 +283,14 @@ def main():
             continue
         avg_ms = tms / cnt
         if kind == xamg.TIMER_PRESMOOTH:
-            # (the Gauss-Seidel sweeps always read 32-bit column indices)
+            # (the Gauss-Seidel sweeps always read 32-bit column indices; with
+            # the Jacobi or Chebyshev smoother a mixed cycle gathers the FP32
+            # copy of its FP64 input that the Krylov step writes)
             gsw = opts["smoother"] == xamg.GAUSS_SEIDEL
             nbytes = presmooth_bytes(prob.n, prob.nnz, m, vb=vb32,
                                      ib=ib32 if mixed and not gsw else 4,
-                                     bb=8, xb=vb32, jacobi=opts["smoother"] == xamg.JACOBI)
+                                     bb=4 if mixed and not gsw else 8, xb=vb32,
+                                     jacobi=opts["smoother"] == xamg.JACOBI)
             what = {xamg.CHEBYSHEV: "Chebyshev", xamg.JACOBI: "Jacobi",
                     xamg.GAUSS_SEIDEL: "Gauss-Seidel forward sweep"}[opts["smoother"]]
             kdesc = (f"rows_kernel<{m}> {what} pre-smoothing pass from zero, finest level "

@@ -76,6 +76,7 @@ struct OpBicgP {
     const ColState* st;
     const double* r;
     double *p, *v, *rh;
+    float* p32 = nullptr;   // optional FP32 copy of p (input of a mixed V-cycle)
     __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
     __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
@@ -100,6 +101,12 @@ struct OpBicgP {
             }
         }
         store_pack<double, CPT>(p + o, pi);
+        if (p32) {
+            Pack<float, CPT> pf;
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) pf.v[t] = float(pi.v[t]);
+            store_pack<float, CPT>(p32 + o, pf);
+        }
         if (reset) {
             store_pack<double, CPT>(v + o, vi);
             store_pack<double, CPT>(rh + o, hi);
@@ -133,6 +140,7 @@ struct OpBicgS {
     const ColState* st;
     const double *r, *v;
     double* s;
+    float* s32 = nullptr;   // optional FP32 copy of s (input of a mixed V-cycle)
     __device__ __forceinline__ bool active_any() const { return st->nactive > 0; }
     __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
     template <int ND>
@@ -148,6 +156,12 @@ struct OpBicgS {
             d[0][t] += so.v[t] * so.v[t];
         }
         store_pack<double, CPT>(s + o, so);
+        if (s32) {
+            Pack<float, CPT> sf;
+#pragma unroll
+            for (int t = 0; t < CPT; ++t) sf.v[t] = float(so.v[t]);
+            store_pack<float, CPT>(s32 + o, sf);
+        }
     }
     static constexpr bool kBegin = true;
     double al_[CPT] = {};
@@ -480,21 +494,21 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         }
         ++it;
         {
-            OpBicgP<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, r, p, v, rh};
+            OpBicgP<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, r, p, v, rh, h.w.p32};
             launch_rows<M, CPT>(h, op, n, cap);
         }
-        vcycle<M>(h, p, ph, 0, nullptr);
+        vcycle<M>(h, p, ph, 0, nullptr, h.w.p32);
         {
             OpAxW<M, CPT, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, ph, v, rh, na};
             const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
             launch_fin(h, nb, M, FinAlphaB{st, M});
         }
         {
-            OpBicgS<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, r, v, s};
+            OpBicgS<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, r, v, s, h.w.s32};
             const int nb = launch_rows<M, CPT>(h, op, n, cap);
             launch_fin(h, nb, M, FinHalf{st, M});
         }
-        vcycle<M>(h, s, sh, 0, nullptr);
+        vcycle<M>(h, s, sh, 0, nullptr, h.w.s32);
         {
             OpAxW<M, CPT, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, sh, t, s, na};
             const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);

@@ -187,6 +187,8 @@ void ensure_work(Handle& h, int mp, bool bicg)
                       h.w.xpad, h.w.bpad})
         h.release(p);
     h.release(h.w.r32);
+    h.release(h.w.p32);
+    h.release(h.w.s32);
     const int mc = std::max(mp, h.w.mcap);
     h.w = Work{};
     h.w.mcap = mc;
@@ -213,6 +215,11 @@ void ensure_work(Handle& h, int mp, bool bicg)
     if (h.opt.precision == XAMG_MIXED && h.opt.method == XAMG_CG &&
         h.opt.smoother != XAMG_GAUSS_SEIDEL && h.nlev > 1)
         h.w.r32 = h.alloc<float>(n0);
+    if (bicg && h.opt.precision == XAMG_MIXED && h.opt.smoother != XAMG_GAUSS_SEIDEL &&
+        h.nlev > 1) {
+        h.w.p32 = h.alloc<float>(n0);
+        h.w.s32 = h.alloc<float>(n0);
+    }
     if (bicg) {
         h.w.rh = h.alloc<double>(n0);
         h.w.v = h.alloc<double>(n0);

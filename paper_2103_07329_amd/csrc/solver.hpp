@@ -79,9 +79,11 @@ struct Work {
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
     double *rh = nullptr, *v = nullptr, *s = nullptr, *ph = nullptr, *sh = nullptr;
     double *bpad = nullptr, *xpad = nullptr;
-    // FP32 copy of r for the finest level of a mixed CG V-cycle (Jacobi or
-    // Chebyshev smoother), kept equal to float(r) wherever r changes
+    // FP32 copies of the finest-level inputs of a mixed V-cycle (Jacobi or
+    // Chebyshev smoother): r for CG, kept equal to float(r) wherever r
+    // changes; p and s for BiCGStab, written by the passes that form them
     float* r32 = nullptr;
+    float *p32 = nullptr, *s32 = nullptr;
 };
 
 struct Handle : xamg_handle {
