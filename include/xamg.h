@@ -109,6 +109,10 @@ typedef struct {
     int32_t flexible;      /* CG beta: 0 Fletcher-Reeves, 1 flexible; MIXED forces 1 */
     int32_t check_every;   /* host convergence poll period in iterations, default 1 */
     int32_t gs_block;      /* Gauss-Seidel block size in rows: 4, 8 (default) or 16 */
+    int32_t precond;       /* 1 (default): the AMG V-cycle preconditions the Krylov
+                              method; 0: no preconditioner (M = I; Table 1 lists the
+                              Krylov solvers apart from their preconditioners).
+                              MG requires 1. */
     void *stream;          /* hipStream_t for all work; NULL = the null stream */
 } xamg_options_t;
 
@@ -118,6 +122,10 @@ typedef struct {
     int32_t converged;   /* 1 if ||b - A x|| / ||b|| <= tol */
     double relres;       /* recurrence residual norm / ||b|| at exit */
     double true_relres;  /* ||b - A x|| / ||b|| recomputed at exit (FP64) */
+    int32_t restarts;    /* times the column restarted: true-residual restarts
+                            (the recurrence residual passed, the recomputed one
+                            did not) plus BiCGStab breakdown restarts */
+    int32_t reserved;    /* 0 */
 } xamg_stats_t;
 
 typedef struct xamg_host_hierarchy xamg_host_hierarchy_t;

@@ -965,7 +965,7 @@ static void apply_prec(const ohier *h, const kopt *ko, const smopt *so, int m,
 
 static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
                const double *B, double *X, int *iters, double *relres,
-               int *conv, vws *w)
+               int *conv, int *restarts, vws *w)
 {
     const ocsr *A = &h->A[0];
     int n = A->nr, j, it, i, rc = ORC_OK;
@@ -994,7 +994,7 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
     dots(n, m, r, r, rr);
     for (j = 0; j < m; j++) {
         bn[j] = sqrt(bn[j]);
-        iters[j] = 0; conv[j] = 0; act[j] = 1;
+        iters[j] = 0; conv[j] = 0; act[j] = 1; restarts[j] = 0;
         if (bn[j] == 0.0) {
             for (i = 0; i < n; i++) X[(size_t)i * m + j] = 0.0;
             relres[j] = 0.0; conv[j] = 1; act[j] = 0;
@@ -1048,6 +1048,7 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
                     }
                     relres[j] = tr;
                     rst[j] = 1;
+                    restarts[j]++;
                 }
             }
         }
@@ -1107,7 +1108,7 @@ static void bicg_reset(int n, int m, int j, const double *r, double *rh, double 
 
 static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
                     const double *B, double *X, int *iters, double *relres,
-                    int *conv, vws *w)
+                    int *conv, int *restarts, vws *w)
 {
     const ocsr *A = &h->A[0];
     int n = A->nr, j, it, rc = ORC_OK;
@@ -1145,7 +1146,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
     for (j = 0; j < m; j++) {
         bn[j] = sqrt(bn[j]);
         rho[j] = alp[j] = omg[j] = 1.0;
-        iters[j] = 0; conv[j] = 0; act[j] = 1;
+        iters[j] = 0; conv[j] = 0; act[j] = 1; restarts[j] = 0;
         if (bn[j] == 0.0) {
             for (i = 0; i < (size_t)n; i++) X[i * m + j] = 0.0;
             relres[j] = 0.0; conv[j] = 1; act[j] = 0;
@@ -1178,6 +1179,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
                 bicg_reset(n, m, j, r, rh, p, v);
                 rho[j] = alp[j] = omg[j] = 1.0;
                 d1[j] = dot_col(n, m, j, rh, r);
+                restarts[j]++;
             }
             beta[j] = (d1[j] / rho[j]) * (alp[j] / omg[j]);
             rho[j] = d1[j];
@@ -1202,6 +1204,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
             if (fabs(d1[j]) <= tiny) {
                 if (++brk[j] >= 2) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
                 rst[j] = 1; skip[j] = 1;
+                restarts[j]++;
                 continue;
             }
             alp[j] = rho[j] / d1[j];
@@ -1250,6 +1253,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
                 if (omg[j] == 0.0) {
                     if (++brk[j] >= 2) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
                     rst[j] = 1;
+                    restarts[j]++;
                 } else {
                     brk[j] = 0;
                 }
@@ -1270,6 +1274,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
                     }
                     relres[j] = tr;
                     rst[j] = 1;
+                    restarts[j]++;
                 }
             }
         }
@@ -1291,7 +1296,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
  */
 static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
                    const double *B, double *X, int *iters, double *relres, int *conv,
-                   vws *w)
+                   int *restarts, vws *w)
 {
     const ocsr *A = &h->A[0];
     int n = A->nr, j, it, i;
@@ -1309,7 +1314,7 @@ static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
     dots(n, m, r, r, rr);
     for (j = 0; j < m; j++) {
         bn[j] = sqrt(bn[j]);
-        iters[j] = 0; conv[j] = 0; act[j] = 1;
+        iters[j] = 0; conv[j] = 0; act[j] = 1; restarts[j] = 0;
         if (bn[j] == 0.0) {
             for (i = 0; i < n; i++) X[(size_t)i * m + j] = 0.0;
             relres[j] = 0.0; conv[j] = 1; act[j] = 0;
@@ -1343,12 +1348,14 @@ static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
 /*
  * Solve A X = B (A = level 0 of h).  X is the initial guess when x0_given,
  * the solution on return.  Per-column outputs: iterations, recurrence
- * relative residual, true relative residual, converged flag.
+ * relative residual, true relative residual, converged flag, and restarts
+ * (breakdown restarts plus true-residual restarts of the column).
  */
 int orc_solve(const ohier *h, int method, int smoother, double omega, int degree,
               double lo_frac, double hi_frac, int gs_block, int flexible, int precond,
               int max_iters, double tol, int x0_given, int m, const double *B,
-              double *X, int *iters, double *relres, double *true_relres, int *conv)
+              double *X, int *iters, double *relres, double *true_relres, int *conv,
+              int *restarts)
 {
     vws w;
     kopt ko = {method, flexible, max_iters, tol, x0_given, precond};
@@ -1359,9 +1366,9 @@ int orc_solve(const ohier *h, int method, int smoother, double omega, int degree
     if (m < 1 || (smoother == 2 && gs_block < 1)) return ORC_EINVAL;
     for (q = 0; q < nm; q++) if (!isfinite(B[q])) return ORC_EINVAL;
     if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
-    if (method == 0) rc = pcg(h, &ko, &so, m, B, X, iters, relres, conv, &w);
-    else if (method == 2) rc = mgsolve(h, &ko, &so, m, B, X, iters, relres, conv, &w);
-    else rc = bicgstab(h, &ko, &so, m, B, X, iters, relres, conv, &w);
+    if (method == 0) rc = pcg(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
+    else if (method == 2) rc = mgsolve(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
+    else rc = bicgstab(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
     vws_free(&w, h->nlev);
     t = (double *)malloc(nm * sizeof(double));
     if (!t) return ORC_ENOMEM;

@@ -231,6 +231,8 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
                 stats[s][j].converged = conv ? 1 : 0;
                 stats[s][j].relres = st.relres[j];
                 stats[s][j].true_relres = st.true_relres[j];
+                stats[s][j].restarts = st.nrst[j];
+                stats[s][j].reserved = 0;
             }
             if (st.failed[j]) rc = XAMG_EBREAKDOWN;
             else if (!conv && rc == XAMG_OK) rc = XAMG_NOT_CONVERGED;

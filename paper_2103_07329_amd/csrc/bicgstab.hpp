@@ -245,6 +245,7 @@ __device__ __forceinline__ void prep_next(ColState* st, int j, double rhr, doubl
             return;
         }
         st->rst[j] = 1;
+        st->nrst[j] += 1;
     }
     if (st->rst[j]) {
         // rh := r, rho = alpha = omega = 1: rho' = (r, r), beta = rho', p = r
@@ -278,6 +279,7 @@ struct FinInitB {   // tot: (b,b)[M], (r,r)[M]
             st->conv[j] = !act;
             st->iters[j] = 0;
             st->brk[j] = st->skip[j] = st->half[j] = st->failed[j] = st->cp[j] = 0;
+            st->nrst[j] = 0;
             st->rst[j] = 1;   // first iteration: rh = r, p = r, v = 0
             st->alpha[j] = st->omega[j] = st->rz[j] = 1.0;
             st->beta[j] = 0.0;
@@ -313,6 +315,7 @@ struct FinAlphaB {   // tot: (rh, v)[M]
                     } else {
                         st->rst[j] = 1;
                         st->skip[j] = 1;
+                        st->nrst[j] += 1;
                     }
                     st->alpha[j] = 0.0;
                 } else {
@@ -354,6 +357,8 @@ struct FinOmega {   // tot: (t, s)[M], (t, t)[M]
                     if (++st->brk[j] >= 2) {
                         // the update below still applies (x += alpha ph)
                         st->failed[j] = 1;
+                    } else {
+                        st->nrst[j] += 1;
                     }
                     st->rst[j] = 1;
                 } else {
@@ -431,6 +436,7 @@ struct FinTrueB {
                 st->active[j] = 1;
                 st->cp[j] = 1;
                 st->relres[j] = tr;
+                st->nrst[j] += 1;
                 atomicAdd(&nr, 1);
             }
         }
@@ -497,7 +503,7 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
             OpBicgP<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, r, p, v, rh, h.w.p32};
             launch_rows<M, CPT>(h, op, n, cap);
         }
-        vcycle<M>(h, p, ph, 0, nullptr, h.w.p32);
+        apply_prec<M>(h, p, ph, 0, nullptr, h.w.p32);
         {
             OpAxW<M, CPT, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, ph, v, rh, na};
             const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
@@ -508,7 +514,7 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
             const int nb = launch_rows<M, CPT>(h, op, n, cap);
             launch_fin(h, nb, M, FinHalf{st, M});
         }
-        vcycle<M>(h, s, sh, 0, nullptr, h.w.s32);
+        apply_prec<M>(h, s, sh, 0, nullptr, h.w.s32);
         {
             OpAxW<M, CPT, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, sh, t, s, na};
             const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);

@@ -42,6 +42,7 @@ struct FinInit {   // tot: (b,b)[M], (r,r)[M]
             st->skip[j] = 0;
             st->half[j] = 0;
             st->failed[j] = 0;
+            st->nrst[j] = 0;
             st->alpha[j] = st->beta[j] = 0.0;
             st->omega[j] = 1.0;
             st->rz[j] = 1.0;
@@ -173,6 +174,7 @@ struct FinTrue {   // tot: (b, b)[M], (t, t)[M];  t = b - A x
                 st->rst[j] = 1;
                 st->cp[j] = 1;
                 st->relres[j] = tr;
+                st->nrst[j] += 1;
                 atomicAdd(&nr, 1);
             }
         }
@@ -474,6 +476,26 @@ int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q,
 }
 
 
+// z = M^-1 r for the Krylov drivers: the V-cycle, or z = r when the handle
+// runs without a preconditioner (the dots of the finest level then come
+// from a vector pass of their own)
+template <int M>
+int apply_prec(Handle& h, const double* r, double* z, int ndots, const double* q,
+               const float* r32 = nullptr)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    if (h.opt.precond) return vcycle<M>(h, r, z, ndots, q, r32);
+    hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
+                       r, M, z, M, h.lev[0].n, M);
+    if (ndots == 0) return 0;
+    if (ndots == 2) {
+        OpDotsBX<M, CPT, 2> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
+        return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+    }
+    OpDotsBX<M, CPT, 1> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};
+    return launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+}
+
 // ---------------------------------------------------------------------------
 // preconditioned CG, all m columns at once
 // ---------------------------------------------------------------------------
@@ -492,7 +514,7 @@ void pcg_precondition(Handle& h)
     constexpr int CPT = cpt_for<double, M>();
     const int flex = pcg_flex<M>(h);
     const int nd = flex ? 2 : 1;
-    const int nb = vcycle<M>(h, h.w.r, h.w.z, nd, h.w.q, h.w.r32);
+    const int nb = apply_prec<M>(h, h.w.r, h.w.z, nd, h.w.q, h.w.r32);
     launch_fin(h, nb, nd * M, FinBeta{h.st, M, flex});
     OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.p, h.w.z};
     launch_rows<M, CPT>(h, up, h.lev[0].n, h.nb_cap);

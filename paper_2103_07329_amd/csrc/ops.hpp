@@ -47,6 +47,7 @@ struct ColState {
     int skip[32];         // rest of this iteration skipped (BiCGStab)
     int half[32];         // converged at the half step (BiCGStab)
     int failed[32];       // stopped by a persistent breakdown
+    int nrst[32];         // restarts so far (true-residual and breakdown)
     int max_iters;        // per-column iteration cap
     int nactive;
     int nrestart;

@@ -266,6 +266,8 @@ static void fill_stats(const Handle& h, int m, xamg_stats_t* stats)
         stats[j].converged = (s.conv[j] && !(s.true_relres[j] > s.tol)) ? 1 : 0;
         stats[j].relres = s.relres[j];
         stats[j].true_relres = s.true_relres[j];
+        stats[j].restarts = s.nrst[j];
+        stats[j].reserved = 0;
     }
 }
 
@@ -343,6 +345,7 @@ void xamg_default_options(xamg_options_t* o)
     o->flexible = 0;
     o->check_every = 1;
     o->gs_block = 8;
+    o->precond = 1;
     o->stream = nullptr;
 }
 
@@ -387,6 +390,9 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     if (o.index_bits == 16 && o.precision != XAMG_MIXED)
         return xamg::fail(XAMG_EINVAL, "16-bit indices apply to the mixed-precision preconditioner");
     if (o.max_iters < 0) return xamg::fail(XAMG_EINVAL, "max_iters");
+    if (o.precond != 0 && o.precond != 1) return xamg::fail(XAMG_EINVAL, "precond must be 0 or 1");
+    if (o.precond == 0 && o.method == XAMG_MG)
+        return xamg::fail(XAMG_EINVAL, "multigrid as the solver needs the V-cycle");
     if (H->nlevels < 1 || H->nlevels > XAMG_MAX_LEVELS || !H->A)
         return xamg::fail(XAMG_EINVAL, "nlevels");
     if (H->nlevels > 1 && (!H->P || !H->R)) return xamg::fail(XAMG_EINVAL, "P/R missing");

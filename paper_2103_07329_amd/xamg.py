@@ -56,12 +56,14 @@ class OptionsT(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("index_bits", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("x0_mode", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("gs_block", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("gs_block", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class StatsT(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
+                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -327,6 +329,7 @@ class Solver:
             "converged": np.array([bool(s.converged) for s in st]),
             "relres": np.array([s.relres for s in st]),
             "true_relres": np.array([s.true_relres for s in st]),
+            "restarts": np.array([s.restarts for s in st], np.int32),
         }
         return rc, stats
 
@@ -409,6 +412,7 @@ class Batch:
                 "converged": np.array([bool(s.converged) for s in st]),
                 "relres": np.array([s.relres for s in st]),
                 "true_relres": np.array([s.true_relres for s in st]),
+                "restarts": np.array([s.restarts for s in st], np.int32),
             })
         return rc, out
 
