@@ -183,6 +183,23 @@ int xamg_setup(const xamg_hierarchy_t *H, const xamg_options_t *opt,
 int xamg_solve(xamg_handle_t *h, const double *B, double *X, int32_t m, double tol,
                xamg_stats_t *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of xamg_solve, same arguments, same kernels and results, with no device
+ * allocation and no autotuning inside the call.  Its work vectors, padding
+ * copies, per-column state and partial sums live in one static device array
+ * of XAMG_NOALLOC_SCRATCH_BYTES per device (held until the process ends);
+ * a solve that needs more returns XAMG_EINVAL (the detail string gives the
+ * bytes needed: roughly (5 + 4 C_G) n m 8 bytes for FP64 CG, C_G the grid
+ * complexity).  Launch shapes are those already tuned for the padded m (by
+ * an earlier xamg_solve or xamg_autotune on the handle), else the setup-time
+ * row-length guess.  Calls on one device share the array: calls that
+ * overlap in time on one device race and must be serialised by the caller.
+ * The kernel timer is inactive during this call. */
+#define XAMG_NOALLOC_SCRATCH_BYTES (128u << 20)
+int xamg_solve_noalloc(xamg_handle_t *h, const double *B, double *X, int32_t m, double tol,
+                       xamg_stats_t *stats);
+
 /* Apply one V(1,1) cycle from a zero guess, X = M^-1 B (device, n x m
  * interleaved, float64), with the smoother and precision of the handle.
  * m in {1, 2, 4, 8, 16, 32}. */

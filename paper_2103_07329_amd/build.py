@@ -18,7 +18,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["common.cpp", "setup.cpp", "solver.hip", "inst_m1.hip", "inst_m2.hip",
            "inst_m4.hip", "inst_m8.hip", "inst_m16.hip", "inst_m32.hip", "batched.hip",
-           "cnn.hip"]
+           "cnn.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -176,6 +176,57 @@ static double encode16(Handle& h, const xamg_csr_t& c, DCsr& d)
 // ---------------------------------------------------------------------------
 // work buffers
 // ---------------------------------------------------------------------------
+// The work buffers of a solve for mc columns, in one fixed order: `get`
+// supplies the memory of each (a device allocation, or a slice of a region
+// the caller owns).  w.lev must already hold h.nlev entries.
+template <class Get>
+static void layout_work(const Handle& h, int mc, bool bicg, bool pad, Work& w, Get&& get)
+{
+    w.mcap = mc;
+    const size_t es = h.opt.precision == XAMG_MIXED ? sizeof(float) : sizeof(double);
+    for (int l = 0; l < h.nlev; ++l) {
+        const size_t n = size_t(h.lev[l].n) * mc;
+        auto& W = w.lev[l];
+        W = LevelWork{};
+        const size_t esl = (h.nlev == 1) ? sizeof(double) : es;
+        if (l > 0) W.B = get(n * esl);
+        if (l + 1 < h.nlev) {
+            W.X = get(n * esl);
+            W.R = get(n * esl);
+            W.T = get(n * esl);
+        }
+        if (l > 0) W.X2 = get(n * esl);
+    }
+    const size_t n0 = size_t(h.lev[0].n) * mc;
+    w.r = static_cast<double*>(get(n0 * sizeof(double)));
+    w.z = static_cast<double*>(get(n0 * sizeof(double)));
+    w.p = static_cast<double*>(get(n0 * sizeof(double)));
+    w.q = static_cast<double*>(get(n0 * sizeof(double)));
+    w.t = static_cast<double*>(get(n0 * sizeof(double)));
+    w.r32 = w.p32 = w.s32 = nullptr;
+    w.rh = w.v = w.s = w.ph = w.sh = nullptr;
+    w.bpad = w.xpad = nullptr;
+    if (h.opt.precision == XAMG_MIXED && h.opt.method == XAMG_CG &&
+        h.opt.smoother != XAMG_GAUSS_SEIDEL && h.nlev > 1)
+        w.r32 = static_cast<float*>(get(n0 * sizeof(float)));
+    if (bicg && h.opt.precision == XAMG_MIXED && h.opt.smoother != XAMG_GAUSS_SEIDEL &&
+        h.nlev > 1) {
+        w.p32 = static_cast<float*>(get(n0 * sizeof(float)));
+        w.s32 = static_cast<float*>(get(n0 * sizeof(float)));
+    }
+    if (bicg) {
+        w.rh = static_cast<double*>(get(n0 * sizeof(double)));
+        w.v = static_cast<double*>(get(n0 * sizeof(double)));
+        w.s = static_cast<double*>(get(n0 * sizeof(double)));
+        w.ph = static_cast<double*>(get(n0 * sizeof(double)));
+        w.sh = static_cast<double*>(get(n0 * sizeof(double)));
+    }
+    if (pad) {
+        w.bpad = static_cast<double*>(get(n0 * sizeof(double)));
+        w.xpad = static_cast<double*>(get(n0 * sizeof(double)));
+    }
+}
+
 void ensure_work(Handle& h, int mp, bool bicg)
 {
     if (h.w.mcap >= mp && (!bicg || h.w.rh)) return;
@@ -191,42 +242,22 @@ void ensure_work(Handle& h, int mp, bool bicg)
     h.release(h.w.s32);
     const int mc = std::max(mp, h.w.mcap);
     h.w = Work{};
-    h.w.mcap = mc;
-    const size_t es = h.opt.precision == XAMG_MIXED ? sizeof(float) : sizeof(double);
     h.w.lev.resize(h.nlev);
-    for (int l = 0; l < h.nlev; ++l) {
-        const size_t n = size_t(h.lev[l].n) * mc;
-        auto& W = h.w.lev[l];
-        const size_t esl = (h.nlev == 1) ? sizeof(double) : es;
-        if (l > 0) W.B = h.alloc_bytes(n * esl);
-        if (l + 1 < h.nlev) {
-            W.X = h.alloc_bytes(n * esl);
-            W.R = h.alloc_bytes(n * esl);
-            W.T = h.alloc_bytes(n * esl);
-        }
-        if (l > 0) W.X2 = h.alloc_bytes(n * esl);
-    }
-    const size_t n0 = size_t(h.lev[0].n) * mc;
-    h.w.r = h.alloc<double>(n0);
-    h.w.z = h.alloc<double>(n0);
-    h.w.p = h.alloc<double>(n0);
-    h.w.q = h.alloc<double>(n0);
-    h.w.t = h.alloc<double>(n0);
-    if (h.opt.precision == XAMG_MIXED && h.opt.method == XAMG_CG &&
-        h.opt.smoother != XAMG_GAUSS_SEIDEL && h.nlev > 1)
-        h.w.r32 = h.alloc<float>(n0);
-    if (bicg && h.opt.precision == XAMG_MIXED && h.opt.smoother != XAMG_GAUSS_SEIDEL &&
-        h.nlev > 1) {
-        h.w.p32 = h.alloc<float>(n0);
-        h.w.s32 = h.alloc<float>(n0);
-    }
-    if (bicg) {
-        h.w.rh = h.alloc<double>(n0);
-        h.w.v = h.alloc<double>(n0);
-        h.w.s = h.alloc<double>(n0);
-        h.w.ph = h.alloc<double>(n0);
-        h.w.sh = h.alloc<double>(n0);
-    }
+    layout_work(h, mc, bicg, false, h.w, [&](size_t bytes) { return h.alloc_bytes(bytes); });
+}
+
+size_t carve_work(const Handle& h, int mp, bool bicg, bool pad, Work& w, char* base,
+                  size_t cap)
+{
+    size_t used = 0;
+    bool fits = true;
+    layout_work(h, mp, bicg, pad, w, [&](size_t bytes) -> void* {
+        const size_t at = used;
+        used += (bytes + 255) & ~size_t(255);
+        fits = fits && used <= cap;
+        return (base && fits) ? static_cast<void*>(base + at) : nullptr;
+    });
+    return used;
 }
 
 void sync_state(Handle& h)
@@ -250,7 +281,7 @@ static int dispatch_m(int mp, F&& f)
     }
 }
 
-static int padded_m(int m)
+int padded_m(int m)
 {
     int mp = 1;
     while (mp < m) mp <<= 1;
@@ -271,23 +302,16 @@ static void fill_stats(const Handle& h, int m, xamg_stats_t* stats)
     }
 }
 
-int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats)
+// The solve proper, on buffers that are already in place: h.w for mp =
+// padded(m) columns (with w.bpad / w.xpad when m is not a power of two),
+// h.st and h.part.  Launches, copies and synchronisations only.
+int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats)
 {
     const int mp = padded_m(m);
     const int n = h.lev[0].n;
-    ensure_work(h, mp, h.opt.method == XAMG_BICGSTAB);
-    if (h.autotune)
-        dispatch_m(mp, [&](auto mc) {
-            autotune<decltype(mc)::value>(h);
-            return 0;
-        });
     const double* Bs = B;
     double* Xs = X;
     if (mp != m) {
-        if (!h.w.bpad) {
-            h.w.bpad = h.alloc<double>(size_t(n) * h.w.mcap);
-            h.w.xpad = h.alloc<double>(size_t(n) * h.w.mcap);
-        }
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
                            B, m, h.w.bpad, mp, n, m);
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0, h.stream,
@@ -319,6 +343,23 @@ int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_st
         return XAMG_EBREAKDOWN;
     }
     return notconv ? XAMG_NOT_CONVERGED : XAMG_OK;
+}
+
+int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats)
+{
+    const int mp = padded_m(m);
+    const int n = h.lev[0].n;
+    ensure_work(h, mp, h.opt.method == XAMG_BICGSTAB);
+    if (h.autotune)
+        dispatch_m(mp, [&](auto mc) {
+            autotune<decltype(mc)::value>(h);
+            return 0;
+        });
+    if (mp != m && !h.w.bpad) {
+        h.w.bpad = h.alloc<double>(size_t(n) * h.w.mcap);
+        h.w.xpad = h.alloc<double>(size_t(n) * h.w.mcap);
+    }
+    return solve_run(h, B, X, m, tol, stats);
 }
 
 }  // namespace xamg
@@ -433,6 +474,7 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
         }
         h->nlev = H->nlevels;
         h->lev.resize(h->nlev);
+        h->w_na.lev.resize(h->nlev);
         const bool mixed = o.precision == XAMG_MIXED;
         for (int l = 0; l < h->nlev; ++l) {
             auto& L = h->lev[l];

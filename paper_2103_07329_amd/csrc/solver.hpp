@@ -94,6 +94,7 @@ struct Handle : xamg_handle {
     xamg_options_t opt{};
     hipStream_t stream = nullptr;
     Work w;
+    Work w_na;   // work of xamg_solve_noalloc: slices of the scratch array (lev sized at setup)
     dev::ColState* st = nullptr;
     dev::ColState* st_host = nullptr;
     double* part = nullptr;
@@ -248,7 +249,14 @@ template <int M>
 void autotune(Handle& h);
 
 void ensure_work(Handle& h, int mp, bool bicg);
+// Lay the work buffers of mp columns (plus the padding copies of B and X
+// when pad) out in the region base[0, cap): fills w (whose lev must hold
+// nlev entries) when the region is large enough; returns the bytes needed.
+size_t carve_work(const Handle& h, int mp, bool bicg, bool pad, Work& w, char* base,
+                  size_t cap);
 void sync_state(Handle& h);
+int padded_m(int m);
 int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats);
+int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats);
 
 }  // namespace xamg

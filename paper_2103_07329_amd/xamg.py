@@ -71,7 +71,7 @@ _lib = None
 EXPORTS = [
     "xamg_default_setup_params", "xamg_hierarchy_build", "xamg_hierarchy_view",
     "xamg_hierarchy_cf", "xamg_hierarchy_free", "xamg_default_options", "xamg_setup",
-    "xamg_solve", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_index16_fraction",
+    "xamg_solve", "xamg_solve_noalloc", "xamg_vcycle", "xamg_spmm", "xamg_info", "xamg_index16_fraction",
     "xamg_batch_create", "xamg_solve_batched", "xamg_batch_destroy",
     "xamg_autotune", "xamg_tuning", "xamg_set_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
@@ -105,6 +105,7 @@ def lib():
         L.xamg_setup.argtypes = [ctypes.POINTER(HierT), ctypes.POINTER(OptionsT),
                                  ctypes.POINTER(vp)]
         L.xamg_solve.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(StatsT)]
+        L.xamg_solve_noalloc.argtypes = [vp, vp, vp, i32, dbl, ctypes.POINTER(StatsT)]
         L.xamg_vcycle.argtypes = [vp, vp, vp, i32]
         L.xamg_spmm.argtypes = [vp, i32, i32, i32, vp, vp]
         L.xamg_info.argtypes = [vp, ctypes.POINTER(i64), i32]
@@ -332,6 +333,26 @@ class Solver:
             "restarts": np.array([s.restarts for s in st], np.int32),
         }
         return rc, stats
+
+    def solve_noalloc(self, B, X, tol=1e-8, check=True):
+        """xamg_solve_noalloc: as solve(), with every work buffer in the
+        library's static scratch array (no device allocation in the call)."""
+        m = B.shape[1] if B.dim() == 2 else 1
+        st = (StatsT * m)()
+        rc = lib().xamg_solve_noalloc(self._h, _ptr(B), _ptr(X), m, tol, st)
+        if check:
+            _check(rc, "xamg_solve_noalloc", allow=(OK, NOT_CONVERGED))
+        return rc, self._stats(st)
+
+    @staticmethod
+    def _stats(st):
+        return {
+            "iters": np.array([s.iters for s in st], np.int32),
+            "converged": np.array([bool(s.converged) for s in st]),
+            "relres": np.array([s.relres for s in st]),
+            "true_relres": np.array([s.true_relres for s in st]),
+            "restarts": np.array([s.restarts for s in st], np.int32),
+        }
 
     def vcycle(self, B, X):
         m = B.shape[1]
