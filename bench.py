@@ -127,26 +127,39 @@ def stored_traffic(workload, kernel):
         return None
 
 
-def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
-    """Device-to-device copy rate (GB/s, read + write bytes) of a plain
-    torch copy of nbytes, best of reps, timed with events on the current
-    stream: the practical ceiling for a streaming kernel on this device."""
-    n = nbytes // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
+def _best_ms(torch, fn, reps):
+    fn()
     best = None
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        b.copy_(a)
+        fn()
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         best = ms if best is None else min(best, ms)
+    return best
+
+
+def stream_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Streaming rates of this device (GB/s of bytes read + written), timed
+    with events on the current stream, best of reps: a plain torch copy of
+    nbytes (a blit of 256 workgroups) and the elementwise sum c = a + b over
+    three arrays of nbytes/2 (torch's vectorised elementwise kernel, every
+    CU busy).  The larger is the practical ceiling of a streaming kernel."""
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    copy_gbs = 2.0 * n * 8 / (_best_ms(torch, lambda: b.copy_(a), reps) * 1e-3) / 1e9
     del a, b
+    h = n // 2
+    x = torch.ones(h, dtype=torch.float64, device="cuda")
+    y = torch.ones(h, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(x)
+    add_gbs = 3.0 * h * 8 / (_best_ms(torch, lambda: torch.add(x, y, out=z), reps) * 1e-3) / 1e9
+    del x, y, z
     torch.cuda.empty_cache()
-    return 2.0 * n * 8 / (best * 1e-3) / 1e9
+    return {"copy_gbs": copy_gbs, "add_gbs": add_gbs, "ceiling_gbs": max(copy_gbs, add_gbs)}
 
 
 def timed_solves(S, Bd, Xd, steps, tol, stream, torch):
@@ -331,13 +344,16 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["total_ms_per_step"])
     K = kernels[dom]
     traffic = stored_traffic(wl, dom)
-    cgbs = copy_bandwidth(torch)
-    log(f"[bench] device copy {cgbs:.0f} GB/s; roofline kernel {K['achieved_gbs'] / cgbs:.1%} of it")
+    sb = stream_bandwidth(torch)
+    cgbs = sb["ceiling_gbs"]
+    log(f"[bench] device copy {sb['copy_gbs']:.0f} GB/s, elementwise a + b {sb['add_gbs']:.0f} GB/s; "
+        f"roofline kernel {K['achieved_gbs'] / cgbs:.1%} of the faster")
     roofline = {"kernel": K["kernel"], "bound": "hbm", "achieved": K["achieved_gbs"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": K["achieved_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic, "algorithmic_bytes": K["algorithmic_bytes"],
                 "avg_us": K["avg_us"], "launches_timed": K["launches"],
-                "measured_copy_gbs": cgbs, "frac_of_copy": K["achieved_gbs"] / cgbs}
+                "measured_copy_gbs": sb["copy_gbs"], "measured_add_gbs": sb["add_gbs"],
+                "stream_ceiling_gbs": cgbs, "frac_of_stream": K["achieved_gbs"] / cgbs}
 
     extras = {}
     if not args.no_extras:
@@ -615,6 +631,40 @@ def bench_warmstart(args, torch, inputs, xamg):
         o.close()
 
 
+def batched_cpu_baseline(systems, sts, Xs, nrhs):
+    """The oracle (FP64 CG, Jacobi V(1,1)) on a bounded sample of the batch:
+    full solves of the systems in increasing order of n x m until about 10 s
+    of oracle time (setup excluded), then scaled to the whole batch by work
+    n x m x iterations (the GPU's per-system iteration counts for the
+    systems not sampled).  Also returns the sampled systems' error of the
+    batched solution against the oracle's."""
+    import oracle
+    work = [p.n * B.shape[1] * int(st["iters"].max()) for (p, B), st in zip(systems, sts)]
+    order = sorted(range(len(systems)), key=lambda s: systems[s][0].n * systems[s][1].shape[1])
+    t_s, w_s, errs, done = 0.0, 0, [], []
+    for s in order:
+        if t_s >= 10.0:
+            break
+        done.append(s)
+        prob, B = systems[s]
+        Ho = oracle.Hierarchy(*prob.csr())
+        t0 = time.perf_counter()
+        Xo, so, rco = Ho.solve(B, method=oracle.CG, smoother=oracle.JACOBI, tol=1e-8)
+        t_s += time.perf_counter() - t0
+        w_s += prob.n * B.shape[1] * int(so["iters"].max())
+        X = Xs[s].cpu().numpy()
+        errs.append(float((np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)).max()))
+    t_all = t_s * sum(work) / w_s
+    log(f"[bench] oracle sample (systems {done}): {t_s:.1f}s -> whole batch {t_all:.1f}s, "
+        f"batched vs oracle max rel err {max(errs):.2e}")
+    return {"value": t_all * 1e3 / nrhs, "unit": "ms/RHS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"full FP64 oracle solves of systems {done} of the batch (least "
+                       f"n x m first, about 10 s; setup excluded), scaled to all 12 by "
+                       f"n x m x iterations"),
+            "sample_rel_err_vs_batched": max(errs)}
+
+
 def bench_batched(args, torch, inputs, xamg):
     """12 jump-coefficient systems of uneven size and column count (seed
     1004), AMG-PCG with an FP32 preconditioner and 16-bit offsets, all
@@ -698,7 +748,7 @@ def bench_batched(args, torch, inputs, xamg):
         "separate_solves": {"mixed_ms": ms_sep_mixed, "fp64_ms": ms_sep_fp64,
                             "fp64_ms_per_rhs": ms_sep_fp64 / nrhs,
                             "max_rel_diff_batched_vs_fp64": err},
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu else batched_cpu_baseline(systems, sts, Xs, nrhs),
     }
     print(json.dumps(out), flush=True)
     batch.close()

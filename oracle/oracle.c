@@ -31,8 +31,9 @@
  * which textbook definition it follows.  Everything is sequential FP64
  * except that independent row loops carry an OpenMP pragma (each row is
  * computed by exactly one thread with a fixed order of operations, so the
- * results do not depend on the thread count).  Dot products are plain
- * sequential sums over rows.
+ * results do not depend on the thread count).  Dot products are sums over
+ * 64 fixed chunks of rows (each chunk in row order, then the chunks in
+ * order), likewise independent of the thread count.
  */
 #include <math.h>
 #include <stdint.h>
@@ -119,40 +120,73 @@ static void residual(const ocsr *a, int m, const double *B, const double *X,
     }
 }
 
+/* Dot products and norms are sums over rows taken in NCHUNK fixed,
+ * contiguous chunks of rows: each chunk is summed in row order, then the
+ * chunk sums in chunk order.  The order depends only on n, never on the
+ * thread count, so the chunks can run in parallel and every result is
+ * reproducible. */
+#define NCHUNK 64
+
+static int chunk_lo(int n, int c) { return (int)(((int64_t)n * c) / NCHUNK); }
+
 /* column j of  b - A x  (one column only), returned as its 2-norm squared */
 static double residual_col_norm2(const ocsr *a, int m, int j, const double *B,
                                  const double *X)
 {
-    double s = 0.0;
-    int i, k;
-    for (i = 0; i < a->nr; i++) {
-        double ax = 0.0, r;
-        for (k = a->rp[i]; k < a->rp[i + 1]; k++)
-            ax += a->v[k] * X[(size_t)a->ci[k] * m + j];
-        r = B[(size_t)i * m + j] - ax;
-        s += r * r;
+    double part[NCHUNK], s = 0.0;
+    int c;
+#pragma omp parallel for schedule(static)
+    for (c = 0; c < NCHUNK; c++) {
+        double t = 0.0;
+        int i, k;
+        for (i = chunk_lo(a->nr, c); i < chunk_lo(a->nr, c + 1); i++) {
+            double ax = 0.0, r;
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++)
+                ax += a->v[k] * X[(size_t)a->ci[k] * m + j];
+            r = B[(size_t)i * m + j] - ax;
+            t += r * r;
+        }
+        part[c] = t;
     }
+    for (c = 0; c < NCHUNK; c++) s += part[c];
     return s;
 }
 
 static double dot_col(int n, int m, int j, const double *X, const double *Y)
 {
-    double s = 0.0;
-    int i;
-    for (i = 0; i < n; i++) s += X[(size_t)i * m + j] * Y[(size_t)i * m + j];
+    double part[NCHUNK], s = 0.0;
+    int c;
+#pragma omp parallel for schedule(static)
+    for (c = 0; c < NCHUNK; c++) {
+        double t = 0.0;
+        int i;
+        for (i = chunk_lo(n, c); i < chunk_lo(n, c + 1); i++)
+            t += X[(size_t)i * m + j] * Y[(size_t)i * m + j];
+        part[c] = t;
+    }
+    for (c = 0; c < NCHUNK; c++) s += part[c];
     return s;
 }
 
-/* all m column dots in one pass over the rows; column j is summed over
- * i = 0..n-1 in order, exactly as dot_col does */
+/* all m column dots in one pass over the rows; column j is summed in the
+ * same order as dot_col */
 static void dots(int n, int m, const double *X, const double *Y, double *out)
 {
-    int i, j;
-    for (j = 0; j < m; j++) out[j] = 0.0;
-    for (i = 0; i < n; i++) {
-        const double *x = X + (size_t)i * m, *y = Y + (size_t)i * m;
-        for (j = 0; j < m; j++) out[j] += x[j] * y[j];
+    double *part = (double *)calloc((size_t)NCHUNK * m + 1, sizeof(double));
+    int c, j;
+#pragma omp parallel for schedule(static)
+    for (c = 0; c < NCHUNK; c++) {
+        double *t = part + (size_t)c * m;
+        int i, jj;
+        for (i = chunk_lo(n, c); i < chunk_lo(n, c + 1); i++) {
+            const double *x = X + (size_t)i * m, *y = Y + (size_t)i * m;
+            for (jj = 0; jj < m; jj++) t[jj] += x[jj] * y[jj];
+        }
     }
+    for (j = 0; j < m; j++) out[j] = 0.0;
+    for (c = 0; c < NCHUNK; c++)
+        for (j = 0; j < m; j++) out[j] += part[(size_t)c * m + j];
+    free(part);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1022,6 +1056,7 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
             alpha[j] = rz[j] / pq[j];
         }
         /* x += alpha p, r -= alpha q (active columns) */
+#pragma omp parallel for private(j) schedule(static)
         for (i = 0; i < n; i++)
             for (j = 0; j < m; j++)
                 if (act[j]) {
@@ -1069,6 +1104,7 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
             }
             rz[j] = rzn[j];
         }
+#pragma omp parallel for private(j) schedule(static)
         for (i = 0; i < n; i++)
             for (j = 0; j < m; j++)
                 if (act[j]) {
@@ -1185,6 +1221,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
             rho[j] = d1[j];
             upd[j] = 1;
         }
+#pragma omp parallel for private(j, k) schedule(static)
         for (i = 0; i < (size_t)n; i++)
             for (j = 0; j < m; j++)
                 if (upd[j]) {
@@ -1210,6 +1247,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
             alp[j] = rho[j] / d1[j];
             upd[j] = 1;
         }
+#pragma omp parallel for private(j, k) schedule(static)
         for (i = 0; i < (size_t)n; i++)
             for (j = 0; j < m; j++)
                 if (upd[j]) {
@@ -1238,6 +1276,7 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
             omg[j] = (d2[j] > 0.0) ? d1[j] / d2[j] : 0.0;
             upd[j] = 1;
         }
+#pragma omp parallel for private(j, k) schedule(static)
         for (i = 0; i < (size_t)n; i++)
             for (j = 0; j < m; j++)
                 if (upd[j]) {
@@ -1329,6 +1368,7 @@ static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
         if (!any) break;
         if (g_verbose) { fprintf(stderr, "[oracle] MG iteration %d\n", it); fflush(stderr); }
         apply_prec(h, ko, so, m, r, z, w);
+#pragma omp parallel for private(j) schedule(static)
         for (i = 0; i < n; i++)
             for (j = 0; j < m; j++)
                 if (act[j]) X[(size_t)i * m + j] += z[(size_t)i * m + j];
@@ -1342,6 +1382,7 @@ static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
         }
     }
     free(r); free(z); free(bn); free(rr); free(act);
+    for (j = 0; j < m; j++) if (!conv[j]) return ORC_NOT_CONVERGED;
     return ORC_OK;
 }
 
