@@ -65,6 +65,8 @@ def lib():
         L.orc_hier_lmax.restype = _c_dbl
         L.orc_vcycle.argtypes = [_vp, _c_int, _c_dbl, _c_int, _c_dbl, _c_dbl,
                                  _c_int, _c_int, _f64p, _f64p]
+        L.orc_vcycle32.argtypes = [_vp, _c_int, _c_dbl, _c_int, _c_dbl, _c_dbl,
+                                   _c_int, _c_int, _f64p, _f64p]
         L.orc_solve.argtypes = [_vp, _c_int, _c_int, _c_dbl, _c_int, _c_dbl,
                                 _c_dbl, _c_int, _c_int, _c_int, _c_int, _c_dbl,
                                 _c_int, _c_int, _f64p, _f64p, _i32p, _f64p, _f64p,
@@ -261,6 +263,20 @@ class Hierarchy:
         X = np.zeros_like(B)
         lib().orc_vcycle(self._h, smoother, omega, degree, lo_frac, hi_frac,
                          gs_block, B.shape[1], B, X)
+        return X[:, 0] if vec else X
+
+    def vcycle32(self, B, smoother=JACOBI, omega=2.0 / 3.0, degree=2,
+                 lo_frac=0.3, hi_frac=1.1, gs_block=8):
+        """The V(1,1) cycle carried out in FP32 (level matrices, D^-1, the
+        coarsest inverse and all vectors rounded to float, float sums); B is
+        rounded to float, the result is returned as float64."""
+        B = np.ascontiguousarray(B, np.float64)
+        vec = B.ndim == 1
+        if vec:
+            B = B[:, None].copy()
+        X = np.zeros_like(B)
+        lib().orc_vcycle32(self._h, smoother, omega, degree, lo_frac, hi_frac,
+                           gs_block, B.shape[1], B, X)
         return X[:, 0] if vec else X
 
     def solve(self, B, X0=None, method=CG, smoother=JACOBI, omega=2.0 / 3.0,

@@ -975,6 +975,205 @@ int orc_vcycle(const ohier *h, int smoother, double omega, int degree,
 }
 
 /* ------------------------------------------------------------------------ */
+/* The same V(1,1) cycle carried out in FP32 (the reduced-precision          */
+/* preconditioner of Section 2.3): every level matrix, D^-1, the coarsest    */
+/* inverse and every vector rounded to float, every sum accumulated in       */
+/* float, the steps in the order of the FP64 cycle above.  Scalars of the    */
+/* smoothers (omega, the Chebyshev coefficients) are formed in FP64 and      */
+/* rounded once.  The input b is rounded to float at level 0 and the result  */
+/* is returned widened to FP64.  The coarsest level multiplies by the        */
+/* inverse of A_L (from the FP64 LU factors, rounded to float).              */
+/* ------------------------------------------------------------------------ */
+typedef struct { int nr, nc; const int *rp, *ci; float *v; } fcsr;
+
+typedef struct {
+    fcsr A[ORC_MAXLEV], P[ORC_MAXLEV], R[ORC_MAXLEV];
+    float *dinv[ORC_MAXLEV];
+    float *inv;                  /* nL x nL, row-major */
+    int nlev, m;
+    float *b[ORC_MAXLEV], *x[ORC_MAXLEV], *r[ORC_MAXLEV], *d[ORC_MAXLEV], *t[ORC_MAXLEV];
+} fws;
+
+static float *f_of(const double *v, size_t n)
+{
+    float *f = (float *)malloc((n + 1) * sizeof(float));
+    size_t q;
+    if (f) for (q = 0; q < n; q++) f[q] = (float)v[q];
+    return f;
+}
+
+static void fcsr_of(const ocsr *a, fcsr *f)
+{
+    f->nr = a->nr; f->nc = a->nc; f->rp = a->rp; f->ci = a->ci;
+    f->v = f_of(a->v, (size_t)nnz_of(a));
+}
+
+static void fspmm(const fcsr *a, int m, const float *X, float *Y)
+{
+    int i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < a->nr; i++) {
+        float *y = Y + (size_t)i * m;
+        int j, k;
+        for (j = 0; j < m; j++) y[j] = 0.0f;
+        for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+            const float aik = a->v[k];
+            const float *x = X + (size_t)a->ci[k] * m;
+            for (j = 0; j < m; j++) y[j] += aik * x[j];
+        }
+    }
+}
+
+static void fresidual(const fcsr *a, int m, const float *B, const float *X, float *R)
+{
+    size_t q, nm = (size_t)a->nr * m;
+    fspmm(a, m, X, R);
+    for (q = 0; q < nm; q++) R[q] = B[q] - R[q];
+}
+
+static void fsmooth(const fws *f, const ohier *h, int l, const smopt *so, int m,
+                    const float *b, float *x)
+{
+    const fcsr *a = &f->A[l];
+    const float *dinv = f->dinv[l];
+    float *r = f->r[l], *d = f->d[l], *t = f->t[l];
+    size_t nm = (size_t)a->nr * m, q;
+    int i, j, k;
+    if (so->smoother == 0) {
+        const float w = (float)so->omega;
+        fresidual(a, m, b, x, t);
+        for (i = 0; i < a->nr; i++)
+            for (j = 0; j < m; j++) x[(size_t)i * m + j] += w * dinv[i] * t[(size_t)i * m + j];
+    } else if (so->smoother == 2) {
+        /* symmetric l1-hybrid Gauss-Seidel: forward x -> t, backward t -> x */
+        int B = so->gs_block, n = a->nr, nblk = (n + B - 1) / B, pass, blk;
+        for (pass = 0; pass < 2; pass++) {
+            const float *xo = pass ? t : x;
+            float *xn = pass ? x : t;
+            for (blk = 0; blk < nblk; blk++) {
+                int lo = blk * B, hi = lo + B < n ? lo + B : n, s2;
+                for (s2 = 0; s2 < hi - lo; s2++) {
+                    int ii = pass ? hi - 1 - s2 : lo + s2;
+                    double dd = 0.0;
+                    const ocsr *a64 = &h->A[l];
+                    float dl;
+                    for (k = a64->rp[ii]; k < a64->rp[ii + 1]; k++) {
+                        int c = a64->ci[k];
+                        if (c == ii) dd += a64->v[k];
+                        else if (c < lo || c >= hi) dd += fabs(a64->v[k]);
+                    }
+                    dl = (float)dd;
+                    for (j = 0; j < m; j++) {
+                        float acc = 0.0f;
+                        for (k = a->rp[ii]; k < a->rp[ii + 1]; k++) {
+                            int c = a->ci[k];
+                            int fresh = c >= lo && c < hi && (pass ? c > ii : c < ii);
+                            acc += a->v[k] * (fresh ? xn[(size_t)c * m + j] : xo[(size_t)c * m + j]);
+                        }
+                        xn[(size_t)ii * m + j] =
+                            xo[(size_t)ii * m + j] + (b[(size_t)ii * m + j] - acc) / dl;
+                    }
+                }
+            }
+        }
+    } else {
+        double lo = so->lo_frac * so->hi_frac * h->lmax[l], hi = so->hi_frac * h->lmax[l];
+        double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+        double sigma = theta / delta, rho = 1.0 / sigma;
+        const float ft = (float)theta;
+        fresidual(a, m, b, x, r);
+        for (i = 0; i < a->nr; i++)
+            for (j = 0; j < m; j++) {
+                r[(size_t)i * m + j] *= dinv[i];
+                d[(size_t)i * m + j] = r[(size_t)i * m + j] / ft;
+            }
+        for (k = 1; k <= so->degree; k++) {
+            for (q = 0; q < nm; q++) x[q] += d[q];
+            if (k < so->degree) {
+                double rn = 1.0 / (2.0 * sigma - rho);
+                const float c1 = (float)(rn * rho), c2 = (float)(2.0 * rn / delta);
+                fspmm(a, m, d, t);
+                for (i = 0; i < a->nr; i++)
+                    for (j = 0; j < m; j++) {
+                        size_t p2 = (size_t)i * m + j;
+                        r[p2] -= dinv[i] * t[p2];
+                        d[p2] = c1 * d[p2] + c2 * r[p2];
+                    }
+                rho = rn;
+            }
+        }
+    }
+}
+
+static void fvcycle_level(const fws *f, const ohier *h, int l, const smopt *so, int m,
+                          const float *b, float *x)
+{
+    size_t nm = (size_t)f->A[l].nr * m, q;
+    if (l == f->nlev - 1) {
+        int nL = f->A[l].nr, i, k, j;
+        for (i = 0; i < nL; i++)
+            for (j = 0; j < m; j++) {
+                float acc = 0.0f;
+                for (k = 0; k < nL; k++) acc += f->inv[(size_t)i * nL + k] * b[(size_t)k * m + j];
+                x[(size_t)i * m + j] = acc;
+            }
+        return;
+    }
+    memset(x, 0, nm * sizeof(float));
+    fsmooth(f, h, l, so, m, b, x);
+    fresidual(&f->A[l], m, b, x, f->r[l]);
+    fspmm(&f->R[l], m, f->r[l], f->b[l + 1]);
+    fvcycle_level(f, h, l + 1, so, m, f->b[l + 1], f->x[l + 1]);
+    fspmm(&f->P[l], m, f->x[l + 1], f->t[l]);
+    for (q = 0; q < nm; q++) x[q] += f->t[l][q];
+    fsmooth(f, h, l, so, m, b, x);
+}
+
+int orc_vcycle32(const ohier *h, int smoother, double omega, int degree, double lo_frac,
+                 double hi_frac, int gs_block, int m, const double *b, double *x)
+{
+    fws f;
+    smopt so = {smoother, omega, degree, lo_frac, hi_frac, gs_block};
+    int l, i, k, nL = h->A[h->nlev - 1].nr, rc = ORC_OK;
+    size_t n0 = (size_t)h->A[0].nr * m, q;
+    float *b0, *x0;
+    double *col;
+    if (smoother == 2 && gs_block < 1) return ORC_EINVAL;
+    memset(&f, 0, sizeof(f));
+    f.nlev = h->nlev; f.m = m;
+    for (l = 0; l < h->nlev; l++) {
+        size_t nm = (size_t)h->A[l].nr * m + 1;
+        fcsr_of(&h->A[l], &f.A[l]);
+        if (l + 1 < h->nlev) { fcsr_of(&h->P[l], &f.P[l]); fcsr_of(&h->R[l], &f.R[l]); }
+        f.dinv[l] = f_of(h->dinv[l], (size_t)h->A[l].nr);
+        f.b[l] = (float *)calloc(nm, sizeof(float));
+        f.x[l] = (float *)calloc(nm, sizeof(float));
+        f.r[l] = (float *)calloc(nm, sizeof(float));
+        f.d[l] = (float *)calloc(nm, sizeof(float));
+        f.t[l] = (float *)calloc(nm, sizeof(float));
+    }
+    /* inverse of the coarsest matrix: LU solves against unit vectors (FP64) */
+    f.inv = (float *)malloc(((size_t)nL * nL + 1) * sizeof(float));
+    col = (double *)malloc(((size_t)nL + 1) * sizeof(double));
+    for (k = 0; k < nL; k++) {
+        for (i = 0; i < nL; i++) col[i] = (i == k) ? 1.0 : 0.0;
+        dense_lu_solve(nL, h->lu, h->piv, col);
+        for (i = 0; i < nL; i++) f.inv[(size_t)i * nL + k] = (float)col[i];
+    }
+    free(col);
+    b0 = f_of(b, n0);
+    x0 = (float *)calloc(n0 + 1, sizeof(float));
+    fvcycle_level(&f, h, 0, &so, m, b0, x0);
+    for (q = 0; q < n0; q++) x[q] = (double)x0[q];
+    free(b0); free(x0); free(f.inv);
+    for (l = 0; l < h->nlev; l++) {
+        free(f.A[l].v); free(f.P[l].v); free(f.R[l].v); free(f.dinv[l]);
+        free(f.b[l]); free(f.x[l]); free(f.r[l]); free(f.d[l]); free(f.t[l]);
+    }
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Krylov solvers, one independent set of scalars per column.                */
 /* Stopping test: ||r_j|| / ||b_j|| <= tol on the recurrence residual; when  */
 /* it passes, the true residual of that column is recomputed, and if it does */

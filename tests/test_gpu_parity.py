@@ -278,28 +278,32 @@ def test_bicgstab_edge_cases(orc, torch, xm, poisson32):
 # mixed precision (FP32 V-cycle, FP64 Krylov) and 16-bit indices
 # --------------------------------------------------------------------------
 # An FP32 V-cycle differs from the FP64 one by the rounding of every stored
-# operand and every operation: unit roundoff 2^-24 ~ 6e-8, amplified by at
-# most a few units per level over ~6-8 levels of smoothing and transfer;
-# 2e-5 relative (max-norm) leaves a margin of ~30 over that estimate.
-MIXED_VCYCLE_TOL = 2e-5
+# operand and every operation.  The oracle's own FP32 cycle is pinned within
+# 64 u (u = 2^-24) of the FP64 cycle (tests/test_oracle_fp32.py, where the
+# bound is derived); the device's FP32 cycle must meet the same bound against
+# the FP64 oracle, and so lie within 128 u of the oracle's FP32 cycle.
+U32 = 2.0 ** -24
 
 
-@pytest.mark.parametrize("smoother", [0, 1])
+@pytest.mark.parametrize("smoother", [0, 1, 2])
 @pytest.mark.parametrize("m", [1, 16])
-def test_vcycle_mixed_vs_fp64(orc, torch, xm, jump24, smoother, m):
+def test_vcycle_mixed_vs_fp32_oracle(orc, torch, xm, jump24, smoother, m):
     p, H = jump24
     _say(f"[vcycle-mixed] jump24 smoother={smoother} m={m}")
     B = inputs.uniform_rhs(p.n, m, 6)
-    Zref = H.vcycle(B, smoother=smoother)
+    Z64 = H.vcycle(B, smoother=smoother)
+    Z32 = H.vcycle32(B, smoother=smoother)
     S = xm.Solver(H.export(), smoother=smoother, precision=xm.MIXED)
     Bd = _dev(torch, B)
     Zd = torch.full_like(Bd, np.nan)
     S.vcycle(Bd, Zd)
     torch.cuda.synchronize()
     Z = Zd.cpu().numpy()
-    err = _relmax(Z, Zref)
-    assert err <= MIXED_VCYCLE_TOL, err
-    assert err > 1e-12          # really computed in reduced precision
+    e64, e32, eo = _relmax(Z, Z64), _relmax(Z, Z32), _relmax(Z32, Z64)
+    _say(f"  |gpu - fp64| {e64:.2e}, |gpu - fp32 oracle| {e32:.2e}, |fp32 oracle - fp64| {eo:.2e}")
+    assert e64 <= 64 * U32, e64
+    assert e32 <= 128 * U32, e32
+    assert e64 > 1e-12          # really computed in reduced precision
     S.close()
 
 
@@ -331,17 +335,19 @@ def test_index16_bitwise_equal_index32(orc, torch, xm, smoother):
     assert np.array_equal(outs[0], outs[1])
 
 
-@pytest.mark.parametrize("method", [0, 1])
-def test_mixed_solve_accuracy(orc, torch, xm, jump24, method):
+@pytest.mark.parametrize("method,smoother,m", [(0, 0, 8), (1, 0, 8), (0, 1, 16), (1, 1, 16),
+                                                (1, 2, 4)])
+def test_mixed_solve_accuracy(orc, torch, xm, jump24, method, smoother, m):
     """FP64 Krylov with an FP32 preconditioner reaches the same tolerance;
     its error against a tight FP64 reference is no worse than twice the
     FP64 oracle's own error at the same tolerance (or 1e-7)."""
     p, H = jump24
-    _say(f"[mixed-solve] jump24 method={method}")
-    B = inputs.uniform_rhs(p.n, 8, 44)
-    Xref, _, _ = H.solve(B, method=method, tol=1e-12)
-    Xalg, so, _ = H.solve(B, method=method, tol=1e-8)
-    S = xm.Solver(H.export(), method=method, precision=xm.MIXED, index_bits=16)
+    _say(f"[mixed-solve] jump24 method={method} smoother={smoother} m={m}")
+    B = inputs.uniform_rhs(p.n, m, 44)
+    Xref, _, _ = H.solve(B, method=method, smoother=smoother, tol=1e-12)
+    Xalg, so, _ = H.solve(B, method=method, smoother=smoother, tol=1e-8)
+    S = xm.Solver(H.export(), method=method, smoother=smoother, precision=xm.MIXED,
+                  index_bits=16)
     Bd = _dev(torch, B)
     Xd = torch.zeros_like(Bd)
     rc, st = S.solve(Bd, Xd, tol=1e-8)
