@@ -107,7 +107,10 @@ typedef struct {
     int32_t max_iters;     /* default 1000 */
     int32_t x0_mode;       /* XAMG_X0_ZERO (default) or XAMG_X0_GIVEN */
     int32_t flexible;      /* CG beta: 0 Fletcher-Reeves, 1 flexible; MIXED forces 1 */
-    int32_t check_every;   /* host convergence poll period in iterations, default 1 */
+    int32_t check_every;   /* host convergence poll: every check_every iterations, or
+                              0 (default): at the iteration predicted from the decay
+                              of the largest active relative residual (16 bytes
+                              copied per poll) */
     int32_t gs_block;      /* Gauss-Seidel block size in rows: 4, 8 (default) or 16 */
     int32_t precond;       /* 1 (default): the AMG V-cycle preconditions the Krylov
                               method; 0: no preconditioner (M = I; Table 1 lists the
@@ -227,19 +230,24 @@ typedef struct xamg_batch xamg_batch_t;
 /* Group nsys CG handles (each with its own hierarchy, size and options)
  * for batched solves.  The handles stay owned by the caller and must
  * outlive the batch; a handle may appear once.  iters_per_launch (0 = 4) is
- * the number of CG iterations of every system captured into the batch's
- * HIP graph.  EINVAL for handles whose method is not CG, or repeated
- * handles. */
+ * the number of CG iterations of every system in the batch's follow-up HIP
+ * graph (see xamg_solve_batched).  EINVAL for handles whose method is not
+ * CG, or repeated handles. */
 int xamg_batch_create(xamg_handle_t *const *handles, int32_t nsys, int32_t iters_per_launch,
                       xamg_batch_t **out);
 
 /* Solve all systems of the batch: B[s], X[s] (device, n_s x m[s], as in
  * xamg_solve), stats[s] (host, m[s] entries, or NULL / stats NULL).  The
- * iterations of every system run from one captured HIP graph, launched
- * repeatedly until each system has converged or reached its max_iters;
- * converged systems' kernels exit immediately.  Per-system results equal
- * those of xamg_solve on the same handle.  Return: the worst of the
- * systems' codes (EBREAKDOWN, NOT_CONVERGED, OK); EINVAL as xamg_solve. */
+ * iterations of every system run from captured HIP graphs (one branch per
+ * system): the first launch runs as many iterations as the batch's previous
+ * solve needed, so a repeated solve is normally one graph launch; then the
+ * host reads 16 bytes per system, and graphs of iters_per_launch iterations
+ * follow until each system has converged or reached its max_iters.
+ * Converged systems' kernels exit immediately.  The true-residual checks of
+ * all finished systems are enqueued together and waited for once.
+ * Per-system results equal those of xamg_solve on the same handle.  Return:
+ * the worst of the systems' codes (EBREAKDOWN, NOT_CONVERGED, OK); EINVAL
+ * as xamg_solve. */
 int xamg_solve_batched(xamg_batch_t *b, const double *const *B, double *const *X,
                        const int32_t *m, double tol, xamg_stats_t *const *stats);
 
@@ -263,18 +271,20 @@ int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
  * the Gauss-Seidel smoother: of its sweeps, lane groups per block of rows),
  * of P_l and of R_l (0 where the operator or pass does not exist): the lane
  * groups per row (1, 2, 4, 8) plus 16 when the pass uses the sweeping
- * launch.  cap >= 4 * nlevels. */
+ * launch; then out[4 nlevels] = the split of the Krylov operator, the FP64
+ * copy of A_0 (a mixed-precision handle tunes it apart from the FP32 A_0 of
+ * its V-cycle).  cap >= 4 * nlevels + 1. */
 int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
 
 /* Set the row splits for m columns: the inverse of xamg_tuning, same layout
  * (in[4l .. 4l+3] for A_l, A_l's pre-smoothing pass, P_l and R_l; entries
  * 1..3 of the coarsest level are ignored), applied to the FP64 and the FP32
- * copies.  Each value is 1, 2, 4 or 8 lane groups per row, plus 16 for the
- * sweeping launch; a split wider than a wavefront allows for m (lanes per
+ * copies, and in[4 nlevels] to the FP64 A_0 of the Krylov method.  Each value
+ * is 1, 2, 4 or 8 lane groups per row, plus 16 for the sweeping launch; a split wider than a wavefront allows for m (lanes per
  * row x groups > 64) runs with the widest that fits.  Marks m as tuned, so
  * the values stay until xamg_autotune(h, m, 1).  For callers that tune
  * offline, and for tests that force every launch shape.  count >= 4 *
- * nlevels.  Returns OK or EINVAL (null pointer, m, count or a value out of
+ * nlevels + 1.  Returns OK or EINVAL (null pointer, m, count or a value out of
  * range); the handle is unchanged on error. */
 int xamg_set_tuning(xamg_handle_t *h, int32_t m, const int32_t *in, int32_t count);
 

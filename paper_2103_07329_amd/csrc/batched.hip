@@ -13,30 +13,47 @@
 // whose coarse levels are latency-bound, overlap with the large ones.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
-#include "cycle.hpp"
+#include "solver.hpp"
 
 struct xamg_batch {};   // opaque ABI tag; the real object is xamg::Batch
 
 namespace xamg {
 
+// One captured graph: `iters` CG iterations of every system.
+struct Captured {
+    int iters = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<uintptr_t> key;   // B, X, m, buffers and launch shapes baked in
+    void reset()
+    {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+};
+
 struct Batch : xamg_batch {
     std::vector<Handle*> hs;
-    int iters_per_launch = 4;
+    int iters_per_launch = 4;     // iterations of the follow-up graph
+    bool predict = true;          // first launch: the iterations the last solve needed
+    int last_iters = 0;           // largest iteration count of the last solve
     hipStream_t s0 = nullptr;
     std::vector<hipStream_t> ss;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> joins;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<uintptr_t> key;   // B, X, m of the captured call
+    Captured main, step;
 
     ~Batch()
     {
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        main.reset();
+        step.reset();
         if (fork) hipEventDestroy(fork);
         for (hipEvent_t e : joins) hipEventDestroy(e);
         for (hipStream_t s : ss) hipStreamDestroy(s);
@@ -124,9 +141,9 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
                 h.w.bpad = h.alloc<double>(size_t(n) * h.w.mcap);
                 h.w.xpad = h.alloc<double>(size_t(n) * h.w.mcap);
             }
-            hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
+            hipLaunchKernelGGL((dev::copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
                                h.stream, B[s], m[s], h.w.bpad, mp[s], n, m[s]);
-            hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
+            hipLaunchKernelGGL((dev::copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
                                h.stream, X[s], m[s], h.w.xpad, mp[s], n, m[s]);
             Bs[s] = h.w.bpad;
             Xs[s] = h.w.xpad;
@@ -138,7 +155,7 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
     }
     bool bad = false;
     for (int s = 0; s < ns; ++s) {
-        sync_state(*b.hs[s]);
+        poll_state(*b.hs[s]);
         bad |= b.hs[s]->st_host->nrestart < 0;
     }
     if (bad) {
@@ -146,7 +163,7 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
         return XAMG_EINVAL;
     }
 
-    // capture (or reuse) the graph of K iterations of every system
+    // capture (or reuse) a graph of K iterations of every system
     std::vector<uintptr_t> key;
     for (int s = 0; s < ns; ++s) {
         key.push_back(reinterpret_cast<uintptr_t>(Bs[s]));
@@ -157,15 +174,15 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
         key.push_back(reinterpret_cast<uintptr_t>(b.hs[s]->part));
         key.push_back(uintptr_t(b.hs[s]->tune_epoch));
     }
-    if (!b.exec || key != b.key) {
-        if (b.exec) { hipGraphExecDestroy(b.exec); b.exec = nullptr; }
-        if (b.graph) { hipGraphDestroy(b.graph); b.graph = nullptr; }
+    auto capture = [&](Captured& g, int iters) {
+        if (g.exec && g.key == key && g.iters == iters) return;
+        g.reset();
         chk(hipStreamBeginCapture(b.s0, hipStreamCaptureModeThreadLocal), "begin capture");
         chk(hipEventRecord(b.fork, b.s0), "fork");
         for (int s = 0; s < ns; ++s) {
             Handle& h = *b.hs[s];
             chk(hipStreamWaitEvent(b.ss[s], b.fork, 0), "fork wait");
-            for (int k = 0; k < b.iters_per_launch; ++k)
+            for (int k = 0; k < iters; ++k)
                 with_m(mp[s], [&](auto mc) {
                     pcg_iteration<decltype(mc)::value>(h, Xs[s]);
                     return 0;
@@ -173,54 +190,80 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
             chk(hipEventRecord(b.joins[s], b.ss[s]), "join");
             chk(hipStreamWaitEvent(b.s0, b.joins[s], 0), "join wait");
         }
-        chk(hipStreamEndCapture(b.s0, &b.graph), "end capture");
-        chk(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0), "instantiate");
-        b.key = key;
-    }
+        chk(hipStreamEndCapture(b.s0, &g.graph), "end capture");
+        chk(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0), "instantiate");
+        g.key = key;
+        g.iters = iters;
+    };
 
     std::vector<char> finished(ns, 0);
     std::vector<int> launched(ns, 0);
     int remaining = ns;
-    // systems with nothing to do (all columns zero or already converged)
-    for (int s = 0; s < ns; ++s) {
-        Handle& h = *b.hs[s];
-        if (h.st_host->nactive == 0) {
-            const int nr = with_m(mp[s], [&](auto mc) {
-                return pcg_true_check<decltype(mc)::value>(h, Bs[s], Xs[s], 1);
-            });
-            if (nr == 0) { finished[s] = 1; --remaining; }
-            else sync_state(h);
-        }
-    }
-    while (remaining > 0) {
-        chk(hipGraphLaunch(b.exec, b.s0), "graph launch");
-        chk(hipStreamSynchronize(b.s0), "graph sync");
+    // true-residual checks of every system whose columns have all stopped:
+    // enqueued on the systems' streams, one wait, then restarts (rare)
+    auto check_done = [&](bool after_launch) {
+        std::vector<int> chk_s;
         for (int s = 0; s < ns; ++s) {
             if (finished[s]) continue;
             Handle& h = *b.hs[s];
-            launched[s] += b.iters_per_launch;
-            sync_state(h);
-            const bool capped = launched[s] >= h.opt.max_iters;
+            const bool capped = after_launch && launched[s] >= h.opt.max_iters;
             if (h.st_host->nactive == 0 || capped) {
-                const int nr = with_m(mp[s], [&](auto mc) {
-                    return pcg_true_check<decltype(mc)::value>(h, Bs[s], Xs[s], capped ? 0 : 1);
+                with_m(mp[s], [&](auto mc) {
+                    pcg_true_enqueue<decltype(mc)::value>(h, Bs[s], Xs[s], capped ? 0 : 1);
+                    return 0;
                 });
-                if (nr == 0 || capped) {
-                    finished[s] = 1;
-                    --remaining;
-                } else {
-                    sync_state(h);
-                }
+                chk_s.push_back(s);
             }
         }
+        for (int s : chk_s) chk(hipStreamSynchronize(b.hs[s]->stream), "check sync");
+        for (int s : chk_s) {
+            Handle& h = *b.hs[s];
+            const bool capped = after_launch && launched[s] >= h.opt.max_iters;
+            const int nr = with_m(mp[s], [&](auto mc) {
+                return pcg_true_finish<decltype(mc)::value>(h);
+            });
+            if (nr == 0 || capped) {
+                finished[s] = 1;
+                --remaining;
+            } else {
+                chk(hipStreamSynchronize(h.stream), "restart sync");
+            }
+        }
+    };
+    // systems with nothing to do (all columns zero or already converged)
+    check_done(false);
+    // the first launch runs as many iterations as the last solve needed (one
+    // graph launch and one poll in the common case); further launches run
+    // iters_per_launch iterations each
+    bool first = true;
+    while (remaining > 0) {
+        Captured* g = &b.step;
+        if (first && b.predict && b.last_iters > b.iters_per_launch) {
+            capture(b.main, b.last_iters);
+            g = &b.main;
+        } else {
+            capture(b.step, b.iters_per_launch);
+        }
+        first = false;
+        chk(hipGraphLaunch(g->exec, b.s0), "graph launch");
+        // after the graph: the 16 polled bytes of every running system, all
+        // copied on the batch stream, then one wait
+        for (int s = 0; s < ns; ++s)
+            if (!finished[s])
+                chk(hipMemcpyAsync(b.hs[s]->st_host, b.hs[s]->st, 16, hipMemcpyDeviceToHost, b.s0),
+                    "poll copy");
+        chk(hipStreamSynchronize(b.s0), "graph sync");
+        for (int s = 0; s < ns; ++s)
+            if (!finished[s]) launched[s] += g->iters;
+        check_done(true);
     }
 
-    int rc = XAMG_OK;
+    int rc = XAMG_OK, maxit = 0;
     for (int s = 0; s < ns; ++s) {
         Handle& h = *b.hs[s];
         const int n = h.lev[0].n;
         if (mp[s] != m[s])
-            hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
+            hipLaunchKernelGGL((dev::copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
                                h.stream, h.w.xpad, mp[s], X[s], m[s], n, m[s]);
         h.check(hipStreamSynchronize(h.stream), "batched sync");
         const dev::ColState& st = *h.st_host;
@@ -236,8 +279,10 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
             }
             if (st.failed[j]) rc = XAMG_EBREAKDOWN;
             else if (!conv && rc == XAMG_OK) rc = XAMG_NOT_CONVERGED;
+            maxit = std::max(maxit, int(st.iters[j]));
         }
     }
+    b.last_iters = maxit;
     return rc;
 }
 

@@ -479,11 +479,12 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         OpFixCols<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, nullptr, nullptr, X};
         launch_rows<M, CPT>(h, op, n, cap);
     }
-    sync_state(h);
+    poll_state(h);
     if (h.st_host->nrestart < 0) return XAMG_EINVAL;
 
     int it = 0;
-    const int every = std::max(1, h.opt.check_every);
+    PollPlan plan{h.opt.check_every};
+    int next = plan.next_after(0, h.st_host->worst, tol);
     for (;;) {
         if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
             OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, t,
@@ -495,7 +496,9 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
             OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, st, r, t, nullptr};
             launch_rows<M, CPT>(h, cp, n, cap);
             launch_fin(h, nb, 2 * M, FinRestartB{st, M});   // partials of (b,b),(t,t) still valid
-            sync_state(h);
+            poll_state(h);
+            plan = PollPlan{h.opt.check_every};
+            next = plan.next_after(it, h.st_host->worst, tol);
             continue;
         }
         ++it;
@@ -525,7 +528,10 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
             const int nb = launch_rows<M, CPT>(h, op, n, cap);
             launch_fin(h, nb, 2 * M, FinRRB{st, M});
         }
-        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
+        if (it >= next || it >= h.opt.max_iters) {
+            poll_state(h);
+            next = plan.next_after(it, h.st_host->worst, tol);
+        }
     }
     return XAMG_OK;
 }

@@ -588,8 +588,11 @@ void pcg_iteration(Handle& h, double* X)
 // true residual of the columns the recurrence froze; columns that fail it
 // restart (r = b - A x; their next iteration takes z = M^-1 r, p = z).
 // Synchronises; returns the number of restarted columns.
+// In two halves, so a batch can check many systems with one wait: enqueue
+// the check and the copy of the column state, then (after the stream has
+// been synchronised) act on the restarts.
 template <int M>
-int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
+void pcg_true_enqueue(Handle& h, const double* B, double* X, int allow_restart)
 {
     constexpr int CPT = cpt_for<double, M>();
     const int n = h.lev[0].n;
@@ -599,14 +602,29 @@ int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
                                                           nullptr};
     const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
     launch_fin(h, nb, 2 * M, FinTrue{h.st, M, allow_restart});
-    sync_state(h);
+    h.check(hipMemcpyAsync(h.st_host, h.st, sizeof(ColState), hipMemcpyDeviceToHost, h.stream),
+            "state copy");
+}
+
+template <int M>
+int pcg_true_finish(Handle& h)
+{
+    constexpr int CPT = cpt_for<double, M>();
     const int nr = h.st_host->nrestart;
     if (nr > 0) {
         OpFixCols<M, CPT> cp{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.r, h.w.t, nullptr};
-        launch_rows<M, CPT>(h, cp, n, h.nb_cap);
+        launch_rows<M, CPT>(h, cp, h.lev[0].n, h.nb_cap);
         sync_r32<M>(h);
     }
     return nr;
+}
+
+template <int M>
+int pcg_true_check(Handle& h, const double* B, double* X, int allow_restart)
+{
+    pcg_true_enqueue<M>(h, B, X, allow_restart);
+    h.check(hipStreamSynchronize(h.stream), "stream sync");
+    return pcg_true_finish<M>(h);
 }
 
 // Multigrid as a standalone solver (Section 2.1, Table 1): per column
@@ -620,9 +638,10 @@ int mg_solve(Handle& h, const double* B, double* X, double tol)
     const DCsr& A = h.lev[0].A64;
     const double* av = static_cast<const double*>(A.v);
     pcg_start<M>(h, B, X, tol);   // r = b - A x, column state
-    sync_state(h);
+    poll_state(h);
     if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
-    const int every = std::max(1, h.opt.check_every);
+    PollPlan plan{h.opt.check_every};
+    int next = plan.next_after(0, h.st_host->worst, tol);
     for (int it = 0; h.st_host->nactive > 0 && it < h.opt.max_iters;) {
         ++it;
         vcycle<M>(h, h.w.r, h.w.z, 0, nullptr);
@@ -632,8 +651,12 @@ int mg_solve(Handle& h, const double* B, double* X, double tol)
                                                               nullptr};
         const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
         launch_fin(h, nb, 2 * M, FinMG{h.st, M});
-        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
+        if (it >= next || it >= h.opt.max_iters) {
+            poll_state(h);
+            next = plan.next_after(it, h.st_host->worst, tol);
+        }
     }
+    sync_state(h);
     return XAMG_OK;
 }
 
@@ -641,20 +664,25 @@ template <int M>
 int pcg(Handle& h, const double* B, double* X, double tol)
 {
     pcg_start<M>(h, B, X, tol);
-    sync_state(h);
+    poll_state(h);
     if (h.st_host->nrestart < 0) return XAMG_EINVAL;   // NaN/Inf in B
     int it = 0;
-    const int every = std::max(1, h.opt.check_every);
+    PollPlan plan{h.opt.check_every};
+    int next = plan.next_after(0, h.st_host->worst, tol);
     for (;;) {
         if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
             const int nr = pcg_true_check<M>(h, B, X, it < h.opt.max_iters ? 1 : 0);
             if (nr == 0 || it >= h.opt.max_iters) break;
-            sync_state(h);
+            plan = PollPlan{h.opt.check_every};
+            next = plan.next_after(it, h.st_host->worst, tol);
             continue;
         }
         ++it;
         pcg_iteration<M>(h, X);
-        if (it % every == 0 || it >= h.opt.max_iters) sync_state(h);
+        if (it >= next || it >= h.opt.max_iters) {
+            poll_state(h);
+            next = plan.next_after(it, h.st_host->worst, tol);
+        }
     }
     return XAMG_OK;
 }

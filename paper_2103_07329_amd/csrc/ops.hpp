@@ -30,6 +30,12 @@ namespace dev {
 
 // Per-column Krylov state, resident on the device (one solve at a time).
 struct ColState {
+    // polled by the host (the first 16 bytes): columns still iterating, the
+    // restart count of the last true-residual check (-1: B not finite), and
+    // the largest recurrence relative residual among the active columns
+    int nactive;
+    int nrestart;
+    double worst;
     double bn2[32];       // ||b_j||^2
     double rz[32];        // CG: (r, z); BiCGStab: rho
     double alpha[32], beta[32], omega[32];
@@ -49,8 +55,6 @@ struct ColState {
     int failed[32];       // stopped by a persistent breakdown
     int nrst[32];         // restarts so far (true-residual and breakdown)
     int max_iters;        // per-column iteration cap
-    int nactive;
-    int nrestart;
 };
 
 // ------------------------------------------------------------------------

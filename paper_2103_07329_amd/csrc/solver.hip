@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -267,6 +268,13 @@ void sync_state(Handle& h)
     h.check(hipStreamSynchronize(h.stream), "stream sync");
 }
 
+void poll_state(Handle& h)
+{
+    static_assert(offsetof(ColState, bn2) == 16, "the polled fields lead the column state");
+    h.check(hipMemcpyAsync(h.st_host, h.st, 16, hipMemcpyDeviceToHost, h.stream), "poll copy");
+    h.check(hipStreamSynchronize(h.stream), "stream sync");
+}
+
 template <class F>
 static int dispatch_m(int mp, F&& f)
 {
@@ -384,7 +392,7 @@ void xamg_default_options(xamg_options_t* o)
     o->max_iters = 1000;
     o->x0_mode = XAMG_X0_ZERO;
     o->flexible = 0;
-    o->check_every = 1;
+    o->check_every = 0;
     o->gs_block = 8;
     o->precond = 1;
     o->stream = nullptr;
@@ -719,7 +727,7 @@ int xamg_tuning(const xamg_handle_t* hh, int32_t m, int32_t* out, int32_t cap)
     if (!h || !out) return xamg::fail(XAMG_EINVAL, "null argument");
     if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
         return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
-    if (cap < 4 * h->nlev) return xamg::fail(XAMG_EINVAL, "output too short");
+    if (cap < 4 * h->nlev + 1) return xamg::fail(XAMG_EINVAL, "output too short");
     int k = 0;
     while ((1 << k) < m) ++k;
     const bool mixed = h->opt.precision == XAMG_MIXED;
@@ -732,6 +740,7 @@ int xamg_tuning(const xamg_handle_t* hh, int32_t m, int32_t* out, int32_t cap)
         out[4 * l + 2] = last ? 0 : (mixed ? L.P32 : L.P64).split[k];
         out[4 * l + 3] = last ? 0 : (mixed ? L.R32 : L.R64).split[k];
     }
+    out[4 * h->nlev] = h->lev[0].A64.split[k];   // the Krylov operator (FP64 A_0)
     return XAMG_OK;
 }
 
@@ -742,7 +751,7 @@ int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t cou
     if (!h || !in) return xamg::fail(XAMG_EINVAL, "null argument");
     if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
         return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
-    if (count < 4 * h->nlev) return xamg::fail(XAMG_EINVAL, "input too short");
+    if (count < 4 * h->nlev + 1) return xamg::fail(XAMG_EINVAL, "input too short");
     const auto valid = [](int v) {
         const int s = v & ~xamg::kSweep;
         return (v & ~(xamg::kSweep | 15)) == 0 && (s == 1 || s == 2 || s == 4 || s == 8);
@@ -755,6 +764,11 @@ int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t cou
                                 in[4 * l + e], l, e);
                 return XAMG_EINVAL;
             }
+    }
+    if (!valid(in[4 * h->nlev])) {
+        xamg::set_error("split %d of the Krylov operator is not 1, 2, 4 or 8 (+16)",
+                        in[4 * h->nlev]);
+        return XAMG_EINVAL;
     }
     int k = 0;
     while ((1 << k) < m) ++k;
@@ -769,6 +783,7 @@ int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t cou
         L.P64.split[k] = L.P32.split[k] = in[4 * l + 2];
         L.R64.split[k] = L.R32.split[k] = in[4 * l + 3];
     }
+    h->lev[0].A64.split[k] = in[4 * h->nlev];
     h->tuned_mask |= 1u << k;
     h->tune_epoch += 1;
     return XAMG_OK;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -227,10 +228,40 @@ __device__ __forceinline__ void recount_active(dev::ColState* st, int M)
     __syncthreads();
     if (threadIdx.x == 0) {
         int c = 0;
-        for (int j = 0; j < M; ++j) c += st->active[j];
+        double w = 0.0;
+        for (int j = 0; j < M; ++j) {
+            c += st->active[j];
+            if (st->active[j]) w = fmax(w, st->relres[j]);
+        }
         st->nactive = c;
+        st->worst = w;
     }
 }
+
+// When the host next reads the solve's progress (16 bytes: active columns
+// and the largest active relative residual).  every > 0: a fixed period.
+// every == 0: predicted from the observed decay of the largest residual,
+// assumed geometric, so that the read falls on the iteration where it
+// should pass tol; never more than 16 iterations ahead.
+struct PollPlan {
+    int every = 0;
+    int last_it = 0;
+    double last_worst = 0.0;
+    int next_after(int it, double worst, double tol)
+    {
+        if (every > 0) return it + every;
+        int step = 1;
+        if (last_it > 0 && last_worst > 0.0 && worst > 0.0 && worst < last_worst && tol > 0.0 &&
+            worst > tol) {
+            const double rate = std::log(worst / last_worst) / double(it - last_it);
+            const double need = std::log(tol / worst) / rate;
+            if (need > 1.0) step = int(std::min(16.0, std::ceil(need)));
+        }
+        last_it = it;
+        last_worst = worst;
+        return it + step;
+    }
+};
 
 // ---- solver entry points (explicitly instantiated for M = 1..32) ----------
 template <int M>
@@ -244,6 +275,16 @@ template <int M>
 int mg_solve(Handle& h, const double* B, double* X, double tol);
 template <int M>
 void spmm64(Handle& h, const DCsr& d, const double* X, double* Y);
+// the CG driver in enqueue-only pieces (no host synchronisation inside), for
+// the batched solver's graph capture
+template <int M>
+void pcg_start(Handle& h, const double* B, double* X, double tol);
+template <int M>
+void pcg_iteration(Handle& h, double* X);
+template <int M>
+void pcg_true_enqueue(Handle& h, const double* B, double* X, int allow_restart);
+template <int M>
+int pcg_true_finish(Handle& h);
 // time each operator's SpMM over the row splits and keep the fastest
 template <int M>
 void autotune(Handle& h);
@@ -255,6 +296,8 @@ void ensure_work(Handle& h, int mp, bool bicg);
 size_t carve_work(const Handle& h, int mp, bool bicg, bool pad, Work& w, char* base,
                   size_t cap);
 void sync_state(Handle& h);
+// copy the 16 polled bytes of the column state to the host and wait
+void poll_state(Handle& h);
 int padded_m(int m);
 int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats);
 int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats);

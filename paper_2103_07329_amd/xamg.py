@@ -362,14 +362,16 @@ class Solver:
         _check(lib().xamg_autotune(self._h, m, 1 if enable else 0), "xamg_autotune")
 
     def tuning(self, m):
-        """Per level (A, A pre-smoothing, P, R) row splits (see xamg_tuning)."""
-        out = (ctypes.c_int32 * (4 * self.nlev))()
+        """Per level (A, A pre-smoothing, P, R) row splits, then a last
+        1-tuple: the Krylov operator's (FP64 A_0) split (see xamg_tuning)."""
+        out = (ctypes.c_int32 * (4 * self.nlev + 1))()
         _check(lib().xamg_tuning(self._h, m, out, len(out)), "xamg_tuning")
-        return [tuple(out[4 * l:4 * l + 4]) for l in range(self.nlev)]
+        return [tuple(out[4 * l:4 * l + 4]) for l in range(self.nlev)] + [(out[4 * self.nlev],)]
 
     def set_tuning(self, m, splits):
         """Force the row splits for m columns: one (A, A pre-smoothing, P, R)
-        tuple per level, as tuning() returns (see xamg_set_tuning)."""
+        tuple per level and the Krylov operator's 1-tuple, as tuning()
+        returns (see xamg_set_tuning)."""
         flat = [int(v) for t in splits for v in t]
         arr = (ctypes.c_int32 * len(flat))(*flat)
         _check(lib().xamg_set_tuning(self._h, m, arr, len(flat)), "xamg_set_tuning")

@@ -51,9 +51,9 @@ def _relmax(a, b):
 
 
 def _force(S, m, v):
-    S.set_tuning(m, [(v, v, v, v)] * S.nlev)
+    S.set_tuning(m, [(v, v, v, v)] * S.nlev + [(v,)])
     got = S.tuning(m)
-    assert got[0][0] == v and got[-1][0] == v
+    assert got[0][0] == v and got[-2][0] == v and got[-1] == (v,)
     if S.nlev > 1:
         assert got[0][1:] == (v, v, v)
 
@@ -112,14 +112,17 @@ def test_set_tuning_rejects_bad_values(orc, torch, xm, jump23):
     p, H = jump23
     _say("[shapes] bad split values")
     S = xm.Solver(H.export())
-    S.set_tuning(16, [(2, 4, 1, 8 | 16)] * S.nlev)
+    S.set_tuning(16, [(2, 4, 1, 8 | 16)] * S.nlev + [(4,)])
     before = S.tuning(16)
-    for bad in (0, 3, 5, 32, 16, -1, 8 | 32):
+    for bad in (0, 3, 5, 16, -1, 8 | 128):
         with pytest.raises(xm.XamgError):
-            S.set_tuning(16, [(bad, 1, 1, 1)] + [(1, 1, 1, 1)] * (S.nlev - 1))
+            S.set_tuning(16, [(bad, 1, 1, 1)] + [(1, 1, 1, 1)] * (S.nlev - 1) + [(1,)])
+        assert S.tuning(16) == before
+        with pytest.raises(xm.XamgError):
+            S.set_tuning(16, [(1, 1, 1, 1)] * S.nlev + [(bad,)])
         assert S.tuning(16) == before
     with pytest.raises(xm.XamgError):
-        S.set_tuning(16, [(1, 1, 1, 1)] * (S.nlev - 1))   # too short
+        S.set_tuning(16, [(1, 1, 1, 1)] * S.nlev)          # too short
     with pytest.raises(xm.XamgError):
-        S.set_tuning(12, [(1, 1, 1, 1)] * S.nlev)          # m not a power of two
+        S.set_tuning(12, [(1, 1, 1, 1)] * S.nlev + [(1,)])  # m not a power of two
     S.close()
