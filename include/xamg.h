@@ -255,12 +255,15 @@ int xamg_batch_destroy(xamg_batch_t *b);
 
 /* Autotuner (Section 2.2's kernels, tuned for this device): for each
  * operator A_l, P_l, R_l of the copy the V-cycle uses (A_l twice: on the
- * residual pass and on the pre-smoothing pass, which gathers b and D^-1),
- * time the SpMM for m columns with 1, 2, 4 and 8 lane groups splitting a
- * row's nonzeros, each with one block per tile of rows or with a sweeping
- * launch (at most 2048 blocks and no more than the device holds at once,
- * taking the tiles in block order), with HIP events on the solver's
- * stream, and keep the fastest.  Runs by itself
+ * residual pass and on the pre-smoothing pass, which gathers b against
+ * A D^-1) and the Krylov operator, time the pass for m columns with 1, 2, 4
+ * and 8 lane groups splitting a row's nonzeros, each with one block per
+ * tile of rows or with a sweeping launch (at most 2048 blocks and no more
+ * than the device holds at once, taking the tiles in block order); then,
+ * one at a time on top of the fastest, the 32-bit indices of a 16-bit
+ * encoded operator, twice the columns per lane, and 512-thread blocks; a
+ * change is kept when it is more than 3% faster.  Timed with HIP events on
+ * the solver's stream.  Runs by itself
  * on the first solve for each padded m; this call re-runs it now (enable
  * = 1) or switches automatic tuning off (enable = 0; the setup-time
  * row-length heuristic stays in use).  m in {1, 2, 4, 8, 16, 32}. */
@@ -270,8 +273,12 @@ int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
  * residual and post-smoothing passes), of A_l's pre-smoothing pass (with
  * the Gauss-Seidel smoother: of its sweeps, lane groups per block of rows),
  * of P_l and of R_l (0 where the operator or pass does not exist): the lane
- * groups per row (1, 2, 4, 8) plus 16 when the pass uses the sweeping
- * launch; then out[4 nlevels] = the split of the Krylov operator, the FP64
+ * groups per row (1, 2, 4, 8) plus the flags 16 (a sweeping launch: no more
+ * blocks than the device holds at once, each taking every gridDim-th tile),
+ * 32 (blocks of 512 threads instead of 256: tiles of twice the rows), 64
+ * (the operator's 32-bit column indices although it has 16-bit offsets)
+ * and 128 (twice the columns per lane: 32 instead of 16 bytes of a row's
+ * columns per gathered nonzero); then out[4 nlevels] = the split of the Krylov operator, the FP64
  * copy of A_0 (a mixed-precision handle tunes it apart from the FP32 A_0 of
  * its V-cycle).  cap >= 4 * nlevels + 1. */
 int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
@@ -280,7 +287,9 @@ int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
  * (in[4l .. 4l+3] for A_l, A_l's pre-smoothing pass, P_l and R_l; entries
  * 1..3 of the coarsest level are ignored), applied to the FP64 and the FP32
  * copies, and in[4 nlevels] to the FP64 A_0 of the Krylov method.  Each value
- * is 1, 2, 4 or 8 lane groups per row, plus 16 for the sweeping launch; a split wider than a wavefront allows for m (lanes per
+ * is 1, 2, 4 or 8 lane groups per row plus any of the flags 16, 32, 64, 128
+ * (see xamg_tuning; a flag that does not apply, such as 128 where the row's
+ * columns do not fill twice the lanes, is ignored); a split wider than a wavefront allows for m (lanes per
  * row x groups > 64) runs with the widest that fits.  Marks m as tuned, so
  * the values stay until xamg_autotune(h, m, 1).  For callers that tune
  * offline, and for tests that force every launch shape.  count >= 4 *

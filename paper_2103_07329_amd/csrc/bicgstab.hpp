@@ -471,8 +471,11 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                            nullptr, M, z, M, n, 0);
     {
-        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, r, nullptr};
-        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+        const int nb = launch_op<M, double, double>(
+            h, A, A.template split_of<M>(), n, cap, [&](auto cpt, auto ix) {
+                return OpResid<M, decltype(cpt)::value, double, double, double, decltype(ix), 2>{
+                    A.rp, av, ix, X, B, r, nullptr};
+            });
         launch_fin(h, nb, 2 * M, FinInitB{st, tol, M});
     }
     if (h.opt.x0_mode == XAMG_X0_GIVEN) {
@@ -487,9 +490,11 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
     int next = plan.next_after(0, h.st_host->worst, tol);
     for (;;) {
         if (h.st_host->nactive == 0 || it >= h.opt.max_iters) {
-            OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, t,
-                                                                  nullptr};
-            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+            const int nb = launch_op<M, double, double>(
+                h, A, A.template split_of<M>(), n, cap, [&](auto cpt, auto ix) {
+                    return OpResid<M, decltype(cpt)::value, double, double, double, decltype(ix),
+                                   2>{A.rp, av, ix, X, B, t, nullptr};
+                });
             launch_fin(h, nb, 2 * M, FinTrueB{st, M, it < h.opt.max_iters ? 1 : 0});
             sync_state(h);
             if (h.st_host->nrestart == 0 || it >= h.opt.max_iters) break;
@@ -508,8 +513,11 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         }
         apply_prec<M>(h, p, ph, 0, nullptr, h.w.p32);
         {
-            OpAxW<M, CPT, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, ph, v, rh, na};
-            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+            const int nb = launch_op<M, double, double>(
+                h, A, A.template split_of<M>(), n, cap, [&](auto cpt, auto ix) {
+                    return OpAxW<M, decltype(cpt)::value, double, decltype(ix), 1>{
+                        A.rp, av, ix, ph, v, rh, na};
+                });
             launch_fin(h, nb, M, FinAlphaB{st, M});
         }
         {
@@ -519,8 +527,11 @@ int bicgstab(Handle& h, const double* B, double* X, double tol)
         }
         apply_prec<M>(h, s, sh, 0, nullptr, h.w.s32);
         {
-            OpAxW<M, CPT, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, sh, t, s, na};
-            const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, cap);
+            const int nb = launch_op<M, double, double>(
+                h, A, A.template split_of<M>(), n, cap, [&](auto cpt, auto ix) {
+                    return OpAxW<M, decltype(cpt)::value, double, decltype(ix), 2>{
+                        A.rp, av, ix, sh, t, s, na};
+                });
             launch_fin(h, nb, 2 * M, FinOmega{st, M});
         }
         {

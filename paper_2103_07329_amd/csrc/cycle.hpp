@@ -216,21 +216,6 @@ static const DCsr& matR(const LevelDev& L) { if constexpr (sizeof(T) == 8) retur
 template <typename T>
 static const T* dinv_of(const LevelDev& L) { if constexpr (sizeof(T) == 8) return L.dinv64; else return L.dinv32; }
 
-// Calls f(idx) with the index decoder of matrix d (16-bit if encoded).
-template <class F>
-static void with_idx(const DCsr& d, F&& f)
-{
-    if (d.off) {
-        Idx16 ix;
-        ix.off = d.off;
-        ix.ci = d.ci;
-        ix.base = d.base;
-        f(ix);
-    } else {
-        f(Idx32{d.ci});
-    }
-}
-
 template <typename T>
 static T* lvbuf(void* p) { return static_cast<T*>(p); }
 
@@ -315,7 +300,6 @@ template <int M, typename T, typename BT, typename OT>
 static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q,
                   const double* bd = nullptr)
 {
-    constexpr int CPT = cpt_for<T, M>();
     const LevelDev& L = h.lev[l];
     const int* na = &h.st->nactive;
     const int cap = h.nb_cap;
@@ -346,58 +330,59 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
     const T omega = T(h.opt.smoother == XAMG_CHEBYSHEV ? ch.omega_deg1 : h.opt.omega);
     const int* rp = A.rp;
     const T* av = static_cast<const T*>(A.v);
+    const T* avd = static_cast<const T*>(A.vd);
+    const int sA = A.template split_of<M>(), sPre = A.template split_pre_of<M>();
 
     const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
     if (!gs && !A.vd) {
         set_error("internal: level %d has no column-scaled matrix for pre-smoothing", l);
         throw DevFail{XAMG_EINVAL};
     }
+    // r = b - A X (the residual after pre-smoothing)
+    auto residual_pass = [&]() {
+        launch_op<M, T, T>(h, A, sA, L.n, cap, [&](auto cpt, auto ix) {
+            return OpResid<M, decltype(cpt)::value, T, T, BT, decltype(ix), 0>{rp, av, ix, X, b, R,
+                                                                               na};
+        });
+    };
     // pre-smoothing from zero (+ residual)
-    with_idx(A, [&](auto ix) {
-        using IX = decltype(ix);
-        if (l == 0) h.timer_begin(XAMG_TIMER_PRESMOOTH);
-        if (gs) {
-            // symmetric sweep from zero: forward into T, backward into X
-            const T* dl1 = dl1_of<T>(L);
-            launch_hgs<M, false, true>(h, A, dl1, b, static_cast<const T*>(nullptr), Tb, na,
-                                       A.template split_pre_of<M>());
-            if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
-            launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), X, na,
-                                       A.template split_pre_of<M>());
-            OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
-            launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
-        } else if (!cheb2) {
-            const T* avd = static_cast<const T*>(A.vd);
-            OpJacPre<M, CPT, T, T, BT, IX> op{rp, avd, ix, dinv, omega, b, X, R, na};
-            launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
-            if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
-        } else {
-            const T* avd = static_cast<const T*>(A.vd);
-            OpChebPre<M, CPT, T, T, BT, IX> op{rp, avd, ix, dinv, T(1.0 / ch.theta), T(ch.c1),
-                                               T(ch.c2), b, X, na};
-            launch_mat<M, CPT>(h, op, A.template split_pre_of<M>(), L.n, cap);
-            if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
-            OpResid<M, CPT, T, T, BT, IX, 0> rs{rp, av, ix, X, b, R, na};
-            launch_mat<M, CPT>(h, rs, A.template split_of<M>(), L.n, cap);
-        }
-    });
+    if (l == 0) h.timer_begin(XAMG_TIMER_PRESMOOTH);
+    if (gs) {
+        // symmetric sweep from zero: forward into T, backward into X
+        const T* dl1 = dl1_of<T>(L);
+        launch_hgs<M, false, true>(h, A, dl1, b, static_cast<const T*>(nullptr), Tb, na, sPre);
+        if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
+        launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), X, na, sPre);
+        residual_pass();
+    } else if (!cheb2) {
+        launch_op<M, T, T>(h, A, sPre, L.n, cap, [&](auto cpt, auto ix) {
+            return OpJacPre<M, decltype(cpt)::value, T, T, BT, decltype(ix)>{rp, avd, ix, dinv,
+                                                                             omega, b, X, R, na};
+        });
+        if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
+    } else {
+        launch_op<M, T, T>(h, A, sPre, L.n, cap, [&](auto cpt, auto ix) {
+            return OpChebPre<M, decltype(cpt)::value, T, T, BT, decltype(ix)>{
+                rp, avd, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), b, X, na};
+        });
+        if (l == 0) h.timer_end(XAMG_TIMER_PRESMOOTH);
+        residual_pass();
+    }
     // restriction b_{l+1} = R_l r_l
     {
         const DCsr& Rm = matR<T>(L);
-        with_idx(Rm, [&](auto ix) {
-            using IX = decltype(ix);
-            OpAx<M, CPT, T, T, IX, 0> op{Rm.rp, static_cast<const T*>(Rm.v), ix, R, Bc, na};
-            launch_mat<M, CPT>(h, op, Rm.template split_of<M>(), Rm.nr, cap);
+        launch_op<M, T, T>(h, Rm, Rm.template split_of<M>(), Rm.nr, cap, [&](auto cpt, auto ix) {
+            return OpAx<M, decltype(cpt)::value, T, T, decltype(ix), 0>{
+                Rm.rp, static_cast<const T*>(Rm.v), ix, R, Bc, na};
         });
     }
     vlevel<M, T, T, T>(h, l + 1, Bc, Xc, 0, nullptr);
     // prolongation x_l += P_l x_{l+1}
     {
         const DCsr& Pm = matP<T>(L);
-        with_idx(Pm, [&](auto ix) {
-            using IX = decltype(ix);
-            OpProlongAdd<M, CPT, T, T, IX> op{Pm.rp, static_cast<const T*>(Pm.v), ix, Xc, X, na};
-            launch_mat<M, CPT>(h, op, Pm.template split_of<M>(), Pm.nr, cap);
+        launch_op<M, T, T>(h, Pm, Pm.template split_of<M>(), Pm.nr, cap, [&](auto cpt, auto ix) {
+            return OpProlongAdd<M, decltype(cpt)::value, T, T, decltype(ix)>{
+                Pm.rp, static_cast<const T*>(Pm.v), ix, Xc, X, na};
         });
     }
     // post-smoothing (+ finest-level dots).  The last pass of the finest
@@ -405,46 +390,45 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
     // of its dots: it takes the FP64 lane layout (16 bytes of those rows per
     // lane; measured 3% faster on the mixed solve than the FP32 layout's
     // two loads per lane)
-    constexpr int CPO = sizeof(OT) > sizeof(T) ? cpt_for<OT, M>() : CPT;
-    with_idx(A, [&](auto ix) {
-        using IX = decltype(ix);
-        auto post = [&](auto dots_tag) {
-            constexpr int D = decltype(dots_tag)::value;
-            if (gs) {
-                // symmetric sweep: forward X -> T, backward T -> xout; the
-                // finest level's dots in a pass of their own
-                const T* dl1 = dl1_of<T>(L);
-                launch_hgs<M, false, false>(h, A, dl1, b, static_cast<const T*>(X), Tb, na,
-                                            A.template split_pre_of<M>());
-                launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), xout, na,
-                                           A.template split_pre_of<M>());
-                if constexpr (D > 0) {
-                    if constexpr (std::is_same<BT, double>::value && std::is_same<OT, double>::value) {
-                        constexpr int CPD = cpt_for<double, M>();
-                        OpDotsBX<M, CPD, D> op;
-                        op.b = b;
-                        op.x = xout;
-                        op.q = q;
-                        nb = launch_rows<M, CPD>(h, op, L.n, cap);
-                    }
+    using LT = std::conditional_t<(sizeof(OT) > sizeof(T)), OT, T>;   // lane layout of that pass
+    auto post = [&](auto dots_tag) {
+        constexpr int D = decltype(dots_tag)::value;
+        if (gs) {
+            // symmetric sweep: forward X -> T, backward T -> xout; the
+            // finest level's dots in a pass of their own
+            const T* dl1 = dl1_of<T>(L);
+            launch_hgs<M, false, false>(h, A, dl1, b, static_cast<const T*>(X), Tb, na, sPre);
+            launch_hgs<M, true, false>(h, A, dl1, b, static_cast<const T*>(Tb), xout, na, sPre);
+            if constexpr (D > 0) {
+                if constexpr (std::is_same<BT, double>::value && std::is_same<OT, double>::value) {
+                    constexpr int CPD = cpt_for<double, M>();
+                    OpDotsBX<M, CPD, D> op;
+                    op.b = b;
+                    op.x = xout;
+                    op.q = q;
+                    nb = launch_rows<M, CPD>(h, op, L.n, cap);
                 }
-            } else if (!cheb2) {
-                OpJacPost<M, CPO, T, T, BT, OT, IX, D> op{rp, av, ix, dinv, omega, X, b, xout,
-                                                          q, na, bd};
-                nb = launch_mat<M, CPO>(h, op, A.template split_of<M>(), L.n, cap);
-            } else {
-                OpChebPost1<M, CPT, T, T, BT, IX> p1{rp, av, ix, dinv, X, b, Tb, na};
-                launch_mat<M, CPT>(h, p1, A.template split_of<M>(), L.n, cap);
-                OpChebPost2<M, CPO, T, T, BT, OT, IX, D> p2{
-                    rp, av, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q, na,
-                    bd};
-                nb = launch_mat<M, CPO>(h, p2, A.template split_of<M>(), L.n, cap);
             }
-        };
-        if (ndots == 2) post(std::integral_constant<int, 2>{});
-        else if (ndots == 1) post(std::integral_constant<int, 1>{});
-        else post(std::integral_constant<int, 0>{});
-    });
+        } else if (!cheb2) {
+            nb = launch_op<M, LT, T>(h, A, sA, L.n, cap, [&](auto cpt, auto ix) {
+                return OpJacPost<M, decltype(cpt)::value, T, T, BT, OT, decltype(ix), D>{
+                    rp, av, ix, dinv, omega, X, b, xout, q, na, bd};
+            });
+        } else {
+            launch_op<M, T, T>(h, A, sA, L.n, cap, [&](auto cpt, auto ix) {
+                return OpChebPost1<M, decltype(cpt)::value, T, T, BT, decltype(ix)>{
+                    rp, av, ix, dinv, X, b, Tb, na};
+            });
+            nb = launch_op<M, LT, T>(h, A, sA, L.n, cap, [&](auto cpt, auto ix) {
+                return OpChebPost2<M, decltype(cpt)::value, T, T, BT, OT, decltype(ix), D>{
+                    rp,  av, ix, dinv, T(1.0 / ch.theta), T(ch.c1), T(ch.c2), Tb, X, b, xout, q,
+                    na,  bd};
+            });
+        }
+    };
+    if (ndots == 2) post(std::integral_constant<int, 2>{});
+    else if (ndots == 1) post(std::integral_constant<int, 1>{});
+    else post(std::integral_constant<int, 0>{});
     return nb;
 }
 
@@ -541,9 +525,11 @@ void pcg_start(Handle& h, const double* B, double* X, double tol)
         hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                            nullptr, M, X, M, n, 0);
     {
-        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, h.w.r,
-                                                              nullptr};
-        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+        const int nb = launch_op<M, double, double>(
+            h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpResid<M, decltype(cpt)::value, double, double, double, decltype(ix), 2>{
+                    A.rp, av, ix, X, B, h.w.r, nullptr};
+            });
         launch_fin(h, nb, 2 * M, FinInit{h.st, tol, M, h.opt.max_iters});
     }
     if (h.opt.x0_mode == XAMG_X0_GIVEN) {
@@ -571,10 +557,12 @@ void pcg_iteration(Handle& h, double* X)
     ColState* st = h.st;
     pcg_precondition<M>(h);
     {
-        OpAx<M, CPT, double, double, Idx32, 1> op{A.rp, av, Idx32{A.ci}, h.w.p, h.w.q,
-                                                   &st->nactive};
         h.timer_begin(XAMG_TIMER_KRYLOV_SPMM);
-        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+        const int nb = launch_op<M, double, double>(
+            h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpAx<M, decltype(cpt)::value, double, double, decltype(ix), 1>{
+                    A.rp, av, ix, h.w.p, h.w.q, &st->nactive};
+            });
         h.timer_end(XAMG_TIMER_KRYLOV_SPMM);
         launch_fin(h, nb, M, FinAlpha{st, M});
     }
@@ -598,9 +586,11 @@ void pcg_true_enqueue(Handle& h, const double* B, double* X, int allow_restart)
     const int n = h.lev[0].n;
     const DCsr& A = h.lev[0].A64;
     const double* av = static_cast<const double*>(A.v);
-    OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, h.w.t,
-                                                          nullptr};
-    const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+    const int nb = launch_op<M, double, double>(
+        h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
+            return OpResid<M, decltype(cpt)::value, double, double, double, decltype(ix), 2>{
+                A.rp, av, ix, X, B, h.w.t, nullptr};
+        });
     launch_fin(h, nb, 2 * M, FinTrue{h.st, M, allow_restart});
     h.check(hipMemcpyAsync(h.st_host, h.st, sizeof(ColState), hipMemcpyDeviceToHost, h.stream),
             "state copy");
@@ -647,9 +637,11 @@ int mg_solve(Handle& h, const double* B, double* X, double tol)
         vcycle<M>(h, h.w.r, h.w.z, 0, nullptr);
         OpAddActive<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, X, h.w.z};
         launch_rows<M, CPT>(h, up, n, h.nb_cap);
-        OpResid<M, CPT, double, double, double, Idx32, 2> op{A.rp, av, Idx32{A.ci}, X, B, h.w.r,
-                                                              nullptr};
-        const int nb = launch_mat<M, CPT>(h, op, A.template split_of<M>(), n, h.nb_cap);
+        const int nb = launch_op<M, double, double>(
+            h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpResid<M, decltype(cpt)::value, double, double, double, decltype(ix), 2>{
+                    A.rp, av, ix, X, B, h.w.r, nullptr};
+            });
         launch_fin(h, nb, 2 * M, FinMG{h.st, M});
         if (it >= next || it >= h.opt.max_iters) {
             poll_state(h);
@@ -690,10 +682,12 @@ int pcg(Handle& h, const double* B, double* X, double tol)
 template <int M>
 void spmm64(Handle& h, const DCsr& d, const double* X, double* Y)
 {
-    constexpr int CPT = cpt_for<double, M>();
-    OpAx<M, CPT, double, double, Idx32, 0> op{d.rp, static_cast<const double*>(d.v),
-                                              Idx32{d.ci}, X, Y, nullptr};
-    launch_mat<M, CPT>(h, op, d.template split_of<M>(), d.nr, h.nb_cap);
+    launch_op<M, double, double>(h, d, d.template split_of<M>(), d.nr, h.nb_cap,
+                                 [&](auto cpt, auto ix) {
+                                     return OpAx<M, decltype(cpt)::value, double, double,
+                                                 decltype(ix), 0>{
+                                         d.rp, static_cast<const double*>(d.v), ix, X, Y, nullptr};
+                                 });
 }
 
 
@@ -712,62 +706,67 @@ template <int M, typename T>
 float time_op(Handle& h, const DCsr& d, int kind, const T* dinv, int split, T* x, T* y, T* z,
               hipEvent_t e0, hipEvent_t e1)
 {
-    constexpr int CPT = cpt_for<T, M>();
-    float best = 0.0f;
-    with_idx(d, [&](auto ix) {
-        using IX = decltype(ix);
-        auto run = [&]() {
-            const T* av = static_cast<const T*>(d.v);
-            if (kind == 0) {
-                OpResid<M, CPT, T, T, T, IX, 0> op{d.rp, av, ix, x, z, y, nullptr};
-                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
-            } else if (kind == 1) {
-                OpAx<M, CPT, T, T, IX, 0> op{d.rp, av, ix, x, y, nullptr};
-                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
-            } else if (kind == 3) {
-                OpProlongAdd<M, CPT, T, T, IX> op{d.rp, av, ix, x, y, nullptr};
-                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
-            } else if (h.opt.smoother == XAMG_GAUSS_SEIDEL) {
-                launch_hgs<M, false, false>(h, d, dinv, static_cast<const T*>(z),
-                                            static_cast<const T*>(x), y, nullptr, split);
-            } else if (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) {
-                OpChebPre<M, CPT, T, T, T, IX> op{d.rp, static_cast<const T*>(d.vd), ix, dinv, T(1),
-                                                  T(0), T(0), x, y, nullptr};
-                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
-            } else {
-                OpJacPre<M, CPT, T, T, T, IX> op{d.rp, static_cast<const T*>(d.vd), ix, dinv, T(0.5),
-                                                 x, y, z, nullptr};
-                launch_mat<M, CPT>(h, op, split, d.nr, h.nb_cap);
-            }
-        };
-        // Before each timed run: stream through two other work blocks
-        // (Krylov q -> t, n0 x mcap each), so the operator is no longer in
-        // L2 or the memory-side cache, then rewrite the run's input blocks
-        // (zeros), so they are -- as in the V-cycle, where a pass reads the
-        // vectors the previous pass of the level has just written while the
-        // matrix streams from HBM.
-        auto prepare = [&]() {
-            const int mc = h.w.mcap;
-            hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(4096), dim3(256), 0,
-                               h.stream, h.w.q, mc, h.w.t, mc, h.lev[0].n, mc);
-            hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
-                               static_cast<const T*>(nullptr), M, x, M, d.nc, 0);
-            if (kind == 0)
-                hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
-                                   static_cast<const T*>(nullptr), M, z, M, d.nr, 0);
-        };
-        run();
-        for (int r = 0; r < 5; ++r) {
-            float ms = 0.0f;
-            prepare();
-            h.check(hipEventRecord(e0, h.stream), "tune event");
-            run();
-            h.check(hipEventRecord(e1, h.stream), "tune event");
-            h.check(hipEventSynchronize(e1), "tune sync");
-            h.check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
-            if (r == 0 || ms < best) best = ms;
+    const T* av = static_cast<const T*>(d.v);
+    const T* avd = static_cast<const T*>(d.vd);
+    auto launch = [&]() {
+        if (kind == 2 && h.opt.smoother == XAMG_GAUSS_SEIDEL) {
+            launch_hgs<M, false, false>(h, d, dinv, static_cast<const T*>(z),
+                                        static_cast<const T*>(x), y, nullptr, split);
+        } else if (kind == 0) {
+            launch_op<M, T, T>(h, d, split, d.nr, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpResid<M, decltype(cpt)::value, T, T, T, decltype(ix), 0>{d.rp, av, ix, x, z,
+                                                                                  y, nullptr};
+            });
+        } else if (kind == 1) {
+            launch_op<M, T, T>(h, d, split, d.nr, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpAx<M, decltype(cpt)::value, T, T, decltype(ix), 0>{d.rp, av, ix, x, y,
+                                                                            nullptr};
+            });
+        } else if (kind == 3) {
+            launch_op<M, T, T>(h, d, split, d.nr, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpProlongAdd<M, decltype(cpt)::value, T, T, decltype(ix)>{d.rp, av, ix, x,
+                                                                                 y, nullptr};
+            });
+        } else if (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) {
+            launch_op<M, T, T>(h, d, split, d.nr, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpChebPre<M, decltype(cpt)::value, T, T, T, decltype(ix)>{
+                    d.rp, avd, ix, dinv, T(1), T(0), T(0), x, y, nullptr};
+            });
+        } else {
+            launch_op<M, T, T>(h, d, split, d.nr, h.nb_cap, [&](auto cpt, auto ix) {
+                return OpJacPre<M, decltype(cpt)::value, T, T, T, decltype(ix)>{
+                    d.rp, avd, ix, dinv, T(0.5), x, y, z, nullptr};
+            });
         }
-    });
+    };
+    // Before each timed run: stream through two other work blocks (Krylov
+    // q -> t, n0 x mcap each), so the operator is no longer in L2 or the
+    // memory-side cache, then rewrite the run's input blocks (zeros), so
+    // they are -- as in the V-cycle, where a pass reads the vectors the
+    // previous pass of the level has just written while the matrix streams
+    // from HBM.
+    auto prepare = [&]() {
+        const int mc = h.w.mcap;
+        hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(4096), dim3(256), 0, h.stream,
+                           h.w.q, mc, h.w.t, mc, h.lev[0].n, mc);
+        hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
+                           static_cast<const T*>(nullptr), M, x, M, d.nc, 0);
+        if (kind == 0)
+            hipLaunchKernelGGL((copy_cols_kernel<T, T>), dim3(2048), dim3(256), 0, h.stream,
+                               static_cast<const T*>(nullptr), M, z, M, d.nr, 0);
+    };
+    float best = 0.0f;
+    launch();
+    for (int r = 0; r < 5; ++r) {
+        float ms = 0.0f;
+        prepare();
+        h.check(hipEventRecord(e0, h.stream), "tune event");
+        launch();
+        h.check(hipEventRecord(e1, h.stream), "tune event");
+        h.check(hipEventSynchronize(e1), "tune sync");
+        h.check(hipEventElapsedTime(&ms, e0, e1), "tune elapsed");
+        if (r == 0 || ms < best) best = ms;
+    }
     return best;
 }
 
@@ -775,14 +774,16 @@ template <int M, typename T>
 void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, hipEvent_t e0,
                  hipEvent_t e1)
 {
-    constexpr int G = M / cpt_for<T, M>();
+    constexpr int C0 = cpt_for<T, M>();
+    constexpr int G = M / C0;
     constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
     if (!d.rp || d.nr == 0) return;
     const bool gs_sweep = kind == 2 && h.opt.smoother == XAMG_GAUSS_SEIDEL;
     if (kind == 2 && !gs_sweep && !d.vd) return;
     // candidates from the simplest launch up; a later one replaces the
     // current choice only when it is more than 3% faster, so that near-ties
-    // (within the timing noise) resolve the same way from run to run
+    // (within the timing noise) resolve the same way from run to run.
+    // First the lane groups per row and the launch mode ...
     float best = 0.0f;
     int bestS = 1;
     for (int S : {1, 2, 4, 8}) {
@@ -793,6 +794,22 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
             if ((S == 1 && sw == 0) || t < 0.97f * best) {
                 best = t;
                 bestS = S | sw;
+            }
+        }
+    }
+    // ... then, one at a time on top of the best, the 32-bit indices of a
+    // 16-bit-encoded operator, twice the columns per lane, and blocks of
+    // twice the threads (the Gauss-Seidel sweep has none of these)
+    if (!gs_sweep) {
+        std::vector<int> flags;
+        if (d.off) flags.push_back(kIdx32);
+        if (2 * C0 <= M) flags.push_back(kWide);
+        flags.push_back(kBig);
+        for (int f : flags) {
+            const float t = time_op<M, T>(h, d, kind, dinv, bestS | f, x, y, z, e0, e1);
+            if (t < 0.97f * best) {
+                best = t;
+                bestS |= f;
             }
         }
     }

@@ -31,7 +31,8 @@
 namespace xamg {
 namespace dev {
 
-constexpr int kBlock = 256;      // threads per block of the row kernels
+constexpr int kBlock = 256;      // threads per block of the row kernels (default)
+constexpr int kMaxBlock = 512;   // the larger block a launch may take instead
 constexpr int kMaxDots = 2;      // dots per kernel
 constexpr int kNumXcd = 8;
 constexpr int kUnroll = 8;      // nonzeros per batch in the row loop
@@ -43,8 +44,10 @@ constexpr bool kSelfCapture = false;
 // ---------------------------------------------------------------------------
 // vector loads/stores of CPT consecutive elements
 // ---------------------------------------------------------------------------
+// (aligned to its size up to 16 bytes: a 32-byte pack is two 16-byte loads,
+// and the ABI promises callers' blocks 16-byte alignment only)
 template <typename T, int N>
-struct alignas(sizeof(T) * N) Pack {
+struct alignas(sizeof(T) * N > 16 ? 16 : sizeof(T) * N) Pack {
     T v[N];
 };
 
@@ -163,8 +166,8 @@ __device__ __forceinline__ void reduce_dots(double (&d)[ND > 0 ? ND : 1][CPT],
 {
     if constexpr (ND > 0) {
         constexpr int G = M / CPT;
-        constexpr int RPB = kBlock / G;
-        __shared__ double sh[ND * RPB * M];
+        const int RPB = int(blockDim.x) / G;
+        __shared__ double sh[ND * (kMaxBlock / G) * M];
         const int g = threadIdx.x % G, rl = threadIdx.x / G;
 #pragma unroll
         for (int q = 0; q < ND; ++q)
@@ -209,14 +212,15 @@ template <class T>
 struct op_has_begin<T, std::void_t<decltype(T::kBegin)>> : std::bool_constant<T::kBegin> {};
 
 template <int M, int CPT, int S, class Op>
-__global__ __launch_bounds__(kBlock) void rows_kernel(Op op_in, int nrows, double* part)
+__global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, double* part)
 {
     Op op = op_in;
     // G lanes share the columns of a row; S such groups split the row's
     // nonzeros (long rows of coarse levels) and combine their sums with a
     // fixed butterfly over the wavefront; U nonzeros per batch and group.
+    // A block of kBlock or kMaxBlock threads holds RPB rows (a tile).
     constexpr int G = M / CPT;
-    constexpr int RPB = kBlock / (G * S);
+    const int RPB = int(blockDim.x) / (G * S);
     constexpr int U = S == 1 ? kUnroll : (S == 2 ? kUnroll / 2 : 2);
     constexpr int ND = Op::kDots;
     static_assert(G * S <= 64, "a row must stay inside one wavefront");

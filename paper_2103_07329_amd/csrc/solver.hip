@@ -752,21 +752,22 @@ int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t cou
     if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
         return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
     if (count < 4 * h->nlev + 1) return xamg::fail(XAMG_EINVAL, "input too short");
-    const auto valid = [](int v) {
-        const int s = v & ~xamg::kSweep;
-        return (v & ~(xamg::kSweep | 15)) == 0 && (s == 1 || s == 2 || s == 4 || s == 8);
+    const int flags = xamg::kSweep | xamg::kBig | xamg::kIdx32 | xamg::kWide;
+    const auto valid = [flags](int v) {
+        const int s = v & 15;
+        return (v & ~(flags | 15)) == 0 && (s == 1 || s == 2 || s == 4 || s == 8);
     };
     for (int l = 0; l < h->nlev; ++l) {
         const bool last = l + 1 == h->nlev;
         for (int e = 0; e < (last ? 1 : 4); ++e)
             if (!valid(in[4 * l + e])) {
-                xamg::set_error("split %d (level %d, entry %d) is not 1, 2, 4 or 8 (+16)",
-                                in[4 * l + e], l, e);
+                xamg::set_error("split %d (level %d, entry %d) is not 1, 2, 4 or 8 plus flags "
+                                "16, 32, 64, 128", in[4 * l + e], l, e);
                 return XAMG_EINVAL;
             }
     }
     if (!valid(in[4 * h->nlev])) {
-        xamg::set_error("split %d of the Krylov operator is not 1, 2, 4 or 8 (+16)",
+        xamg::set_error("split %d of the Krylov operator is not 1, 2, 4 or 8 plus flags",
                         in[4 * h->nlev]);
         return XAMG_EINVAL;
     }

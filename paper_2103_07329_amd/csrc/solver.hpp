@@ -142,34 +142,45 @@ inline int split_for(int64_t nnz, int nrows)
     return avg > 48.0 ? 8 : (avg > 24.0 ? 4 : 1);
 }
 
-// A row split value is S (1, 2, 4 or 8 lane groups per row) plus kSweep
-// when the launch uses at most `cap` blocks (no more than the device holds
-// at once) that sweep the tiles instead of one block per tile (better
-// reuse of the gathered vector on most operators; the autotuner decides per
-// operator).
+// A launch shape ("row split" value): S (1, 2, 4 or 8 lane groups per row)
+// plus the flags below, chosen per operator and pass by the autotuner.
+//   kSweep: at most `cap` blocks (no more than the device holds at once)
+//           sweep the tiles instead of one block per tile;
+//   kBig:   blocks of kMaxBlock threads (tiles of twice the rows);
+//   kIdx32: an operator that also has 16-bit column offsets is read through
+//           its 32-bit indices;
+//   kWide:  each lane takes twice the default columns (32 instead of 16
+//           bytes of the row's columns per gathered nonzero).
 constexpr int kSweep = 16;
+constexpr int kBig = 32;
+constexpr int kIdx32 = 64;
+constexpr int kWide = 128;
 constexpr int kSweepPerCu = 5;
 
-// blocks of rows_kernel<M, CPT, S, Op> that the device holds at once (its
-// occupancy, from the kernel's registers and LDS, times the CU count)
+// blocks of rows_kernel<M, CPT, S, Op> of `block` threads that the device
+// holds at once (its occupancy, from the kernel's registers and LDS, times
+// the CU count)
 template <int M, int CPT, int S, class Op>
-int resident_blocks(const Handle& h)
+int resident_blocks(const Handle& h, int block)
 {
-    static const int per_cu = [] {
-        int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, dev::rows_kernel<M, CPT, S, Op>,
-                                                         dev::kBlock, 0) != hipSuccess)
-            b = 1;
-        return std::max(1, b);
-    }();
-    return per_cu * h.num_cu;
+    static int per_cu[2] = {0, 0};
+    int& b = per_cu[block == dev::kMaxBlock ? 1 : 0];
+    if (b == 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, dev::rows_kernel<M, CPT, S, Op>,
+                                                         block, 0) != hipSuccess)
+            v = 1;
+        b = std::max(1, v);
+    }
+    return b * h.num_cu;
 }
 
 template <int M, int CPT, int S, class Op>
-int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = false)
+int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = false,
+                  int block = dev::kBlock)
 {
     constexpr int G = M / CPT;
-    constexpr int RPB = dev::kBlock / (G * S);
+    const int RPB = block / (G * S);
     const int ntiles = (nrows + RPB - 1) / RPB;
     // one tile per block, unless the kernel has dot products (at most `cap`
     // blocks so their partial sums stay few) or the operator sweeps; a
@@ -181,12 +192,12 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     const bool capped = Op::kDots > 0 || sweep;
     int nb = ntiles;
     if (capped)
-        nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h),
-                       Op::kMatrix ? kSweepPerCu * h.num_cu : ntiles});
+        nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h, block),
+                       Op::kMatrix ? kSweepPerCu * h.num_cu * dev::kBlock / block : ntiles});
     nb = std::max(1, nb);
     if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;   // even over the 8 XCDs
-    hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(dev::kBlock), 0,
-                       h.stream, op, nrows, h.part);
+    hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(block), 0, h.stream, op,
+                       nrows, h.part);
     return nb;
 }
 
@@ -197,23 +208,53 @@ int launch_rows(Handle& h, const Op& op, int nrows, int cap)
     return launch_rows_s<M, CPT, 1>(h, op, nrows, cap);
 }
 
-// operation over the rows of matrix d, with d's row split (see kSweep)
+// operation over the rows of matrix d, with d's launch shape (see kSweep)
 template <int M, int CPT, class Op>
 int launch_mat(Handle& h, const Op& op, int split, int nrows, int cap)
 {
     constexpr int G = M / CPT;
     const bool sweep = (split & kSweep) != 0;
+    const int block = (split & kBig) ? dev::kMaxBlock : dev::kBlock;
     const int s = split & (kSweep - 1);
     if constexpr (G * 8 <= 64) {
-        if (s >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap, sweep);
+        if (s >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap, sweep, block);
     }
     if constexpr (G * 4 <= 64) {
-        if (s >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap, sweep);
+        if (s >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap, sweep, block);
     }
     if constexpr (G * 2 <= 64) {
-        if (s >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap, sweep);
+        if (s >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap, sweep, block);
     }
-    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap, sweep);
+    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap, sweep, block);
+}
+
+// The op that make(cpt, ix) builds, launched with the shape `split` over
+// the rows of matrix d: cpt (std::integral_constant) is the columns per
+// lane -- cpt_for<T, M>(), or twice that with kWide where the row's columns
+// allow it -- and ix the column-index decoder of d (its 16-bit offsets when
+// it has them, unless kIdx32).
+// (Only FP32 copies carry 16-bit offsets: MT is d's value type.)
+template <int M, typename T, typename MT, class Make>
+int launch_op(Handle& h, const DCsr& d, int split, int nrows, int cap, Make&& make)
+{
+    constexpr int C0 = cpt_for<T, M>();
+    auto go = [&](auto cpt) {
+        constexpr int CPT = decltype(cpt)::value;
+        if constexpr (sizeof(MT) == 4) {
+            if (d.off && !(split & kIdx32)) {
+                dev::Idx16 ix;
+                ix.off = d.off;
+                ix.ci = d.ci;
+                ix.base = d.base;
+                return launch_mat<M, CPT>(h, make(cpt, ix), split, nrows, cap);
+            }
+        }
+        return launch_mat<M, CPT>(h, make(cpt, dev::Idx32{d.ci}), split, nrows, cap);
+    };
+    if constexpr (2 * C0 <= M) {
+        if (split & kWide) return go(std::integral_constant<int, 2 * C0>{});
+    }
+    return go(std::integral_constant<int, C0>{});
 }
 
 template <class Fin>

@@ -1,6 +1,8 @@
 """Every launch shape the autotuner can choose, forced through
 xamg_set_tuning: 1, 2, 4 or 8 lane groups per row, each with one block per
-tile or with the sweeping launch, on a jump-coefficient problem of 23^3 =
+tile or with the sweeping launch, and with 512-thread blocks, 32-bit indices
+of a 16-bit-encoded operator and twice the columns per lane, on a
+jump-coefficient problem of 23^3 =
 12167 rows, which leaves a ragged last tile on every level.  For each shape:
 one V-cycle (Jacobi, Chebyshev, symmetric Gauss-Seidel) against the
 oracle's, element-wise within 1e-12 (FP64: only the rounding of fused
@@ -17,7 +19,11 @@ from paper_2103_07329_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [s | sw for s in (1, 2, 4, 8) for sw in (0, 16)]
+# lane groups x launch mode, then the flags: 32 = 512-thread blocks, 64 =
+# 32-bit indices of a 16-bit-encoded operator, 128 = twice the columns per lane
+SHAPES = [s | sw for s in (1, 2, 4, 8) for sw in (0, 16)] + [
+    1 | 32, 2 | 16 | 32, 4 | 128, 8 | 16 | 128, 1 | 32 | 128, 2 | 16 | 32 | 128, 4 | 64,
+    8 | 16 | 32 | 64 | 128]
 
 
 def _say(*a):
@@ -75,22 +81,22 @@ def test_forced_shapes_vcycle(orc, torch, xm, jump23, smoother, m):
         Z = Zd.cpu().numpy()
         assert np.isfinite(Z).all(), v
         err = _relmax(Z, Zref)
-        _say(f"   split {v:2d}: rel err {err:.2e}")
+        _say(f"   split {v:3d}: rel err {err:.2e}")
         assert err <= 1e-12, v
     S.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_forced_shapes_pcg(orc, torch, xm, jump23, precision):
+@pytest.mark.parametrize("precision,index_bits", [(0, 32), (1, 32), (1, 16)])
+def test_forced_shapes_pcg(orc, torch, xm, jump23, precision, index_bits):
     p, H = jump23
     m = 8
-    _say(f"[shapes pcg] jump23 m={m} precision={precision}")
+    _say(f"[shapes pcg] jump23 m={m} precision={precision} index_bits={index_bits}")
     B = inputs.uniform_rhs(p.n, m, 239)
     Xo, so, rco = H.solve(B, smoother=1, tol=1e-8)
     assert rco == 0
     import scipy.sparse as sp
     A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
-    S = xm.Solver(H.export(), smoother=1, precision=precision)
+    S = xm.Solver(H.export(), smoother=1, precision=precision, index_bits=index_bits)
     Bd = torch.from_numpy(B).cuda()
     for v in SHAPES:
         _force(S, m, v)
@@ -99,7 +105,7 @@ def test_forced_shapes_pcg(orc, torch, xm, jump23, precision):
         assert rc == xm.OK, v
         X = Xd.cpu().numpy()
         tr = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
-        _say(f"   split {v:2d}: iters {st['iters'].tolist()}, true relres {tr.max():.2e}")
+        _say(f"   split {v:3d}: iters {st['iters'].tolist()}, true relres {tr.max():.2e}")
         assert np.all(tr <= 1e-8), v
         if precision == 0:
             assert np.array_equal(st["iters"], so["iters"]), v
@@ -114,7 +120,7 @@ def test_set_tuning_rejects_bad_values(orc, torch, xm, jump23):
     S = xm.Solver(H.export())
     S.set_tuning(16, [(2, 4, 1, 8 | 16)] * S.nlev + [(4,)])
     before = S.tuning(16)
-    for bad in (0, 3, 5, 16, -1, 8 | 128):
+    for bad in (0, 3, 5, 16, -1, 8 | 256, 32, 64 | 128):
         with pytest.raises(xm.XamgError):
             S.set_tuning(16, [(bad, 1, 1, 1)] + [(1, 1, 1, 1)] * (S.nlev - 1) + [(1,)])
         assert S.tuning(16) == before
@@ -125,4 +131,37 @@ def test_set_tuning_rejects_bad_values(orc, torch, xm, jump23):
         S.set_tuning(16, [(1, 1, 1, 1)] * S.nlev)          # too short
     with pytest.raises(xm.XamgError):
         S.set_tuning(12, [(1, 1, 1, 1)] * S.nlev + [(1,)])  # m not a power of two
+    S.close()
+
+
+U32 = 2.0 ** -24
+
+
+@pytest.mark.parametrize("m", [4, 16])
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_forced_shapes_vcycle_mixed_index16(orc, torch, xm, jump23, smoother, m):
+    """The FP32 V-cycle with 16-bit offsets under every shape: within the
+    FP32 rounding bound of the oracle's FP32 cycle (128 u, as in the parity
+    tests), and the 32-bit-index form (flag 64) bitwise equal to the 16-bit
+    form of the same shape (same columns in the same order)."""
+    p, H = jump23
+    _say(f"[shapes vcycle mixed16] jump23 smoother={smoother} m={m}")
+    B = inputs.uniform_rhs(p.n, m, 330 + m)
+    Z32 = H.vcycle32(B, smoother=smoother)
+    S = xm.Solver(H.export(), smoother=smoother, precision=xm.MIXED, index_bits=16)
+    Bd = torch.from_numpy(B).cuda()
+    outs = {}
+    for v in SHAPES:
+        _force(S, m, v)
+        Zd = torch.full_like(Bd, float("nan"))
+        S.vcycle(Bd, Zd)
+        torch.cuda.synchronize()
+        Z = Zd.cpu().numpy()
+        err = _relmax(Z, Z32)
+        _say(f"   split {v:3d}: rel err vs FP32 oracle {err:.2e}")
+        assert err <= 128 * U32, v
+        outs[v] = Z
+    for v in SHAPES:
+        if v & 64 and (v & ~64) in outs:
+            assert np.array_equal(outs[v], outs[v & ~64]), v
     S.close()
