@@ -384,6 +384,31 @@ def main():
                                    "max_true_relres": trg}
             log(f"[bench] MG as solver: {msg / m:.3f} ms/RHS, iters {int(itg.max())}")
             Sg.close()
+        # aggressive coarsening of the finest level (a second RS pass on the
+        # distance-two strength, one path; multipass interpolation): smaller
+        # operator complexity, more iterations
+        if wl in ("poisson128", "aniso256"):
+            t0 = time.time()
+            Ha = xamg.HostHierarchy(*prob.csr(), agg_levels=1, num_paths=1)
+            t_agg = time.time() - t0
+            Sa = xamg.Solver(Ha, stream=stream.cuda_stream, **opts)
+            Xa = torch.zeros_like(Bd)
+            Sa.solve(Bd, Xa, tol=1e-8)
+            msa, ita, tra, rca = timed_solves(Sa, Bd, Xa, args.steps, 1e-8, stream, torch)
+            agg = {"agg_levels": 1, "num_paths": 1, "levels": Ha.sizes(),
+                   "operator_complexity": sum(Sa.nnzA) / Sa.nnzA[0],
+                   "grid_complexity": sum(Sa.sizes) / Sa.sizes[0],
+                   "ms_per_rhs": msa / m, "iters": int(ita.max()), "max_true_relres": tra,
+                   "host_setup_s": round(t_agg, 1)}
+            if opts["method"] == xamg.CG and opts["smoother"] in (xamg.JACOBI, xamg.CHEBYSHEV):
+                agg["bytes_per_iteration"] = pcg_iteration_bytes(
+                    Sa, m, opts["smoother"] == xamg.CHEBYSHEV, mixed, flexible=mixed)
+            extras["aggressive"] = agg
+            log(f"[bench] aggressive level 0: levels {Ha.sizes()}, C_A "
+                f"{agg['operator_complexity']:.3f}, C_G {agg['grid_complexity']:.3f}, "
+                f"{msa / m:.3f} ms/RHS, iters {int(ita.max())}")
+            Sa.close()
+            del Ha
         # multi-RHS gain P_m = m T_1 / T_m
         if wl in ("poisson128", "gs150"):
             res = {}

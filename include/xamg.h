@@ -83,6 +83,12 @@ typedef struct {
     int32_t max_coarse;    /* stop when a level has <= this many rows, default 64 */
     int32_t max_levels;    /* error (XAMG_EBREAKDOWN) beyond this, default 40 */
     int32_t lanczos_steps; /* steps of the lambda_max estimate, default 10 */
+    int32_t agg_levels;    /* aggressive coarsening on the first agg_levels levels
+                              (the paper's mg_agg_num_levels, Section 2.4): a second
+                              RS pass over the C points on their distance-two
+                              strength, with multipass interpolation; default 0 */
+    int32_t num_paths;     /* paths of length <= 2 that make a distance-two strong
+                              connection (mg_num_paths), default 1 */
 } xamg_setup_params_t;
 
 /* Solver options. */
@@ -136,7 +142,8 @@ typedef struct xamg_handle xamg_handle_t;
 
 /* ---- host setup (prerequisite, not part of the timed solve) -------------- */
 
-/* Defaults: theta 0.25, max_coarse 64, max_levels 40, lanczos_steps 10. */
+/* Defaults: theta 0.25, max_coarse 64, max_levels 40, lanczos_steps 10,
+ * agg_levels 0, num_paths 1. */
 void xamg_default_setup_params(xamg_setup_params_t *p);
 
 /* Build the classical AMG hierarchy of A on the host (Section 2.3: the

@@ -55,7 +55,7 @@ def lib():
             build()
         L = ctypes.CDLL(_LIB)
         L.orc_build.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _c_int,
-                                _c_int, _c_int, ctypes.POINTER(_vp)]
+                                _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_vp)]
         L.orc_hier_free.argtypes = [_vp]
         L.orc_hier_nlev.argtypes = [_vp]
         L.orc_hier_info.argtypes = [_vp, _c_int, _c_int, _i32p]
@@ -87,6 +87,7 @@ def lib():
         L.orc_sm64_uniform.restype = _c_dbl
         L.orc_dense_solve.argtypes = [_c_int, _f64p, _c_int, _f64p]
         L.orc_rs_split.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _i32p]
+        L.orc_agg_split.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl, _c_int, _i32p]
         L.orc_strength_count.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_dbl,
                                          _i32p]
         L.orc_conv3d_fwd.argtypes = [_c_int, _c_int, _c_int, _f64p, _f64p, _f64p]
@@ -182,6 +183,16 @@ def rs_split(rp, ci, v, theta=0.25):
     return st
 
 
+def agg_split(rp, ci, v, theta=0.25, num_paths=1):
+    """C/F split of aggressive coarsening (first RS pass, then a second pass
+    over its C points on their distance-two strength): 1 = C, 2 = F."""
+    rp, ci, v = _csr(rp, ci, v)
+    st = np.empty(rp.size - 1, np.int32)
+    rc = lib().orc_agg_split(rp.size - 1, rp, ci, v, theta, num_paths, st)
+    assert rc == 0
+    return st
+
+
 def strength_counts(rp, ci, v, theta=0.25):
     rp, ci, v = _csr(rp, ci, v)
     c = np.empty(rp.size - 1, np.int32)
@@ -196,11 +207,12 @@ class Hierarchy:
     """Owns an oracle hierarchy handle; exports its arrays as NumPy."""
 
     def __init__(self, rp, ci, v, theta=0.25, max_coarse=64, max_levels=40,
-                 lanczos_steps=10):
+                 lanczos_steps=10, agg_levels=0, num_paths=1):
         rp, ci, v = _csr(rp, ci, v)
         h = _vp()
         rc = lib().orc_build(rp.size - 1, rp, ci, v, theta, max_coarse,
-                             max_levels, lanczos_steps, ctypes.byref(h))
+                             max_levels, lanczos_steps, agg_levels, num_paths,
+                             ctypes.byref(h))
         if rc != 0:
             raise RuntimeError(f"oracle hierarchy build failed: {rc}")
         self._h = h

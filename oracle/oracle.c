@@ -412,6 +412,194 @@ static int direct_interp(const ocsr *a, const int *srp, const int *sci,
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Aggressive coarsening (the paper's mg_agg_num_levels / mg_num_paths,     */
+/* Section 2.4): after the first RS pass, a second RS pass runs over the C   */
+/* points alone, on their distance-two strength: for C points i != j, j is   */
+/* a strong connection of i when the paths of length one or two from i to j  */
+/* in S number at least num_paths (one for j in S_i, one for every k in S_i  */
+/* with j in S_k).  C points the second pass makes F become F.               */
+/* ------------------------------------------------------------------------ */
+static int aggressive_second_pass(int n, const int *srp, const int *sci, int num_paths,
+                                  int *state)
+{
+    int *loc = (int *)malloc((size_t)(n + 1) * sizeof(int));
+    int *pts = (int *)malloc((size_t)(n + 1) * sizeof(int));
+    int *paths = (int *)calloc((size_t)(n + 1), sizeof(int));
+    int *s2rp, *s2ci = NULL, *t2rp, *t2ci, *st2;
+    int nc = 0, i, a, k, kk, cap = 16, cnt = 0;
+    if (!loc || !pts || !paths) return -1;
+    for (i = 0; i < n; i++) {
+        loc[i] = -1;
+        if (state[i] == PT_C) { loc[i] = nc; pts[nc++] = i; }
+    }
+    s2rp = (int *)calloc((size_t)nc + 1, sizeof(int));
+    s2ci = (int *)malloc((size_t)cap * sizeof(int));
+    if (!s2rp || !s2ci) return -1;
+    for (a = 0; a < nc; a++) {
+        i = pts[a];
+        /* count the paths to every point, then keep the C points reached
+           often enough, in increasing index (scan of the row's reach) */
+        for (k = srp[i]; k < srp[i + 1]; k++) {
+            int j = sci[k];
+            paths[j]++;
+            for (kk = srp[j]; kk < srp[j + 1]; kk++) paths[sci[kk]]++;
+        }
+        {
+            int b;
+            for (b = 0; b < nc; b++) {
+                int j = pts[b];
+                if (j != i && paths[j] >= num_paths) {
+                    if (cnt == cap) {
+                        cap *= 2;
+                        s2ci = (int *)realloc(s2ci, (size_t)cap * sizeof(int));
+                        if (!s2ci) return -1;
+                    }
+                    s2ci[cnt++] = b;
+                }
+            }
+        }
+        for (k = srp[i]; k < srp[i + 1]; k++) {
+            int j = sci[k];
+            paths[j] = 0;
+            for (kk = srp[j]; kk < srp[j + 1]; kk++) paths[sci[kk]] = 0;
+        }
+        s2rp[a + 1] = cnt;
+    }
+    if (pattern_transpose(nc, s2rp, s2ci, &t2rp, &t2ci)) return -1;
+    st2 = (int *)malloc((size_t)(nc + 1) * sizeof(int));
+    if (!st2 || rs_first_pass(nc, s2rp, s2ci, t2rp, t2ci, st2)) return -1;
+    for (a = 0; a < nc; a++) state[pts[a]] = st2[a];
+    free(loc); free(pts); free(paths); free(s2rp); free(s2ci); free(t2rp); free(t2ci); free(st2);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Multipass interpolation (Stueben 2001, multi-pass interpolation), used on */
+/* the aggressively coarsened levels.  C points have unit rows (pass 0).     */
+/* Pass p takes every F point not yet interpolated that depends strongly on  */
+/* a point of an earlier pass; its interpolatory set P_i is its strong        */
+/* neighbours of earlier passes, its weights w_ij those of direct            */
+/* interpolation over P_i, and its row is sum_{j in P_i} w_ij (row of j).     */
+/* Pass 1 is therefore direct interpolation.  Unreached F points keep a      */
+/* zero row; entries that come out exactly 0.0 are dropped.                  */
+/* ------------------------------------------------------------------------ */
+typedef struct { int n, cap; int *c; double *v; } orow;
+
+static int orow_push(orow *r, int c, double v)
+{
+    if (r->n == r->cap) {
+        r->cap = r->cap ? 2 * r->cap : 4;
+        r->c = (int *)realloc(r->c, (size_t)r->cap * sizeof(int));
+        r->v = (double *)realloc(r->v, (size_t)r->cap * sizeof(double));
+        if (!r->c || !r->v) return -1;
+    }
+    r->c[r->n] = c; r->v[r->n] = v; r->n++;
+    return 0;
+}
+
+static int is_strong(const int *srp, const int *sci, int i, int j)
+{
+    int k;
+    for (k = srp[i]; k < srp[i + 1]; k++) if (sci[k] == j) return 1;
+    return 0;
+}
+
+static int multipass_interp(const ocsr *a, const int *srp, const int *sci, const int *state,
+                            ocsr *P)
+{
+    int n = a->nr, nc = 0, i, k, p, nnz = 0, q;
+    int *cidx = (int *)malloc((size_t)(n + 1) * sizeof(int));
+    int *pass = (int *)malloc((size_t)(n + 1) * sizeof(int));
+    int *newp = (int *)malloc((size_t)(n + 1) * sizeof(int));
+    orow *row = (orow *)calloc((size_t)(n + 1), sizeof(orow));
+    double *acc;
+    if (!cidx || !pass || !newp || !row) return -1;
+    for (i = 0; i < n; i++) {
+        cidx[i] = state[i] == PT_C ? nc++ : -1;
+        pass[i] = state[i] == PT_C ? 0 : -1;
+        if (state[i] == PT_C && orow_push(&row[i], cidx[i], 1.0)) return -1;
+    }
+    acc = (double *)calloc((size_t)nc + 1, sizeof(double));
+    if (!acc) return -1;
+    for (p = 1;; p++) {
+        int m = 0;
+        for (i = 0; i < n; i++) {
+            if (pass[i] >= 0) continue;
+            for (k = srp[i]; k < srp[i + 1]; k++)
+                if (pass[sci[k]] >= 0 && pass[sci[k]] < p) { newp[m++] = i; break; }
+        }
+        if (m == 0) break;
+        for (q = 0; q < m; q++) pass[newp[q]] = p;
+        for (q = 0; q < m; q++) {
+            double aii = 0.0, sneg_n = 0.0, spos_n = 0.0, sneg_p = 0.0, spos_p = 0.0, d,
+                   alpha, beta;
+            int c;
+            i = newp[q];
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k];
+                double aij = a->v[k];
+                if (j == i) { aii += aij; continue; }
+                if (aij < 0.0) sneg_n += aij; else spos_n += aij;
+                if (pass[j] >= 0 && pass[j] < p && is_strong(srp, sci, i, j)) {
+                    if (aij < 0.0) sneg_p += aij; else spos_p += aij;
+                }
+            }
+            d = aii + (spos_p == 0.0 ? spos_n : 0.0);
+            alpha = (sneg_p != 0.0) ? sneg_n / sneg_p : 0.0;
+            beta = (spos_p != 0.0) ? spos_n / spos_p : 0.0;
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k], e;
+                double aij = a->v[k], w;
+                if (j == i || !(pass[j] >= 0 && pass[j] < p && is_strong(srp, sci, i, j)))
+                    continue;
+                w = (aij < 0.0) ? -alpha * aij / d : -beta * aij / d;
+                for (e = 0; e < row[j].n; e++) acc[row[j].c[e]] += w * row[j].v[e];
+            }
+            /* collect the accumulated coarse columns in increasing order */
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k], e;
+                if (j == i || !(pass[j] >= 0 && pass[j] < p && is_strong(srp, sci, i, j)))
+                    continue;
+                for (e = 0; e < row[j].n; e++) {
+                    c = row[j].c[e];
+                    if (acc[c] != 0.0) {
+                        /* insertion keeps the row sorted; each column once */
+                        int t = row[i].n, found = 0;
+                        for (t = 0; t < row[i].n; t++) if (row[i].c[t] == c) { found = 1; break; }
+                        if (!found && orow_push(&row[i], c, 0.0)) return -1;
+                    }
+                }
+            }
+            {
+                int t, u;
+                for (t = 1; t < row[i].n; t++)
+                    for (u = t; u > 0 && row[i].c[u] < row[i].c[u - 1]; u--) {
+                        int tc = row[i].c[u]; row[i].c[u] = row[i].c[u - 1]; row[i].c[u - 1] = tc;
+                    }
+                for (t = 0; t < row[i].n; t++) { row[i].v[t] = acc[row[i].c[t]]; }
+                for (t = 0; t < row[i].n; t++) acc[row[i].c[t]] = 0.0;
+            }
+            /* columns whose sum was exactly zero were never added; clear them */
+            for (k = a->rp[i]; k < a->rp[i + 1]; k++) {
+                int j = a->ci[k], e;
+                if (j == i) continue;
+                for (e = 0; e < row[j].n; e++) acc[row[j].c[e]] = 0.0;
+            }
+        }
+    }
+    for (i = 0; i < n; i++) nnz += row[i].n;
+    if (csr_alloc(P, n, nc, nnz)) return -1;
+    nnz = 0;
+    for (i = 0; i < n; i++) {
+        for (k = 0; k < row[i].n; k++) { P->ci[nnz] = row[i].c[k]; P->v[nnz] = row[i].v[k]; nnz++; }
+        P->rp[i + 1] = nnz;
+        free(row[i].c); free(row[i].v);
+    }
+    free(cidx); free(pass); free(newp); free(row); free(acc);
+    return 0;
+}
+
 /* full transpose of a CSR matrix (values included) */
 static int csr_transpose(const ocsr *a, ocsr *t)
 {
@@ -666,7 +854,8 @@ void orc_hier_free(ohier *h)
  * 0.9 of its parent, or when the coarsest matrix is singular.
  */
 int orc_build(int n, const int *rp, const int *ci, const double *v, double theta,
-              int max_coarse, int max_levels, int lanczos_steps, ohier **out)
+              int max_coarse, int max_levels, int lanczos_steps, int agg_levels, int num_paths,
+              ohier **out)
 {
     ohier *h = (ohier *)calloc(1, sizeof(ohier));
     ocsr a0;
@@ -686,7 +875,14 @@ int orc_build(int n, const int *rp, const int *ci, const double *v, double theta
         if (!h->cf[l] || rs_first_pass(h->A[l].nr, srp, sci, trp, tci, h->cf[l])) {
             orc_hier_free(h); return ORC_ENOMEM;
         }
-        if (direct_interp(&h->A[l], srp, sci, h->cf[l], &h->P[l])) { orc_hier_free(h); return ORC_ENOMEM; }
+        if (l < agg_levels) {
+            if (aggressive_second_pass(h->A[l].nr, srp, sci, num_paths, h->cf[l]) ||
+                multipass_interp(&h->A[l], srp, sci, h->cf[l], &h->P[l])) {
+                orc_hier_free(h); return ORC_ENOMEM;
+            }
+        } else if (direct_interp(&h->A[l], srp, sci, h->cf[l], &h->P[l])) {
+            orc_hier_free(h); return ORC_ENOMEM;
+        }
         free(srp); free(sci); free(trp); free(tci);
         if (csr_transpose(&h->P[l], &h->R[l])) { orc_hier_free(h); return ORC_ENOMEM; }
         if (csr_matmul(&h->A[l], &h->P[l], &AP)) { orc_hier_free(h); return ORC_ENOMEM; }
@@ -1711,6 +1907,22 @@ int orc_rs_split(int n, const int *rp, const int *ci, const double *v, double th
     if (strength(&a, theta, &srp, &sci)) return ORC_ENOMEM;
     if (pattern_transpose(n, srp, sci, &trp, &tci)) return ORC_ENOMEM;
     rc = rs_first_pass(n, srp, sci, trp, tci, state);
+    free(srp); free(sci); free(trp); free(tci);
+    return rc ? ORC_ENOMEM : ORC_OK;
+}
+
+/* C/F split of the aggressive coarsening (first pass, then the second pass
+ * over the C points on their distance-two strength) */
+int orc_agg_split(int n, const int *rp, const int *ci, const double *v, double theta,
+                  int num_paths, int *state)
+{
+    ocsr a;
+    int *srp, *sci, *trp, *tci, rc;
+    a.nr = n; a.nc = n; a.rp = (int *)rp; a.ci = (int *)ci; a.v = (double *)v;
+    if (strength(&a, theta, &srp, &sci)) return ORC_ENOMEM;
+    if (pattern_transpose(n, srp, sci, &trp, &tci)) return ORC_ENOMEM;
+    rc = rs_first_pass(n, srp, sci, trp, tci, state) ||
+         aggressive_second_pass(n, srp, sci, num_paths, state);
     free(srp); free(sci); free(trp); free(tci);
     return rc ? ORC_ENOMEM : ORC_OK;
 }

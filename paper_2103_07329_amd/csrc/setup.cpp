@@ -7,7 +7,11 @@
 //   * classical strength of connection, theta = 0.25 by default;
 //   * the first Ruge-Stueben coarsening pass (largest weight first, lowest
 //     index on ties, no second pass);
-//   * direct interpolation;
+//   * direct interpolation; on the first `agg_levels` levels instead
+//     aggressive coarsening (a second RS pass over the C points on their
+//     distance-two strength with `num_paths` paths) and multipass
+//     interpolation -- the paper's mg_agg_num_levels / mg_num_paths
+//     parameters (Section 2.4, its example configuration);
 //   * Galerkin coarse operators A_{l+1} = R_l A_l P_l with R_l = P_l^T;
 //   * stop when a level has at most `max_coarse` rows;
 //   * per level a Lanczos estimate of lambda_max(D^-1 A_l) for Chebyshev.
@@ -205,6 +209,142 @@ void direct_interpolation(const Csr& a, const std::vector<int32_t>& srp,
     }
 }
 
+// ---- aggressive coarsening (the first `agg_levels` levels) ------------------
+// A second Ruge-Stueben pass over the first pass's C points, on the
+// distance-two strength among them: j is a strong connection of i (both C
+// after the first pass, j != i) when there are at least `num_paths` paths of
+// length one or two from i to j in S, i.e. [j in S_i] + |{k in S_i : j in
+// S_k}| >= num_paths.  The points the second pass makes F join the F points;
+// the second pass's C points are the coarse grid.
+void aggressive_split(int n, const std::vector<int32_t>& srp, const std::vector<int32_t>& sci,
+                      int num_paths, std::vector<int8_t>& state)
+{
+    // state holds the first pass's split on entry
+    std::vector<int32_t> cid(n, -1), cpt;
+    for (int i = 0; i < n; ++i)
+        if (state[i] == C) {
+            cid[i] = int32_t(cpt.size());
+            cpt.push_back(i);
+        }
+    const int nc = int(cpt.size());
+    std::vector<int32_t> s2rp(nc + 1, 0), s2ci;
+    std::vector<int> cnt(nc, 0);
+    std::vector<int32_t> touched;
+    for (int a = 0; a < nc; ++a) {
+        const int i = cpt[a];
+        touched.clear();
+        auto add = [&](int j) {
+            const int b = cid[j];
+            if (b < 0 || j == i) return;
+            if (cnt[b]++ == 0) touched.push_back(b);
+        };
+        for (int k = srp[i]; k < srp[i + 1]; ++k) {
+            const int j = sci[k];
+            add(j);
+            for (int kk = srp[j]; kk < srp[j + 1]; ++kk) add(sci[kk]);
+        }
+        std::sort(touched.begin(), touched.end());
+        for (int b : touched) {
+            if (cnt[b] >= num_paths) s2ci.push_back(b);
+            cnt[b] = 0;
+        }
+        s2rp[a + 1] = int32_t(s2ci.size());
+    }
+    if (s2ci.empty()) s2ci.push_back(0);
+    std::vector<int32_t> t2rp, t2ci;
+    transpose_pattern(nc, s2rp, s2ci, t2rp, t2ci);
+    std::vector<int8_t> st2;
+    rs_split(nc, s2rp, s2ci, t2rp, t2ci, st2);
+    for (int a = 0; a < nc; ++a) state[cpt[a]] = st2[a];
+}
+
+// ---- multipass interpolation (the aggressive levels) -------------------------
+// C points are unit rows (pass 0).  Pass p = 1, 2, ... takes the F points
+// not yet interpolated that have a strong connection to a point of an
+// earlier pass; each interpolates, with the direct-interpolation weights,
+// from those strong neighbours P_i of earlier passes, substituting their
+// rows: P_i. = sum_{j in P_i} w_ij P_j.  Pass 1 is direct interpolation
+// from the strong C neighbours.  F points that no pass reaches keep a zero
+// row.  Entries that come out exactly 0.0 are dropped.
+void multipass_interpolation(const Csr& a, const std::vector<int32_t>& srp,
+                             const std::vector<int32_t>& sci, const std::vector<int8_t>& state,
+                             Csr& P)
+{
+    const int n = a.nr;
+    std::vector<int32_t> cidx(n, -1);
+    int nc = 0;
+    for (int i = 0; i < n; ++i)
+        if (state[i] == C) cidx[i] = nc++;
+    std::vector<int> pass(n, -1);
+    for (int i = 0; i < n; ++i)
+        if (state[i] == C) pass[i] = 0;
+    // rows of P as sorted (column, value) lists
+    std::vector<std::vector<std::pair<int32_t, double>>> row(n);
+    for (int i = 0; i < n; ++i)
+        if (state[i] == C) row[i].push_back({cidx[i], 1.0});
+    std::vector<double> acc(nc, 0.0);
+    std::vector<char> mark(nc, 0);
+    std::vector<int32_t> cols;
+    for (int p = 1;; ++p) {
+        std::vector<int> now;
+        for (int i = 0; i < n; ++i) {
+            if (pass[i] >= 0) continue;
+            for (int k = srp[i]; k < srp[i + 1]; ++k)
+                if (pass[sci[k]] >= 0 && pass[sci[k]] < p) {
+                    now.push_back(i);
+                    break;
+                }
+        }
+        if (now.empty()) break;
+        for (int i : now) pass[i] = p;
+        for (int i : now) {
+            double diag = 0.0, neg_all = 0.0, pos_all = 0.0, neg_p = 0.0, pos_p = 0.0;
+            auto in_p = [&](int j) {
+                // strong neighbour from an earlier pass (S_i sorted)
+                if (pass[j] < 0 || pass[j] >= p) return false;
+                return std::binary_search(sci.begin() + srp[i], sci.begin() + srp[i + 1], j);
+            };
+            for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+                const int j = a.ci[k];
+                const double x = a.v[k];
+                if (j == i) { diag += x; continue; }
+                (x < 0.0 ? neg_all : pos_all) += x;
+                if (in_p(j)) (x < 0.0 ? neg_p : pos_p) += x;
+            }
+            if (pos_p == 0.0) diag += pos_all;
+            const double alpha = neg_p != 0.0 ? neg_all / neg_p : 0.0;
+            const double beta = pos_p != 0.0 ? pos_all / pos_p : 0.0;
+            cols.clear();
+            for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+                const int j = a.ci[k];
+                if (j == i || !in_p(j)) continue;
+                const double x = a.v[k];
+                const double w = -(x < 0.0 ? alpha : beta) * x / diag;
+                for (const auto& e : row[j]) {
+                    if (!mark[e.first]) { mark[e.first] = 1; cols.push_back(e.first); }
+                    acc[e.first] += w * e.second;
+                }
+            }
+            std::sort(cols.begin(), cols.end());
+            for (int c : cols) {
+                if (acc[c] != 0.0) row[i].push_back({c, acc[c]});
+                acc[c] = 0.0;
+                mark[c] = 0;
+            }
+        }
+    }
+    P.nr = n;
+    P.nc = nc;
+    P.rp.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) P.rp[i + 1] = P.rp[i] + int32_t(row[i].size());
+    P.ci.resize(std::max<int64_t>(P.rp[n], 1));
+    P.v.resize(std::max<int64_t>(P.rp[n], 1));
+    for (int i = 0; i < n; ++i) {
+        int pos = P.rp[i];
+        for (const auto& e : row[i]) { P.ci[pos] = e.first; P.v[pos] = e.second; ++pos; }
+    }
+}
+
 void transpose(const Csr& a, Csr& t)
 {
     t.nr = a.nc;
@@ -395,7 +535,12 @@ int build_hierarchy(const xamg_csr_t* a0, const xamg_setup_params_t* prm,
             std::vector<int8_t> st;
             rs_split(a.nr, srp, sci, trp, tci, st);
             Csr P, R, AP, Ac;
-            direct_interpolation(a, srp, sci, st, P);
+            if (int(h->A.size()) <= prm->agg_levels) {
+                aggressive_split(a.nr, srp, sci, prm->num_paths, st);
+                multipass_interpolation(a, srp, sci, st, P);
+            } else {
+                direct_interpolation(a, srp, sci, st, P);
+            }
             transpose(P, R);
             spgemm(a, P, AP);
             spgemm(R, AP, Ac);
@@ -497,6 +642,8 @@ void xamg_default_setup_params(xamg_setup_params_t* p)
     p->max_coarse = 64;
     p->max_levels = 40;
     p->lanczos_steps = 10;
+    p->agg_levels = 0;
+    p->num_paths = 1;
 }
 
 int xamg_hierarchy_build(const xamg_csr_t* A, const xamg_setup_params_t* params,
@@ -510,7 +657,8 @@ int xamg_hierarchy_build(const xamg_csr_t* A, const xamg_setup_params_t* params,
     int rc = xamg::validate_csr(A, true, "A");
     if (rc) return rc;
     if (!(p->theta > 0.0 && p->theta <= 1.0) || p->max_coarse < 1 || p->max_levels < 1 ||
-        p->max_levels > XAMG_MAX_LEVELS || p->lanczos_steps < 1)
+        p->max_levels > XAMG_MAX_LEVELS || p->lanczos_steps < 1 || p->agg_levels < 0 ||
+        p->num_paths < 1)
         return xamg::fail(XAMG_EINVAL, "bad setup parameters");
     xamg::HostHierarchy* h = nullptr;
     rc = xamg::build_hierarchy(A, p, &h);

@@ -46,7 +46,8 @@ class HierT(ctypes.Structure):
 
 class SetupParamsT(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("max_coarse", ctypes.c_int32),
-                ("max_levels", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32)]
+                ("max_levels", ctypes.c_int32), ("lanczos_steps", ctypes.c_int32),
+                ("agg_levels", ctypes.c_int32), ("num_paths", ctypes.c_int32)]
 
 
 class OptionsT(ctypes.Structure):
@@ -163,10 +164,10 @@ def _csr_struct(rp, ci, v, ncols=None, keep=None):
 # ---------------------------------------------------------------------------
 class HostHierarchy:
     def __init__(self, rp, ci, v, theta=0.25, max_coarse=64, max_levels=40,
-                 lanczos_steps=10):
+                 lanczos_steps=10, agg_levels=0, num_paths=1):
         keep = []
         a = _csr_struct(rp, ci, v, keep=keep)
-        prm = SetupParamsT(theta, max_coarse, max_levels, lanczos_steps)
+        prm = SetupParamsT(theta, max_coarse, max_levels, lanczos_steps, agg_levels, num_paths)
         h = ctypes.c_void_p()
         _check(lib().xamg_hierarchy_build(ctypes.byref(a), ctypes.byref(prm), ctypes.byref(h)),
                "xamg_hierarchy_build")

@@ -11,7 +11,8 @@
 
 typedef struct ohier ohier;
 int orc_build(int n, const int *rp, const int *ci, const double *v, double theta,
-              int max_coarse, int max_levels, int lanczos_steps, ohier **out);
+              int max_coarse, int max_levels, int lanczos_steps, int agg_levels, int num_paths,
+              ohier **out);
 void orc_hier_free(ohier *h);
 int orc_hier_nlev(const ohier *h);
 int orc_hier_info(const ohier *h, int which, int l, int *info);
@@ -70,7 +71,7 @@ static void stencil(int N, const double *k, int **rp, int **ci, double **v)
 
 static double urand(unsigned *s) { *s = *s * 1664525u + 1013904223u; return (*s >> 8) / 16777216.0 * 2 - 1; }
 
-static void exercise(int N, double jump)
+static void exercise(int N, double jump, int agg_levels, int num_paths)
 {
     int n = N * N * N, m = 3, l, method, smoother, j, rc;
     int *rp, *ci;
@@ -79,7 +80,7 @@ static void exercise(int N, double jump)
     ohier *h = NULL;
     for (j = 0; j < n; j++) k[j] = (j / 8) % 2 ? jump : 1.0;
     stencil(N, k, &rp, &ci, &v);
-    CHECK(orc_build(n, rp, ci, v, 0.25, 20, 40, 10, &h) == 0);
+    CHECK(orc_build(n, rp, ci, v, 0.25, 20, 40, 10, agg_levels, num_paths, &h) == 0);
     for (l = 0; l < orc_hier_nlev(h); l++) {
         int info[3], w;
         for (w = 0; w < 3; w++) {
@@ -145,8 +146,10 @@ static void cnn(void)
 
 int main(void)
 {
-    exercise(6, 1.0);
-    exercise(7, 1000.0);    /* ragged blocks, jump coefficient */
+    exercise(6, 1.0, 0, 1);
+    exercise(7, 1000.0, 0, 1);    /* ragged blocks, jump coefficient */
+    exercise(9, 1.0, 1, 1);       /* aggressive coarsening, multipass interpolation */
+    exercise(9, 1000.0, 2, 2);
     cnn();
     printf("oracle driver ok\n");
     return 0;

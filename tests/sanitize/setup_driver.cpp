@@ -42,6 +42,8 @@ int main()
             xamg_csr_t a{N * N * N, N * N * N, int64_t(ci.size()), rp.data(), ci.data(), v.data()};
             xamg_setup_params_t prm;
             xamg_default_setup_params(&prm);
+            prm.agg_levels = N == 12 ? 2 : (N == 9 ? 1 : 0);
+            prm.num_paths = kz < 1.0 ? 2 : 1;
             xamg_host_hierarchy_t* h = nullptr;
             CHECK(xamg_hierarchy_build(&a, &prm, &h) == XAMG_OK);
             xamg_hierarchy_t view;

@@ -1,7 +1,9 @@
 """The library's host AMG setup against the oracle's (CPU only).
 
 Both follow the same definitions (classical strength, first-pass RS with
-lowest-index ties, direct interpolation, Galerkin), written independently:
+lowest-index ties, direct interpolation, Galerkin; on aggressive levels a
+second RS pass on the distance-two strength among the C points and
+multipass interpolation), written independently:
 C/F splits and sparsity patterns must agree exactly, values to rounding.
 """
 import numpy as np
@@ -30,11 +32,15 @@ def xm():
     return xamg
 
 
-@pytest.mark.parametrize("name", ["poisson16", "aniso12", "jump16", "poisson32"])
-def test_setup_matches_oracle(orc, xm, name):
+@pytest.mark.parametrize("name,agg,paths", [
+    ("poisson16", 0, 1), ("aniso12", 0, 1), ("jump16", 0, 1), ("poisson32", 0, 1),
+    ("poisson16", 1, 1), ("aniso12", 1, 2), ("jump16", 2, 1), ("poisson32", 2, 2)])
+def test_setup_matches_oracle(orc, xm, name, agg, paths):
+    """agg > 0: aggressive coarsening with multipass interpolation on the
+    first agg levels, num_paths = paths."""
     p = _problems()[name]
-    Ho = orc.Hierarchy(*p.csr())
-    Hp = xm.HostHierarchy(*p.csr())
+    Ho = orc.Hierarchy(*p.csr(), agg_levels=agg, num_paths=paths)
+    Hp = xm.HostHierarchy(*p.csr(), agg_levels=agg, num_paths=paths)
     assert Hp.nlev == Ho.nlev
     assert Hp.sizes() == Ho.sizes()
     for l in range(Ho.nlev - 1):
