@@ -272,6 +272,8 @@ def main():
         rc, st = S.solve(Bd, Xd, tol=1e-8)
         assert rc == xamg.OK, rc
 
+    log(f"[bench] launch shapes (A, A pre-smoothing, P, R per level; Krylov A_0): "
+        f"{S.tuning(m if m in (1, 2, 4, 8, 16, 32) else 1 << (m - 1).bit_length())}")
     # timed region: K complete solves, with the library's event timer on the
     # fine-level pre-smoothing pass (kernel A) -- then on the Krylov SpMM
     # (kernel B) in an identical second pass

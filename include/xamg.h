@@ -268,8 +268,9 @@ int xamg_batch_destroy(xamg_batch_t *b);
  * tile of rows or with a sweeping launch (at most 2048 blocks and no more
  * than the device holds at once, taking the tiles in block order); then,
  * one at a time on top of the fastest, the 32-bit indices of a 16-bit
- * encoded operator, twice the columns per lane, and 512-thread blocks; a
- * change is kept when it is more than 3% faster.  Timed with HIP events on
+ * encoded operator, twice the columns per lane, and 512-thread blocks, and
+ * last the banded XCD walk with three segment lengths; a change is kept
+ * when it is more than 3% faster.  Timed with HIP events on
  * the solver's stream.  Runs by itself
  * on the first solve for each padded m; this call re-runs it now (enable
  * = 1) or switches automatic tuning off (enable = 0; the setup-time
@@ -283,9 +284,12 @@ int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
  * groups per row (1, 2, 4, 8) plus the flags 16 (a sweeping launch: no more
  * blocks than the device holds at once, each taking every gridDim-th tile),
  * 32 (blocks of 512 threads instead of 256: tiles of twice the rows), 64
- * (the operator's 32-bit column indices although it has 16-bit offsets)
- * and 128 (twice the columns per lane: 32 instead of 16 bytes of a row's
- * columns per gathered nonzero); then out[4 nlevels] = the split of the Krylov operator, the FP64
+ * (the operator's 32-bit column indices although it has 16-bit offsets),
+ * 128 (twice the columns per lane: 32 instead of 16 bytes of a row's
+ * columns per gathered nonzero) and 256 / 512 / 768 (the banded XCD walk:
+ * the tiles cut into segments of one, a half or a quarter of the
+ * operator's bandwidth, each segment into 8 chunks, the blocks of XCD k
+ * taking chunk k of every segment in order); then out[4 nlevels] = the split of the Krylov operator, the FP64
  * copy of A_0 (a mixed-precision handle tunes it apart from the FP32 A_0 of
  * its V-cycle).  cap >= 4 * nlevels + 1. */
 int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
@@ -294,8 +298,8 @@ int xamg_tuning(const xamg_handle_t *h, int32_t m, int32_t *out, int32_t cap);
  * (in[4l .. 4l+3] for A_l, A_l's pre-smoothing pass, P_l and R_l; entries
  * 1..3 of the coarsest level are ignored), applied to the FP64 and the FP32
  * copies, and in[4 nlevels] to the FP64 A_0 of the Krylov method.  Each value
- * is 1, 2, 4 or 8 lane groups per row plus any of the flags 16, 32, 64, 128
- * (see xamg_tuning; a flag that does not apply, such as 128 where the row's
+ * is 1, 2, 4 or 8 lane groups per row plus any of the flags 16, 32, 64, 128,
+ * 256, 512, 768 (see xamg_tuning; a flag that does not apply, such as 128 where the row's
  * columns do not fill twice the lanes, is ignored); a split wider than a wavefront allows for m (lanes per
  * row x groups > 64) runs with the widest that fits.  Marks m as tuned, so
  * the values stay until xamg_autotune(h, m, 1).  For callers that tune

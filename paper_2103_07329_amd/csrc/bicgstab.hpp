@@ -62,6 +62,9 @@ struct OpAxW {   // KIND 1: (w, y); KIND 2: (w, y), (y, y)
             if constexpr (KIND == 2) d[1][t] += yo.v[t] * yo.v[t];
         }
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // p = r + beta (p - omega v); on a reset column: rh = r, p = r, v = 0

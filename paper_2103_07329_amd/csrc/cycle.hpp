@@ -812,6 +812,18 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
                 bestS |= f;
             }
         }
+        // ... and the banded XCD walk with segments of one, a half and a
+        // quarter bandwidth (square operators)
+        if (d.bw > 0) {
+            const int base = bestS;
+            for (int f : {kSegBw, kSegHalf, kSegQuarter}) {
+                const float t = time_op<M, T>(h, d, kind, dinv, base | f, x, y, z, e0, e1);
+                if (t < 0.97f * best) {
+                    best = t;
+                    bestS = base | f;
+                }
+            }
+        }
     }
     (kind == 2 ? d.split_pre : d.split)[k] = bestS;
 }

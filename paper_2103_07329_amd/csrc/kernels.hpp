@@ -211,8 +211,16 @@ struct op_has_begin : std::false_type {};
 template <class T>
 struct op_has_begin<T, std::void_t<decltype(T::kBegin)>> : std::bool_constant<T::kBegin> {};
 
+// seg > 0 (matrix passes): the banded XCD walk.  The tiles are cut into
+// segments of seg tiles (a multiple of the XCD count), each segment into
+// kNumXcd equal chunks; the blocks of XCD k (blocks are dealt to the XCDs
+// round-robin) take chunk k of every segment, segment after segment.  With
+// a segment about one bandwidth of the matrix long, a row's couplings lie
+// in the same chunk of the neighbouring segments, so the vector rows they
+// share are reused from the XCD's own L2.
 template <int M, int CPT, int S, class Op>
-__global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, double* part)
+__global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, double* part,
+                                                         int seg)
 {
     Op op = op_in;
     // G lanes share the columns of a row; S such groups split the row's
@@ -249,14 +257,26 @@ __global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, do
         // faster.
         const int ntiles = (nrows + RPB - 1) / RPB;
         int tb = 0, te = ntiles, t0 = blockIdx.x, tstep = gridDim.x;
-        if (!Op::kMatrix && gridDim.x % kNumXcd == 0 && int(gridDim.x) < ntiles) {
+        const int xcd = blockIdx.x % kNumXcd;
+        const int ct = seg / kNumXcd;   // tiles per chunk of a segment
+        if (seg > 0) {
+            // this XCD's visits: chunk `xcd` of every segment, in order
+            te = ((ntiles + seg - 1) / seg) * ct;
+            t0 = blockIdx.x / kNumXcd;
+            tstep = gridDim.x / kNumXcd;
+        } else if (!Op::kMatrix && gridDim.x % kNumXcd == 0 && int(gridDim.x) < ntiles) {
             const int per = (ntiles + kNumXcd - 1) / kNumXcd;
-            tb = (blockIdx.x % kNumXcd) * per;
+            tb = xcd * per;
             te = min(ntiles, tb + per);
             t0 = tb + blockIdx.x / kNumXcd;
             tstep = gridDim.x / kNumXcd;
         }
-        for (int t = t0; t < te; t += tstep) {
+        for (int v = t0; v < te; v += tstep) {
+            int t = v;
+            if (seg > 0) {
+                const int sgm = v / ct;
+                t = sgm * seg + xcd * ct + (v - sgm * ct);
+            }
             const int i = t * RPB + rl;
             const bool live = i < nrows;
             AT acc[CPT];
@@ -271,7 +291,8 @@ __global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, do
                 if (live) {
                     auto idx = op.idx;
                     idx.row_begin(i);
-                    const int kb = op.rp[i], ke = op.rp[i + 1];
+                    const int kb = op.rowlen ? i * op.rowlen : op.rp[i];
+                    const int ke = op.rowlen ? kb + op.rowlen : op.rp[i + 1];
                     for (int k0 = kb + sg * U; k0 < ke; k0 += S * U) {
                         int cc[U];
                         AT aa[U];

@@ -110,6 +110,9 @@ struct OpAx {
             for (int t = 0; t < CPT; ++t) d[0][t] += double(xi.v[t]) * double(o.v[t]);
         }
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -144,6 +147,9 @@ struct OpProlongAdd {
         for (int t = 0; t < CPT; ++t) o.v[t] = T(AT(o.v[t]) + acc[t]);
         store_pack<T, CPT>(xf + size_t(i) * M + j0, o);
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -187,6 +193,9 @@ struct OpResid {
             }
         }
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -233,6 +242,9 @@ struct OpJacPre {
         store_pack<T, CPT>(x + size_t(i) * M + j0, xo);
         store_pack<T, CPT>(r + size_t(i) * M + j0, ro);
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -309,6 +321,9 @@ struct OpJacPost {
             for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * double(o.v[t]);
         }
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -357,6 +372,9 @@ struct OpChebPre {
         }
         store_pack<T, CPT>(x + size_t(i) * M + j0, o);
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -395,6 +413,9 @@ struct OpChebPost1 {
         for (int t = 0; t < CPT; ++t) o.v[t] = T((AT(bi.v[t]) - acc[t]) * di);
         store_pack<T, CPT>(r0 + size_t(i) * M + j0, o);
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------
@@ -485,6 +506,9 @@ struct OpChebPost2 {
             for (int t = 0; t < CPT; ++t) d[1][t] += qi.v[t] * double(o.v[t]);
         }
     }
+    // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
+    // pointers are read); 0: CSR row pointers
+    int rowlen = 0;
 };
 
 // ------------------------------------------------------------------------

@@ -120,6 +120,10 @@ static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
     for (int k = 0; k < 6; ++k) d.split[k] = d.split_pre[k] = split_for(c.nnz, int(c.nrows));
     d.rp = upload(h, c.row_ptr, size_t(c.nrows) + 1);
     d.ci = upload(h, c.col, size_t(c.nnz));
+    if (c.nrows == c.ncols)
+        for (int64_t i = 0; i < c.nrows; ++i)
+            for (int64_t k = c.row_ptr[i]; k < c.row_ptr[i + 1]; ++k)
+                d.bw = std::max<int64_t>(d.bw, c.col[k] > i ? c.col[k] - i : i - c.col[k]);
     if (fp32) {
         std::vector<float> v(c.val, c.val + c.nnz);
         d.v = upload(h, v.data(), v.size());
@@ -128,6 +132,52 @@ static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
         d.v = upload(h, c.val, size_t(c.nnz));
     }
     return d;
+}
+
+// A square operator whose rows are (nearly) all of one length, with the
+// shorter rows padded to that length by explicit zeros at columns the row
+// does not hold (the nearest ones, i +- 1, i +- 2, ...), in sorted order.
+// The zeros add exact zeros to every row sum, so results are unchanged.
+// Padded only when the maximum row length is at most 32 and the padding
+// adds at most 15% entries.
+bool pad_uniform(const xamg_csr_t& c, UniformCsr& u)
+{
+    if (c.nrows != c.ncols || c.nrows < 1) return false;
+    const int n = int(c.nrows);
+    int w = 0;
+    for (int i = 0; i < n; ++i) w = std::max(w, c.row_ptr[i + 1] - c.row_ptr[i]);
+    if (w < 1 || w > 32 || double(n) * w > 1.15 * double(c.nnz) || w > n) return false;
+    u.rowlen = w;
+    u.rp.resize(size_t(n) + 1);
+    u.ci.resize(size_t(n) * w);
+    u.v.resize(size_t(n) * w);
+    std::vector<int32_t> cols;
+    for (int i = 0; i < n; ++i) {
+        const int b = c.row_ptr[i], e = c.row_ptr[i + 1];
+        cols.assign(c.col + b, c.col + e);
+        for (int dist = 1; int(cols.size()) < w; ++dist)
+            for (int cand : {i - dist, i + dist})
+                if (int(cols.size()) < w && cand >= 0 && cand < n &&
+                    !std::binary_search(c.col + b, c.col + e, cand))
+                    cols.push_back(cand);
+        std::sort(cols.begin(), cols.end());
+        int k = b;
+        for (int q = 0; q < w; ++q) {
+            const size_t o = size_t(i) * w + q;
+            u.ci[o] = cols[q];
+            if (k < e && c.col[k] == cols[q]) u.v[o] = c.val[k++];
+            else u.v[o] = 0.0;
+        }
+        u.rp[i] = i * w;
+    }
+    u.rp[n] = n * w;
+    u.view.nrows = c.nrows;
+    u.view.ncols = c.ncols;
+    u.view.nnz = int64_t(n) * w;
+    u.view.row_ptr = u.rp.data();
+    u.view.col = u.ci.data();
+    u.view.val = u.v.data();
+    return true;
 }
 
 // 16-bit index encoding of a CSR pattern (see Idx16 in kernels.hpp): per
@@ -486,10 +536,15 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
         const bool mixed = o.precision == XAMG_MIXED;
         for (int l = 0; l < h->nlev; ++l) {
             auto& L = h->lev[l];
-            const xamg_csr_t& a = H->A[l];
+            // rows of (nearly) uniform length are stored padded to exactly
+            // that length, so the row kernels need no row pointers
+            xamg::UniformCsr pad;
+            const bool padded = l + 1 < h->nlev && xamg::pad_uniform(H->A[l], pad);
+            const xamg_csr_t& a = padded ? pad.view : H->A[l];
             L.n = int(a.nrows);
             L.lmax = H->lmax ? H->lmax[l] : 0.0;
             L.A64 = xamg::upload_csr(*h, a, false);
+            if (padded) L.A64.rowlen = pad.rowlen, L.A64.nnz = H->A[l].nnz;
             std::vector<double> d(L.n);
             for (int i = 0; i < L.n; ++i)
                 for (int k = a.row_ptr[i]; k < a.row_ptr[i + 1]; ++k)
@@ -501,6 +556,7 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
             }
             if (mixed && l + 1 < h->nlev) {
                 L.A32 = xamg::upload_csr(*h, a, true);
+                if (padded) L.A32.rowlen = pad.rowlen, L.A32.nnz = H->A[l].nnz;
                 L.P32 = xamg::upload_csr(*h, H->P[l], true);
                 L.R32 = xamg::upload_csr(*h, H->R[l], true);
                 if (o.index_bits == 16) {
@@ -752,7 +808,7 @@ int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t cou
     if (m < 1 || m > XAMG_MAX_M || (m & (m - 1)) != 0)
         return xamg::fail(XAMG_EINVAL, "m must be a power of two in 1..32");
     if (count < 4 * h->nlev + 1) return xamg::fail(XAMG_EINVAL, "input too short");
-    const int flags = xamg::kSweep | xamg::kBig | xamg::kIdx32 | xamg::kWide;
+    const int flags = xamg::kShapeFlags;
     const auto valid = [flags](int v) {
         const int s = v & 15;
         return (v & ~(flags | 15)) == 0 && (s == 1 || s == 2 || s == 4 || s == 8);
@@ -762,7 +818,7 @@ int xamg_set_tuning(xamg_handle_t* hh, int32_t m, const int32_t* in, int32_t cou
         for (int e = 0; e < (last ? 1 : 4); ++e)
             if (!valid(in[4 * l + e])) {
                 xamg::set_error("split %d (level %d, entry %d) is not 1, 2, 4 or 8 plus flags "
-                                "16, 32, 64, 128", in[4 * l + e], l, e);
+                                "16, 32, 64, 128, 256, 512", in[4 * l + e], l, e);
                 return XAMG_EINVAL;
             }
     }

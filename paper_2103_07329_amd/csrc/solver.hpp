@@ -25,6 +25,10 @@ struct DevFail {
 struct DCsr {
     int nr = 0, nc = 0;
     int64_t nnz = 0;
+    int bw = 0;   // bandwidth max |j - i| of a square operator (0: rectangular)
+    // > 0: stored with exactly rowlen entries per row (shorter rows padded
+    // with explicit zeros at unused columns), so row i starts at i * rowlen
+    int rowlen = 0;
     int* rp = nullptr;
     int* ci = nullptr;
     void* v = nullptr;
@@ -53,6 +57,15 @@ struct DCsr {
         return split_pre[M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5];
     }
 };
+
+// a square CSR operator padded to one row length (host copy for the upload)
+struct UniformCsr {
+    int rowlen = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+    xamg_csr_t view{};
+};
+bool pad_uniform(const xamg_csr_t& c, UniformCsr& u);
 
 struct LevelDev {
     int n = 0;
@@ -151,10 +164,17 @@ inline int split_for(int64_t nnz, int nrows)
 //           its 32-bit indices;
 //   kWide:  each lane takes twice the default columns (32 instead of 16
 //           bytes of the row's columns per gathered nonzero).
+//   kSeg*:  (two bits) the banded XCD walk of rows_kernel with segments of
+//           the operator's bandwidth (kSegBw), half (kSegHalf) or a quarter
+//           (kSegQuarter) of it.
 constexpr int kSweep = 16;
 constexpr int kBig = 32;
 constexpr int kIdx32 = 64;
 constexpr int kWide = 128;
+constexpr int kSegShift = 8;
+constexpr int kSegMask = 3 << kSegShift;
+constexpr int kSegBw = 1 << kSegShift, kSegHalf = 2 << kSegShift, kSegQuarter = 3 << kSegShift;
+constexpr int kShapeFlags = kSweep | kBig | kIdx32 | kWide | kSegMask;
 constexpr int kSweepPerCu = 5;
 
 // blocks of rows_kernel<M, CPT, S, Op> of `block` threads that the device
@@ -177,11 +197,19 @@ int resident_blocks(const Handle& h, int block)
 
 template <int M, int CPT, int S, class Op>
 int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = false,
-                  int block = dev::kBlock)
+                  int block = dev::kBlock, int seg_rows = 0)
 {
     constexpr int G = M / CPT;
     const int RPB = block / (G * S);
     const int ntiles = (nrows + RPB - 1) / RPB;
+    // banded XCD walk: segments of seg_rows rows, in tiles, rounded up to a
+    // multiple of the XCD count; off for operators of fewer than 4 segments
+    int seg = 0;
+    if (seg_rows > 0) {
+        seg = (seg_rows + RPB - 1) / RPB;
+        seg = (seg + dev::kNumXcd - 1) / dev::kNumXcd * dev::kNumXcd;
+        if (ntiles < 4 * seg) seg = 0;
+    }
     // one tile per block, unless the kernel has dot products (at most `cap`
     // blocks so their partial sums stay few) or the operator sweeps; a
     // sweeping grid is no larger than what the device holds at once, so
@@ -190,14 +218,16 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     // rows the sweep works on at a time; measured best on 7- and 19-point
     // rows whatever the occupancy; streaming vector ops use every slot)
     const bool capped = Op::kDots > 0 || sweep;
-    int nb = ntiles;
+    // one block per visit (a banded walk pads each segment to whole chunks)
+    int nb = seg > 0 ? (ntiles + seg - 1) / seg * seg : ntiles;
     if (capped)
         nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h, block),
                        Op::kMatrix ? kSweepPerCu * h.num_cu * dev::kBlock / block : ntiles});
     nb = std::max(1, nb);
     if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;   // even over the 8 XCDs
+    if (seg > 0 && nb < dev::kNumXcd) seg = 0;                   // the walk needs every XCD
     hipLaunchKernelGGL((dev::rows_kernel<M, CPT, S, Op>), dim3(nb), dim3(block), 0, h.stream, op,
-                       nrows, h.part);
+                       nrows, h.part, seg);
     return nb;
 }
 
@@ -209,23 +239,26 @@ int launch_rows(Handle& h, const Op& op, int nrows, int cap)
 }
 
 // operation over the rows of matrix d, with d's launch shape (see kSweep)
+// (bw: the operator's bandwidth max |j - i|, for the banded XCD walk)
 template <int M, int CPT, class Op>
-int launch_mat(Handle& h, const Op& op, int split, int nrows, int cap)
+int launch_mat(Handle& h, const Op& op, int split, int nrows, int cap, int bw = 0)
 {
     constexpr int G = M / CPT;
     const bool sweep = (split & kSweep) != 0;
     const int block = (split & kBig) ? dev::kMaxBlock : dev::kBlock;
+    const int sm = (split & kSegMask) >> kSegShift;
+    const int seg_rows = (sm == 0 || bw <= 0) ? 0 : bw >> (sm - 1);
     const int s = split & (kSweep - 1);
     if constexpr (G * 8 <= 64) {
-        if (s >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap, sweep, block);
+        if (s >= 8) return launch_rows_s<M, CPT, 8>(h, op, nrows, cap, sweep, block, seg_rows);
     }
     if constexpr (G * 4 <= 64) {
-        if (s >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap, sweep, block);
+        if (s >= 4) return launch_rows_s<M, CPT, 4>(h, op, nrows, cap, sweep, block, seg_rows);
     }
     if constexpr (G * 2 <= 64) {
-        if (s >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap, sweep, block);
+        if (s >= 2) return launch_rows_s<M, CPT, 2>(h, op, nrows, cap, sweep, block, seg_rows);
     }
-    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap, sweep, block);
+    return launch_rows_s<M, CPT, 1>(h, op, nrows, cap, sweep, block, seg_rows);
 }
 
 // The op that make(cpt, ix) builds, launched with the shape `split` over
@@ -246,10 +279,14 @@ int launch_op(Handle& h, const DCsr& d, int split, int nrows, int cap, Make&& ma
                 ix.off = d.off;
                 ix.ci = d.ci;
                 ix.base = d.base;
-                return launch_mat<M, CPT>(h, make(cpt, ix), split, nrows, cap);
+                auto op = make(cpt, ix);
+                op.rowlen = d.rowlen;
+                return launch_mat<M, CPT>(h, op, split, nrows, cap, d.bw);
             }
         }
-        return launch_mat<M, CPT>(h, make(cpt, dev::Idx32{d.ci}), split, nrows, cap);
+        auto op = make(cpt, dev::Idx32{d.ci});
+        op.rowlen = d.rowlen;
+        return launch_mat<M, CPT>(h, op, split, nrows, cap, d.bw);
     };
     if constexpr (2 * C0 <= M) {
         if (split & kWide) return go(std::integral_constant<int, 2 * C0>{});

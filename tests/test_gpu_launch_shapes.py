@@ -1,7 +1,8 @@
 """Every launch shape the autotuner can choose, forced through
 xamg_set_tuning: 1, 2, 4 or 8 lane groups per row, each with one block per
 tile or with the sweeping launch, and with 512-thread blocks, 32-bit indices
-of a 16-bit-encoded operator and twice the columns per lane, on a
+of a 16-bit-encoded operator, twice the columns per lane and the banded XCD
+walk, on a
 jump-coefficient problem of 23^3 =
 12167 rows, which leaves a ragged last tile on every level.  For each shape:
 one V-cycle (Jacobi, Chebyshev, symmetric Gauss-Seidel) against the
@@ -20,10 +21,13 @@ from paper_2103_07329_amd import inputs
 pytestmark = pytest.mark.gpu
 
 # lane groups x launch mode, then the flags: 32 = 512-thread blocks, 64 =
-# 32-bit indices of a 16-bit-encoded operator, 128 = twice the columns per lane
+# 32-bit indices of a 16-bit-encoded operator, 128 = twice the columns per
+# lane, 256 / 512 / 768 = the banded XCD walk with segments of one, a half
+# and a quarter bandwidth
 SHAPES = [s | sw for s in (1, 2, 4, 8) for sw in (0, 16)] + [
     1 | 32, 2 | 16 | 32, 4 | 128, 8 | 16 | 128, 1 | 32 | 128, 2 | 16 | 32 | 128, 4 | 64,
-    8 | 16 | 32 | 64 | 128]
+    8 | 16 | 32 | 64 | 128, 1 | 256, 2 | 16 | 512, 4 | 768, 1 | 32 | 128 | 256,
+    8 | 16 | 32 | 768]
 
 
 def _say(*a):
@@ -120,7 +124,7 @@ def test_set_tuning_rejects_bad_values(orc, torch, xm, jump23):
     S = xm.Solver(H.export())
     S.set_tuning(16, [(2, 4, 1, 8 | 16)] * S.nlev + [(4,)])
     before = S.tuning(16)
-    for bad in (0, 3, 5, 16, -1, 8 | 256, 32, 64 | 128):
+    for bad in (0, 3, 5, 16, -1, 8 | 1024, 32, 64 | 128, 768):
         with pytest.raises(xm.XamgError):
             S.set_tuning(16, [(bad, 1, 1, 1)] + [(1, 1, 1, 1)] * (S.nlev - 1) + [(1,)])
         assert S.tuning(16) == before

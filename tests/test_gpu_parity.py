@@ -427,8 +427,8 @@ def test_autotune_choices_and_invariance(orc, torch, xm, jump24):
     tun = S.tuning(16)
     _say("   splits (A, A pre-smoothing, P, R) per level:", tun)
     # lane groups plus any of the flags sweep 16, 512-thread blocks 32,
-    # 32-bit indices 64, twice the columns per lane 128
-    ok = {s | f for s in (1, 2, 4, 8) for f in range(0, 256, 16)}
+    # 32-bit indices 64, twice the columns per lane 128, banded walk 256..768
+    ok = {s | f for s in (1, 2, 4, 8) for f in range(0, 1024, 16)}
     for l, t in enumerate(tun[:-1]):
         assert t[0] in ok
         if l + 1 < S.nlev:
