@@ -68,7 +68,7 @@ def lib():
         L.orc_vcycle32.argtypes = [_vp, _c_int, _c_dbl, _c_int, _c_dbl, _c_dbl,
                                    _c_int, _c_int, _f64p, _f64p]
         L.orc_solve.argtypes = [_vp, _c_int, _c_int, _c_dbl, _c_int, _c_dbl,
-                                _c_dbl, _c_int, _c_int, _c_int, _c_int, _c_dbl,
+                                _c_dbl, _c_int, _c_int, _c_int, _c_int, _c_int, _c_dbl,
                                 _c_int, _c_int, _f64p, _f64p, _i32p, _f64p, _f64p,
                                 _i32p, _i32p]
         L.orc_hgs_sweep.argtypes = [_c_int, _i32p, _i32p, _f64p, _c_int, _c_int,
@@ -293,9 +293,10 @@ class Hierarchy:
 
     def solve(self, B, X0=None, method=CG, smoother=JACOBI, omega=2.0 / 3.0,
               degree=2, lo_frac=0.3, hi_frac=1.1, flexible=False, precond=True,
-              max_iters=1000, tol=1e-8, gs_block=8):
+              max_iters=1000, tol=1e-8, gs_block=8, merged=False):
         """Returns (X, stats dict, return code).  precond=False solves without
-        a preconditioner (M = I).  stats: iters, relres, true_relres,
+        a preconditioner (M = I); merged=True runs CG in its merged form
+        (x's update deferred into the next p update).  stats: iters, relres, true_relres,
         converged, restarts (breakdown plus true-residual restarts) per
         column."""
         B = np.ascontiguousarray(B, np.float64)
@@ -315,7 +316,8 @@ class Hierarchy:
         cv = np.zeros(m, np.int32)
         rs = np.zeros(m, np.int32)
         rc = lib().orc_solve(self._h, method, smoother, omega, degree, lo_frac,
-                             hi_frac, gs_block, int(flexible), int(precond), max_iters,
+                             hi_frac, gs_block, int(flexible), int(precond), int(merged),
+                             max_iters,
                              tol, given, m, B, X, it, rr, tr, cv, rs)
         st = {"iters": it, "relres": rr, "true_relres": tr,
               "converged": cv.astype(bool), "restarts": rs}

@@ -1383,6 +1383,7 @@ typedef struct {
     double tol;
     int x0_given;
     int precond;       /* 1 = V-cycle, 0 = none (identity) */
+    int merged;        /* CG: 1 = merged form (x's update deferred, see pcg) */
 } kopt;
 
 static void apply_prec(const ohier *h, const kopt *ko, const smopt *so, int m,
@@ -1390,6 +1391,34 @@ static void apply_prec(const ohier *h, const kopt *ko, const smopt *so, int m,
 {
     if (ko->precond) vcycle_level(h, 0, so, m, r, z, w);
     else memcpy(z, r, (size_t)h->A[0].nr * m * sizeof(double));
+}
+
+/*
+ * Preconditioned CG per column (Hestenes-Stiefel; Section 2.1):
+ *   r = b - A x, z = M r, p = z;
+ *   loop: q = A p, alpha = (r, z)/(p, q), x += alpha p, r -= alpha q,
+ *         test ||r||/||b||, z = M r, beta = (r_new, z_new)/(r, z)
+ *         (flexible: -alpha (z_new, q)/(r, z)), p = z + beta p.
+ * Merged form (ko->merged; Section 2.1's merged formulations regroup the
+ * vector updates so fewer passes read and write the vectors): the
+ * recurrences and every operation on an element are the same, but x's
+ * update of iteration k is postponed into the pass of iteration k + 1 that
+ * forms p = z + beta p, which reads the old p anyway (here: the same
+ * iteration's last pass, so nothing is pending when the loop ends).  A
+ * column's pending alpha is applied before its true residual is formed, so
+ * x, and every other result, equals the standard form's.
+ */
+static void apply_pending_x(int n, int m, const int *only, const double *xp,
+                            const double *p, double *X)
+{
+    int i, j;
+#pragma omp parallel for private(j) schedule(static)
+    for (i = 0; i < n; i++)
+        for (j = 0; j < m; j++)
+            if ((only == NULL || only[j]) && xp[j] != 0.0) {
+                size_t k = (size_t)i * m + j;
+                X[k] += xp[j] * p[k];
+            }
 }
 
 static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
@@ -1413,8 +1442,10 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
     double *beta = (double *)malloc((size_t)m * sizeof(double));
     int *act = (int *)malloc((size_t)m * sizeof(int));
     int *rst = (int *)calloc((size_t)m, sizeof(int));
+    double *xp = (double *)calloc((size_t)m, sizeof(double));   /* merged: pending alpha */
+    int *one = (int *)calloc((size_t)m, sizeof(int));
     if (!r || !z || !p || !q || !bn || !rz || !rzn || !zq || !pq || !rr || !alpha ||
-        !beta || !act || !rst)
+        !beta || !act || !rst || !xp || !one)
         return ORC_ENOMEM;
 
     if (!ko->x0_given) memset(X, 0, nm * sizeof(double));
@@ -1450,13 +1481,15 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
             if (!(pq[j] > 0.0) || !isfinite(pq[j])) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
             alpha[j] = rz[j] / pq[j];
         }
-        /* x += alpha p, r -= alpha q (active columns) */
+        /* x += alpha p (merged: pending), r -= alpha q (active columns) */
+        if (ko->merged)
+            for (j = 0; j < m; j++) xp[j] = act[j] ? alpha[j] : 0.0;
 #pragma omp parallel for private(j) schedule(static)
         for (i = 0; i < n; i++)
             for (j = 0; j < m; j++)
                 if (act[j]) {
                     size_t k = (size_t)i * m + j;
-                    X[k] += alpha[j] * p[k];
+                    if (!ko->merged) X[k] += alpha[j] * p[k];
                     r[k] -= alpha[j] * q[k];
                 }
         dots(n, m, r, r, rr);
@@ -1465,7 +1498,14 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
             iters[j] = it;
             relres[j] = sqrt(rr[j]) / bn[j];
             if (relres[j] <= ko->tol) {
-                double tr = sqrt(residual_col_norm2(A, m, j, B, X)) / bn[j];
+                double tr;
+                if (ko->merged) {   /* bring x_j up to date first */
+                    one[j] = 1;
+                    apply_pending_x(n, m, one, xp, p, X);
+                    one[j] = 0;
+                    xp[j] = 0.0;
+                }
+                tr = sqrt(residual_col_norm2(A, m, j, B, X)) / bn[j];
                 if (tr <= ko->tol) { conv[j] = 1; act[j] = 0; }
                 else {
                     /* recurrence drifted: restart column j from its iterate */
@@ -1499,6 +1539,11 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
             }
             rz[j] = rzn[j];
         }
+        /* merged: the pending x += alpha p_old, before p changes */
+        if (ko->merged) {
+            apply_pending_x(n, m, NULL, xp, p, X);
+            for (j = 0; j < m; j++) xp[j] = 0.0;
+        }
 #pragma omp parallel for private(j) schedule(static)
         for (i = 0; i < n; i++)
             for (j = 0; j < m; j++)
@@ -1509,7 +1554,7 @@ static int pcg(const ohier *h, const kopt *ko, const smopt *so, int m,
     }
     for (j = 0; j < m; j++) if (!conv[j] && rc == ORC_OK) rc = ORC_NOT_CONVERGED;
     free(r); free(z); free(p); free(q); free(bn); free(rz); free(rzn); free(zq);
-    free(pq); free(rr); free(alpha); free(beta); free(act); free(rst);
+    free(pq); free(rr); free(alpha); free(beta); free(act); free(rst); free(xp); free(one);
     return rc;
 }
 
@@ -1789,12 +1834,12 @@ static int mgsolve(const ohier *h, const kopt *ko, const smopt *so, int m,
  */
 int orc_solve(const ohier *h, int method, int smoother, double omega, int degree,
               double lo_frac, double hi_frac, int gs_block, int flexible, int precond,
-              int max_iters, double tol, int x0_given, int m, const double *B,
+              int merged, int max_iters, double tol, int x0_given, int m, const double *B,
               double *X, int *iters, double *relres, double *true_relres, int *conv,
               int *restarts)
 {
     vws w;
-    kopt ko = {method, flexible, max_iters, tol, x0_given, precond};
+    kopt ko = {method, flexible, max_iters, tol, x0_given, precond, merged};
     smopt so = {smoother, omega, degree, lo_frac, hi_frac, gs_block};
     int rc, j, n = h->A[0].nr;
     size_t q, nm = (size_t)n * m;

@@ -23,7 +23,7 @@ int orc_vcycle(const ohier *h, int smoother, double omega, int degree, double lo
                double hi_frac, int gs_block, int m, const double *b, double *x);
 int orc_solve(const ohier *h, int method, int smoother, double omega, int degree,
               double lo_frac, double hi_frac, int gs_block, int flexible, int precond,
-              int max_iters, double tol, int x0_given, int m, const double *B, double *X,
+              int merged, int max_iters, double tol, int x0_given, int m, const double *B, double *X,
               int *iters, double *relres, double *true_relres, int *conv, int *restarts);
 void orc_spmm(int n, int ncols, const int *rp, const int *ci, const double *v, int m,
               const double *X, double *Y);
@@ -113,17 +113,21 @@ static void exercise(int N, double jump, int agg_levels, int num_paths)
         CHECK(orc_vcycle(h, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, m, B, X) == 0);
     for (method = 0; method < 3; method++)
         for (smoother = 0; smoother < 3; smoother++) {
-            rc = orc_solve(h, method, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, 0, 1, 200, 1e-8, 0,
+            rc = orc_solve(h, method, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, 0, 1, 0, 200, 1e-8, 0,
+                           m, B, X, it, rr, tr, cv, rs);
+            CHECK(rc == 0);
+            /* merged CG form */
+            rc = orc_solve(h, method, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, 0, 1, 1, 200, 1e-8, 0,
                            m, B, X, it, rr, tr, cv, rs);
             CHECK(rc == 0);
             /* given initial guess, iteration cap, no preconditioner */
             for (j = 0; j < n * m; j++) X[j] = urand(&seed);
-            rc = orc_solve(h, method, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, 1, method != 2, 1,
-                           1e-14, 1, m, B, X, it, rr, tr, cv, rs);
+            rc = orc_solve(h, method, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, 1, method != 2,
+                           method == 0, 1, 1e-14, 1, m, B, X, it, rr, tr, cv, rs);
             CHECK(rc == 1);
         }
     B[5] = NAN;
-    CHECK(orc_solve(h, 0, 0, 2.0 / 3.0, 2, 0.3, 1.1, 8, 0, 1, 10, 1e-8, 0, m, B, X, it, rr, tr,
+    CHECK(orc_solve(h, 0, 0, 2.0 / 3.0, 2, 0.3, 1.1, 8, 0, 1, 0, 10, 1e-8, 0, m, B, X, it, rr, tr,
                     cv, rs) == -1);
     orc_hier_free(h);
     free(B); free(X); free(Y); free(k); free(rp); free(ci); free(v);
