@@ -65,13 +65,17 @@ def presmooth_bytes(n, nnz, m, vb=8, ib=4, bb=8, xb=8, jacobi=False):
             + (n * m * xb if jacobi else 0))
 
 
-def pcg_iteration_bytes(S, m, chebyshev, mixed, flexible, idx16=None):
+def pcg_iteration_bytes(S, m, chebyshev, mixed, flexible, idx16=None, merged=1):
     """Algorithmic bytes of one PCG iteration: every array each kernel of
     the iteration reads or writes, counted once per kernel.  The V-cycle is
     Jacobi or Chebyshev-2 V(1,1) (FP32 vectors and values when mixed; its
-    level-0 input r and output z are FP64), then the Krylov SpMM q = A p
-    with its dot, x += a p and r -= a q with (r, r), and p = z + b p.
-    idx16[l] = fraction of 16-bit column indices of (A_l, P_l, R_l)."""
+    level-0 input r and output z are FP64), then the Krylov passes of the
+    CG form: merged = 0: q = A p with its dot, x += a p and r -= a q with
+    (r, r), p = z + b p; 1: q = A p, r -= a q, then x += a p_old with
+    p = z + b p in one pass; 2: q = A (z + b p) writing the new p and
+    updating x in the SpMM, then r -= a q.  Mixed: r -= a q also writes the
+    FP32 copy of r.  idx16[l] = fraction of 16-bit column indices of
+    (A_l, P_l, R_l)."""
     n, nnzA, nnzP, L = S.sizes, S.nnzA, S.nnzP, S.nlev
     vb = 4 if mixed else 8
     tot = 0.0
@@ -102,8 +106,18 @@ def pcg_iteration_bytes(S, m, chebyshev, mixed, flexible, idx16=None):
         if l == 0:
             tot += n[0] * m * 8 * (1 if flexible else 0) + (0 if not chebyshev else n[0] * m * 8)
     V0 = n[0] * m * 8
-    tot += nnzA[0] * 12 + 4 * (n[0] + 1) + 2 * V0  # q = A p (FP64)
-    tot += 6 * V0 + 3 * V0                         # x, r update; p update
+    A0 = nnzA[0] * 12 + 4 * (n[0] + 1)
+    r32 = n[0] * m * 4 if mixed else 0
+    if merged == 2:
+        tot += A0 + 6 * V0                         # gather z, p; write p', q; x read, write
+        tot += 3 * V0 + r32                        # r update
+    elif merged == 1:
+        tot += A0 + 2 * V0                         # q = A p
+        tot += 3 * V0 + r32                        # r update
+        tot += 5 * V0                              # x += a p_old, p = z + b p
+    else:
+        tot += A0 + 2 * V0                         # q = A p
+        tot += 6 * V0 + r32 + 3 * V0               # x, r update; p update
     return tot
 
 
@@ -334,7 +348,7 @@ def main():
                 xamg.lib().xamg_index16_fraction(S._h, l, fr)
                 idx16.append(tuple(fr))
         ib = pcg_iteration_bytes(S, m, smo == xamg.CHEBYSHEV, mixed,
-                                 flexible=mixed, idx16=idx16)
+                                 flexible=mixed, idx16=idx16, merged=S.options.merged)
         it = int(iters0.max())
         gbs_it = ib * it / (ms_step * 1e-3) / 1e9
         iteration = {"bytes": ib, "iters": it, "ms_per_iteration": ms_step / it,
@@ -376,6 +390,29 @@ def main():
         log(f"[bench] {other}: {msm / m:.3f} ms/RHS, iters {int(itm.max())}, "
             f"rel diff {dx:.2e}")
         Sm.close()
+        # the CG forms (standard, x's update in the p pass, p pass in the
+        # SpMM) on the launch shapes tuned for this solve: bitwise the same
+        # iterates, different passes over the vectors
+        if opts["method"] == xamg.CG and wl == "poisson128":
+            forms = {}
+            mp = 1 << (m - 1).bit_length()
+            tun = S.tuning(mp)
+            for f in (0, 1, 2):
+                Sf = xamg.Solver(Hh, stream=stream.cuda_stream, **dict(opts, merged=f))
+                Sf.set_tuning(mp, tun)
+                Xf = torch.zeros_like(Bd)
+                Sf.solve(Bd, Xf, tol=1e-8)
+                msf, itf, trf, rcf = timed_solves(Sf, Bd, Xf, args.steps, 1e-8, stream, torch)
+                forms[f"merged{f}"] = {
+                    "ms_per_rhs": msf / m, "iters": int(itf.max()),
+                    "bitwise_equal_to_default": bool(torch.equal(Xf, Xd)),
+                    "bytes_per_iteration": pcg_iteration_bytes(
+                        Sf, m, smo == xamg.CHEBYSHEV, mixed, flexible=mixed, merged=f)}
+                log(f"[bench] CG form merged={f}: {msf / m:.4f} ms/RHS, iters {int(itf.max())}, "
+                    f"{forms[f'merged{f}']['bytes_per_iteration'] / 1e9:.2f} GB/iteration, "
+                    f"bitwise equal {forms[f'merged{f}']['bitwise_equal_to_default']}")
+                Sf.close()
+            extras["cg_forms"] = forms
         # multigrid as the solver (no Krylov acceleration), same smoother
         if wl == "poisson128":
             Sg = xamg.Solver(Hh, stream=stream.cuda_stream, **dict(opts, method=xamg.MG))
@@ -404,7 +441,8 @@ def main():
                    "host_setup_s": round(t_agg, 1)}
             if opts["method"] == xamg.CG and opts["smoother"] in (xamg.JACOBI, xamg.CHEBYSHEV):
                 agg["bytes_per_iteration"] = pcg_iteration_bytes(
-                    Sa, m, opts["smoother"] == xamg.CHEBYSHEV, mixed, flexible=mixed)
+                    Sa, m, opts["smoother"] == xamg.CHEBYSHEV, mixed, flexible=mixed,
+                    merged=Sa.options.merged)
             extras["aggressive"] = agg
             log(f"[bench] aggressive level 0: levels {Ha.sizes()}, C_A "
                 f"{agg['operator_complexity']:.3f}, C_G {agg['grid_complexity']:.3f}, "

@@ -122,6 +122,19 @@ typedef struct {
                               method; 0: no preconditioner (M = I; Table 1 lists the
                               Krylov solvers apart from their preconditioners).
                               MG requires 1. */
+    int32_t merged;        /* CG in a merged form (Section 2.1: merged formulations
+                              regroup the vector updates so that fewer passes read
+                              and write the vectors); the recurrences, and so the
+                              iterates, are those of the standard form.  0: standard
+                              (q = A p; x += alpha p, r -= alpha q; z = M r;
+                              p = z + beta p); 1: x's update of an iteration is
+                              applied in the next iteration's p = z + beta p pass,
+                              which reads the old p anyway (one vector read less
+                              per iteration); 2: that pass rides in the SpMM as
+                              well -- q = A (z + beta p), with the new p written to
+                              a second buffer (one pass less per iteration, one
+                              more n x m FP64 block of work memory).  Default 1;
+                              BiCGStab and MG ignore it. */
     void *stream;          /* hipStream_t for all work; NULL = the null stream */
 } xamg_options_t;
 

@@ -44,10 +44,12 @@ struct FinInit {   // tot: (b,b)[M], (r,r)[M]
             st->failed[j] = 0;
             st->nrst[j] = 0;
             st->alpha[j] = st->beta[j] = 0.0;
+            st->xpend[j] = 0.0;
             st->omega[j] = 1.0;
             st->rz[j] = 1.0;
         }
         if (j == 0) {
+            st->ppar = 0;
             st->tol = tol;
             st->max_iters = max_iters;
             int bad = 0;
@@ -61,6 +63,8 @@ struct FinInit {   // tot: (b,b)[M], (r,r)[M]
 struct FinAlpha {   // tot: (p, q)[M]
     ColState* st;
     int M;
+    int merged = 0;   // merged CG form: alpha also becomes the pending x update;
+                      // form 2 swaps the p buffers its SpMM just used
     __device__ void operator()(const double* tot) const
     {
         const int j = threadIdx.x;
@@ -76,7 +80,9 @@ struct FinAlpha {   // tot: (p, q)[M]
                 }
             }
             st->alpha[j] = a;
+            if (merged) st->xpend[j] = a;
         }
+        if (merged == 2 && j == 0) st->ppar ^= 1;
         recount_active(st, M);
     }
 };
@@ -491,17 +497,42 @@ int pcg_flex(const Handle& h)
     return h.opt.precision == XAMG_MIXED ? 1 : h.opt.flexible;
 }
 
-// z = M^-1 r (dots (r, z) [, (z, q)]), beta, p = z + beta p
+// z = M^-1 r (dots (r, z) [, (z, q)]), beta, p = z + beta p (merged form
+// 1: with x += xpend p before p changes; form 2: in the SpMM that follows)
 template <int M>
-void pcg_precondition(Handle& h)
+void pcg_precondition(Handle& h, double* X)
 {
     constexpr int CPT = cpt_for<double, M>();
     const int flex = pcg_flex<M>(h);
     const int nd = flex ? 2 : 1;
     const int nb = apply_prec<M>(h, h.w.r, h.w.z, nd, h.w.q, h.w.r32);
     launch_fin(h, nb, nd * M, FinBeta{h.st, M, flex});
+    if (h.opt.merged == 2) return;
+    if (h.opt.merged == 1) {
+        OpUpdPX<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.p, X, h.w.z};
+        launch_rows<M, CPT>(h, up, h.lev[0].n, h.nb_cap);
+        return;
+    }
     OpUpdP<M, CPT> up{nullptr, nullptr, Idx32{nullptr}, h.st, h.w.p, h.w.z};
     launch_rows<M, CPT>(h, up, h.lev[0].n, h.nb_cap);
+}
+
+template <int M>
+__global__ void clear_xpend_kernel(ColState* st)
+{
+    if (int(threadIdx.x) < M) st->xpend[threadIdx.x] = 0.0;
+}
+
+// merged CG: apply the pending x += xpend p and clear xpend (before a true
+// residual is formed from x)
+template <int M>
+void pcg_flush(Handle& h, double* X)
+{
+    constexpr int CPT = cpt_for<double, M>();
+    if (h.opt.merged == 0) return;
+    OpFlushX<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, h.st, X, h.w.p, h.w.p2};
+    launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
+    hipLaunchKernelGGL(clear_xpend_kernel<M>, dim3(1), dim3(64), 0, h.stream, h.st);
 }
 
 // r32 = float(r), where a pass other than OpUpdXR has rewritten r
@@ -555,19 +586,31 @@ void pcg_iteration(Handle& h, double* X)
     const DCsr& A = h.lev[0].A64;
     const double* av = static_cast<const double*>(A.v);
     ColState* st = h.st;
-    pcg_precondition<M>(h);
+    const int merged = h.opt.merged;
+    pcg_precondition<M>(h, X);
     {
         h.timer_begin(XAMG_TIMER_KRYLOV_SPMM);
-        const int nb = launch_op<M, double, double>(
-            h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
-                return OpAx<M, decltype(cpt)::value, double, double, decltype(ix), 1>{
-                    A.rp, av, ix, h.w.p, h.w.q, &st->nactive};
-            });
+        int nb;
+        if (merged == 2) {
+            nb = launch_op<M, double, double>(
+                h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
+                    return OpAxPX<M, decltype(cpt)::value, decltype(ix)>{
+                        A.rp, av, ix, st, h.w.p, h.w.p2, h.w.z, h.w.q, X};
+                });
+        } else {
+            nb = launch_op<M, double, double>(
+                h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
+                    return OpAx<M, decltype(cpt)::value, double, double, decltype(ix), 1>{
+                        A.rp, av, ix, h.w.p, h.w.q, &st->nactive};
+                });
+        }
         h.timer_end(XAMG_TIMER_KRYLOV_SPMM);
-        launch_fin(h, nb, M, FinAlpha{st, M});
+        launch_fin(h, nb, M, FinAlpha{st, M, merged});
     }
     {
-        OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st, X, h.w.r, h.w.p, h.w.q, h.w.r32};
+        // merged: r only (x's update waits in xpend; p is not read)
+        OpUpdXR<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, st,      merged ? nullptr : X,
+                           h.w.r,   h.w.p,   h.w.q,          h.w.r32};
         const int nb = launch_rows<M, CPT>(h, op, n, h.nb_cap);
         launch_fin(h, nb, M, FinRR{st, M});
     }
@@ -582,10 +625,10 @@ void pcg_iteration(Handle& h, double* X)
 template <int M>
 void pcg_true_enqueue(Handle& h, const double* B, double* X, int allow_restart)
 {
-    constexpr int CPT = cpt_for<double, M>();
     const int n = h.lev[0].n;
     const DCsr& A = h.lev[0].A64;
     const double* av = static_cast<const double*>(A.v);
+    pcg_flush<M>(h, X);
     const int nb = launch_op<M, double, double>(
         h, A, A.template split_of<M>(), n, h.nb_cap, [&](auto cpt, auto ix) {
             return OpResid<M, decltype(cpt)::value, double, double, double, decltype(ix), 2>{

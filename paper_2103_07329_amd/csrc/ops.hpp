@@ -39,6 +39,7 @@ struct ColState {
     double bn2[32];       // ||b_j||^2
     double rz[32];        // CG: (r, z); BiCGStab: rho
     double alpha[32], beta[32], omega[32];
+    double xpend[32];     // merged CG: alpha of the x += alpha p not yet applied
     double rr[32];        // ||r_j||^2 (recurrence)
     double relres[32];
     double true_relres[32];
@@ -55,6 +56,7 @@ struct ColState {
     int failed[32];       // stopped by a persistent breakdown
     int nrst[32];         // restarts so far (true-residual and breakdown)
     int max_iters;        // per-column iteration cap
+    int ppar;             // merged CG form 2: the current p is in the second buffer
 };
 
 // ------------------------------------------------------------------------
@@ -514,7 +516,8 @@ struct OpChebPost2 {
 // ------------------------------------------------------------------------
 // Krylov vector updates (no matrix)
 // ------------------------------------------------------------------------
-// CG: x += alpha p, r -= alpha q on active columns; dot (r, r)
+// CG: x += alpha p, r -= alpha q on active columns; dot (r, r).  x null
+// (merged form): r only, x's update is applied later (OpUpdPX, OpAxPX)
 template <int M, int CPT>
 struct OpUpdXR {
     using AT = double;
@@ -534,19 +537,21 @@ struct OpUpdXR {
                                         double (&d)[ND][CPT]) const
     {
         const size_t o = size_t(i) * M + j0;
-        auto xi = load_pack<double, CPT>(x + o);
         auto ri = load_pack<double, CPT>(r + o);
-        const auto pi = load_pack<double, CPT>(p + o);
         const auto qi = load_pack<double, CPT>(q + o);
+        if (x) {
+            auto xi = load_pack<double, CPT>(x + o);
+            const auto pi = load_pack<double, CPT>(p + o);
+#pragma unroll
+            for (int t = 0; t < CPT; ++t)
+                if (ac_[t]) xi.v[t] = fma(al_[t], pi.v[t], xi.v[t]);
+            store_pack<double, CPT>(x + o, xi);
+        }
 #pragma unroll
         for (int t = 0; t < CPT; ++t) {
-            if (ac_[t]) {
-                xi.v[t] += al_[t] * pi.v[t];
-                ri.v[t] -= al_[t] * qi.v[t];
-            }
+            if (ac_[t]) ri.v[t] -= al_[t] * qi.v[t];
             d[0][t] += ri.v[t] * ri.v[t];
         }
-        store_pack<double, CPT>(x + o, xi);
         store_pack<double, CPT>(r + o, ri);
         if (r32) {
             Pack<float, CPT> rf;
@@ -592,7 +597,7 @@ struct OpUpdP {
         const auto zi = load_pack<double, CPT>(z + o);
 #pragma unroll
         for (int t = 0; t < CPT; ++t)
-            if (ac_[t]) pi.v[t] = pz_[t] ? zi.v[t] : zi.v[t] + be_[t] * pi.v[t];
+            if (ac_[t]) pi.v[t] = pz_[t] ? zi.v[t] : fma(be_[t], pi.v[t], zi.v[t]);
         store_pack<double, CPT>(p + o, pi);
     }
     static constexpr bool kBegin = true;
@@ -606,6 +611,164 @@ struct OpUpdP {
             pz_[t] = st->pz[j0 + t];
             be_[t] = st->beta[j0 + t];
         }
+    }
+};
+
+// Merged CG (Section 2.1's merged formulations: vector updates regrouped
+// so fewer passes read and write the vectors).  x's update of an iteration
+// is postponed into the pass of the next iteration that reads the old p
+// anyway; its alpha waits in ColState::xpend (FinAlpha stores it, OpFlushX
+// applies what is left before a true residual).  The pass always runs, also
+// with no active column, so xpend is applied exactly once; x only changes
+// where xpend != 0 (p of an inactive column need not be finite).
+//
+// the per-column coefficients both merged passes load once per thread
+template <int CPT>
+struct MergedCoef {
+    double be[CPT] = {}, xp[CPT] = {};
+    int ac[CPT] = {}, pz[CPT] = {};
+    __device__ __forceinline__ void load(const ColState* st, int j0)
+    {
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            ac[t] = st->active[j0 + t];
+            pz[t] = st->pz[j0 + t];
+            be[t] = st->beta[j0 + t];
+            xp[t] = st->xpend[j0 + t];
+        }
+    }
+    // the new p of one row (as OpUpdP forms it)
+    __device__ __forceinline__ Pack<double, CPT> pnew(const Pack<double, CPT>& z,
+                                                      const Pack<double, CPT>& p) const
+    {
+        Pack<double, CPT> o;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+            o.v[t] = ac[t] ? (pz[t] ? z.v[t] : fma(be[t], p.v[t], z.v[t])) : p.v[t];
+        return o;
+    }
+    __device__ __forceinline__ void addx(double* x, const Pack<double, CPT>& p) const
+    {
+        auto xi = load_pack<double, CPT>(x);
+#pragma unroll
+        for (int t = 0; t < CPT; ++t)
+            if (xp[t] != 0.0) xi.v[t] = fma(xp[t], p.v[t], xi.v[t]);
+        store_pack<double, CPT>(x, xi);
+    }
+};
+
+// merged CG, standalone pass: x += xpend p, then p = z + beta p
+template <int M, int CPT>
+struct OpUpdPX {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = 0;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const ColState* st;
+    double *p, *x;
+    const double* z;
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        const auto pi = load_pack<double, CPT>(p + o);
+        const auto zi = load_pack<double, CPT>(z + o);
+        cf_.addx(x + o, pi);
+        store_pack<double, CPT>(p + o, cf_.pnew(zi, pi));
+    }
+    static constexpr bool kBegin = true;
+    MergedCoef<CPT> cf_;
+    __device__ __forceinline__ void begin(int j0) { cf_.load(st, j0); }
+};
+
+// merged CG, in the SpMM: q = A pn with pn = z + beta p formed where A
+// gathers it (from z and the old p), pn written to the other p buffer
+// (other rows still gather the old one; ColState::ppar says which buffer
+// holds the current p and FinAlpha flips it, so a captured graph of any
+// number of iterations stays valid), x += xpend p_old; dot (pn, q)
+template <int M, int CPT, class IdxT>
+struct OpAxPX {
+    using AT = double;
+    static constexpr bool kMatrix = true;
+    static constexpr int kDots = 1;
+    const int* rp;
+    const double* val;
+    IdxT idx;
+    const ColState* st;
+    double *pa, *pb;   // the two p buffers
+    const double* z;
+    double *q, *x;
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int c, int j0) const
+    {
+        const size_t o = size_t(c) * M + j0;
+        return cf_.pnew(load_pack<double, CPT>(z + o), load_pack<double, CPT>(pin_ + o));
+    }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
+                                        double (&d)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        const auto pi = load_pack<double, CPT>(pin_ + o);
+        const auto pn = cf_.pnew(load_pack<double, CPT>(z + o), pi);
+        cf_.addx(x + o, pi);
+        store_pack<double, CPT>(pout_ + o, pn);
+        Pack<double, CPT> qo;
+#pragma unroll
+        for (int t = 0; t < CPT; ++t) {
+            qo.v[t] = acc[t];
+            d[0][t] += pn.v[t] * qo.v[t];
+        }
+        store_pack<double, CPT>(q + o, qo);
+    }
+    static constexpr bool kBegin = true;
+    MergedCoef<CPT> cf_;
+    const double* pin_ = nullptr;
+    double* pout_ = nullptr;
+    __device__ __forceinline__ void begin(int j0)
+    {
+        cf_.load(st, j0);
+        const bool second = st->ppar != 0;
+        pin_ = second ? pb : pa;
+        pout_ = second ? pa : pb;
+    }
+    int rowlen = 0;
+};
+
+// merged CG: the update still pending, x += xpend p (all columns; p from
+// the buffer ColState::ppar names, pb null when there is one buffer)
+template <int M, int CPT>
+struct OpFlushX {
+    using AT = double;
+    static constexpr bool kMatrix = false;
+    static constexpr int kDots = 0;
+    const int* rp = nullptr;
+    const double* val = nullptr;
+    Idx32 idx{nullptr};
+    const ColState* st;
+    double* x;
+    const double *pa, *pb;
+    __device__ __forceinline__ bool active_any() const { return true; }
+    __device__ __forceinline__ Pack<AT, CPT> fetch(int, int) const { return Pack<AT, CPT>{}; }
+    template <int ND>
+    __device__ __forceinline__ void out(int i, int j0, const AT (&)[CPT],
+                                        double (&)[ND][CPT]) const
+    {
+        const size_t o = size_t(i) * M + j0;
+        cf_.addx(x + o, load_pack<double, CPT>(p_ + o));
+    }
+    static constexpr bool kBegin = true;
+    MergedCoef<CPT> cf_;
+    const double* p_ = nullptr;
+    __device__ __forceinline__ void begin(int j0)
+    {
+        cf_.load(st, j0);
+        p_ = (pb && st->ppar) ? pb : pa;
     }
 };
 

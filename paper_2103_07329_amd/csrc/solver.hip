@@ -254,6 +254,9 @@ static void layout_work(const Handle& h, int mc, bool bicg, bool pad, Work& w, G
     w.p = static_cast<double*>(get(n0 * sizeof(double)));
     w.q = static_cast<double*>(get(n0 * sizeof(double)));
     w.t = static_cast<double*>(get(n0 * sizeof(double)));
+    w.p2 = nullptr;
+    if (h.opt.method == XAMG_CG && h.opt.merged == 2)
+        w.p2 = static_cast<double*>(get(n0 * sizeof(double)));
     w.r32 = w.p32 = w.s32 = nullptr;
     w.rh = w.v = w.s = w.ph = w.sh = nullptr;
     w.bpad = w.xpad = nullptr;
@@ -285,8 +288,8 @@ void ensure_work(Handle& h, int mp, bool bicg)
     for (auto& W : h.w.lev) {
         h.release(W.B); h.release(W.X); h.release(W.X2); h.release(W.R); h.release(W.T);
     }
-    for (double* p : {h.w.r, h.w.z, h.w.p, h.w.q, h.w.t, h.w.rh, h.w.v, h.w.s, h.w.ph, h.w.sh,
-                      h.w.xpad, h.w.bpad})
+    for (double* p : {h.w.r, h.w.z, h.w.p, h.w.p2, h.w.q, h.w.t, h.w.rh, h.w.v, h.w.s, h.w.ph,
+                      h.w.sh, h.w.xpad, h.w.bpad})
         h.release(p);
     h.release(h.w.r32);
     h.release(h.w.p32);
@@ -445,6 +448,7 @@ void xamg_default_options(xamg_options_t* o)
     o->check_every = 0;
     o->gs_block = 8;
     o->precond = 1;
+    o->merged = 1;
     o->stream = nullptr;
 }
 
@@ -492,6 +496,7 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     if (o.precond != 0 && o.precond != 1) return xamg::fail(XAMG_EINVAL, "precond must be 0 or 1");
     if (o.precond == 0 && o.method == XAMG_MG)
         return xamg::fail(XAMG_EINVAL, "multigrid as the solver needs the V-cycle");
+    if (o.merged < 0 || o.merged > 2) return xamg::fail(XAMG_EINVAL, "merged must be 0, 1 or 2");
     if (H->nlevels < 1 || H->nlevels > XAMG_MAX_LEVELS || !H->A)
         return xamg::fail(XAMG_EINVAL, "nlevels");
     if (H->nlevels > 1 && (!H->P || !H->R)) return xamg::fail(XAMG_EINVAL, "P/R missing");

@@ -91,6 +91,7 @@ struct Work {
     int mcap = 0;
     std::vector<LevelWork> lev;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
+    double* p2 = nullptr;   // merged CG form 2: the second p buffer (ColState::ppar)
     double *rh = nullptr, *v = nullptr, *s = nullptr, *ph = nullptr, *sh = nullptr;
     double *bpad = nullptr, *xpad = nullptr;
     // FP32 copies of the finest-level inputs of a mixed V-cycle (Jacobi or

@@ -58,7 +58,7 @@ class OptionsT(ctypes.Structure):
                 ("max_iters", ctypes.c_int32), ("x0_mode", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("gs_block", ctypes.c_int32), ("precond", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("merged", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class StatsT(ctypes.Structure):

@@ -49,9 +49,18 @@ def test_pcg_iteration_bytes_two_levels_by_hand():
     cheb = ((MA + V0 + d + V0) + (MA + V0 + V0 + V0) + (MR + V0 + V1) + (MP + V1 + 2 * V0)
             + (MA + V0 + V0 + d + V0) + (MA + V0 + V0 + d + V0) + V0)      # + (b, z) dot
     coarse = n1 * n1 * 8 + 2 * V1
-    krylov = (a0 * 12 + 4 * (n0 + 1) + 2 * V0) + 9 * V0
+    # Krylov passes of the default CG form (merged = 1): q = A p; r -= a q
+    # (r, q read, r written); x += a p_old with p = z + b p (p, z, x read;
+    # p, x written)
+    krylov = (a0 * 12 + 4 * (n0 + 1) + 2 * V0) + 3 * V0 + 5 * V0
     got = bench.pcg_iteration_bytes(S, m, chebyshev=True, mixed=False, flexible=False)
     assert got == pytest.approx(cheb + coarse + krylov)
+    # standard form: x and r together (6 vectors), then p (3)
+    got = bench.pcg_iteration_bytes(S, m, chebyshev=True, mixed=False, flexible=False, merged=0)
+    assert got == pytest.approx(cheb + coarse + (a0 * 12 + 4 * (n0 + 1) + 2 * V0) + 9 * V0)
+    # p pass inside the SpMM: z, p gathered, p', q written, x read and written
+    got = bench.pcg_iteration_bytes(S, m, chebyshev=True, mixed=False, flexible=False, merged=2)
+    assert got == pytest.approx(cheb + coarse + (a0 * 12 + 4 * (n0 + 1) + 6 * V0) + 3 * V0)
     jac = ((MA + V0 + d + 2 * V0) + (MR + V0 + V1) + (MP + V1 + 2 * V0)
            + (MA + V0 + V0 + d + V0))
     got = bench.pcg_iteration_bytes(S, m, chebyshev=False, mixed=False, flexible=False)
