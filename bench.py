@@ -200,6 +200,9 @@ def main():
     ap.add_argument("--ws-pairs", type=int, default=2048,
                     help="warmstart: (B, X) training pairs generated by the FP64 solver")
     ap.add_argument("--ws-epochs", type=int, default=20)
+    ap.add_argument("--ws-objective", choices=["residual", "solution"], default="residual",
+                    help="warmstart: train on ||b - A f(b)||^2/||b||^2 (the quantity the "
+                         "fallback judges) or on ||f(b) - x||^2/||x||^2")
     ap.add_argument("--ws-weights", default=None,
                     help="warmstart: load trained weights (.npy) instead of training")
     ap.add_argument("--ws-save", default=None,
@@ -562,9 +565,10 @@ def bench_warmstart(args, torch, inputs, xamg):
         nval = args.ws_pairs // 8
         t0 = time.time()
         hist = W.train(net, xs, ts, perm[nval:], perm[:nval], torch, epochs=args.ws_epochs,
-                       batch=8, lr=1e-3, seed=5)
+                       batch=8, lr=1e-3, seed=5, objective=args.ws_objective, solver=S0)
         t_train = time.time() - t0
-        train_info = {"pairs": args.ws_pairs, "train": int(args.ws_pairs - nval),
+        train_info = {"objective": args.ws_objective,
+                      "pairs": args.ws_pairs, "train": int(args.ws_pairs - nval),
                       "validation": int(nval), "epochs": len(hist), "batch": 8, "lr": 1e-3,
                       "pair_solve_iters": float(it.mean()), "pairs_s": round(t_pairs, 1),
                       "train_s": round(t_train, 1), "final_train_loss": hist[-1][1],
@@ -686,6 +690,7 @@ def bench_warmstart(args, torch, inputs, xamg):
                        "max_rel_diff_vs_zero_guess_solution": diff},
         "raw_guess": {"median_rel_error": float(np.median(raw_err)),
                       "median_initial_relres": float(np.median(raw_res)),
+                      "max_initial_relres": float(raw_res.max()),
                       "iters_without_fallback": st_raw["iters"].tolist()},
         "training": train_info,
         "roofline": roofline,

@@ -370,6 +370,17 @@ int xamg_cnn_set_weights(xamg_cnn_t *h, const float *w_host);
 int xamg_cnn_pass(xamg_cnn_t *h, const float *x, const float *t, int32_t S, float *y_out,
                   double *loss);
 
+/* As xamg_cnn_pass with targets, but with the residual loss: the network's
+ * output judged as a solver's initial guess, L = (1/S) sum_s ||x_s - A
+ * f(x_s)||^2 / ||x_s||^2 with A the finest-level operator of `solver`
+ * (same grid, n = N^3; symmetric, as CG's operator is: the gradient
+ * dL/dy = -2 A (x - A y) / (||x||^2 S) uses A for A^T).  This is the
+ * quantity xamg_warmstart's fallback judges; no solved targets are needed.
+ * r = x - A y is formed with FP64 products and stored FP32.  EINVAL for a
+ * null argument or a solver of another size. */
+int xamg_cnn_pass_residual(xamg_cnn_t *h, xamg_handle_t *solver, const float *x, int32_t S,
+                           double *loss);
+
 /* Weight gradients of the last pass (host, XAMG_CNN_PARAMS floats). */
 int xamg_cnn_get_grads(xamg_cnn_t *h, float *g_host);
 

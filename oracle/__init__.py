@@ -425,6 +425,40 @@ def cnn_loss_and_grads(N, Ws, xs, ts, quantize=False):
     return loss, grads
 
 
+def cnn_residual_loss_and_grads(N, Ws, xs, A, quantize=False):
+    """Residual loss of the network as a solver's initial guess: the mean
+    over samples of ||x - A f(x)||^2 / ||x||^2 (x a normalised right-hand
+    side, A = (rp, ci, v) the operator on the N^3 grid), and its gradient
+    with respect to each layer's weights.  dL/dy = -2 A^T (x - A y) /
+    (||x||^2 S), then backpropagation as in cnn_loss_and_grads."""
+    import scipy.sparse as sp
+    rp, ci, v = _csr(*A)
+    n = N ** 3
+    At = sp.csr_matrix((v, ci, rp), shape=(n, n)).T.tocsr()   # A^T, a library transpose
+    q = bf16 if quantize else (lambda a: np.asarray(a, np.float64))
+    grads = [np.zeros_like(np.asarray(W, np.float64)) for W in Ws]
+    loss = 0.0
+    S = len(xs)
+    for x in xs:
+        b = np.asarray(x, np.float64).reshape(-1)
+        a0 = q(b.reshape(n, 1))
+        a1, a2, a3, y = cnn_forward(N, Ws, x, quantize)
+        y = y.reshape(-1)
+        r = b - spmm(rp, ci, v, y[:, None])[:, 0]
+        bb = float(b @ b)
+        loss += float(r @ r) / bb / S
+        g = (-2.0 / (bb * S) * spmm(At.indptr, At.indices, At.data, r[:, None])[:, 0]).reshape(-1, 1)
+        acts = [a0, a1, a2, a3]
+        for l in (3, 2, 1, 0):
+            grads[l] += conv3d_wgrad(N, g, acts[l], Ws[l].shape[1], Ws[l].shape[0])
+            if l > 0:
+                d = conv3d_dgrad(N, q(Ws[l]), g)
+                g = d * (acts[l] > 0)
+                if quantize:
+                    g = q(g)
+    return loss, grads
+
+
 def adam_step(w, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam update (Kingma and Ba, ICLR 2015, Algorithm 1) in float64:
     moments m, v updated in place, bias-corrected with step count t >= 1,

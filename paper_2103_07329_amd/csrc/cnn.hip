@@ -396,6 +396,58 @@ __global__ void loss_grad(const float* __restrict__ y, const float* __restrict__
         dy[r] = s * (y[r] - t[r]);
 }
 
+// Residual loss (the guess judged as a solver's initial guess): r = x - A y
+// with A's CSR rows (FP64 products and sums, r kept FP32), and per block
+// the partial sums of r^2 and x^2, in the loss_parts layout.
+__global__ __launch_bounds__(256) void res_parts(const float* __restrict__ x,
+                                                const float* __restrict__ y,
+                                                const int* __restrict__ rp,
+                                                const int* __restrict__ ci,
+                                                const double* __restrict__ av, long n,
+                                                float* __restrict__ r, double* __restrict__ part)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += long(gridDim.x) * blockDim.x) {
+        double ax = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) ax += av[k] * double(y[ci[k]]);
+        const double e = double(x[i]) - ax;
+        r[i] = float(e);
+        a += e * e;
+        b += double(x[i]) * double(x[i]);
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (threadIdx.x < h) {
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+            s2[threadIdx.x] += s2[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s1[0];
+        part[2 * blockIdx.x + 1] = s2[0];
+    }
+}
+
+// dL/dy = -(2 / (||x||^2 S)) A^T r, with A^T = A (the symmetric operator of
+// CG); sc[1] = 2 / (||x||^2 S) from loss_finish
+__global__ void res_grad(const float* __restrict__ r, const int* __restrict__ rp,
+                         const int* __restrict__ ci, const double* __restrict__ av, long n,
+                         const double* __restrict__ sc, float* __restrict__ dy)
+{
+    const double s = sc[1];
+    for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += long(gridDim.x) * blockDim.x) {
+        double ar = 0.0;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) ar += av[k] * double(r[ci[k]]);
+        dy[i] = float(-s * ar);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // weights: Adam on FP32 masters, then BF16 copies in each kernel's layout
 // ---------------------------------------------------------------------------
@@ -554,6 +606,7 @@ struct Net : xamg_cnn {
     uint16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
     uint16_t *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
     float *y = nullptr, *dy = nullptr, *wpart = nullptr;
+    float* rres = nullptr;   // residual of the residual loss
     double *lpart = nullptr, *lacc = nullptr, *scales = nullptr, *sums = nullptr;
     double* cpart = nullptr;   // col_sq partials
     int64_t adam_t = 0;
@@ -713,6 +766,7 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
         net->g3 = net->alloc<uint16_t>(n * kC);
         net->y = net->alloc<float>(n);
         net->dy = net->alloc<float>(n);
+        net->rres = net->alloc<float>(n);
         net->wpart = net->alloc<float>(size_t(kWgBlocks) * kParams2);
         net->lpart = net->alloc<double>(2 * 1024);
         net->lacc = net->alloc<double>(2);
@@ -804,6 +858,53 @@ int xamg_cnn_pass(xamg_cnn_t* h, const float* x, const float* t, int32_t S, floa
             *loss = l[0];
         }
         net->chk(hipGetLastError(), "cnn pass");
+        if (net->ev_used) {
+            net->chk(hipStreamSynchronize(net->stream), "sync");
+            net->tcollect();
+        }
+    } catch (const xamg::DevFail& f) {
+        return f.code;
+    }
+    return XAMG_OK;
+}
+
+// Forward and backward with the residual loss over S samples: the operator
+// is level 0 of a solver handle on the same grid (FP64 CSR).
+int xamg_cnn_pass_residual(xamg_cnn_t* h, xamg_handle_t* solver, const float* x, int32_t S,
+                           double* loss)
+{
+    using namespace xamg::cnn;
+    xamg::clear_error();
+    Net* net = static_cast<Net*>(h);
+    if (!net || !solver || !x || S < 1) return xamg::fail(XAMG_EINVAL, "bad arguments");
+    const xamg::Handle* sh = static_cast<const xamg::Handle*>(solver);
+    if (sh->lev[0].n != net->n) return xamg::fail(XAMG_EINVAL, "solver size differs from the network grid");
+    try {
+        const long n = net->n;
+        const xamg::DCsr& A = sh->lev[0].A64;
+        const double* av = static_cast<const double*>(A.v);
+        net->chk(hipMemsetAsync(net->g, 0, kParams * sizeof(float), net->stream), "grad zero");
+        net->chk(hipMemsetAsync(net->lacc, 0, 2 * sizeof(double), net->stream), "loss zero");
+        for (int s = 0; s < S; ++s) {
+            const float* xs = x + size_t(s) * n;
+            hipLaunchKernelGGL(f32_to_bf16, dim3(1024), dim3(256), 0, net->stream, xs, n, net->a0);
+            net->forward();
+            hipLaunchKernelGGL(res_parts, dim3(1024), dim3(256), 0, net->stream, xs, net->y, A.rp,
+                               A.ci, av, n, net->rres, net->lpart);
+            hipLaunchKernelGGL(loss_finish, dim3(1), dim3(64), 0, net->stream, net->lpart, 1024, S,
+                               net->lacc);
+            hipLaunchKernelGGL(res_grad, dim3(1024), dim3(256), 0, net->stream, net->rres, A.rp, A.ci,
+                               av, n, net->lacc, net->dy);
+            net->backward();
+        }
+        if (loss) {
+            double l[2];
+            net->chk(hipMemcpyAsync(l, net->lacc, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                    net->stream), "loss copy");
+            net->chk(hipStreamSynchronize(net->stream), "sync");
+            *loss = l[0];
+        }
+        net->chk(hipGetLastError(), "cnn residual pass");
         if (net->ev_used) {
             net->chk(hipStreamSynchronize(net->stream), "sync");
             net->tcollect();

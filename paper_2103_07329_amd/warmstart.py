@@ -13,7 +13,9 @@ Recipe (extension of the method, not in the paper):
   * samples: Gaussian-source right-hand sides (``inputs.gaussian_params``),
     solved to relative residual 1e-8; a pair is (b / s, x / s) with
     s = ||b|| / sqrt(n), in FP32;
-  * loss: mean over the mini-batch of ||f(b/s) - x/s||^2 / ||x/s||^2;
+  * loss ("solution"): mean over the mini-batch of ||f(b/s) - x/s||^2 /
+    ||x/s||^2; or ("residual") the quantity the zero-guess fallback judges,
+    ||b/s - A f(b/s)||^2 / ||b/s||^2, which needs no solved targets;
   * Adam, lr 1e-3, betas (0.9, 0.999), eps 1e-8, FP32 master weights;
   * He-normal initial weights (std sqrt(2 / fan_in); the output layer
     sqrt(1 / fan_in)), fixed seed;
@@ -71,28 +73,37 @@ def make_pairs(solver, N, count, seed, torch, chunk=32, tol=1e-8):
 
 
 def train(net, xs, ts, train_idx, val_idx, torch, epochs=20, batch=8, lr=1e-3, seed=5,
-          max_seconds=None):
+          max_seconds=None, objective="solution", solver=None):
     """Mini-batch Adam over ``train_idx``; validation loss after each epoch.
-    Returns the history [(epoch, train_loss, val_loss, seconds)]."""
+    objective "residual" trains on ||x - A f(x)||^2 / ||x||^2 with A the
+    finest operator of ``solver`` (``ts`` unused).  Returns the history
+    [(epoch, train_loss, val_loss, seconds)]."""
     rng = np.random.default_rng(seed)
     hist = []
     t0 = time.time()
     vi = torch.as_tensor(val_idx, device="cuda")
+    if objective == "residual":
+        def step(idx):
+            return net.residual_loss_and_grads(xs.index_select(0, idx).contiguous(), solver)
+    elif objective == "solution":
+        def step(idx):
+            return net.loss_and_grads(xs.index_select(0, idx).contiguous(),
+                                      ts.index_select(0, idx).contiguous())
+    else:
+        raise ValueError(objective)
     for ep in range(1, epochs + 1):
         order = rng.permutation(train_idx)
         tot, nb = 0.0, 0
         for k in range(0, len(order) - batch + 1, batch):
             idx = torch.as_tensor(order[k:k + batch], device="cuda")
-            loss = net.loss_and_grads(xs.index_select(0, idx).contiguous(),
-                                      ts.index_select(0, idx).contiguous())
+            loss = step(idx)
             net.adam(lr)
             tot += loss
             nb += 1
         vl = 0.0
         for k in range(0, len(val_idx), 32):
             sl = vi[k:k + 32]
-            vl += net.loss_and_grads(xs.index_select(0, sl).contiguous(),
-                                     ts.index_select(0, sl).contiguous()) * len(sl)
+            vl += step(sl) * len(sl)
         vl /= len(val_idx)
         el = time.time() - t0
         hist.append((ep, tot / max(nb, 1), vl, el))

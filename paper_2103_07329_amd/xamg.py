@@ -77,7 +77,7 @@ EXPORTS = [
     "xamg_autotune", "xamg_tuning", "xamg_set_tuning", "xamg_timer_enable", "xamg_timer_read", "xamg_destroy",
     "xamg_strerror", "xamg_last_error",
     "xamg_cnn_create", "xamg_cnn_get_weights", "xamg_cnn_set_weights", "xamg_cnn_pass",
-    "xamg_cnn_get_grads", "xamg_cnn_adam", "xamg_cnn_layer", "xamg_warmstart",
+    "xamg_cnn_pass_residual", "xamg_cnn_get_grads", "xamg_cnn_adam", "xamg_cnn_layer", "xamg_warmstart",
     "xamg_cnn_timer_enable", "xamg_cnn_timer_read", "xamg_cnn_destroy",
 ]
 
@@ -130,6 +130,7 @@ def lib():
         L.xamg_cnn_get_weights.argtypes = [vp, f32p]
         L.xamg_cnn_set_weights.argtypes = [vp, f32p]
         L.xamg_cnn_pass.argtypes = [vp, vp, vp, i32, vp, ctypes.POINTER(dbl)]
+        L.xamg_cnn_pass_residual.argtypes = [vp, vp, vp, i32, ctypes.POINTER(dbl)]
         L.xamg_cnn_get_grads.argtypes = [vp, f32p]
         L.xamg_cnn_adam.argtypes = [vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float]
@@ -523,6 +524,16 @@ class Cnn:
         loss = ctypes.c_double()
         _check(lib().xamg_cnn_pass(self._h, _ptr(x, "float32"), _ptr(t, "float32"), S, None,
                                    ctypes.byref(loss)), "xamg_cnn_pass")
+        return loss.value
+
+    def residual_loss_and_grads(self, x, solver):
+        """One forward + backward over the samples with the residual loss
+        ||x - A f(x)||^2 / ||x||^2 (A = the solver's finest operator);
+        returns the loss (see xamg_cnn_pass_residual)."""
+        S = x.shape[0]
+        loss = ctypes.c_double()
+        _check(lib().xamg_cnn_pass_residual(self._h, solver._h, _ptr(x, "float32"), S,
+                                            ctypes.byref(loss)), "xamg_cnn_pass_residual")
         return loss.value
 
     def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

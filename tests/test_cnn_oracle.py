@@ -1,8 +1,12 @@
 """Pins of the oracle's warm-start CNN (forward, input and weight gradients,
-loss gradient, BF16 rounding) against facts independent of its code:
+loss gradients, BF16 rounding) against facts independent of its code:
 scipy's n-D correlation, an impulse response written out by coordinates,
 adjointness, linearity in the weights, positive homogeneity, central finite
-differences and torch's own float32 -> bfloat16 conversion."""
+differences and torch's own float32 -> bfloat16 conversion.  The residual
+loss (the network's guess judged as a solver's initial guess) is pinned by
+central differences on a nonsymmetric operator (a transposed operand would
+fail it), by its reduction to the solution loss with target x when A = I,
+and by its value 1 for the zero network."""
 import numpy as np
 import pytest
 import torch
@@ -218,3 +222,63 @@ def test_adam_constant_gradient_limit():
     for t in range(1, 51):
         w = oracle.adam_step(w, g, m, v, t, lr=0.01)
     assert np.allclose(w, -50 * 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-10)
+
+
+def _nonsym_csr(n, seed):
+    """Nonsymmetric diagonally dominant sparse matrix (CSR arrays)."""
+    rng = np.random.default_rng(seed)
+    A = np.diag(4.0 + rng.uniform(0.0, 1.0, n))
+    for i in range(n - 1):
+        A[i, i + 1] = -1.0 + 0.6 * rng.uniform(-1.0, 1.0)
+        A[i + 1, i] = -1.0 - 0.6 * rng.uniform(-1.0, 1.0)
+    for i in range(n - 5):
+        A[i, i + 5] = 0.5 * rng.uniform(-1.0, 1.0)
+    rows, cols = np.nonzero(A)
+    rp = np.searchsorted(rows, np.arange(n + 1)).astype(np.int32)
+    return rp, cols.astype(np.int32), A[rows, cols]
+
+
+def test_residual_loss_gradient_central_differences():
+    N = 4
+    rng = np.random.default_rng(9)
+    Ws = _rand_weights(rng, 2.0)
+    A = _nonsym_csr(N ** 3, 10)
+    xs = [rng.standard_normal(N ** 3) for _ in range(2)]
+    loss, grads = oracle.cnn_residual_loss_and_grads(N, Ws, xs, A)
+    h = 1e-6
+    for l in range(4):
+        flat = Ws[l].reshape(-1)
+        for k in rng.choice(flat.size, 6, replace=False):
+            Wp = [W.copy() for W in Ws]
+            Wm = [W.copy() for W in Ws]
+            Wp[l].reshape(-1)[k] += h
+            Wm[l].reshape(-1)[k] -= h
+            lp, _ = oracle.cnn_residual_loss_and_grads(N, Wp, xs, A)
+            lm, _ = oracle.cnn_residual_loss_and_grads(N, Wm, xs, A)
+            fd = (lp - lm) / (2 * h)
+            an = grads[l].reshape(-1)[k]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (l, k, fd, an)
+
+
+def test_residual_loss_with_identity_is_solution_loss():
+    # A = I: ||x - f(x)||^2 / ||x||^2 is the solution loss with target t = x
+    N = 5
+    n = N ** 3
+    rng = np.random.default_rng(12)
+    Ws = _rand_weights(rng, 2.0)
+    I = (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.ones(n))
+    xs = [rng.standard_normal(n) for _ in range(3)]
+    lr, gr = oracle.cnn_residual_loss_and_grads(N, Ws, xs, I)
+    ls, gs = oracle.cnn_loss_and_grads(N, Ws, xs, xs)
+    assert lr == pytest.approx(ls, rel=1e-13)
+    for a, b in zip(gr, gs):
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * np.abs(b).max())
+
+
+def test_residual_loss_of_zero_network_is_one():
+    N = 4
+    rng = np.random.default_rng(13)
+    Ws = [np.zeros((co, ci, 27)) for ci, co in oracle.CNN_LAYERS]
+    xs = [rng.standard_normal(N ** 3) for _ in range(2)]
+    loss, _ = oracle.cnn_residual_loss_and_grads(N, Ws, xs, _nonsym_csr(N ** 3, 14))
+    assert loss == pytest.approx(1.0, abs=1e-15)

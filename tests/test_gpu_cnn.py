@@ -194,6 +194,39 @@ def test_full_pass_loss_and_gradients(torch, xm):
     net.close()
 
 
+def test_residual_pass_loss_and_gradients(torch, xm):
+    """The residual loss ||x - A f(x)||^2 / ||x||^2 with A the solver's
+    finest operator (7-point Poisson, stored padded to 7 entries a row)
+    against the oracle's BF16-rounded network."""
+    N, S = 16, 2
+    n = N ** 3
+    _say(f"[cnn residual pass] N={N} S={S}")
+    Ws = _weights(300)
+    net = xm.Cnn(N, xm.join_weights(Ws))
+    prob = inputs.poisson7(N)
+    solver = xm.Solver(xm.HostHierarchy(*prob.csr()))
+    rng = np.random.default_rng(43)
+    xs = [rng.standard_normal(n).astype(np.float32) for _ in range(S)]
+    loss_o, grads_o = oracle.cnn_residual_loss_and_grads(N, [oracle.bf16(W) for W in Ws], xs,
+                                                         prob.csr(), quantize=True)
+    loss_d = net.residual_loss_and_grads(_f32_dev(torch, np.stack(xs)), solver)
+    grads_d = xm.split_weights(net.grads().astype(np.float64))
+    _say(f"  loss dev {loss_d:.8f} oracle {loss_o:.8f}")
+    assert abs(loss_d - loss_o) <= 1e-5 * loss_o
+    for l in range(4):
+        rel = np.linalg.norm(grads_d[l] - grads_o[l]) / np.linalg.norm(grads_o[l])
+        _say(f"  layer {l + 1} gradient rel err {rel:.3e}")
+        assert rel <= 2e-3
+    with pytest.raises(xm.XamgError):   # operator of another grid size
+        other = xm.Solver(xm.HostHierarchy(*inputs.poisson7(8).csr()))
+        try:
+            net.residual_loss_and_grads(_f32_dev(torch, np.stack(xs)), other)
+        finally:
+            other.close()
+    solver.close()
+    net.close()
+
+
 def test_adam_matches_oracle(torch, xm):
     # gradient buffer from one weight-gradient call (matches the oracle to
     # FP32 accumulation), then two Adam steps on it

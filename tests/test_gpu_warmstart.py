@@ -1,15 +1,24 @@
 """What the trained warm-start network gains over the zero guess (3D Poisson
 32^3, Gaussian-source right-hand sides), trained on the device by the
-library's own kernels on pairs from its own FP64 solver.
+library's own kernels.
 
-Checked: training lowers the validation loss; on fresh right-hand sides the
-raw network guess is closer to the solution than X0 = 0 (the quantity it is
-trained on); the warm-started solve (with the per-column zero-guess
-fallback) converges to the same solution as the zero-guess solve and never
-takes more iterations than it.  The iteration counts and the initial
-residuals are printed: the guess is rough at the grid scale, so its residual
-||b - A x0|| is usually not below ||b|| and the fallback takes the column
-back to X0 = 0.
+Two training objectives:
+
+* the solution loss ||f(b) - x||^2 / ||x||^2 on pairs from the library's
+  FP64 solver.  Training lowers it and the raw guess is closer to x than
+  X0 = 0 (checked), but its residual ||b - A x0|| is not below ||b|| on most
+  columns: the guess is rough at the grid scale, so the fallback sends those
+  columns back to X0 = 0 and the solve gains nothing there;
+* the residual loss ||b - A f(b)||^2 / ||b||^2, the quantity the fallback
+  judges.  Every column keeps the network's guess (checked), the
+  warm-started solve converges to the zero-guess solution and never needs
+  more iterations than the zero guess (checked per column; with guesses
+  kept, this bound is no longer met trivially).
+
+The guess cannot cut the iteration count much: a 9^3 receptive field
+cannot carry the 1/r far field of a charged source, so the initial residual
+stays a sizeable fraction of ||b||, while one AMG-PCG iteration already
+reduces the residual about tenfold.
 """
 import sys
 
@@ -26,54 +35,97 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def test_trained_warmstart_gain():
+@pytest.fixture(scope="module")
+def setup():
     import torch
     from paper_2103_07329_amd import warmstart as W
     from paper_2103_07329_amd import xamg
     N, count, m, tol = 32, 256, 16, 1e-8
-    _say(f"[warmstart gain] N={N} pairs={count} m={m}")
+    _say(f"[warmstart] N={N} pairs={count} m={m}")
     prob = inputs.poisson7(N)
     Hh = xamg.HostHierarchy(*prob.csr())
     S0 = xamg.Solver(Hh, smoother=xamg.CHEBYSHEV)
     S1 = xamg.Solver(Hh, smoother=xamg.CHEBYSHEV, x0_mode=xamg.X0_GIVEN)
     xs, ts, it = W.make_pairs(S0, N, count, 1005, torch)
-    net = xamg.Cnn(N, W.he_init(7))
     perm = np.random.default_rng(5).permutation(count)
     val, tr = perm[:32], perm[32:]
-    vi = torch.as_tensor(val, device="cuda")
-    loss0 = net.loss_and_grads(xs.index_select(0, vi).contiguous(),
-                               ts.index_select(0, vi).contiguous())
-    hist = W.train(net, xs, ts, tr, val, torch, epochs=6, batch=8)
-    _say(f"  validation loss {loss0:.4f} -> {hist[-1][2]:.4f}")
-    assert hist[-1][2] < 0.5 * loss0
-
     B = inputs.gaussian_rhs_torch(N, inputs.gaussian_params(N, m, 1006), list(range(m)), torch,
                                   "cuda")
     Xref = torch.zeros_like(B)
     rc, st0 = S0.solve(B, Xref, tol)
     assert rc == xamg.OK
-    X0raw = torch.zeros_like(B)
-    net.warmstart(B, X0raw, None)
-    err = (torch.linalg.vector_norm(Xref - X0raw, dim=0)
-           / torch.linalg.vector_norm(Xref, dim=0)).cpu().numpy()
-    R = torch.empty_like(B)
-    S0.spmm(xamg.OP_A, 0, X0raw, R)
-    res = (torch.linalg.vector_norm(B - R, dim=0) / torch.linalg.vector_norm(B, dim=0)).cpu().numpy()
-    _say(f"  raw guess rel error: median {np.median(err):.3f}, max {err.max():.3f}")
-    _say(f"  raw guess initial rel residual: median {np.median(res):.3f}")
-    assert np.all(err < 1.0) and np.median(err) < 0.6
+    yield dict(torch=torch, W=W, xamg=xamg, N=N, m=m, tol=tol, S0=S0, S1=S1, xs=xs, ts=ts,
+               val=val, tr=tr, B=B, Xref=Xref, st0=st0)
+    S0.close()
+    S1.close()
 
-    X0 = torch.zeros_like(B)
-    fb = net.warmstart(B, X0, S1)
-    assert np.array_equal(fb, (~(res < 1.0)).astype(np.int32))
+
+def _initial_relres(c, X0):
+    torch, xamg = c["torch"], c["xamg"]
+    R = torch.empty_like(c["B"])
+    c["S0"].spmm(xamg.OP_A, 0, X0, R)
+    return (torch.linalg.vector_norm(c["B"] - R, dim=0)
+            / torch.linalg.vector_norm(c["B"], dim=0)).cpu().numpy()
+
+
+def _warm_solve(c, net):
+    torch = c["torch"]
+    X0 = torch.zeros_like(c["B"])
+    fb = net.warmstart(c["B"], X0, c["S1"])
     X = X0.clone()
-    rc, st1 = S1.solve(B, X, tol)
-    assert rc == xamg.OK
-    _say(f"  iterations zero guess {st0['iters'].tolist()}")
-    _say(f"  iterations warm start {st1['iters'].tolist()} (fallbacks {int(fb.sum())}/{m})")
-    assert np.all(st1["true_relres"] <= tol)
-    assert np.all(st1["iters"] <= st0["iters"])
-    d = (torch.linalg.vector_norm(X - Xref, dim=0) / torch.linalg.vector_norm(Xref, dim=0)).max()
+    rc, st1 = c["S1"].solve(c["B"], X, c["tol"])
+    assert rc == c["xamg"].OK
+    assert np.all(st1["true_relres"] <= c["tol"])
+    d = (torch.linalg.vector_norm(X - c["Xref"], dim=0)
+         / torch.linalg.vector_norm(c["Xref"], dim=0)).max()
     assert d.item() <= 1e-6
-    for o in (S0, S1, net):
-        o.close()
+    _say(f"  iterations zero guess {c['st0']['iters'].tolist()}")
+    _say(f"  iterations warm start {st1['iters'].tolist()} (fallbacks {int(fb.sum())}/{c['m']})")
+    return fb, st1
+
+
+def test_solution_loss_guess_mostly_falls_back(setup):
+    c = setup
+    torch, W, xamg = c["torch"], c["W"], c["xamg"]
+    net = xamg.Cnn(c["N"], W.he_init(7))
+    vi = torch.as_tensor(c["val"], device="cuda")
+    loss0 = net.loss_and_grads(c["xs"].index_select(0, vi).contiguous(),
+                               c["ts"].index_select(0, vi).contiguous())
+    hist = W.train(net, c["xs"], c["ts"], c["tr"], c["val"], torch, epochs=6, batch=8)
+    _say(f"  solution loss: validation {loss0:.4f} -> {hist[-1][2]:.4f}")
+    assert hist[-1][2] < 0.5 * loss0
+    X0raw = torch.zeros_like(c["B"])
+    net.warmstart(c["B"], X0raw, None)
+    err = (torch.linalg.vector_norm(c["Xref"] - X0raw, dim=0)
+           / torch.linalg.vector_norm(c["Xref"], dim=0)).cpu().numpy()
+    res = _initial_relres(c, X0raw)
+    _say(f"  raw guess rel error: median {np.median(err):.3f}, max {err.max():.3f}; "
+         f"initial rel residual: median {np.median(res):.3f}")
+    assert np.all(err < 1.0) and np.median(err) < 0.6
+    fb, st1 = _warm_solve(c, net)
+    # the fallback is exactly the residual rule
+    assert np.array_equal(fb, (~(res < 1.0)).astype(np.int32))
+    # a fallen-back column repeats the zero-guess solve exactly
+    for j in np.nonzero(fb)[0]:
+        assert st1["iters"][j] == c["st0"]["iters"][j]
+    net.close()
+
+
+def test_residual_loss_guess_is_kept(setup):
+    c = setup
+    torch, W, xamg = c["torch"], c["W"], c["xamg"]
+    net = xamg.Cnn(c["N"], W.he_init(7))
+    vi = torch.as_tensor(c["val"], device="cuda")
+    loss0 = net.residual_loss_and_grads(c["xs"].index_select(0, vi).contiguous(), c["S0"])
+    hist = W.train(net, c["xs"], None, c["tr"], c["val"], torch, epochs=6, batch=8,
+                   objective="residual", solver=c["S0"])
+    _say(f"  residual loss: validation {loss0:.4f} -> {hist[-1][2]:.4f}")
+    assert hist[-1][2] < min(1.0, loss0)
+    X0raw = torch.zeros_like(c["B"])
+    net.warmstart(c["B"], X0raw, None)
+    res = _initial_relres(c, X0raw)
+    _say(f"  initial rel residual of the guess: median {np.median(res):.3f}, max {res.max():.3f}")
+    fb, st1 = _warm_solve(c, net)
+    assert fb.sum() == 0                      # every column keeps the guess
+    assert np.all(st1["iters"] <= c["st0"]["iters"])
+    net.close()
