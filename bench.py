@@ -199,6 +199,10 @@ def main():
                              "warmstart"])
     ap.add_argument("--ws-pairs", type=int, default=2048,
                     help="warmstart: (B, X) training pairs generated by the FP64 solver")
+    ap.add_argument("--krylov-split", type=int, default=0,
+                    help="after tuning, force this launch shape on the FP64 A_0 (the Krylov "
+                         "SpMM; on an FP64 handle also the finest residual and post-smoothing "
+                         "passes), e.g. 513 for the banded XCD walk (see xamg_tuning)")
     ap.add_argument("--ws-epochs", type=int, default=20)
     ap.add_argument("--ws-objective", choices=["residual", "solution"], default="residual",
                     help="warmstart: train on ||b - A f(b)||^2/||b||^2 (the quantity the "
@@ -288,9 +292,16 @@ def main():
     for _ in range(args.warmup):
         rc, st = S.solve(Bd, Xd, tol=1e-8)
         assert rc == xamg.OK, rc
+    mp = m if m in (1, 2, 4, 8, 16, 32) else 1 << (m - 1).bit_length()
+    if args.krylov_split:
+        # the tuned shapes, with the FP64 A_0's replaced (for profiling a shape)
+        tun = S.tuning(mp)
+        tun[-1] = (args.krylov_split,)
+        S.set_tuning(mp, tun)
+        S.solve(Bd, Xd, tol=1e-8)
 
     log(f"[bench] launch shapes (A, A pre-smoothing, P, R per level; Krylov A_0): "
-        f"{S.tuning(m if m in (1, 2, 4, 8, 16, 32) else 1 << (m - 1).bit_length())}")
+        f"{S.tuning(mp)}")
     # timed region: K complete solves, with the library's event timer on the
     # fine-level pre-smoothing pass (kernel A) -- then on the Krylov SpMM
     # (kernel B) in an identical second pass
@@ -522,6 +533,9 @@ def main():
             "operator_complexity": round(sum(nnzA) / nnzA[0], 3),
             "grid_complexity": round(sum(S.sizes) / S.sizes[0], 3),
             "host_setup_s": round(t_setup, 2),
+            "cg_form": f"merged{S.options.merged}" if opts.get("method", xamg.CG) == xamg.CG
+            else None,
+            "launch_shapes": [list(t) for t in S.tuning(mp)],
         },
         "roofline": roofline,
         "kernels": kernels,
