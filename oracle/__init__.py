@@ -23,7 +23,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EBREAKDOWN = 0, 1, -1, -2, -5
-CG, BICGSTAB, MG = 0, 1, 2
+CG, BICGSTAB, MG, PBICGSTAB = 0, 1, 2, 3
 JACOBI, CHEBYSHEV, GAUSS_SEIDEL = 0, 1, 2
 A_, P_, R_ = 0, 1, 2
 

@@ -1766,6 +1766,230 @@ static int bicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
 }
 
 /*
+ * Pipelined BiCGStab (Cools and Vanroose, Parallel Computing 2017; Section
+ * 2.1 lists it), right-preconditioned: the BiCGStab above on K = A M,
+ * rewritten so that neither product with K in an iteration waits for a dot
+ * product.  With s = K p, z = K s, v = K z, w = K r, t = K w, q = r - alpha s
+ * (BiCGStab's s) and y = K q, every vector follows from a recurrence:
+ *   p = r + beta (p - omega s),  s = w + beta (s - omega z),
+ *   z = t + beta (z - omega v),  q = r - alpha s,  y = w - alpha z,
+ *   [v = K z],  omega = (q, y) / (y, y),
+ *   r' = q - omega y,  w' = y - omega (t - alpha v),  [t' = K w'],
+ *   beta' = (alpha / omega) (rh, r') / (rh, r),
+ *   alpha' = (rh, r') / ((rh, w') + beta' (rh, s) - beta' omega (rh, z)).
+ * x follows the M-images of the same recurrences (the V-cycle inside each
+ * product with K already yields zh = M z and wh = M w; rt = M r):
+ *   ph = rt + beta (ph - omega sh),  sh = wh + beta (sh - omega zh),
+ *   qh = rt - alpha sh,  x += alpha ph + omega qh,
+ *   rt' = qh - omega (wh - alpha zh).
+ * In exact arithmetic the iterates are those of BiCGStab.  Start, and
+ * restart of a column from its iterate: rh = r, rt = M r, w = A rt,
+ * wh = M w, t = A wh, alpha = (rh, r) / (rh, w), beta = 0.  A column
+ * converges at the half step as in BiCGStab (||q|| <= tol ||b||:
+ * x += alpha ph).  A breakdown (|(rh, r)| or the denominator of alpha
+ * <= 1e-300 ||b||^2, or omega = 0) stops the column with ORC_EBREAKDOWN:
+ * restarting it would take two more products with K for that column alone.
+ */
+static void col_copy(int n, int m, int j, const double *src, double *dst)
+{
+    size_t i;
+    for (i = 0; i < (size_t)n; i++) dst[i * m + j] = src[i * m + j];
+}
+
+typedef struct {
+    double *r, *rh, *rt, *w, *wh, *t, *p, *s, *z, *v, *ph, *sh, *zh, *q, *y, *qh, *ta, *tb;
+} pbvec;
+
+/* (re)start the columns with mask[j]: rh = r, rt = M r, w = A rt, wh = M w,
+ * t = A wh, p = s = z = v = ph = sh = zh = 0, alpha, beta = 0.  The products
+ * run over every column; only the masked ones take the results. */
+static void pb_start_cols(const ohier *h, const kopt *ko, const smopt *so, int m,
+                          const int *mask, pbvec *V, double *bn, double *rho, double *alp,
+                          double *omg, double *beta, int *act, int *rc, vws *w)
+{
+    const ocsr *A = &h->A[0];
+    int n = A->nr, j;
+    double d1, d2, tiny;
+    apply_prec(h, ko, so, m, V->r, V->ta, w);
+    for (j = 0; j < m; j++) if (mask[j]) col_copy(n, m, j, V->ta, V->rt);
+    spmm(A, m, V->rt, V->tb);
+    for (j = 0; j < m; j++) if (mask[j]) col_copy(n, m, j, V->tb, V->w);
+    apply_prec(h, ko, so, m, V->w, V->ta, w);
+    for (j = 0; j < m; j++) if (mask[j]) col_copy(n, m, j, V->ta, V->wh);
+    spmm(A, m, V->wh, V->tb);
+    for (j = 0; j < m; j++) {
+        size_t i, k;
+        if (!mask[j]) continue;
+        col_copy(n, m, j, V->tb, V->t);
+        col_copy(n, m, j, V->r, V->rh);
+        for (i = 0; i < (size_t)n; i++) {
+            k = i * m + j;
+            V->p[k] = V->s[k] = V->z[k] = V->v[k] = V->ph[k] = V->sh[k] = V->zh[k] = 0.0;
+        }
+        d1 = dot_col(n, m, j, V->rh, V->r);
+        d2 = dot_col(n, m, j, V->rh, V->w);
+        tiny = 1e-300 * bn[j] * bn[j];
+        if (fabs(d1) <= tiny || fabs(d2) <= tiny) { act[j] = 0; *rc = ORC_EBREAKDOWN; continue; }
+        rho[j] = d1;
+        alp[j] = d1 / d2;
+        beta[j] = 0.0;
+        omg[j] = 1.0;
+    }
+}
+
+static int pbicgstab(const ohier *h, const kopt *ko, const smopt *so, int m,
+                     const double *B, double *X, int *iters, double *relres,
+                     int *conv, int *restarts, vws *w)
+{
+    const ocsr *A = &h->A[0];
+    int n = A->nr, j, it, rc = ORC_OK, bad = 0;
+    size_t nm = (size_t)n * m, i, k;
+    pbvec V;
+    double **all[] = {&V.r, &V.rh, &V.rt, &V.w, &V.wh, &V.t, &V.p, &V.s, &V.z, &V.v, &V.ph,
+                      &V.sh, &V.zh, &V.q, &V.y, &V.qh, &V.ta, &V.tb};
+    double *bn = (double *)malloc((size_t)m * sizeof(double));
+    double *rho = (double *)malloc((size_t)m * sizeof(double));
+    double *alp = (double *)malloc((size_t)m * sizeof(double));
+    double *omg = (double *)malloc((size_t)m * sizeof(double));
+    double *beta = (double *)malloc((size_t)m * sizeof(double));
+    double *qq = (double *)malloc((size_t)m * sizeof(double));
+    double *qy = (double *)malloc((size_t)m * sizeof(double));
+    double *yy = (double *)malloc((size_t)m * sizeof(double));
+    double *rs = (double *)malloc((size_t)m * sizeof(double));
+    double *rz = (double *)malloc((size_t)m * sizeof(double));
+    double *rr = (double *)malloc((size_t)m * sizeof(double));
+    double *rhr = (double *)malloc((size_t)m * sizeof(double));
+    double *rhw = (double *)malloc((size_t)m * sizeof(double));
+    int *act = (int *)malloc((size_t)m * sizeof(int));
+    int *half = (int *)calloc((size_t)m, sizeof(int));
+    int *full = (int *)calloc((size_t)m, sizeof(int));   /* takes the omega step */
+    int *rst = (int *)calloc((size_t)m, sizeof(int));    /* restart from its iterate */
+    for (j = 0; j < (int)(sizeof(all) / sizeof(all[0])); j++) {
+        *all[j] = (double *)calloc(nm + 1, sizeof(double));
+        bad |= *all[j] == NULL;
+    }
+    if (bad || !bn || !rho || !alp || !omg || !beta || !qq || !qy || !yy || !rs || !rz || !rr ||
+        !rhr || !rhw || !act || !half || !full || !rst)
+        return ORC_ENOMEM;
+
+    if (!ko->x0_given) memset(X, 0, nm * sizeof(double));
+    residual(A, m, B, X, V.r);
+    dots(n, m, B, B, bn);
+    dots(n, m, V.r, V.r, rr);
+    for (j = 0; j < m; j++) {
+        bn[j] = sqrt(bn[j]);
+        iters[j] = 0; conv[j] = 0; act[j] = 1; restarts[j] = 0;
+        if (bn[j] == 0.0) {
+            for (i = 0; i < (size_t)n; i++) X[i * m + j] = 0.0;
+            relres[j] = 0.0; conv[j] = 1; act[j] = 0;
+            continue;
+        }
+        relres[j] = sqrt(rr[j]) / bn[j];
+        if (relres[j] <= ko->tol) { conv[j] = 1; act[j] = 0; }
+    }
+    pb_start_cols(h, ko, so, m, act, &V, bn, rho, alp, omg, beta, act, &rc, w);
+
+    for (it = 1; it <= ko->max_iters; it++) {
+        int any = 0;
+        for (j = 0; j < m; j++) any |= act[j];
+        if (!any) break;
+        if (g_verbose) { fprintf(stderr, "[oracle] pipelined BiCGStab iteration %d\n", it); fflush(stderr); }
+        /* the recurrences of p, s, z (and ph, sh) from their old values; q, y, qh */
+#pragma omp parallel for private(j, k) schedule(static)
+        for (i = 0; i < (size_t)n; i++)
+            for (j = 0; j < m; j++)
+                if (act[j]) {
+                    double po, so_, zo, pho, sho;
+                    k = i * m + j;
+                    po = V.p[k]; so_ = V.s[k]; zo = V.z[k]; pho = V.ph[k]; sho = V.sh[k];
+                    V.p[k] = V.r[k] + beta[j] * (po - omg[j] * so_);
+                    V.s[k] = V.w[k] + beta[j] * (so_ - omg[j] * zo);
+                    V.z[k] = V.t[k] + beta[j] * (zo - omg[j] * V.v[k]);
+                    V.ph[k] = V.rt[k] + beta[j] * (pho - omg[j] * sho);
+                    V.sh[k] = V.wh[k] + beta[j] * (sho - omg[j] * V.zh[k]);
+                    V.q[k] = V.r[k] - alp[j] * V.s[k];
+                    V.y[k] = V.w[k] - alp[j] * V.z[k];
+                    V.qh[k] = V.rt[k] - alp[j] * V.sh[k];
+                }
+        dots(n, m, V.q, V.q, qq);
+        dots(n, m, V.q, V.y, qy);
+        dots(n, m, V.y, V.y, yy);
+        dots(n, m, V.rh, V.s, rs);
+        dots(n, m, V.rh, V.z, rz);
+        for (j = 0; j < m; j++) {
+            half[j] = full[j] = rst[j] = 0;
+            if (!act[j]) continue;
+            iters[j] = it;
+            if (sqrt(qq[j]) / bn[j] <= ko->tol) { half[j] = 1; continue; }
+            omg[j] = yy[j] > 0.0 ? qy[j] / yy[j] : 0.0;
+            if (omg[j] == 0.0) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
+            full[j] = 1;
+        }
+        /* v = K z: zh = M z, v = A zh */
+        apply_prec(h, ko, so, m, V.z, V.zh, w);
+        spmm(A, m, V.zh, V.v);
+#pragma omp parallel for private(j, k) schedule(static)
+        for (i = 0; i < (size_t)n; i++)
+            for (j = 0; j < m; j++) {
+                k = i * m + j;
+                if (half[j]) {
+                    X[k] += alp[j] * V.ph[k];
+                    V.r[k] = V.q[k];
+                } else if (full[j]) {
+                    X[k] += alp[j] * V.ph[k] + omg[j] * V.qh[k];
+                    V.r[k] = V.q[k] - omg[j] * V.y[k];
+                    V.w[k] = V.y[k] - omg[j] * (V.t[k] - alp[j] * V.v[k]);
+                    V.rt[k] = V.qh[k] - omg[j] * (V.wh[k] - alp[j] * V.zh[k]);
+                }
+            }
+        /* t = K w: wh = M w, t = A wh */
+        apply_prec(h, ko, so, m, V.w, V.wh, w);
+        spmm(A, m, V.wh, V.t);
+        dots(n, m, V.r, V.r, rr);
+        dots(n, m, V.rh, V.r, rhr);
+        dots(n, m, V.rh, V.w, rhw);
+        for (j = 0; j < m; j++) {
+            double tiny, del;
+            if (!half[j] && !full[j]) continue;
+            relres[j] = sqrt(rr[j]) / bn[j];
+            if (half[j] || relres[j] <= ko->tol) {
+                double tr = sqrt(residual_col_norm2(A, m, j, B, X)) / bn[j];
+                if (tr <= ko->tol) { conv[j] = 1; act[j] = 0; }
+                else {
+                    /* recurrence drifted: restart column j from its iterate */
+                    for (i = 0; i < (size_t)n; i++) {
+                        double ax = 0.0;
+                        int kk;
+                        for (kk = A->rp[i]; kk < A->rp[i + 1]; kk++)
+                            ax += A->v[kk] * X[(size_t)A->ci[kk] * m + j];
+                        V.r[i * m + j] = B[i * m + j] - ax;
+                    }
+                    relres[j] = tr;
+                    rst[j] = 1;
+                    restarts[j]++;
+                }
+                continue;
+            }
+            tiny = 1e-300 * bn[j] * bn[j];
+            beta[j] = (alp[j] / omg[j]) * (rhr[j] / rho[j]);
+            del = rhw[j] + beta[j] * rs[j] - beta[j] * omg[j] * rz[j];
+            if (fabs(rhr[j]) <= tiny || fabs(del) <= tiny) { act[j] = 0; rc = ORC_EBREAKDOWN; continue; }
+            alp[j] = rhr[j] / del;
+            rho[j] = rhr[j];
+        }
+        any = 0;
+        for (j = 0; j < m; j++) any |= rst[j];
+        if (any) pb_start_cols(h, ko, so, m, rst, &V, bn, rho, alp, omg, beta, act, &rc, w);
+    }
+    for (j = 0; j < m; j++) if (!conv[j] && rc == ORC_OK) rc = ORC_NOT_CONVERGED;
+    for (j = 0; j < (int)(sizeof(all) / sizeof(all[0])); j++) free(*all[j]);
+    free(bn); free(rho); free(alp); free(omg); free(beta); free(qq); free(qy); free(yy);
+    free(rs); free(rz); free(rr); free(rhr); free(rhw); free(act); free(half); free(full);
+    free(rst);
+    return rc;
+}
+
+/*
  * Multigrid as a standalone solver (Section 2.1, Table 1 lists MultiGrid as
  * a solver as well as a preconditioner): the stationary iteration
  *   x <- x + V(b - A x),
@@ -1849,6 +2073,7 @@ int orc_solve(const ohier *h, int method, int smoother, double omega, int degree
     if (vws_alloc(&w, h, m)) { vws_free(&w, h->nlev); return ORC_ENOMEM; }
     if (method == 0) rc = pcg(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
     else if (method == 2) rc = mgsolve(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
+    else if (method == 3) rc = pbicgstab(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
     else rc = bicgstab(h, &ko, &so, m, B, X, iters, relres, conv, restarts, &w);
     vws_free(&w, h->nlev);
     t = (double *)malloc(nm * sizeof(double));

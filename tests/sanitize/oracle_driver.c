@@ -111,7 +111,7 @@ static void exercise(int N, double jump, int agg_levels, int num_paths)
     free(st);
     for (smoother = 0; smoother < 3; smoother++)
         CHECK(orc_vcycle(h, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, m, B, X) == 0);
-    for (method = 0; method < 3; method++)
+    for (method = 0; method < 4; method++)
         for (smoother = 0; smoother < 3; smoother++) {
             rc = orc_solve(h, method, smoother, 2.0 / 3.0, 2, 0.3, 1.1, 8, 0, 1, 0, 200, 1e-8, 0,
                            m, B, X, it, rr, tr, cv, rs);
