@@ -427,6 +427,19 @@ def main():
                     f"bitwise equal {forms[f'merged{f}']['bitwise_equal_to_default']}")
                 Sf.close()
             extras["cg_forms"] = forms
+        # pipelined BiCGStab beside BiCGStab (FP64 cycle only: its recurrences
+        # need a linear preconditioner)
+        if opts["method"] == xamg.BICGSTAB and not mixed:
+            Sp = xamg.Solver(Hh, stream=stream.cuda_stream, **dict(opts, method=xamg.PBICGSTAB))
+            Xp = torch.zeros_like(Bd)
+            Sp.solve(Bd, Xp, tol=1e-8)
+            msp, itp, trp, rcp = timed_solves(Sp, Bd, Xp, args.steps, 1e-8, stream, torch)
+            dxp = (torch.linalg.norm(Xp - Xd, dim=0) / torch.linalg.norm(Xd, dim=0)).max().item()
+            extras["pipelined_bicgstab"] = {"ms_per_rhs": msp / m, "iters": int(itp.max()),
+                                            "max_true_relres": trp, "max_rel_diff": dxp}
+            log(f"[bench] pipelined BiCGStab: {msp / m:.3f} ms/RHS, iters {int(itp.max())}, "
+                f"rel diff {dxp:.2e}")
+            Sp.close()
         # multigrid as the solver (no Krylov acceleration), same smoother
         if wl == "poisson128":
             Sg = xamg.Solver(Hh, stream=stream.cuda_stream, **dict(opts, method=xamg.MG))

@@ -51,7 +51,7 @@ extern "C" {
 #define XAMG_MAX_M 32 /* columns per solve: 1..32 */
 
 /* ---- enums --------------------------------------------------------------- */
-enum { XAMG_CG = 0, XAMG_BICGSTAB = 1, XAMG_MG = 2 };
+enum { XAMG_CG = 0, XAMG_BICGSTAB = 1, XAMG_MG = 2, XAMG_PBICGSTAB = 3 };
 enum { XAMG_JACOBI = 0, XAMG_CHEBYSHEV = 1, XAMG_GAUSS_SEIDEL = 2 };
 enum { XAMG_FP64 = 0, XAMG_MIXED = 1 };
 enum { XAMG_X0_ZERO = 0, XAMG_X0_GIVEN = 1 };
@@ -93,9 +93,18 @@ typedef struct {
 
 /* Solver options. */
 typedef struct {
-    int32_t method;        /* XAMG_CG (default), XAMG_BICGSTAB, or XAMG_MG: multigrid as
+    int32_t method;        /* XAMG_CG (default), XAMG_BICGSTAB, XAMG_MG: multigrid as
                               the solver (Table 1), x <- x + V(b - A x) per column
-                              until the true relative residual is <= tol */
+                              until the true relative residual is <= tol, or
+                              XAMG_PBICGSTAB: pipelined BiCGStab (Section 2.1;
+                              Cools and Vanroose 2017), BiCGStab's iterates with
+                              recurrences in which neither product with A M waits
+                              for a dot product; more work vectors (16 n x m FP64
+                              blocks) and more vector traffic per iteration; a
+                              breakdown stops the column (no restart).  Its
+                              recurrences carry images under the preconditioner,
+                              which must therefore be linear: it needs
+                              precision XAMG_FP64 (EINVAL with XAMG_MIXED) */
     int32_t smoother;      /* XAMG_JACOBI (default), XAMG_CHEBYSHEV or XAMG_GAUSS_SEIDEL:
                               symmetric Gauss-Seidel (Section 2.1, Table 1; the
                               smoother of Section 3.1) in its l1-hybrid form --

@@ -529,7 +529,7 @@ template <int M>
 void pcg_flush(Handle& h, double* X)
 {
     constexpr int CPT = cpt_for<double, M>();
-    if (h.opt.merged == 0) return;
+    if (h.opt.merged == 0 || h.opt.method != XAMG_CG) return;
     OpFlushX<M, CPT> op{nullptr, nullptr, Idx32{nullptr}, h.st, X, h.w.p, h.w.p2};
     launch_rows<M, CPT>(h, op, h.lev[0].n, h.nb_cap);
     hipLaunchKernelGGL(clear_xpend_kernel<M>, dim3(1), dim3(64), 0, h.stream, h.st);

@@ -1,5 +1,6 @@
 // inst_m1.hip -- the solver templates instantiated for M = 1 columns.
 #include "bicgstab.hpp"
+#include "pbicgstab.hpp"
 #include "cycle.hpp"
 
 namespace xamg {
@@ -8,6 +9,7 @@ template int vcycle<1>(Handle&, const double*, double*, int, const double*, cons
 template int pcg<1>(Handle&, const double*, double*, double);
 template int mg_solve<1>(Handle&, const double*, double*, double);
 template int bicgstab<1>(Handle&, const double*, double*, double);
+template int pbicgstab<1>(Handle&, const double*, double*, double);
 template void spmm64<1>(Handle&, const DCsr&, const double*, double*);
 template void autotune<1>(Handle&);
 template void pcg_start<1>(Handle&, const double*, double*, double);

@@ -1,5 +1,6 @@
 // inst_m32.hip -- the solver templates instantiated for M = 32 columns.
 #include "bicgstab.hpp"
+#include "pbicgstab.hpp"
 #include "cycle.hpp"
 
 namespace xamg {
@@ -8,6 +9,7 @@ template int vcycle<32>(Handle&, const double*, double*, int, const double*, con
 template int pcg<32>(Handle&, const double*, double*, double);
 template int mg_solve<32>(Handle&, const double*, double*, double);
 template int bicgstab<32>(Handle&, const double*, double*, double);
+template int pbicgstab<32>(Handle&, const double*, double*, double);
 template void spmm64<32>(Handle&, const DCsr&, const double*, double*);
 template void autotune<32>(Handle&);
 template void pcg_start<32>(Handle&, const double*, double*, double);

@@ -1,5 +1,6 @@
 // inst_m8.hip -- the solver templates instantiated for M = 8 columns.
 #include "bicgstab.hpp"
+#include "pbicgstab.hpp"
 #include "cycle.hpp"
 
 namespace xamg {
@@ -8,6 +9,7 @@ template int vcycle<8>(Handle&, const double*, double*, int, const double*, cons
 template int pcg<8>(Handle&, const double*, double*, double);
 template int mg_solve<8>(Handle&, const double*, double*, double);
 template int bicgstab<8>(Handle&, const double*, double*, double);
+template int pbicgstab<8>(Handle&, const double*, double*, double);
 template void spmm64<8>(Handle&, const DCsr&, const double*, double*);
 template void autotune<8>(Handle&);
 template void pcg_start<8>(Handle&, const double*, double*, double);

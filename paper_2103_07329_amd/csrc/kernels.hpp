@@ -33,7 +33,7 @@ namespace dev {
 
 constexpr int kBlock = 256;      // threads per block of the row kernels (default)
 constexpr int kMaxBlock = 512;   // the larger block a launch may take instead
-constexpr int kMaxDots = 2;      // dots per kernel
+constexpr int kMaxDots = 5;      // dots per kernel
 constexpr int kNumXcd = 8;
 constexpr int kUnroll = 8;      // nonzeros per batch in the row loop
 // ops that need the row's own input may take it from the gathered diagonal
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, do
 // ---------------------------------------------------------------------------
 constexpr int kFinThreads = 1024;
 
-// npair <= 64 partial sums per block; thread t takes pair t % P and slice
+// npair <= kMaxDots * 32 partial sums per block; thread t takes pair t % P and slice
 // t / P (P = npair rounded up to a power of two), sums the blocks of its
 // slice in increasing order (8 loads in flight), then the slices are
 // combined by a fixed tree in LDS.
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double* __r
                                                                int nb, int npair, Fin fin)
 {
     __shared__ double red[kFinThreads];
-    __shared__ double tot[64];
+    __shared__ double tot[kMaxDots * 32];
     int P = 1;
     while (P < npair) P <<= 1;
     const int nsl = kFinThreads / P;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kFinThreads) void finalize_kernel(const double* __r
         if (s < h) red[threadIdx.x] += red[threadIdx.x + h * P];
         __syncthreads();
     }
-    if (threadIdx.x < 64) tot[threadIdx.x] = threadIdx.x < npair ? red[threadIdx.x] : 0.0;
+    if (threadIdx.x < kMaxDots * 32) tot[threadIdx.x] = threadIdx.x < npair ? red[threadIdx.x] : 0.0;
     __syncthreads();
     fin(tot);
 }

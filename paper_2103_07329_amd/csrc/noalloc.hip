@@ -94,7 +94,7 @@ extern "C" int xamg_solve_noalloc(xamg_handle_t* hh, const double* B, double* X,
     if ((reinterpret_cast<uintptr_t>(B) & 15u) || (reinterpret_cast<uintptr_t>(X) & 15u))
         return xamg::fail(XAMG_EINVAL, "B and X must be 16-byte aligned");
     const int mp = xamg::padded_m(m);
-    const bool bicg = h->opt.method == XAMG_BICGSTAB;
+    const bool bicg = xamg::bicg_like(h->opt);
     const bool pad = mp != m;
     const size_t st_bytes = xamg::round256(sizeof(xamg::dev::ColState));
     const size_t part_bytes =

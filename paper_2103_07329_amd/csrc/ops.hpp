@@ -40,6 +40,7 @@ struct ColState {
     double rz[32];        // CG: (r, z); BiCGStab: rho
     double alpha[32], beta[32], omega[32];
     double xpend[32];     // merged CG: alpha of the x += alpha p not yet applied
+    double rhs[32], rhz[32];   // pipelined BiCGStab: (rh, s) and (rh, z) of the iteration
     double rr[32];        // ||r_j||^2 (recurrence)
     double relres[32];
     double true_relres[32];

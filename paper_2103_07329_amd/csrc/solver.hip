@@ -275,6 +275,10 @@ static void layout_work(const Handle& h, int mc, bool bicg, bool pad, Work& w, G
         w.ph = static_cast<double*>(get(n0 * sizeof(double)));
         w.sh = static_cast<double*>(get(n0 * sizeof(double)));
     }
+    w.rt = w.pw = w.wh = w.y = w.zh = w.qh = nullptr;
+    if (bicg && h.opt.method == XAMG_PBICGSTAB)
+        for (double** q : {&w.rt, &w.pw, &w.wh, &w.y, &w.zh, &w.qh})
+            *q = static_cast<double*>(get(n0 * sizeof(double)));
     if (pad) {
         w.bpad = static_cast<double*>(get(n0 * sizeof(double)));
         w.xpad = static_cast<double*>(get(n0 * sizeof(double)));
@@ -283,13 +287,14 @@ static void layout_work(const Handle& h, int mc, bool bicg, bool pad, Work& w, G
 
 void ensure_work(Handle& h, int mp, bool bicg)
 {
-    if (h.w.mcap >= mp && (!bicg || h.w.rh)) return;
+    const bool pipe = h.opt.method == XAMG_PBICGSTAB;
+    if (h.w.mcap >= mp && (!bicg || h.w.rh) && (!pipe || h.w.rt)) return;
     // free old
     for (auto& W : h.w.lev) {
         h.release(W.B); h.release(W.X); h.release(W.X2); h.release(W.R); h.release(W.T);
     }
     for (double* p : {h.w.r, h.w.z, h.w.p, h.w.p2, h.w.q, h.w.t, h.w.rh, h.w.v, h.w.s, h.w.ph,
-                      h.w.sh, h.w.xpad, h.w.bpad})
+                      h.w.sh, h.w.xpad, h.w.bpad, h.w.rt, h.w.pw, h.w.wh, h.w.y, h.w.zh, h.w.qh})
         h.release(p);
     h.release(h.w.r32);
     h.release(h.w.p32);
@@ -383,6 +388,7 @@ int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_sta
     int rc = dispatch_m(mp, [&](auto mc) {
         constexpr int M = decltype(mc)::value;
         if (h.opt.method == XAMG_BICGSTAB) return bicgstab<M>(h, Bs, Xs, tol);
+        if (h.opt.method == XAMG_PBICGSTAB) return pbicgstab<M>(h, Bs, Xs, tol);
         if (h.opt.method == XAMG_MG) return mg_solve<M>(h, Bs, Xs, tol);
         return pcg<M>(h, Bs, Xs, tol);
     });
@@ -400,7 +406,8 @@ int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_sta
         notconv |= !(s.conv[j] && !(s.true_relres[j] > s.tol));
     }
     if (failed) {
-        set_error("Krylov breakdown persisted after restart");
+        set_error("Krylov breakdown: a column stopped (BiCGStab: a breakdown persisted after "
+                  "its restart; pipelined BiCGStab: any breakdown)");
         return XAMG_EBREAKDOWN;
     }
     return notconv ? XAMG_NOT_CONVERGED : XAMG_OK;
@@ -410,7 +417,7 @@ int solve_impl(Handle& h, const double* B, double* X, int m, double tol, xamg_st
 {
     const int mp = padded_m(m);
     const int n = h.lev[0].n;
-    ensure_work(h, mp, h.opt.method == XAMG_BICGSTAB);
+    ensure_work(h, mp, bicg_like(h.opt));
     if (h.autotune)
         dispatch_m(mp, [&](auto mc) {
             autotune<decltype(mc)::value>(h);
@@ -476,7 +483,8 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     *out = nullptr;
     xamg_options_t o;
     if (opt) o = *opt; else xamg_default_options(&o);
-    if (o.method != XAMG_CG && o.method != XAMG_BICGSTAB && o.method != XAMG_MG)
+    if (o.method != XAMG_CG && o.method != XAMG_BICGSTAB && o.method != XAMG_MG &&
+        o.method != XAMG_PBICGSTAB)
         return xamg::fail(XAMG_EINVAL, "method");
     if (o.smoother != XAMG_JACOBI && o.smoother != XAMG_CHEBYSHEV &&
         o.smoother != XAMG_GAUSS_SEIDEL)
@@ -497,6 +505,11 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
     if (o.precond == 0 && o.method == XAMG_MG)
         return xamg::fail(XAMG_EINVAL, "multigrid as the solver needs the V-cycle");
     if (o.merged < 0 || o.merged > 2) return xamg::fail(XAMG_EINVAL, "merged must be 0, 1 or 2");
+    if (o.method == XAMG_PBICGSTAB && o.precision == XAMG_MIXED)
+        return xamg::fail(XAMG_EINVAL,
+                          "pipelined BiCGStab needs the FP64 V-cycle: its recurrences assume a "
+                          "linear preconditioner, and the FP32 cycle is linear only to FP32 "
+                          "accuracy");
     if (H->nlevels < 1 || H->nlevels > XAMG_MAX_LEVELS || !H->A)
         return xamg::fail(XAMG_EINVAL, "nlevels");
     if (H->nlevels > 1 && (!H->P || !H->R)) return xamg::fail(XAMG_EINVAL, "P/R missing");
@@ -768,7 +781,7 @@ int xamg_autotune(xamg_handle_t* hh, int32_t m, int32_t enable)
     h->autotune = enable ? 1 : 0;
     if (!enable) return XAMG_OK;
     try {
-        xamg::ensure_work(*h, m, h->opt.method == XAMG_BICGSTAB);
+        xamg::ensure_work(*h, m, xamg::bicg_like(h->opt));
         int k = 0;
         while ((1 << k) < m) ++k;
         h->tuned_mask &= ~(1u << k);

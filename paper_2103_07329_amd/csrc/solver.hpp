@@ -92,6 +92,9 @@ struct Work {
     std::vector<LevelWork> lev;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *t = nullptr;
     double* p2 = nullptr;   // merged CG form 2: the second p buffer (ColState::ppar)
+    // pipelined BiCGStab: rt = M r, w = K r, wh = M w, y = K q, zh = M z, qh = M q
+    double *rt = nullptr, *pw = nullptr, *wh = nullptr, *y = nullptr, *zh = nullptr,
+           *qh = nullptr;
     double *rh = nullptr, *v = nullptr, *s = nullptr, *ph = nullptr, *sh = nullptr;
     double *bpad = nullptr, *xpad = nullptr;
     // FP32 copies of the finest-level inputs of a mixed V-cycle (Jacobi or
@@ -351,6 +354,8 @@ int pcg(Handle& h, const double* B, double* X, double tol);
 template <int M>
 int bicgstab(Handle& h, const double* B, double* X, double tol);
 template <int M>
+int pbicgstab(Handle& h, const double* B, double* X, double tol);
+template <int M>
 int mg_solve(Handle& h, const double* B, double* X, double tol);
 template <int M>
 void spmm64(Handle& h, const DCsr& d, const double* X, double* Y);
@@ -369,6 +374,11 @@ template <int M>
 void autotune(Handle& h);
 
 void ensure_work(Handle& h, int mp, bool bicg);
+// the BiCGStab work vectors (r-hat, v, s, p-hat, s-hat) are needed
+inline bool bicg_like(const xamg_options_t& o)
+{
+    return o.method == XAMG_BICGSTAB || o.method == XAMG_PBICGSTAB;
+}
 // Lay the work buffers of mp columns (plus the padding copies of B and X
 // when pad) out in the region base[0, cap): fills w (whose lev must hold
 // nlev entries) when the region is large enough; returns the bytes needed.

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxamg.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, ENODEV, EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
-CG, BICGSTAB, MG = 0, 1, 2
+CG, BICGSTAB, MG, PBICGSTAB = 0, 1, 2, 3
 JACOBI, CHEBYSHEV, GAUSS_SEIDEL = 0, 1, 2
 FP64, MIXED = 0, 1
 X0_ZERO, X0_GIVEN = 0, 1
