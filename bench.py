@@ -203,6 +203,8 @@ def main():
                     help="after tuning, force this launch shape on the FP64 A_0 (the Krylov "
                          "SpMM; on an FP64 handle also the finest residual and post-smoothing "
                          "passes), e.g. 513 for the banded XCD walk (see xamg_tuning)")
+    ap.add_argument("--fine-pre-split", type=int, default=0,
+                    help="after tuning, force this launch shape on the finest pre-smoothing pass")
     ap.add_argument("--ws-epochs", type=int, default=20)
     ap.add_argument("--ws-objective", choices=["residual", "solution"], default="residual",
                     help="warmstart: train on ||b - A f(b)||^2/||b||^2 (the quantity the "
@@ -293,10 +295,14 @@ def main():
         rc, st = S.solve(Bd, Xd, tol=1e-8)
         assert rc == xamg.OK, rc
     mp = m if m in (1, 2, 4, 8, 16, 32) else 1 << (m - 1).bit_length()
-    if args.krylov_split:
-        # the tuned shapes, with the FP64 A_0's replaced (for profiling a shape)
+    if args.krylov_split or args.fine_pre_split:
+        # the tuned shapes, with the FP64 A_0's and/or the finest pre-smoothing
+        # pass's replaced (for profiling a shape)
         tun = S.tuning(mp)
-        tun[-1] = (args.krylov_split,)
+        if args.krylov_split:
+            tun[-1] = (args.krylov_split,)
+        if args.fine_pre_split:
+            tun[0] = (tun[0][0], args.fine_pre_split) + tuple(tun[0][2:])
         S.set_tuning(mp, tun)
         S.solve(Bd, Xd, tol=1e-8)
 
