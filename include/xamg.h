@@ -157,6 +157,11 @@ typedef struct {
                             (the recurrence residual passed, the recomputed one
                             did not) plus BiCGStab breakdown restarts */
     int32_t reserved;    /* 0 */
+    double ms;           /* host wall time (ms) of the solve that produced the column,
+                            from its first launch to its final synchronisation (the
+                            same for every column of a call; a batched solve reports
+                            the whole batch); excludes the autotuning and work
+                            allocation of a first call */
 } xamg_stats_t;
 
 typedef struct xamg_host_hierarchy xamg_host_hierarchy_t;

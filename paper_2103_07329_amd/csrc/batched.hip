@@ -11,6 +11,7 @@
 // This extends the paper's multi-RHS solve (many right-hand sides of one
 // matrix, Sections 2.2 and 3.2) to many matrices at once: small systems,
 // whose coarse levels are latency-bound, overlap with the large ones.
+#include <chrono>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -123,7 +124,7 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
         }
     } restore{b, saved, saved_timer};
 
-    // per system: buffers, tuning, padding, start of CG
+    // per system: buffers and tuning, then (timed) padding and the start of CG
     for (int s = 0; s < ns; ++s) {
         Handle& h = *b.hs[s];
         mp[s] = padded(m[s]);
@@ -133,6 +134,10 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
                 autotune<decltype(mc)::value>(h);
                 return 0;
             });
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int s = 0; s < ns; ++s) {
+        Handle& h = *b.hs[s];
         Bs[s] = B[s];
         Xs[s] = X[s];
         const int n = h.lev[0].n;
@@ -265,7 +270,12 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
         if (mp[s] != m[s])
             hipLaunchKernelGGL((dev::copy_cols_kernel<double, double>), dim3(2048), dim3(256), 0,
                                h.stream, h.w.xpad, mp[s], X[s], m[s], n, m[s]);
-        h.check(hipStreamSynchronize(h.stream), "batched sync");
+    }
+    for (int s = 0; s < ns; ++s) b.hs[s]->check(hipStreamSynchronize(b.hs[s]->stream), "batched sync");
+    const double ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (int s = 0; s < ns; ++s) {
+        Handle& h = *b.hs[s];
         const dev::ColState& st = *h.st_host;
         for (int j = 0; j < m[s]; ++j) {
             const bool conv = st.conv[j] && !(st.true_relres[j] > st.tol);
@@ -276,6 +286,7 @@ int solve_batched(Batch& b, const double* const* B, double* const* X, const int3
                 stats[s][j].true_relres = st.true_relres[j];
                 stats[s][j].restarts = st.nrst[j];
                 stats[s][j].reserved = 0;
+                stats[s][j].ms = ms;
             }
             if (st.failed[j]) rc = XAMG_EBREAKDOWN;
             else if (!conv && rc == XAMG_OK) rc = XAMG_NOT_CONVERGED;

@@ -12,6 +12,7 @@
 //               set of scalars per column; every vector operation and dot
 //               is a device kernel, the scalars stay on the device, and the
 //               host only polls the number of still-active columns.
+#include <chrono>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -354,7 +355,7 @@ int padded_m(int m)
     return mp;
 }
 
-static void fill_stats(const Handle& h, int m, xamg_stats_t* stats)
+static void fill_stats(const Handle& h, int m, xamg_stats_t* stats, double ms)
 {
     if (!stats) return;
     const ColState& s = *h.st_host;
@@ -365,6 +366,7 @@ static void fill_stats(const Handle& h, int m, xamg_stats_t* stats)
         stats[j].true_relres = s.true_relres[j];
         stats[j].restarts = s.nrst[j];
         stats[j].reserved = 0;
+        stats[j].ms = ms;
     }
 }
 
@@ -373,6 +375,7 @@ static void fill_stats(const Handle& h, int m, xamg_stats_t* stats)
 // h.st and h.part.  Launches, copies and synchronisations only.
 int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_stats_t* stats)
 {
+    const auto t0 = std::chrono::steady_clock::now();
     const int mp = padded_m(m);
     const int n = h.lev[0].n;
     const double* Bs = B;
@@ -398,7 +401,9 @@ int solve_run(Handle& h, const double* B, double* X, int m, double tol, xamg_sta
     h.check(hipStreamSynchronize(h.stream), "solve sync");
     h.timer_collect();
     if (rc != XAMG_OK) return rc;
-    fill_stats(h, m, stats);
+    fill_stats(h, m, stats,
+               std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                   .count());
     const ColState& s = *h.st_host;
     bool failed = false, notconv = false;
     for (int j = 0; j < m; ++j) {

@@ -64,7 +64,8 @@ class OptionsT(ctypes.Structure):
 class StatsT(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("relres", ctypes.c_double), ("true_relres", ctypes.c_double),
-                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -333,6 +334,7 @@ class Solver:
             "relres": np.array([s.relres for s in st]),
             "true_relres": np.array([s.true_relres for s in st]),
             "restarts": np.array([s.restarts for s in st], np.int32),
+            "ms": float(st[0].ms) if len(st) else 0.0,
         }
         return rc, stats
 
@@ -354,6 +356,7 @@ class Solver:
             "relres": np.array([s.relres for s in st]),
             "true_relres": np.array([s.true_relres for s in st]),
             "restarts": np.array([s.restarts for s in st], np.int32),
+            "ms": float(st[0].ms) if len(st) else 0.0,
         }
 
     def vcycle(self, B, X):
@@ -438,6 +441,7 @@ class Batch:
                 "relres": np.array([s.relres for s in st]),
                 "true_relres": np.array([s.true_relres for s in st]),
                 "restarts": np.array([s.restarts for s in st], np.int32),
+                "ms": float(st[0].ms) if len(st) else 0.0,
             })
         return rc, out
 

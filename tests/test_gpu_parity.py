@@ -123,6 +123,7 @@ def test_pcg_fp64_poisson32(orc, torch, xm, poisson32, smoother, m):
     assert np.all(tr <= 1e-8)
     assert np.allclose(st["true_relres"], tr, rtol=1e-6, atol=1e-14)
     assert st["converged"].all()
+    assert st["ms"] > 0.0          # the solve's wall time
     S.close()
 
 
@@ -471,6 +472,7 @@ def test_batched_equals_individual(orc, torch, xm, precision):
             assert np.array_equal(st["iters"], itr)
             assert np.array_equal(X.cpu().numpy(), Xr)
             assert st["converged"].all()
+            assert st["ms"] == sts[0]["ms"] > 0.0   # the whole batch's wall time
     batch.close()
     for S in solvers:
         S.close()
