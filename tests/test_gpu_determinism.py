@@ -53,6 +53,8 @@ CASES = [
     dict(method=1, smoother=0, precision=1, index_bits=16, m=8),
     dict(method=2, smoother=2, precision=0, m=4),
     dict(method=0, smoother=2, precision=1, m=5),
+    dict(method=3, smoother=1, precision=0, m=16),             # pipelined BiCGStab
+    dict(method=0, smoother=1, precision=0, merged=2, m=8),    # CG, p pass in the SpMM
 ]
 
 
