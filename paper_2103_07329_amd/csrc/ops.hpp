@@ -741,6 +741,24 @@ struct OpAxPX {
     int rowlen = 0;
 };
 
+// The two Krylov SpMM kernels of CG, q = A p with the dot (p, q) and merged
+// form 2's OpAxPX, are launched on one grid size, so their dots add the
+// same per-block partial sums in the same order and the forms' iterates
+// agree bitwise: a sweeping launch of either is capped by the occupancy of
+// both (grid_twin names the other kernel's op).
+template <class Op>
+struct grid_twin {
+    using type = void;
+};
+template <int M, int CPT, class IdxT>
+struct grid_twin<OpAx<M, CPT, double, double, IdxT, 1>> {
+    using type = OpAxPX<M, CPT, IdxT>;
+};
+template <int M, int CPT, class IdxT>
+struct grid_twin<OpAxPX<M, CPT, IdxT>> {
+    using type = OpAx<M, CPT, double, double, IdxT, 1>;
+};
+
 // merged CG: the update still pending, x += xpend p (all columns; p from
 // the buffer ColState::ppar names, pb null when there is one buffer)
 template <int M, int CPT>

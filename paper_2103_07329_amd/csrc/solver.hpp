@@ -224,9 +224,14 @@ int launch_rows_s(Handle& h, const Op& op, int nrows, int cap, bool sweep = fals
     const bool capped = Op::kDots > 0 || sweep;
     // one block per visit (a banded walk pads each segment to whole chunks)
     int nb = seg > 0 ? (ntiles + seg - 1) / seg * seg : ntiles;
-    if (capped)
-        nb = std::min({ntiles, cap, resident_blocks<M, CPT, S, Op>(h, block),
+    if (capped) {
+        int res = resident_blocks<M, CPT, S, Op>(h, block);
+        using Twin = typename dev::grid_twin<Op>::type;
+        if constexpr (!std::is_void_v<Twin>)
+            res = std::min(res, resident_blocks<M, CPT, S, Twin>(h, block));
+        nb = std::min({ntiles, cap, res,
                        Op::kMatrix ? kSweepPerCu * h.num_cu * dev::kBlock / block : ntiles});
+    }
     nb = std::max(1, nb);
     if (capped && nb >= dev::kNumXcd) nb -= nb % dev::kNumXcd;   // even over the 8 XCDs
     if (seg > 0 && nb < dev::kNumXcd) seg = 0;                   // the walk needs every XCD

@@ -103,6 +103,20 @@ def test_merged_forms_match(orc, torch, xm, smoother, m):
     assert err.max() <= 1e-7, err
 
 
+def test_merged_forms_match_occupancy_capped_sweep(torch, xm):
+    # 48^3 rows make 3456 tiles of 32 rows, more than a sweeping launch's
+    # blocks, so the Krylov SpMM grids are capped by the kernels' occupancy;
+    # form 2's SpMM holds more registers than the standard one, and both
+    # must still run on one grid for the dots to agree bit for bit
+    _say("[merged] poisson 48^3 m=16 (sweeps capped by occupancy)")
+    p = inputs.poisson7(48)
+    H = xm.HostHierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 16, 47)
+    out = _forms(torch, xm, H, B, smoother=1)
+    _bitwise(out)
+    assert out[0][2] == xm.OK
+
+
 @pytest.mark.parametrize("smoother", [0, 1])
 def test_merged_mixed_precision(orc, torch, xm, smoother):
     _say(f"[merged] jump 20^3 mixed precision smoother={smoother}")
