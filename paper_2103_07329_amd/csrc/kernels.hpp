@@ -36,10 +36,6 @@ constexpr int kMaxBlock = 512;   // the larger block a launch may take instead
 constexpr int kMaxDots = 5;      // dots per kernel
 constexpr int kNumXcd = 8;
 constexpr int kUnroll = 8;      // nonzeros per batch in the row loop
-// ops that need the row's own input may take it from the gathered diagonal
-// entry instead of loading it again; with 16-byte lanes the extra registers
-// cost more than the load saves (whole-solve timing), so it is off
-constexpr bool kSelfCapture = false;
 
 // ---------------------------------------------------------------------------
 // vector loads/stores of CPT consecutive elements
@@ -148,13 +144,6 @@ __device__ __forceinline__ void grp_share(const V (&own)[PL], V (&out)[U])
         grp_share<G, U, PL, V, u + 1>(own, out);
     }
 }
-
-// ops whose epilogue needs the row's own gathered input (the diagonal
-// entry's value) define out_self(i, j0, acc, have, self, d)
-template <class T, class = void>
-struct op_wants_self : std::false_type {};
-template <class T>
-struct op_wants_self<T, std::void_t<decltype(T::kWantSelf)>> : std::bool_constant<T::kWantSelf> {};
 
 
 // ---------------------------------------------------------------------------
@@ -282,8 +271,6 @@ __global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, do
             AT acc[CPT];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) acc[c] = AT(0);
-            Pack<AT, CPT> self{};   // the row's own gathered input (S == 1)
-            bool have_self = false;
             if constexpr (Op::kMatrix) {
                 // nonzeros in batches of U: all column indices and values
                 // first, then every gather, then the multiply-adds in
@@ -331,14 +318,6 @@ __global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, do
                             vv[u] = Pack<AT, CPT>{};
                             if (cc[u] >= 0) vv[u] = op.fetch(cc[u], j0);
                         }
-                        if constexpr (kSelfCapture && op_wants_self<Op>::value && S == 1) {
-#pragma unroll
-                            for (int u = 0; u < U; ++u)
-                                if (cc[u] == i) {
-                                    self = vv[u];
-                                    have_self = true;
-                                }
-                        }
 #pragma unroll
                         for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -352,12 +331,7 @@ __global__ __launch_bounds__(kMaxBlock) void rows_kernel(Op op_in, int nrows, do
                         for (int c = 0; c < CPT; ++c) acc[c] += __shfl_xor(acc[c], off, 64);
                 }
             }
-            if (live && sg == 0) {
-                if constexpr (kSelfCapture && op_wants_self<Op>::value)
-                    op.out_self(i, j0, acc, have_self, self, dsum);
-                else
-                    op.out(i, j0, acc, dsum);
-            }
+            if (live && sg == 0) op.out(i, j0, acc, dsum);
         }
     }
     reduce_dots<M, CPT, ND>(dsum, part, blk);

@@ -87,30 +87,14 @@ struct OpAx {
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
                                         double (&d)[ND][CPT]) const
     {
-        out_self(i, j0, acc, false, Pack<AT, CPT>{}, d);
-    }
-    // with the dot, x_i is the diagonal entry's gathered value when the row
-    // kernel has it (no second load of the row's own input)
-    static constexpr bool kWantSelf = DOT > 0;
-    template <int ND>
-    __device__ __forceinline__ void out_self(int i, int j0, const AT (&acc)[CPT], bool have,
-                                             const Pack<AT, CPT>& xs, double (&d)[ND][CPT]) const
-    {
         Pack<T, CPT> o;
 #pragma unroll
         for (int t = 0; t < CPT; ++t) o.v[t] = T(acc[t]);
         store_pack<T, CPT>(y + size_t(i) * M + j0, o);
         if constexpr (DOT > 0) {
-            Pack<AT, CPT> xi;
-            if (have) {
-                xi = xs;
-            } else {
-                const auto xl = load_pack<T, CPT>(x + size_t(i) * M + j0);
+            const auto xl = load_pack<T, CPT>(x + size_t(i) * M + j0);
 #pragma unroll
-                for (int t = 0; t < CPT; ++t) xi.v[t] = AT(xl.v[t]);
-            }
-#pragma unroll
-            for (int t = 0; t < CPT; ++t) d[0][t] += double(xi.v[t]) * double(o.v[t]);
+            for (int t = 0; t < CPT; ++t) d[0][t] += double(AT(xl.v[t])) * double(o.v[t]);
         }
     }
     // > 0: every row holds exactly rowlen entries, row i at i * rowlen (no row
@@ -285,23 +269,11 @@ struct OpJacPost {
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
                                         double (&d)[ND][CPT]) const
     {
-        out_self(i, j0, acc, false, Pack<AT, CPT>{}, d);
-    }
-    // x_i from the gathered diagonal entry when the row kernel has it
-    static constexpr bool kWantSelf = true;
-    template <int ND>
-    __device__ __forceinline__ void out_self(int i, int j0, const AT (&acc)[CPT], bool have,
-                                             const Pack<AT, CPT>& xs, double (&d)[ND][CPT]) const
-    {
         const auto bi = load_pack<BT, CPT>(b + size_t(i) * M + j0);
+        const auto xl = load_pack<T, CPT>(x + size_t(i) * M + j0);
         Pack<AT, CPT> xi;
-        if (have) {
-            xi = xs;
-        } else {
-            const auto xl = load_pack<T, CPT>(x + size_t(i) * M + j0);
 #pragma unroll
-            for (int t = 0; t < CPT; ++t) xi.v[t] = AT(xl.v[t]);
-        }
+        for (int t = 0; t < CPT; ++t) xi.v[t] = AT(xl.v[t]);
         const AT wd = omega * dinv[i];
         Pack<OT, CPT> o;
 #pragma unroll
@@ -471,22 +443,10 @@ struct OpChebPost2 {
     __device__ __forceinline__ void out(int i, int j0, const AT (&acc)[CPT],
                                         double (&d)[ND][CPT]) const
     {
-        out_self(i, j0, acc, false, Pack<AT, CPT>{}, d);
-    }
-    // r0_i from the gathered diagonal entry when the row kernel has it
-    static constexpr bool kWantSelf = true;
-    template <int ND>
-    __device__ __forceinline__ void out_self(int i, int j0, const AT (&acc)[CPT], bool have,
-                                             const Pack<AT, CPT>& rs, double (&d)[ND][CPT]) const
-    {
+        const auto rl = load_pack<T, CPT>(r0 + size_t(i) * M + j0);
         Pack<AT, CPT> ri;
-        if (have) {
-            ri = rs;
-        } else {
-            const auto rl = load_pack<T, CPT>(r0 + size_t(i) * M + j0);
 #pragma unroll
-            for (int t = 0; t < CPT; ++t) ri.v[t] = AT(rl.v[t]);
-        }
+        for (int t = 0; t < CPT; ++t) ri.v[t] = AT(rl.v[t]);
         const auto xi = load_pack<T, CPT>(x + size_t(i) * M + j0);
         const AT di = dinv[i];
         Pack<OT, CPT> o;
