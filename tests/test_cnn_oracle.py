@@ -282,3 +282,32 @@ def test_residual_loss_of_zero_network_is_one():
     xs = [rng.standard_normal(N ** 3) for _ in range(2)]
     loss, _ = oracle.cnn_residual_loss_and_grads(N, Ws, xs, _nonsym_csr(N ** 3, 14))
     assert loss == pytest.approx(1.0, abs=1e-15)
+
+
+def test_output_voxel_depends_only_on_its_9cube():
+    # four 3^3 layers without bias: an output voxel sees the inputs within 4
+    # cells, so the forward over a 9^3 patch (aligned to the volume's faces
+    # within 4 cells of them, where both apply the same zero padding) gives
+    # the full volume's output there; the full-size GPU test relies on this
+    N = 20
+    rng = np.random.default_rng(20)
+    Ws = [oracle.bf16(rng.standard_normal((co, ci, 27)) / np.sqrt(27 * ci))
+          for ci, co in oracle.CNN_LAYERS]
+    x = rng.standard_normal(N ** 3)
+    full = oracle.cnn_forward(N, Ws, x, quantize=True)[-1].reshape(N, N, N)
+    vol = x.reshape(N, N, N)
+    pts = [(0, 0, 0), (19, 19, 19), (0, 10, 19), (3, 4, 16), (10, 10, 10), (4, 15, 2),
+           (19, 0, 7), (5, 5, 5), (14, 14, 14)]
+    for pt in pts:
+        lo = [min(max(c - 4, 0), N - 9) for c in pt]
+        patch = vol[lo[0]:lo[0] + 9, lo[1]:lo[1] + 9, lo[2]:lo[2] + 9]
+        y = oracle.cnn_forward(9, Ws, np.ascontiguousarray(patch).reshape(-1),
+                               quantize=True)[-1].reshape(9, 9, 9)
+        got = y[pt[0] - lo[0], pt[1] - lo[1], pt[2] - lo[2]]
+        assert got == full[pt], (pt, got, full[pt])
+    # a 7^3 patch (too small) does not reproduce an interior voxel
+    pt = (10, 10, 10)
+    patch = vol[7:14, 7:14, 7:14]
+    y = oracle.cnn_forward(7, Ws, np.ascontiguousarray(patch).reshape(-1),
+                           quantize=True)[-1].reshape(7, 7, 7)
+    assert y[3, 3, 3] != full[pt]
