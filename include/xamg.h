@@ -299,9 +299,16 @@ int xamg_batch_destroy(xamg_batch_t *b);
  * last the banded XCD walk with three segment lengths; a change is kept
  * when it is more than 3% faster.  Timed with HIP events on
  * the solver's stream.  Runs by itself
- * on the first solve for each padded m; this call re-runs it now (enable
- * = 1) or switches automatic tuning off (enable = 0; the setup-time
- * row-length heuristic stays in use).  m in {1, 2, 4, 8, 16, 32}. */
+ * on the first solve for each padded m.  The choices are kept for the
+ * process in a tuning cache per device, keyed by the operator's shape and
+ * storage (rows, columns, nonzeros, stored row length, bandwidth, value and
+ * index width), the pass, the pre-smoothing variant and m: a handle whose
+ * operator matches a cached key takes that choice without timing, so equal
+ * problems run on equal launch shapes and give bit-identical results.  This
+ * call re-runs the tuning now, timing every choice afresh and replacing the
+ * cached ones (enable = 1), or switches automatic tuning off (enable = 0;
+ * the setup-time row-length heuristic stays in use).  m in {1, 2, 4, 8, 16,
+ * 32}. */
 int xamg_autotune(xamg_handle_t *h, int32_t m, int32_t enable);
 
 /* Row splits in use for m columns: out[4l .. 4l+3] = split of A_l (the

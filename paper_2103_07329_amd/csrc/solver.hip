@@ -552,6 +552,7 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
                     hipSuccess &&
                 ncu > 0)
                 h->num_cu = ncu;
+            h->device = dev;
         }
         h->nlev = H->nlevels;
         h->lev.resize(h->nlev);
@@ -790,10 +791,17 @@ int xamg_autotune(xamg_handle_t* hh, int32_t m, int32_t enable)
         int k = 0;
         while ((1 << k) < m) ++k;
         h->tuned_mask &= ~(1u << k);
-        xamg::dispatch_m(m, [&](auto mc) {
-            xamg::autotune<decltype(mc)::value>(*h);
-            return 0;
-        });
+        h->tune_fresh = true;   // a request times afresh and replaces cached choices
+        try {
+            xamg::dispatch_m(m, [&](auto mc) {
+                xamg::autotune<decltype(mc)::value>(*h);
+                return 0;
+            });
+        } catch (...) {
+            h->tune_fresh = false;
+            throw;
+        }
+        h->tune_fresh = false;
     } catch (const xamg::DevFail& f) {
         return f.code;
     }

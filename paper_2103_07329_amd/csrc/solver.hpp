@@ -118,9 +118,11 @@ struct Handle : xamg_handle {
     double* part = nullptr;
     int nb_cap = 1024;
     int num_cu = 256;            // compute units of the device (sizes sweeping launches)
+    int device = 0;              // the device the handle was set up on
     std::vector<void*> allocs;
     int autotune = 1;            // tune row splits on the first solve per M
     unsigned tuned_mask = 0;     // bit k: M = 2^k tuned
+    bool tune_fresh = false;     // time every choice again (not from the tuning cache)
     int tune_epoch = 0;          // bumped whenever launch shapes may change
     // kernel timer (measurement only)
     int timer_kind = 0;

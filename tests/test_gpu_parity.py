@@ -443,6 +443,39 @@ def test_autotune_choices_and_invariance(orc, torch, xm, jump24):
     S.close()
 
 
+def test_tuning_cache_shared_across_handles(orc, torch, xm, jump24):
+    """The autotuner's choices are cached per operator key: a second handle
+    on the same hierarchy takes the first one's launch shapes without timing,
+    so the two solve bit for bit alike; a re-tune on one handle times afresh
+    and replaces the cached choices, which a third handle then takes."""
+    p, H = jump24
+    _say("[autotune] tuning cache, jump24 m=8")
+    B = inputs.uniform_rhs(p.n, 8, 72)
+    Bd = _dev(torch, B)
+    out = []
+
+    def solve_new():
+        S = xm.Solver(H.export(), smoother=xm.CHEBYSHEV)
+        X = torch.zeros_like(Bd)
+        rc, _ = S.solve(Bd, X)
+        assert rc == xm.OK
+        out.append((S, X))
+        return S, X
+
+    S1, X1 = solve_new()
+    S2, X2 = solve_new()
+    assert S2.tuning(8) == S1.tuning(8)
+    assert torch.equal(X1, X2)
+    S2.autotune(8, enable=True)
+    S3, X3 = solve_new()
+    assert S3.tuning(8) == S2.tuning(8)
+    X2b = torch.zeros_like(Bd)
+    S2.solve(Bd, X2b)
+    assert torch.equal(X3, X2b)
+    for S, _ in out:
+        S.close()
+
+
 # --------------------------------------------------------------------------
 # batched uneven systems (one captured graph)
 # --------------------------------------------------------------------------
