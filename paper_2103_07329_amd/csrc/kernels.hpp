@@ -145,7 +145,6 @@ __device__ __forceinline__ void grp_share(const V (&own)[PL], V (&out)[U])
     }
 }
 
-
 // ---------------------------------------------------------------------------
 // block-level deterministic reduction of per-column dots
 // ---------------------------------------------------------------------------
