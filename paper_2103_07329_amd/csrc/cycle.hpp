@@ -932,9 +932,19 @@ void autotune(Handle& h)
     // scratch: the Krylov r and z blocks (n0 x mcap doubles), zero-filled
     hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                        nullptr, M, h.w.r, M, n0, 0);
-    hipEvent_t e0, e1;
-    h.check(hipEventCreate(&e0), "hipEventCreate");
-    h.check(hipEventCreate(&e1), "hipEventCreate");
+    // the timing events, released however the tuning ends (a device error
+    // throws out of it)
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events()
+        {
+            for (hipEvent_t ev : e)
+                if (ev) hipEventDestroy(ev);
+        }
+    } ev;
+    h.check(hipEventCreate(&ev.e[0]), "hipEventCreate");
+    h.check(hipEventCreate(&ev.e[1]), "hipEventCreate");
+    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
     const bool mixed = h.opt.precision == XAMG_MIXED;
     const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
     double* x = h.w.r;
@@ -966,8 +976,6 @@ void autotune(Handle& h)
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     h.tuned_mask |= 1u << k;
     h.tune_epoch += 1;
 }
