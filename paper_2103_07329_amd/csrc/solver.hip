@@ -139,8 +139,8 @@ static DCsr upload_csr(Handle& h, const xamg_csr_t& c, bool fp32)
 // shorter rows padded to that length by explicit zeros at columns the row
 // does not hold (the nearest ones, i +- 1, i +- 2, ...), in sorted order.
 // The zeros add exact zeros to every row sum, so results are unchanged.
-// Padded only when the maximum row length is at most 32 and the padding
-// adds at most 15% entries.
+// Padded only when the maximum row length is at most 32, the padding adds
+// at most 15% entries and the padded count fits 32-bit offsets.
 bool pad_uniform(const xamg_csr_t& c, UniformCsr& u)
 {
     if (c.nrows != c.ncols || c.nrows < 1) return false;
@@ -148,6 +148,8 @@ bool pad_uniform(const xamg_csr_t& c, UniformCsr& u)
     int w = 0;
     for (int i = 0; i < n; ++i) w = std::max(w, c.row_ptr[i + 1] - c.row_ptr[i]);
     if (w < 1 || w > 32 || double(n) * w > 1.15 * double(c.nnz) || w > n) return false;
+    // entry offsets i * rowlen are 32-bit, like the CSR row pointers
+    if (int64_t(n) * w > int64_t(INT32_MAX)) return false;
     u.rowlen = w;
     u.rp.resize(size_t(n) + 1);
     u.ci.resize(size_t(n) * w);
