@@ -229,8 +229,9 @@ int xamg_solve(xamg_handle_t *h, const double *B, double *X, int32_t m, double t
  * a solve that needs more returns XAMG_EINVAL (the detail string gives the
  * bytes needed: roughly (5 + 4 C_G) n m 8 bytes for FP64 CG, C_G the grid
  * complexity).  Launch shapes are those already tuned for the padded m (by
- * an earlier xamg_solve or xamg_autotune on the handle), else the setup-time
- * row-length guess.  Calls on one device share the array: calls that
+ * an earlier xamg_solve or xamg_autotune on the handle), else the tuning
+ * cache's choices for its operators (see xamg_autotune; a host lookup, no
+ * timing), else the setup-time row-length guess.  Calls on one device share the array: calls that
  * overlap in time on one device race and must be serialised by the caller.
  * The kernel timer is inactive during this call. */
 #define XAMG_NOALLOC_SCRATCH_BYTES (128u << 20)

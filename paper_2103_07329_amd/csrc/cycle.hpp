@@ -847,6 +847,40 @@ inline std::mutex& tune_cache_mutex()
     return mu;
 }
 
+// whether pass `kind` over d is tuned at all (it exists and runs)
+inline bool tuned_pass(const Handle& h, const DCsr& d, int kind)
+{
+    if (!d.rp || d.nr == 0) return false;
+    const bool gs_sweep = kind == 2 && h.opt.smoother == XAMG_GAUSS_SEIDEL;
+    return !(kind == 2 && !gs_sweep && !d.vd);
+}
+
+template <int M, typename T>
+TuneKey tune_key(const Handle& h, const DCsr& d, int kind)
+{
+    const bool gs_sweep = kind == 2 && h.opt.smoother == XAMG_GAUSS_SEIDEL;
+    // the pre-smoothing pass runs a different kernel per smoother
+    const int variant = kind != 2 ? 0
+                        : gs_sweep ? 100 + h.opt.gs_block
+                        : (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) ? 2
+                                                                                          : 1;
+    return TuneKey{h.device, d.nr, d.nc, d.nnz, d.rowlen, d.bw, int(sizeof(T)),
+                   d.off != nullptr ? 1 : 0, kind, variant, M};
+}
+
+// the cached choice for pass `kind` over d, if any, applied without timing
+template <int M, typename T>
+bool cached_choice(const Handle& h, DCsr& d, int kind)
+{
+    constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
+    if (!tuned_pass(h, d, kind)) return true;
+    std::lock_guard<std::mutex> lock(tune_cache_mutex());
+    const auto it = tune_cache().find(tune_key<M, T>(h, d, kind));
+    if (it == tune_cache().end()) return false;
+    (kind == 2 ? d.split_pre : d.split)[k] = it->second;
+    return true;
+}
+
 template <int M, typename T>
 void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, hipEvent_t e0,
                  hipEvent_t e1)
@@ -854,25 +888,11 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
     constexpr int C0 = cpt_for<T, M>();
     constexpr int G = M / C0;
     constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
-    if (!d.rp || d.nr == 0) return;
+    if (!tuned_pass(h, d, kind)) return;
+    if (!h.tune_fresh && cached_choice<M, T>(h, d, kind)) return;
     const bool gs_sweep = kind == 2 && h.opt.smoother == XAMG_GAUSS_SEIDEL;
-    if (kind == 2 && !gs_sweep && !d.vd) return;
-    // the pre-smoothing pass runs a different kernel per smoother
-    const int variant = kind != 2 ? 0
-                        : gs_sweep ? 100 + h.opt.gs_block
-                        : (h.opt.smoother == XAMG_CHEBYSHEV && h.opt.cheby_degree == 2) ? 2
-                                                                                          : 1;
-    const TuneKey key{h.device, d.nr, d.nc, d.nnz, d.rowlen, d.bw, int(sizeof(T)),
-                      d.off != nullptr ? 1 : 0, kind, variant, M};
+    const TuneKey key = tune_key<M, T>(h, d, kind);
     int& slot = (kind == 2 ? d.split_pre : d.split)[k];
-    if (!h.tune_fresh) {
-        std::lock_guard<std::mutex> lock(tune_cache_mutex());
-        const auto it = tune_cache().find(key);
-        if (it != tune_cache().end()) {
-            slot = it->second;
-            return;
-        }
-    }
     // candidates from the simplest launch up; a later one replaces the
     // current choice only when it is more than 3% faster, so that near-ties
     // (within the timing noise) resolve the same way from run to run.
@@ -923,6 +943,35 @@ void tune_matrix(Handle& h, DCsr& d, int kind, const T* dinv, T* x, T* y, T* z, 
     tune_cache()[key] = bestS;
 }
 
+// the passes the autotuner times, in order: f(T{}, d, kind, dinv) for the
+// FP64 (T = double) or FP32 (T = float) copy of each operator the V-cycle
+// and the Krylov method run
+template <int M, class F>
+void for_each_tuned_pass(Handle& h, F&& f)
+{
+    const bool mixed = h.opt.precision == XAMG_MIXED;
+    const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
+    for (int l = 0; l < h.nlev; ++l) {
+        auto& L = h.lev[l];
+        const bool last = l + 1 == h.nlev;
+        if (l == 0 || !mixed) {
+            f(double{}, L.A64, 0, L.dinv64);
+            if (!last && !mixed) f(double{}, L.A64, 2, gs ? L.dl1inv64 : L.dinv64);
+        }
+        if (!last) {
+            if (!mixed) {
+                f(double{}, L.P64, 3, L.dinv64);
+                f(double{}, L.R64, 1, L.dinv64);
+            } else {
+                f(float{}, L.A32, 0, L.dinv32);
+                f(float{}, L.A32, 2, gs ? L.dl1inv32 : L.dinv32);
+                f(float{}, L.P32, 3, L.dinv32);
+                f(float{}, L.R32, 1, L.dinv32);
+            }
+        }
+    }
+}
+
 template <int M>
 void autotune(Handle& h)
 {
@@ -944,40 +993,33 @@ void autotune(Handle& h)
     } ev;
     h.check(hipEventCreate(&ev.e[0]), "hipEventCreate");
     h.check(hipEventCreate(&ev.e[1]), "hipEventCreate");
-    hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
-    const bool mixed = h.opt.precision == XAMG_MIXED;
-    const bool gs = h.opt.smoother == XAMG_GAUSS_SEIDEL;
-    double* x = h.w.r;
-    double* y = h.w.z;
     double* z = h.w.p;   // right-hand side of the residual pass (finite: zeroed)
     hipLaunchKernelGGL((copy_cols_kernel<double, double>), dim3(1024), dim3(256), 0, h.stream,
                        nullptr, M, z, M, n0, 0);
-    float* xf = reinterpret_cast<float*>(x);
-    float* yf = reinterpret_cast<float*>(y);
-    float* zf = reinterpret_cast<float*>(z);
-    for (int l = 0; l < h.nlev; ++l) {
-        auto& L = h.lev[l];
-        const bool last = l + 1 == h.nlev;
-        if (l == 0 || !mixed) {
-            tune_matrix<M, double>(h, L.A64, 0, L.dinv64, x, y, z, e0, e1);
-            if (!last && !mixed)
-                tune_matrix<M, double>(h, L.A64, 2, gs ? L.dl1inv64 : L.dinv64, x, y, z, e0, e1);
-        }
-        if (!last) {
-            if (!mixed) {
-                tune_matrix<M, double>(h, L.P64, 3, L.dinv64, x, y, z, e0, e1);
-                tune_matrix<M, double>(h, L.R64, 1, L.dinv64, x, y, z, e0, e1);
-            } else {
-                tune_matrix<M, float>(h, L.A32, 0, L.dinv32, xf, yf, zf, e0, e1);
-                tune_matrix<M, float>(h, L.A32, 2, gs ? L.dl1inv32 : L.dinv32, xf, yf, zf, e0,
-                                      e1);
-                tune_matrix<M, float>(h, L.P32, 3, L.dinv32, xf, yf, zf, e0, e1);
-                tune_matrix<M, float>(h, L.R32, 1, L.dinv32, xf, yf, zf, e0, e1);
-            }
-        }
-    }
+    for_each_tuned_pass<M>(h, [&](auto tag, DCsr& d, int kind, const auto* dinv) {
+        using T = decltype(tag);
+        tune_matrix<M, T>(h, d, kind, dinv, reinterpret_cast<T*>(h.w.r),
+                          reinterpret_cast<T*>(h.w.z), reinterpret_cast<T*>(z), ev.e[0], ev.e[1]);
+    });
     h.tuned_mask |= 1u << k;
     h.tune_epoch += 1;
+}
+
+// For a handle not yet tuned for M: the choices the tuning cache holds for
+// its passes, applied without timing, launching or touching work memory
+// (passes without a cached choice keep their current shape).  The
+// allocation-free solve calls it.
+template <int M>
+void apply_cached_tuning(Handle& h)
+{
+    constexpr int k = M == 1 ? 0 : M == 2 ? 1 : M == 4 ? 2 : M == 8 ? 3 : M == 16 ? 4 : 5;
+    if (!h.autotune || (h.tuned_mask & (1u << k))) return;
+    bool changed = false;
+    for_each_tuned_pass<M>(h, [&](auto tag, DCsr& d, int kind, const auto*) {
+        using T = decltype(tag);
+        changed |= tuned_pass(h, d, kind) && cached_choice<M, T>(h, d, kind);
+    });
+    if (changed) h.tune_epoch += 1;
 }
 
 }  // namespace xamg

@@ -12,6 +12,7 @@ template int bicgstab<1>(Handle&, const double*, double*, double);
 template int pbicgstab<1>(Handle&, const double*, double*, double);
 template void spmm64<1>(Handle&, const DCsr&, const double*, double*);
 template void autotune<1>(Handle&);
+template void apply_cached_tuning<1>(Handle&);
 template void pcg_start<1>(Handle&, const double*, double*, double);
 template void pcg_iteration<1>(Handle&, double*);
 template void pcg_true_enqueue<1>(Handle&, const double*, double*, int);

@@ -12,6 +12,7 @@ template int bicgstab<16>(Handle&, const double*, double*, double);
 template int pbicgstab<16>(Handle&, const double*, double*, double);
 template void spmm64<16>(Handle&, const DCsr&, const double*, double*);
 template void autotune<16>(Handle&);
+template void apply_cached_tuning<16>(Handle&);
 template void pcg_start<16>(Handle&, const double*, double*, double);
 template void pcg_iteration<16>(Handle&, double*);
 template void pcg_true_enqueue<16>(Handle&, const double*, double*, int);

@@ -12,6 +12,7 @@ template int bicgstab<2>(Handle&, const double*, double*, double);
 template int pbicgstab<2>(Handle&, const double*, double*, double);
 template void spmm64<2>(Handle&, const DCsr&, const double*, double*);
 template void autotune<2>(Handle&);
+template void apply_cached_tuning<2>(Handle&);
 template void pcg_start<2>(Handle&, const double*, double*, double);
 template void pcg_iteration<2>(Handle&, double*);
 template void pcg_true_enqueue<2>(Handle&, const double*, double*, int);

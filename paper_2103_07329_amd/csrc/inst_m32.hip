@@ -12,6 +12,7 @@ template int bicgstab<32>(Handle&, const double*, double*, double);
 template int pbicgstab<32>(Handle&, const double*, double*, double);
 template void spmm64<32>(Handle&, const DCsr&, const double*, double*);
 template void autotune<32>(Handle&);
+template void apply_cached_tuning<32>(Handle&);
 template void pcg_start<32>(Handle&, const double*, double*, double);
 template void pcg_iteration<32>(Handle&, double*);
 template void pcg_true_enqueue<32>(Handle&, const double*, double*, int);

@@ -12,6 +12,7 @@ template int bicgstab<4>(Handle&, const double*, double*, double);
 template int pbicgstab<4>(Handle&, const double*, double*, double);
 template void spmm64<4>(Handle&, const DCsr&, const double*, double*);
 template void autotune<4>(Handle&);
+template void apply_cached_tuning<4>(Handle&);
 template void pcg_start<4>(Handle&, const double*, double*, double);
 template void pcg_iteration<4>(Handle&, double*);
 template void pcg_true_enqueue<4>(Handle&, const double*, double*, int);

@@ -12,6 +12,7 @@ template int bicgstab<8>(Handle&, const double*, double*, double);
 template int pbicgstab<8>(Handle&, const double*, double*, double);
 template void spmm64<8>(Handle&, const DCsr&, const double*, double*);
 template void autotune<8>(Handle&);
+template void apply_cached_tuning<8>(Handle&);
 template void pcg_start<8>(Handle&, const double*, double*, double);
 template void pcg_iteration<8>(Handle&, double*);
 template void pcg_true_enqueue<8>(Handle&, const double*, double*, int);

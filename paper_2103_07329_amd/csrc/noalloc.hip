@@ -120,6 +120,16 @@ extern "C" int xamg_solve_noalloc(xamg_handle_t* hh, const double* B, double* X,
         hipLaunchKernelGGL((xamg::dev::copy_cols_kernel<double, double>), dim3(4), dim3(256), 0,
                            h->stream, static_cast<const double*>(nullptr), 1,
                            reinterpret_cast<double*>(base), 1, int(st_bytes / sizeof(double)), 0);
+        // a handle not yet tuned for mp takes the tuning cache's choices for
+        // its operators (a host lookup: no timing, no launch, no allocation)
+        switch (mp) {
+        case 1: xamg::apply_cached_tuning<1>(*h); break;
+        case 2: xamg::apply_cached_tuning<2>(*h); break;
+        case 4: xamg::apply_cached_tuning<4>(*h); break;
+        case 8: xamg::apply_cached_tuning<8>(*h); break;
+        case 16: xamg::apply_cached_tuning<16>(*h); break;
+        default: xamg::apply_cached_tuning<32>(*h); break;
+        }
         rc = xamg::solve_run(*h, B, X, m, tol, stats);
         if (rc == XAMG_EINVAL && xamg::last_error()[0] == '\0')
             xamg::set_error("B contains NaN or Inf");

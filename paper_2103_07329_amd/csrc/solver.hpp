@@ -379,6 +379,9 @@ int pcg_true_finish(Handle& h);
 // time each operator's SpMM over the row splits and keep the fastest
 template <int M>
 void autotune(Handle& h);
+// the tuning cache's choices for a handle not yet tuned for M, no timing
+template <int M>
+void apply_cached_tuning(Handle& h);
 
 void ensure_work(Handle& h, int mp, bool bicg);
 // the BiCGStab work vectors (r-hat, v, s, p-hat, s-hat) are needed

@@ -104,3 +104,21 @@ def test_noalloc_rejects_work_beyond_the_scratch(torch, xm):
     assert rc == xm.EINVAL
     assert b"scratch" in xm.lib().xamg_last_error()
     S.close()
+
+
+def test_noalloc_on_a_fresh_handle_takes_the_cached_shapes(torch, xm):
+    # a handle never tuned takes the shapes the tuning cache holds for its
+    # operators (tuned here by another handle's first solve): no timing, no
+    # allocation, and the other handle's solution bit for bit
+    p = inputs.poisson7(20)
+    H = xm.HostHierarchy(*p.csr())
+    B = inputs.uniform_rhs(p.n, 16, 44)
+    _say("[noalloc] poisson20 m=16: fresh handle after another handle's tuning")
+    S1 = xm.Solver(H, smoother=xm.CHEBYSHEV)
+    Xr, sr, rcr = _run(torch, S1.solve, B, 1e-10)
+    S2 = xm.Solver(H, smoother=xm.CHEBYSHEV)
+    X, st, rc = _run(torch, S2.solve_noalloc, B, 1e-10)
+    assert S2.tuning(16) == S1.tuning(16)
+    assert _compare(X, st, rc, Xr, sr, rcr)
+    S1.close()
+    S2.close()
