@@ -203,7 +203,9 @@ void xamg_default_options(xamg_options_t *o);
  * D^-1 per level, the inverse of the coarsest matrix from its LU
  * factorisation (EBREAKDOWN if singular), FP32 copies and 16-bit index
  * encodings when the options ask for them.  opt may be NULL (defaults).
- * EINVAL on inconsistent sizes or invalid CSR; ENODEV without a gfx950
+ * The coarsest level may have up to 1024 rows (its inverse is applied from
+ * LDS up to 64 rows, from global memory above).  EINVAL on inconsistent
+ * sizes, invalid CSR or a larger coarsest level; ENODEV without a gfx950
  * device; ENOMEM when device memory runs out. */
 int xamg_setup(const xamg_hierarchy_t *H, const xamg_options_t *opt,
                xamg_handle_t **out);

@@ -305,6 +305,20 @@ struct OpDotsBX {
 // (BT), xout: corrected solution (OT).  At the finest level the last pass
 // also accumulates the dots (b, xout) [and (q, xout)].  Returns the block
 // count of the last launch (the one that wrote partial dots).
+// x = A_L^-1 b on the coarsest level (nL rows): the inverse staged in LDS by
+// one block up to kCoarseLds rows, else read from global memory by one
+// thread per entry of x (the same sums in the same order)
+template <int M, typename T>
+void launch_coarse(Handle& h, const T* inv, int nL, const T* b, T* x, const int* nactive)
+{
+    if (nL <= kCoarseLds)
+        hipLaunchKernelGGL((coarse_kernel<M, T>), dim3(1), dim3(256), 0, h.stream, inv, nL, b, x,
+                           nactive);
+    else
+        hipLaunchKernelGGL((coarse_global_kernel<M, T>), dim3((nL * M + 255) / 256), dim3(256), 0,
+                           h.stream, inv, nL, b, x, nactive);
+}
+
 template <int M, typename T, typename BT, typename OT>
 static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const double* q,
                   const double* bd = nullptr)
@@ -315,12 +329,11 @@ static int vlevel(Handle& h, int l, const BT* b, OT* xout, int ndots, const doub
     auto& W = h.w.lev[l];
     int nb = 1;
     if (l == h.nlev - 1) {
-        // coarsest level: dense inverse in LDS
+        // coarsest level: the dense inverse applied
         if constexpr (std::is_same<BT, T>::value && std::is_same<OT, T>::value) {
             const T* inv;
             if constexpr (sizeof(T) == 8) inv = h.inv64; else inv = h.inv32;
-            hipLaunchKernelGGL((coarse_kernel<M, T>), dim3(1), dim3(256), 0, h.stream, inv,
-                               L.n, b, xout, na);
+            launch_coarse<M, T>(h, inv, L.n, b, xout, na);
         } else {
             set_error("internal: coarsest level with mixed boundary types");
             throw DevFail{XAMG_EINVAL};
@@ -449,8 +462,7 @@ int vcycle(Handle& h, const double* r, double* z, int ndots, const double* q,
 {
     constexpr int CPT = cpt_for<double, M>();
     if (h.nlev == 1) {
-        hipLaunchKernelGGL((coarse_kernel<M, double>), dim3(1), dim3(256), 0, h.stream,
-                           h.inv64, h.lev[0].n, r, z, &h.st->nactive);
+        launch_coarse<M, double>(h, h.inv64, h.lev[0].n, r, z, &h.st->nactive);
         if (ndots == 0) return 0;
         if (ndots == 2) {
             OpDotsBX<M, CPT, 2> op{nullptr, nullptr, Idx32{nullptr}, r, z, q};

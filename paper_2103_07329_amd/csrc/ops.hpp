@@ -984,5 +984,23 @@ __global__ __launch_bounds__(256) void coarse_kernel(const T* __restrict__ inv, 
     }
 }
 
+// the same product for a coarsest level too large for LDS: the inverse is
+// read from global memory (it stays in L2 across cycles), one thread per
+// entry of x, the sum over k in the same increasing order
+template <int M, typename T>
+__global__ __launch_bounds__(256) void coarse_global_kernel(const T* __restrict__ inv, int nL,
+                                                            const T* __restrict__ b,
+                                                            T* __restrict__ x, const int* nactive)
+{
+    if (nactive && *nactive == 0) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nL * M) return;
+    const int i = e / M, j = e % M;
+    const T* row = inv + size_t(i) * nL;
+    T s = T(0);
+    for (int k = 0; k < nL; ++k) s += row[k] * b[size_t(k) * M + j];
+    x[e] = s;
+}
+
 }  // namespace dev
 }  // namespace xamg

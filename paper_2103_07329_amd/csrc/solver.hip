@@ -538,7 +538,8 @@ int xamg_setup(const xamg_hierarchy_t* H, const xamg_options_t* opt, xamg_handle
         }
     }
     const int nL = int(H->A[H->nlevels - 1].nrows);
-    if (nL > 64) return xamg::fail(XAMG_EINVAL, "coarsest level must have <= 64 rows");
+    if (nL > xamg::kMaxCoarse)
+        return xamg::fail(XAMG_EINVAL, "coarsest level must have <= 1024 rows");
     int rc = device_ok();
     if (rc) return rc;
 

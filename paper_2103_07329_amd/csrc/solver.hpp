@@ -182,6 +182,10 @@ constexpr int kSegMask = 3 << kSegShift;
 constexpr int kSegBw = 1 << kSegShift, kSegHalf = 2 << kSegShift, kSegQuarter = 3 << kSegShift;
 constexpr int kShapeFlags = kSweep | kBig | kIdx32 | kWide | kSegMask;
 constexpr int kSweepPerCu = 5;
+// coarsest level sizes: up to kCoarseLds rows its dense inverse is applied
+// from LDS, up to kMaxCoarse rows from global memory
+constexpr int kCoarseLds = 64;
+constexpr int kMaxCoarse = 1024;
 
 // blocks of rows_kernel<M, CPT, S, Op> of `block` threads that the device
 // holds at once (its occupancy, from the kernel's registers and LDS, times

@@ -67,7 +67,7 @@ def test_setup_argument_errors_without_device():
     bad = xamg.default_options(method=xamg.PBICGSTAB, precision=xamg.MIXED)
     assert L.xamg_setup(ctypes.byref(H), ctypes.byref(bad), ctypes.byref(h)) == xamg.EINVAL
     assert b"linear" in L.xamg_last_error()
-    big = inputs.poisson7(5)                        # 125 rows > 64 on the coarsest level
+    big = inputs.poisson7(11)                       # 1331 rows > 1024 on the coarsest level
     b = xamg._csr_struct(*big.csr(), keep=keep)
     H2 = xamg.HierT(1, ctypes.pointer(b), None, None, None)
     assert L.xamg_setup(ctypes.byref(H2), None, ctypes.byref(h)) == xamg.EINVAL

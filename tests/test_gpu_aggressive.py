@@ -94,3 +94,35 @@ def test_library_setup_aggressive_equals_oracle_solution(orc, torch, xm):
     assert rc == xm.OK and np.array_equal(st["iters"], so["iters"])
     err = np.linalg.norm(Xd.cpu().numpy() - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
     assert err.max() <= 1e-7
+
+
+def test_paper_parameter_example(orc, torch, xm):
+    """The configuration of the paper's parameter example (Section 2.4):
+    pipelined BiCGStab, at most 20 iterations, AMG with two aggressive
+    levels and two paths, coarsening to at most 500 rows, Chebyshev degree 2
+    smoothing.  The library's own setup against the oracle's: the same
+    hierarchy sizes, the oracle's iteration counts, error <= 1e-7."""
+    p = inputs.poisson7(32)
+    kw = dict(max_coarse=500, agg_levels=2, num_paths=2)
+    Hl = xm.HostHierarchy(*p.csr(), **kw)
+    Ho = orc.Hierarchy(*p.csr(), **kw)
+    _say(f"[paper example] poisson32 levels {Hl.sizes()}")
+    assert Hl.sizes() == Ho.sizes()
+    assert Hl.sizes()[-1] <= 500
+    B = inputs.uniform_rhs(p.n, 8, 78)
+    Xo, so, rco = Ho.solve(B, method=orc.PBICGSTAB, smoother=orc.CHEBYSHEV, max_iters=20,
+                           tol=1e-8)
+    S = xm.Solver(Hl, method=xm.PBICGSTAB, smoother=xm.CHEBYSHEV, max_iters=20)
+    Bd = torch.from_numpy(B).cuda()
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-8)
+    S.close()
+    X = Xd.cpu().numpy()
+    err = np.linalg.norm(X - Xo, axis=0) / np.linalg.norm(Xo, axis=0)
+    A = sp.csr_matrix((p.val, p.col, p.rowptr), shape=(p.n, p.n))
+    tr = np.linalg.norm(B - A @ X, axis=0) / np.linalg.norm(B, axis=0)
+    _say(f"   iters gpu {st['iters'].tolist()} oracle {so['iters'].tolist()}, err {err.max():.1e}, "
+         f"true relres {tr.max():.1e}")
+    assert rc == rco == xm.OK
+    assert np.array_equal(st["iters"], so["iters"])
+    assert err.max() <= 1e-7 and np.all(tr <= 1e-8)

@@ -204,6 +204,49 @@ def test_one_level_hierarchy(orc, torch, xm):
     S.close()
 
 
+def test_coarsest_level_beyond_lds(orc, torch, xm):
+    """A coarsest level of more than 64 rows has its inverse applied from
+    global memory: a one-level hierarchy of 216 rows (CG converges in one
+    step) and a V-cycle coarsened to at most 500 rows (128 here), FP64
+    against the oracle and the FP32 cycle within its rounding bounds."""
+    p = inputs.poisson7(6)
+    H = orc.Hierarchy(*p.csr(), max_coarse=500)
+    assert H.nlev == 1 and p.n == 216
+    _say("[coarse] one level of 216 rows")
+    B = inputs.uniform_rhs(p.n, 3, 14)
+    S = xm.Solver(H.export())
+    Bd = _dev(torch, B)
+    Xd = torch.zeros_like(Bd)
+    rc, st = S.solve(Bd, Xd, tol=1e-12)
+    S.close()
+    Xo, so, _ = H.solve(B, tol=1e-12)
+    assert rc == xm.OK and np.all(st["iters"] == 1)
+    assert _relmax(Xd.cpu().numpy(), Xo) <= 1e-12
+    p = inputs.jump7(24, inputs.jump_kappa(24, np.random.default_rng(15)))
+    H = orc.Hierarchy(*p.csr(), max_coarse=500)
+    nL = H.sizes()[-1]
+    _say(f"[coarse] jump24 levels {H.sizes()}")
+    assert 64 < nL <= 500
+    for m in (1, 16):
+        B = inputs.uniform_rhs(p.n, m, 15 + m)
+        Bd = _dev(torch, B)
+        for smoother in (0, 1):
+            Zref = H.vcycle(B, smoother=smoother)
+            S = xm.Solver(H.export(), smoother=smoother)
+            Zd = torch.full_like(Bd, np.nan)
+            S.vcycle(Bd, Zd)
+            torch.cuda.synchronize()
+            S.close()
+            assert _relmax(Zd.cpu().numpy(), Zref) <= 1e-12, (m, smoother)
+        Z32 = H.vcycle32(B, smoother=1)
+        Sm = xm.Solver(H.export(), smoother=1, precision=xm.MIXED)
+        Zd = torch.full_like(Bd, np.nan)
+        Sm.vcycle(Bd, Zd)
+        torch.cuda.synchronize()
+        Sm.close()
+        assert _relmax(Zd.cpu().numpy(), Z32) <= 128 * 2.0 ** -24, m
+
+
 def test_device_setup_matches_host_setup_solution(orc, torch, xm):
     """The library's own host setup feeds the device solver: the solution
     must match the oracle (own setup) to the same bar."""
