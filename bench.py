@@ -697,15 +697,23 @@ def bench_warmstart(args, torch, inputs, xamg):
     log(f"[bench] zero guess: {ms_zero:.2f} ms/solve, iters {stz['iters'].tolist()}")
     log(f"[bench] warm start: {ms_warm:.2f} ms/solve (CNN + fallback {ms_cnn:.2f} ms), "
         f"iters {stw['iters'].tolist()}, fallbacks {int(fb.sum())}/{m}, max rel diff {diff:.1e}")
-    flops = 2.0 * n * 27 * 16 * 16          # one 16 -> 16 layer over one sample
+    # one 16 -> 16 layer over one sample: 27 * 16 * 16 multiply-adds per voxel
+    # against 64 bytes per voxel (16 BF16 channels read, 16 written): 216
+    # flop/B, below the BF16 ridge of 2.5 PFLOP/s / 8 TB/s = 312 flop/B, so the
+    # layer is bound by HBM (16.8 us at 128^3) before the MFMA (11.6 us)
+    flops = 2.0 * n * 27 * 16 * 16
+    cbytes = 2.0 * n * 16 * 2
     avg_ms = tms / max(cnt, 1)
     tfs = flops / (avg_ms * 1e-3) / 1e12
-    log(f"[bench] conv16 MFMA: {cnt} launches, avg {avg_ms * 1e3:.1f} us, "
-        f"{tfs:.1f} TFLOP/s ({tfs / 2500.0:.2%} of 2.5 PFLOP/s)")
+    gbs = cbytes / (avg_ms * 1e-3) / 1e9
+    log(f"[bench] conv16: {cnt} launches, avg {avg_ms * 1e3:.1f} us, {gbs:.0f} GB/s "
+        f"({gbs / 8000.0:.2%} of 8 TB/s), {tfs:.1f} TFLOP/s ({tfs / 2500.0:.2%} of 2.5 PFLOP/s)")
     roofline = {"kernel": "conv16_lds (16 -> 16 channel 3x3x3 convolution, BF16 MFMA, FP32 "
-                          "accumulation), CNN forward", "bound": "mfma", "achieved": tfs,
-                "peak": 2500.0, "unit": "TFLOP/s", "frac": tfs / 2500.0, "traffic": None,
-                "algorithmic_flops": flops, "avg_us": avg_ms * 1e3, "launches_timed": cnt}
+                          "accumulation), CNN forward", "bound": "hbm", "achieved": gbs,
+                "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None,
+                "algorithmic_bytes": cbytes, "algorithmic_flops": flops,
+                "mfma_tflops": tfs, "mfma_frac": tfs / 2500.0,
+                "avg_us": avg_ms * 1e3, "launches_timed": cnt}
     cpu = None
     if not args.no_cpu:
         import oracle

@@ -420,7 +420,8 @@ int xamg_cnn_adam(xamg_cnn_t *h, float lr, float beta1, float beta2, float eps);
  * the layer's input activation, into `out` (n x 16 BF16).  mode 2: weight
  * gradient from `in` (gradient at the output, as in mode 1) and `mask` (the
  * layer's input activation); the result replaces the gradient buffer
- * (read with xamg_cnn_get_grads; other layers' entries are zero). */
+ * (read with xamg_cnn_get_grads; other layers' entries are zero).
+ * `in`, `mask` and `out` must be 16-byte aligned (XAMG_EINVAL otherwise). */
 int xamg_cnn_layer(xamg_cnn_t *h, int32_t layer, int32_t mode, const void *in, const void *mask,
                    void *out);
 

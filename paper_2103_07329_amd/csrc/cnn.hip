@@ -43,7 +43,7 @@ constexpr int kParams2 = kC * kC * kTaps;
 constexpr int kParams4 = 1 * kC * kTaps;
 constexpr int kParams = kParams1 + 2 * kParams2 + kParams4;   // 14688
 constexpr int kWgBlocks = 1024;
-constexpr int kColBlocks = 512;
+constexpr int kColBlocks = 4096;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -112,133 +112,240 @@ __device__ inline void store16(uint16_t* p, const float* v)
 // 2p + (lane/16)/2, input channel ((lane/16)&1)*8 + j, output channel
 // lane % 16.  out = relu?(acc) * (mask > 0 if mask) in BF16.
 //
-// A block computes a tile of 16 (x) x 4 (y) x 4 (z) output voxels.  It first
-// stages the 18 x 6 x 6 input voxels around the tile (one-voxel halo, zero
-// outside the volume; 16 BF16 channels = 32 bytes each, 20.7 KB) in LDS, so
-// an input voxel is read from memory about 2.5 times per layer instead of
-// once per tap.  Wave w takes z-slice w of the tile: for each tap pair p it
-// reads the A fragments of its 4 rows (16 voxels each) from LDS and issues
-// 4 independent MFMAs, with the 14 packed B fragments held in registers.
+// The volume is cut into tiles of 16 (x) x 4 (y) x 4 (z) output voxels
+// (N is a multiple of 16, so tiles are whole).  For a tile, the 18 x 6 x 6
+// input voxels around it (one-voxel halo, zero outside the volume; 16 BF16
+// channels = 32 bytes each, 20.7 KB) are staged in LDS, so an input voxel is
+// read from memory about 2.5 times per layer instead of once per tap.  The
+// staged channels 0-7 and 8-15 lie in two planes, so the 16 lanes that feed
+// one A fragment read 16 consecutive 16-byte words.
 constexpr int kTX = 16, kTY = 4, kTZ = 4;            // output tile
 constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHalo = kHX * kHY * kHZ;               // 648 staged voxels
+constexpr int kOutPitch = 20;                        // floats per voxel in the output staging
+constexpr int kStageRegs = (kHalo * 2 + 255) / 256;  // 16-byte words a thread stages
 
-__global__ __launch_bounds__(256) void conv16_lds(const uint16_t* __restrict__ in,
+// tile t of the volume -> its first output voxel (x0, y0, z0)
+__device__ inline void tile_origin(int t, int N, int& x0, int& y0, int& z0)
+{
+    const int ntx = N / kTX, nty = N / kTY;
+    x0 = (t % ntx) * kTX;
+    y0 = ((t / ntx) % nty) * kTY;
+    z0 = (t / (ntx * nty)) * kTZ;
+}
+
+// the input words of the halo around the tile at (x0, y0, z0): word e (voxel
+// e / 2, channels (e & 1) * 8 ...) for e = threadIdx.x + 256 q
+__device__ inline void load_halo(const uint16_t* __restrict__ in, int x0, int y0, int z0, int N,
+                                 uint4 (&v)[kStageRegs])
+{
+#pragma unroll
+    for (int q = 0; q < kStageRegs; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        v[q] = make_uint4(0, 0, 0, 0);
+        if (e < kHalo * 2) {
+            const int h = e >> 1;
+            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
+                v[q] = *reinterpret_cast<const uint4*>(in + ((long(gz) * N + gy) * N + gx) * kC +
+                                                       (e & 1) * 8);
+        }
+    }
+}
+
+// voxel h: tile[h] channels 0-7, tile[kHalo + h] channels 8-15
+__device__ inline void store_halo(uint4* tile, const uint4 (&v)[kStageRegs])
+{
+#pragma unroll
+    for (int q = 0; q < kStageRegs; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < kHalo * 2) tile[(e & 1) * kHalo + (e >> 1)] = v[q];
+    }
+}
+
+// Stage the halo of the tile at (x0, y0, z0) in LDS.  No barrier.
+__device__ inline void stage_tile16(const uint16_t* __restrict__ in, uint4* tile, int x0, int y0,
+                                    int z0, int N)
+{
+    uint4 v[kStageRegs];
+    load_halo(in, x0, y0, z0, N, v);
+    store_halo(tile, v);
+}
+
+// halo index of output voxel (lx, ly, lz) of a tile shifted by tap t
+__device__ inline int halo_of(int lx, int ly, int lz, int t)
+{
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    return ((lz + 1 + dz) * kHY + (ly + 1 + dy)) * kHX + (lx + 1 + dx);
+}
+
+// 16 -> 16 layer: each block walks the tiles blockIdx.x, + gridDim.x, ...;
+// the next tile's halo is loaded into registers while the current one is
+// computed.  Wave w takes z-slice w of a tile: for each tap pair p it reads
+// the A fragments of its 4 rows (16 voxels each) from LDS and issues 4
+// independent MFMAs, with the 14 packed B fragments held in registers.  The
+// results go back through LDS (a lane holds one channel of 4 voxels), so
+// that each thread writes the 16 channels of one voxel as two 16-byte stores.
+__global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict__ in,
                                                   const uint4* __restrict__ wpk,
                                                   uint16_t* __restrict__ out,
                                                   const uint16_t* __restrict__ mask, int relu,
                                                   int N)
 {
-    __shared__ uint4 tile[kHalo * 2];   // voxel h: tile[2h] channels 0-7, tile[2h+1] 8-15
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
-    for (int e = threadIdx.x; e < kHalo * 2; e += blockDim.x) {
-        const int h = e >> 1;
-        const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
-            v = *reinterpret_cast<const uint4*>(in + ((long(gz) * N + gy) * N + gx) * kC +
-                                                (e & 1) * 8);
-        tile[e] = v;
-    }
+    __shared__ uint4 tile[kHalo * 2];
+    static_assert(kTX * kTY * kTZ * kOutPitch * 4 <= int(sizeof(uint4)) * kHalo * 2,
+                  "output staging must fit in the input tile");
+    const int ntiles = (N / kTX) * (N / kTY) * (N / kTZ);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
     const int half = kq & 1, tsel = kq >> 1;
     uint4 b[kPairs];
 #pragma unroll
     for (int p = 0; p < kPairs; ++p) b[p] = wpk[p * 64 + lane];
-    __syncthreads();
-    f32x4 acc[kTY];
-#pragma unroll
-    for (int r = 0; r < kTY; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int p = 0; p < kPairs; ++p) {
-        const int t = 2 * p + tsel;
-        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-        // voxel (m, row r, slice wave) shifted by the tap, in halo coordinates
-        const int h0 = ((wave + 1 + dz) * kHY + (1 + dy)) * kHX + (m + 1 + dx);
-#pragma unroll
-        for (int r = 0; r < kTY; ++r) {
-            uint4 a = make_uint4(0, 0, 0, 0);
-            if (t < kTaps) a = tile[(h0 + r * kHX) * 2 + half];
-            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                            __builtin_bit_cast(bf16x8, b[p]),
-                                                            acc[r], 0, 0, 0);
+    uint4 pre[kStageRegs];
+    int t = blockIdx.x;
+    if (t >= ntiles) return;
+    int x0, y0, z0;
+    tile_origin(t, N, x0, y0, z0);
+    load_halo(in, x0, y0, z0, N, pre);
+    for (; t < ntiles; t += gridDim.x) {
+        __syncthreads();   // the previous tile's output staging has been read
+        store_halo(tile, pre);
+        __syncthreads();
+        const int cx = x0, cy = y0, cz = z0;
+        if (t + int(gridDim.x) < ntiles) {
+            tile_origin(t + gridDim.x, N, x0, y0, z0);
+            load_halo(in, x0, y0, z0, N, pre);
         }
-    }
-    // lane holds rows (voxels) 4*kq + j of each 16-voxel row, column (channel) m
+        f32x4 acc[kTY];
 #pragma unroll
-    for (int r = 0; r < kTY; ++r) {
-        const long v0 = (long(z0 + wave) * N + (y0 + r)) * N + x0;
+        for (int r = 0; r < kTY; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const uint4* plane = tile + half * kHalo;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long vv = v0 + 4 * kq + j;
-            float val = acc[r][j];
-            if (relu) val = fmaxf(val, 0.0f);
-            if (mask && !(bf2f(mask[vv * kC + m]) > 0.0f)) val = 0.0f;
-            out[vv * kC + m] = f2bf(val);
+        for (int p = 0; p < kPairs; ++p) {
+            const int tap = 2 * p + tsel;
+            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+            // voxel (m, row r, slice wave) shifted by the tap, in halo coordinates
+            const int h0 = ((wave + 1 + dz) * kHY + (1 + dy)) * kHX + (m + 1 + dx);
+#pragma unroll
+            for (int r = 0; r < kTY; ++r) {
+                uint4 a = make_uint4(0, 0, 0, 0);
+                if (tap < kTaps) a = plane[h0 + r * kHX];
+                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                __builtin_bit_cast(bf16x8, b[p]),
+                                                                acc[r], 0, 0, 0);
+            }
         }
+        // lane holds rows (voxels) 4*kq + j of each 16-voxel row, column (channel) m
+        __syncthreads();
+        float* stage = reinterpret_cast<float*>(tile);
+#pragma unroll
+        for (int r = 0; r < kTY; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int lv = (wave * kTY + r) * kTX + 4 * kq + j;
+                stage[lv * kOutPitch + m] = relu ? fmaxf(acc[r][j], 0.0f) : acc[r][j];
+            }
+        __syncthreads();
+        const int lv = threadIdx.x;   // 256 threads, 256 voxels
+        const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
+        const long vv = (long(cz + lz) * N + (cy + ly)) * N + cx + lx;
+        float o[kC];
+        const float4* s4 = reinterpret_cast<const float4*>(stage + lv * kOutPitch);
+#pragma unroll
+        for (int q = 0; q < kC / 4; ++q) {
+            const float4 w = s4[q];
+            o[4 * q] = w.x;
+            o[4 * q + 1] = w.y;
+            o[4 * q + 2] = w.z;
+            o[4 * q + 3] = w.w;
+        }
+        if (mask) {
+            float mv[kC];
+            load16(mask + vv * kC, mv);
+#pragma unroll
+            for (int c = 0; c < kC; ++c)
+                if (!(mv[c] > 0.0f)) o[c] = 0.0f;
+        }
+        store16(out + vv * kC, o);
     }
 }
 
-// one block per output tile (N is a multiple of 16, so tiles are whole)
+// one block per output tile (the VALU layers)
 inline dim3 conv16_grid(int N) { return dim3(N / kTX, N / kTY, N / kTZ); }
 
 // ---------------------------------------------------------------------------
 // 1 -> 16 layer (VALU), ReLU, BF16 out.  w: [co][t] BF16-valued floats.
+// One block per 16 x 4 x 4 output tile (grid conv16_grid); the input's
+// 18 x 6 x 6 halo (zero outside the volume) is staged in LDS as floats, and
+// each thread forms the 16 channels of one voxel, taps in order.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_in1(const uint16_t* __restrict__ in,
                                                const float* __restrict__ w,
                                                uint16_t* __restrict__ out, int N)
 {
     __shared__ float sw[kC * kTaps];
+    __shared__ float t1[kHalo];
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
     for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    for (int h = threadIdx.x; h < kHalo; h += blockDim.x) {
+        const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+        float v = 0.0f;
+        if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
+            v = bf2f(in[(long(gz) * N + gy) * N + gx]);
+        t1[h] = v;
+    }
     __syncthreads();
-    const long n = long(N) * N * N;
-    const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const int x = int(r % N), y = int((r / N) % N), z = int(r / (long(N) * N));
+    const int lv = threadIdx.x;
+    const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
     float nb[kTaps];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-        long u;
-        nb[t] = neighbour(N, x, y, z, t, r, u) ? bf2f(in[u]) : 0.0f;
-    }
+    for (int t = 0; t < kTaps; ++t) nb[t] = t1[halo_of(lx, ly, lz, t)];
     float o[kC];
 #pragma unroll
     for (int co = 0; co < kC; ++co) {
-        float s = 0.0f;
+        float acc = 0.0f;
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) s += sw[co * kTaps + t] * nb[t];
-        o[co] = fmaxf(s, 0.0f);
+        for (int t = 0; t < kTaps; ++t) acc += sw[co * kTaps + t] * nb[t];
+        o[co] = fmaxf(acc, 0.0f);
     }
+    const long r = (long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx;
     store16(out + r * kC, o);
 }
 
 // ---------------------------------------------------------------------------
 // 16 -> 1 layer (VALU), FP32 out.  w: [ci][t] BF16-valued floats.
+// One block per output tile (grid conv16_grid) over the LDS-staged input
+// tile of the 16 -> 16 layers; each thread sums one voxel, taps in order and
+// channels in order within a tap (taps outside the volume add exact zeros).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_out1(const uint16_t* __restrict__ in,
                                                 const float* __restrict__ w,
                                                 float* __restrict__ out, int N)
 {
     __shared__ float sw[kC * kTaps];
+    __shared__ uint4 tile[kHalo * 2];
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
     for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    stage_tile16(in, tile, x0, y0, z0, N);
     __syncthreads();
-    const long n = long(N) * N * N;
-    const long r = long(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const int x = int(r % N), y = int((r / N) % N), z = int(r / (long(N) * N));
-    float s = 0.0f;
-    for (int t = 0; t < kTaps; ++t) {
-        long u;
-        if (!neighbour(N, x, y, z, t, r, u)) continue;
-        float hv[kC];
-        load16(in + u * kC, hv);
+    const int lv = threadIdx.x;
+    const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
+    float acc = 0.0f;
 #pragma unroll
-        for (int ci = 0; ci < kC; ++ci) s += sw[ci * kTaps + t] * hv[ci];
+    for (int t = 0; t < kTaps; ++t) {
+        const int h = halo_of(lx, ly, lz, t);
+        const uint4 lo = tile[h], hi = tile[kHalo + h];
+        const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            acc += sw[(2 * k) * kTaps + t] * bf_lo(wd[k]);
+            acc += sw[(2 * k + 1) * kTaps + t] * bf_hi(wd[k]);
+        }
     }
-    out[r] = s;
+    out[(long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx] = acc;
 }
 
 // input gradient of the 16 -> 1 layer: g[r, ci] = sum_t w[ci][t] dy[r - off(t)],
@@ -499,15 +606,57 @@ __global__ void pack_weights(const float* __restrict__ w, float* __restrict__ w1
 // ---------------------------------------------------------------------------
 // data preparation / warm start
 // ---------------------------------------------------------------------------
-// column j of an interleaved n x m FP64 block -> BF16 volume scaled by 1/s
-// (a zero column gives a zero volume)
-__global__ void col_to_bf16(const double* __restrict__ B, int m, int j, long n,
-                            const double* __restrict__ s, uint16_t* __restrict__ out)
+// All m columns at once through an LDS tile of kTRows rows x m columns, so
+// that both the interleaved block and the volumes are accessed contiguously.
+constexpr int kTRows = 64;
+
+// vol[j n + r] = BF16(B[r m + j] / s_j) (zero for a zero column)
+__global__ __launch_bounds__(256) void cols_to_bf16(const double* __restrict__ B, int m, long n,
+                                                    const double* __restrict__ s,
+                                                    uint16_t* __restrict__ vol)
 {
-    const float inv = s[j] > 0.0 ? float(1.0 / s[j]) : 0.0f;
-    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
-         r += long(gridDim.x) * blockDim.x)
-        out[r] = f2bf(float(B[r * m + j]) * inv);
+    __shared__ float inv[XAMG_MAX_M];
+    __shared__ uint16_t tb[kTRows * (XAMG_MAX_M + 1)];
+    if (int(threadIdx.x) < m)
+        inv[threadIdx.x] = s[threadIdx.x] > 0.0 ? float(1.0 / s[threadIdx.x]) : 0.0f;
+    __syncthreads();
+    for (long r0 = long(blockIdx.x) * kTRows; r0 < n; r0 += long(gridDim.x) * kTRows) {
+        const int rows = int(n - r0 < kTRows ? n - r0 : kTRows);
+        for (int f = threadIdx.x; f < rows * m; f += blockDim.x) {
+            const int i = f / m, j = f % m;
+            tb[i * (m + 1) + j] = f2bf(float(B[r0 * m + f]) * inv[j]);
+        }
+        __syncthreads();
+        for (int f = threadIdx.x; f < rows * m; f += blockDim.x) {
+            const int j = f / rows, i = f % rows;
+            vol[size_t(j) * n + r0 + i] = tb[i * (m + 1) + j];
+        }
+        __syncthreads();
+    }
+}
+
+// X0[r m + j] = s_j y_j[r] (zero for a zero column)
+__global__ __launch_bounds__(256) void vols_to_cols(const float* __restrict__ y, int m, long n,
+                                                    const double* __restrict__ s,
+                                                    double* __restrict__ X0)
+{
+    __shared__ double sc[XAMG_MAX_M];
+    __shared__ float tb[kTRows * (XAMG_MAX_M + 1)];
+    if (int(threadIdx.x) < m) sc[threadIdx.x] = s[threadIdx.x];
+    __syncthreads();
+    for (long r0 = long(blockIdx.x) * kTRows; r0 < n; r0 += long(gridDim.x) * kTRows) {
+        const int rows = int(n - r0 < kTRows ? n - r0 : kTRows);
+        for (int f = threadIdx.x; f < rows * m; f += blockDim.x) {
+            const int j = f / rows, i = f % rows;
+            tb[i * (m + 1) + j] = y[size_t(j) * n + r0 + i];
+        }
+        __syncthreads();
+        for (int f = threadIdx.x; f < rows * m; f += blockDim.x) {
+            const int i = f / m, j = f % m;
+            X0[r0 * m + f] = sc[j] > 0.0 ? sc[j] * double(tb[i * (m + 1) + j]) : 0.0;
+        }
+        __syncthreads();
+    }
 }
 
 __global__ void f32_to_bf16(const float* __restrict__ x, long n, uint16_t* __restrict__ out)
@@ -517,25 +666,18 @@ __global__ void f32_to_bf16(const float* __restrict__ x, long n, uint16_t* __res
         out[r] = f2bf(x[r]);
 }
 
-// X0[:, j] = s_j * y
-__global__ void y_to_col(const float* __restrict__ y, int m, int j, long n,
-                         const double* __restrict__ s, double* __restrict__ X0)
-{
-    const double sc = s[j];
-    for (long r = long(blockIdx.x) * blockDim.x + threadIdx.x; r < n;
-         r += long(gridDim.x) * blockDim.x)
-        X0[r * m + j] = sc > 0.0 ? sc * double(y[r]) : 0.0;
-}
-
 // Per-column sums of squares over a contiguous row range per block:
 // part[(block * m + j) * 2] = sum b_rj^2 and, with a matrix, part[... + 1] =
 // sum (b - A x)_rj^2.  Thread t < g m (g = 256 / m) takes column t % m and
 // rows q, q + g, ... of the range (q = t / m), so loads stay contiguous.
+// With rows stored at one length (rowlen > 0: row r's entries at r rowlen,
+// padded with exact zeros) four rows are taken at a time with their loads
+// interleaved; every sum keeps the same terms in the same order.
 __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
                                              const double* __restrict__ X,
                                              const int* __restrict__ rp, const int* __restrict__ ci,
                                              const double* __restrict__ v, int m, long n,
-                                             double* __restrict__ part)
+                                             double* __restrict__ part, int rowlen)
 {
     __shared__ double s0[256], s1[256];
     const int t = threadIdx.x, g = 256 / m;
@@ -543,7 +685,33 @@ __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
     const long per = (n + gridDim.x - 1) / gridDim.x;
     const long r0 = long(blockIdx.x) * per, r1 = std::min(n, r0 + per);
     double bb = 0.0, rr = 0.0;
-    if (q < g) {
+    if (q < g && rp && rowlen > 0) {
+        for (long r = r0 + q; r < r1; r += 4L * g) {
+            double bv[4], sv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const long ru = r + long(u) * g;
+                bv[u] = ru < r1 ? B[ru * m + j] : 0.0;
+                sv[u] = bv[u];
+            }
+            for (int k = 0; k < rowlen; ++k) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const long ru = r + long(u) * g;
+                    if (ru < r1) {
+                        const long e = ru * rowlen + k;
+                        sv[u] -= v[e] * X[long(ci[e]) * m + j];
+                    }
+                }
+            }
+            // rows past the range add exact zeros
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bb += bv[u] * bv[u];
+                rr += sv[u] * sv[u];
+            }
+        }
+    } else if (q < g) {
         for (long r = r0 + q; r < r1; r += g) {
             const double b = B[r * m + j];
             bb += b * b;
@@ -568,21 +736,36 @@ __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
     }
 }
 
-// sums[2j + k] = sum over blocks (in block order) of part[(b m + j) 2 + k];
-// with scales, s_j = sqrt(sums[2j] / n)
-__global__ void col_sq_finish(const double* __restrict__ part, int nb, int m, long n,
-                              double* __restrict__ sums, double* __restrict__ scales)
+// sums[2j + k] = the sum over blocks of part[(b m + j) 2 + k], one block per
+// column: thread t adds blocks t, t + 256, ... in order, then a fixed halving
+// tree over the 256 threads (the same order every run); with scales,
+// s_j = sqrt(sums[2j] / n)
+__global__ __launch_bounds__(256) void col_sq_finish(const double* __restrict__ part, int nb, int m,
+                                                     long n, double* __restrict__ sums,
+                                                     double* __restrict__ scales)
 {
-    const int j = threadIdx.x;
-    if (j >= m) return;
+    __shared__ double s0[256], s1[256];
+    const int j = blockIdx.x, t = threadIdx.x;
     double a = 0.0, c = 0.0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = t; b < nb; b += 256) {
         a += part[(size_t(b) * m + j) * 2];
         c += part[(size_t(b) * m + j) * 2 + 1];
     }
-    sums[2 * j] = a;
-    sums[2 * j + 1] = c;
-    if (scales) scales[j] = sqrt(a / double(n));
+    s0[t] = a;
+    s1[t] = c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            s0[t] += s0[t + w];
+            s1[t] += s1[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        sums[2 * j] = s0[0];
+        sums[2 * j + 1] = s1[0];
+        if (scales) scales[j] = sqrt(s0[0] / double(n));
+    }
 }
 
 __global__ void zero_col(double* __restrict__ X0, int m, int j, long n)
@@ -610,6 +793,7 @@ struct Net : xamg_cnn {
     double *lpart = nullptr, *lacc = nullptr, *scales = nullptr, *sums = nullptr;
     double* cpart = nullptr;   // col_sq partials
     int64_t adam_t = 0;
+    int conv_blocks = 1;   // resident blocks of conv16_lds (at most one per tile)
     // kernel timer (measurement only): event pairs around the selected launches
     int timer_kind = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -678,26 +862,55 @@ struct Net : xamg_cnn {
         hipLaunchKernelGGL(pack_weights, dim3(grid(total)), dim3(256), 0, stream, w, w1b, w4b, pk);
     }
 
-    // forward of one normalised sample already in a0; y = f(a0)
-    void forward()
+    // forward of one normalised sample: yout = f(ain) (a1..a3 hold the activations)
+    void forward(const uint16_t* ain, float* yout)
     {
-        hipLaunchKernelGGL(conv_in1, dim3(grid(n)), dim3(256), 0, stream, a0, w1b, a1, N);
         const dim3 g16 = conv16_grid(N);
+        hipLaunchKernelGGL(conv_in1, g16, dim3(256), 0, stream, ain, w1b, a1, N);
         tbegin(XAMG_CNN_TIMER_CONV16);
-        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, a1, pack(0), a2,
+        hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, a1, pack(0), a2,
                            static_cast<const uint16_t*>(nullptr), 1, N);
         tend(XAMG_CNN_TIMER_CONV16);
         tbegin(XAMG_CNN_TIMER_CONV16);
-        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, a2, pack(2), a3,
+        hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, a2, pack(2), a3,
                            static_cast<const uint16_t*>(nullptr), 1, N);
         tend(XAMG_CNN_TIMER_CONV16);
-        hipLaunchKernelGGL(conv_out1, dim3(grid(n)), dim3(256), 0, stream, a3, w4b, y, N);
+        hipLaunchKernelGGL(conv_out1, g16, dim3(256), 0, stream, a3, w4b, yout, N);
+    }
+    void forward() { forward(a0, y); }
+
+    // per-column volumes of the warm start (m BF16 inputs, m FP32 outputs),
+    // grown on demand
+    uint16_t* cols_in = nullptr;
+    float* cols_out = nullptr;
+    int cols_cap = 0;
+    void release(void* p)
+    {
+        if (!p) return;
+        for (size_t k = 0; k < allocs.size(); ++k)
+            if (allocs[k] == p) {
+                allocs.erase(allocs.begin() + long(k));
+                break;
+            }
+        hipFree(p);
+    }
+    void ensure_cols(int m)
+    {
+        if (m <= cols_cap) return;
+        chk(hipStreamSynchronize(stream), "sync");
+        release(cols_in);
+        release(cols_out);
+        cols_in = nullptr;
+        cols_out = nullptr;
+        cols_cap = 0;
+        cols_in = alloc<uint16_t>(size_t(m) * n);
+        cols_out = alloc<float>(size_t(m) * n);
+        cols_cap = m;
     }
 
     // backward of one sample (dy set); weight gradients accumulate into g
     void backward()
     {
-        const dim3 g16 = conv16_grid(N);
         const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         // layer 4: dW4 and g3 = W4^T dy masked by a3 > 0
         hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, stream,
@@ -712,7 +925,7 @@ struct Net : xamg_cnn {
         tend(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
                            kParams2, g + kParams1 + kParams2);
-        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
+        hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
         // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g2,
@@ -720,7 +933,7 @@ struct Net : xamg_cnn {
         tend(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
                            kParams2, g + kParams1);
-        hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
+        hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
         // layer 1: dW1 from (g1, a0)
         hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, stream, g1,
                            static_cast<const float*>(nullptr), a0, N, wpart);
@@ -773,6 +986,15 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
         net->scales = net->alloc<double>(64);
         net->sums = net->alloc<double>(2 * 64);
         net->cpart = net->alloc<double>(size_t(kColBlocks) * 2 * 64);
+        {
+            int dev = 0, cus = 0, per_cu = 0;
+            net->chk(hipGetDevice(&dev), "hipGetDevice");
+            net->chk(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CUs");
+            net->chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv16_lds, 256, 0),
+                     "occupancy");
+            net->conv_blocks = int(std::min<long>(n / (kTX * kTY * kTZ),
+                                                  long(std::max(1, per_cu)) * std::max(1, cus)));
+        }
         net->chk(hipMemcpy(net->w, w_init, kParams * sizeof(float), hipMemcpyHostToDevice), "weights");
         std::vector<float> zero(kParams, 0.0f);
         net->chk(hipMemcpy(net->mo, zero.data(), kParams * sizeof(float), hipMemcpyHostToDevice), "adam");
@@ -962,6 +1184,9 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
     Net* net = static_cast<Net*>(h);
     if (!net || !in || !out || layer < 1 || layer > 4 || mode < 0 || mode > 2)
         return xamg::fail(XAMG_EINVAL, "bad arguments");
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(mask) |
+         reinterpret_cast<uintptr_t>(out)) & 15)
+        return xamg::fail(XAMG_EINVAL, "in, mask and out must be 16-byte aligned");
     try {
         const long n = net->n;
         const int N = net->N;
@@ -971,13 +1196,13 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
         const uint16_t* m16 = static_cast<const uint16_t*>(mask);
         if (mode == 0) {
             if (layer == 1)
-                hipLaunchKernelGGL(conv_in1, dim3(net->grid(n)), dim3(256), 0, net->stream, i16,
-                                   net->w1b, static_cast<uint16_t*>(out), N);
+                hipLaunchKernelGGL(conv_in1, g16, dim3(256), 0, net->stream, i16, net->w1b,
+                                   static_cast<uint16_t*>(out), N);
             else if (layer == 4)
-                hipLaunchKernelGGL(conv_out1, dim3(net->grid(n)), dim3(256), 0, net->stream, i16,
-                                   net->w4b, static_cast<float*>(out), N);
+                hipLaunchKernelGGL(conv_out1, g16, dim3(256), 0, net->stream, i16, net->w4b,
+                                   static_cast<float*>(out), N);
             else
-                hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, net->stream, i16,
+                hipLaunchKernelGGL(conv16_lds, dim3(net->conv_blocks), dim3(256), 0, net->stream, i16,
                                    net->pack(layer == 2 ? 0 : 2), static_cast<uint16_t*>(out),
                                    static_cast<const uint16_t*>(nullptr), 1, N);
         } else if (mode == 1) {
@@ -988,7 +1213,7 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
                                    static_cast<const float*>(in), net->w4b, m16,
                                    static_cast<uint16_t*>(out), N);
             else
-                hipLaunchKernelGGL(conv16_lds, g16, dim3(256), 0, net->stream, i16,
+                hipLaunchKernelGGL(conv16_lds, dim3(net->conv_blocks), dim3(256), 0, net->stream, i16,
                                    net->pack(layer == 2 ? 1 : 3), static_cast<uint16_t*>(out), m16,
                                    0, N);
         } else {
@@ -1041,23 +1266,24 @@ int xamg_warmstart(xamg_cnn_t* h, xamg_handle_t* solver, const double* B, double
         hipLaunchKernelGGL(col_sq, dim3(nbc), dim3(256), 0, net->stream, B,
                            static_cast<const double*>(nullptr), static_cast<const int*>(nullptr),
                            static_cast<const int*>(nullptr), static_cast<const double*>(nullptr),
-                           m, n, net->cpart);
-        hipLaunchKernelGGL(col_sq_finish, dim3(1), dim3(64), 0, net->stream, net->cpart, nbc, m, n,
+                           m, n, net->cpart, 0);
+        hipLaunchKernelGGL(col_sq_finish, dim3(m), dim3(256), 0, net->stream, net->cpart, nbc, m, n,
                            net->sums, net->scales);
-        for (int j = 0; j < m; ++j) {
-            hipLaunchKernelGGL(col_to_bf16, dim3(1024), dim3(256), 0, net->stream, B, m, j, n,
-                               net->scales, net->a0);
-            net->forward();
-            hipLaunchKernelGGL(y_to_col, dim3(1024), dim3(256), 0, net->stream, net->y, m, j, n,
-                               net->scales, X0);
-        }
+        net->ensure_cols(m);
+        const int nbr = int(std::min<long>(4096, (n + kTRows - 1) / kTRows));
+        hipLaunchKernelGGL(cols_to_bf16, dim3(nbr), dim3(256), 0, net->stream, B, m, n,
+                           net->scales, net->cols_in);
+        for (int j = 0; j < m; ++j)
+            net->forward(net->cols_in + size_t(j) * n, net->cols_out + size_t(j) * n);
+        hipLaunchKernelGGL(vols_to_cols, dim3(nbr), dim3(256), 0, net->stream, net->cols_out, m, n,
+                           net->scales, X0);
         net->chk(hipGetLastError(), "warm start");
         if (solver) {
             // fallback: ||b_j - A x0_j|| >= ||b_j||  =>  x0_j = 0
             const xamg::DCsr& A = static_cast<xamg::Handle*>(solver)->lev[0].A64;
             hipLaunchKernelGGL(col_sq, dim3(nbc), dim3(256), 0, net->stream, B, X0, A.rp, A.ci,
-                               static_cast<const double*>(A.v), m, n, net->cpart);
-            hipLaunchKernelGGL(col_sq_finish, dim3(1), dim3(64), 0, net->stream, net->cpart, nbc, m,
+                               static_cast<const double*>(A.v), m, n, net->cpart, A.rowlen);
+            hipLaunchKernelGGL(col_sq_finish, dim3(m), dim3(256), 0, net->stream, net->cpart, nbc, m,
                                n, net->sums, static_cast<double*>(nullptr));
             double sums[2 * 64];
             net->chk(hipMemcpyAsync(sums, net->sums, 2 * m * sizeof(double), hipMemcpyDeviceToHost,

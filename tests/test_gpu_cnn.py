@@ -352,4 +352,7 @@ def test_cnn_argument_errors(torch, xm):
         net.layer(1, 1, x, x, x)          # no input gradient for layer 1
     with pytest.raises(xm.XamgError):
         net.layer(5, 0, x, None, x)
+    xs = torch.zeros(16 ** 3 * 16 + 8, dtype=torch.bfloat16, device="cuda")[1:]
+    with pytest.raises(xm.XamgError):
+        net.layer(2, 0, xs, None, xs)     # 2-byte offset: not 16-byte aligned
     net.close()
