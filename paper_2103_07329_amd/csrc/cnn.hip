@@ -272,43 +272,57 @@ __global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict_
     }
 }
 
-// one block per output tile (the VALU layers)
-inline dim3 conv16_grid(int N) { return dim3(N / kTX, N / kTY, N / kTZ); }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// a.lo * b.lo + a.hi * b.hi + c (BF16 pairs, FP32 sum)
+__device__ inline float dot2(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a),
+                                           __builtin_bit_cast(bf16x2, b), c, false);
+}
 
 // ---------------------------------------------------------------------------
-// 1 -> 16 layer (VALU), ReLU, BF16 out.  w: [co][t] BF16-valued floats.
-// One block per 16 x 4 x 4 output tile (grid conv16_grid); the input's
-// 18 x 6 x 6 halo (zero outside the volume) is staged in LDS as floats, and
-// each thread forms the 16 channels of one voxel, taps in order.
+// 1 -> 16 layer (VALU), ReLU, BF16 out.  w1p: [co][tap pair] BF16 pairs.
+// One block per 16 x 4 x 4 output tile (grid conv_tile_grid); the input's
+// 18 x 6 x 6 halo (zero outside the volume) is staged in LDS, and each
+// thread forms the 16 channels of one voxel from 14 tap pairs, each a
+// two-term BF16 dot product accumulated in FP32, pairs in tap order.
+// (Walking several tiles per block with the next halo prefetched measured
+// no faster: the layer is bound by its dot products and LDS reads.)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_in1(const uint16_t* __restrict__ in,
-                                               const float* __restrict__ w,
+                                               const uint32_t* __restrict__ w1p,
                                                uint16_t* __restrict__ out, int N)
 {
-    __shared__ float sw[kC * kTaps];
-    __shared__ float t1[kHalo];
+    __shared__ uint32_t sw[kC * kPairs];
+    __shared__ uint16_t t1[kHalo];
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
-    for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    for (int e = threadIdx.x; e < kC * kPairs; e += blockDim.x) sw[e] = w1p[e];
     for (int h = threadIdx.x; h < kHalo; h += blockDim.x) {
         const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
         const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-        float v = 0.0f;
+        uint16_t v = 0;
         if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
-            v = bf2f(in[(long(gz) * N + gy) * N + gx]);
+            v = in[(long(gz) * N + gy) * N + gx];
         t1[h] = v;
     }
     __syncthreads();
     const int lv = threadIdx.x;
     const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
-    float nb[kTaps];
+    uint32_t nb[kPairs];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) nb[t] = t1[halo_of(lx, ly, lz, t)];
+    for (int q = 0; q < kPairs; ++q) {
+        const uint32_t lo = t1[halo_of(lx, ly, lz, 2 * q)];
+        const uint32_t hi = 2 * q + 1 < kTaps ? uint32_t(t1[halo_of(lx, ly, lz, 2 * q + 1)]) : 0u;
+        nb[q] = lo | (hi << 16);
+    }
     float o[kC];
 #pragma unroll
     for (int co = 0; co < kC; ++co) {
         float acc = 0.0f;
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) acc += sw[co * kTaps + t] * nb[t];
+        for (int q = 0; q < kPairs; ++q) acc = dot2(nb[q], sw[co * kPairs + q], acc);
         o[co] = fmaxf(acc, 0.0f);
     }
     const long r = (long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx;
@@ -316,19 +330,21 @@ __global__ __launch_bounds__(256) void conv_in1(const uint16_t* __restrict__ in,
 }
 
 // ---------------------------------------------------------------------------
-// 16 -> 1 layer (VALU), FP32 out.  w: [ci][t] BF16-valued floats.
-// One block per output tile (grid conv16_grid) over the LDS-staged input
-// tile of the 16 -> 16 layers; each thread sums one voxel, taps in order and
-// channels in order within a tap (taps outside the volume add exact zeros).
+// 16 -> 1 layer (VALU), FP32 out.  w4p: [t][channel pair] BF16 pairs.
+// One block per output tile (grid conv_tile_grid) over the LDS-staged input
+// halo of the 16 -> 16 layers; each thread sums one voxel, taps in order and
+// channel pairs in order within a tap, each pair a two-term BF16 dot product
+// accumulated in FP32 (taps outside the volume add exact zeros).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void conv_out1(const uint16_t* __restrict__ in,
-                                                const float* __restrict__ w,
+                                                const uint32_t* __restrict__ w4p,
                                                 float* __restrict__ out, int N)
 {
-    __shared__ float sw[kC * kTaps];
+    __shared__ uint4 sw[kTaps * 2];
     __shared__ uint4 tile[kHalo * 2];
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
-    for (int e = threadIdx.x; e < kC * kTaps; e += blockDim.x) sw[e] = w[e];
+    for (int e = threadIdx.x; e < kTaps * 2; e += blockDim.x)
+        sw[e] = reinterpret_cast<const uint4*>(w4p)[e];
     stage_tile16(in, tile, x0, y0, z0, N);
     __syncthreads();
     const int lv = threadIdx.x;
@@ -338,15 +354,21 @@ __global__ __launch_bounds__(256) void conv_out1(const uint16_t* __restrict__ in
     for (int t = 0; t < kTaps; ++t) {
         const int h = halo_of(lx, ly, lz, t);
         const uint4 lo = tile[h], hi = tile[kHalo + h];
-        const uint32_t wd[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            acc += sw[(2 * k) * kTaps + t] * bf_lo(wd[k]);
-            acc += sw[(2 * k + 1) * kTaps + t] * bf_hi(wd[k]);
-        }
+        const uint4 wl = sw[2 * t], wh = sw[2 * t + 1];
+        acc = dot2(lo.x, wl.x, acc);
+        acc = dot2(lo.y, wl.y, acc);
+        acc = dot2(lo.z, wl.z, acc);
+        acc = dot2(lo.w, wl.w, acc);
+        acc = dot2(hi.x, wh.x, acc);
+        acc = dot2(hi.y, wh.y, acc);
+        acc = dot2(hi.z, wh.z, acc);
+        acc = dot2(hi.w, wh.w, acc);
     }
     out[(long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx] = acc;
 }
+
+// one block per output tile (the VALU layers; N is a multiple of 16)
+inline dim3 conv_tile_grid(int N) { return dim3(N / kTX, N / kTY, N / kTZ); }
 
 // input gradient of the 16 -> 1 layer: g[r, ci] = sum_t w[ci][t] dy[r - off(t)],
 // times (act[r, ci] > 0), BF16 out
@@ -575,15 +597,29 @@ __global__ void adam_step(float* __restrict__ w, const float* __restrict__ g, fl
 
 // Layer offsets in the flat master array: W1 [16][1][27], W2, W3 [16][16][27],
 // W4 [1][16][27].
-__global__ void pack_weights(const float* __restrict__ w, float* __restrict__ w1b,
-                             float* __restrict__ w4b, uint16_t* __restrict__ pk)
+// w1p[co * kPairs + q]: BF16 W1[co][2q] (low half) and W1[co][2q + 1] (high
+// half, zero for q = 13); w4p[t * 8 + k]: BF16 W4[2k][t] and W4[2k + 1][t]
+__global__ void pack_weights(const float* __restrict__ w, float* __restrict__ w4b,
+                             uint16_t* __restrict__ pk,
+                             uint32_t* __restrict__ w1p, uint32_t* __restrict__ w4p)
 {
     // pk: 4 packs of kPairs*64*8 BF16: [W2 fwd, W2 dgrad, W3 fwd, W3 dgrad]
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < kParams1) w1b[e] = bf2f(f2bf(w[e]));   // [co][t]
     if (e < kParams4) {
         // W4 [0][ci][t] -> [ci][t]
         w4b[e] = bf2f(f2bf(w[kParams1 + 2 * kParams2 + e]));
+    }
+    if (e < kC * kPairs) {
+        const int co = e / kPairs, q = e % kPairs;
+        const uint32_t lo = f2bf(w[co * kTaps + 2 * q]);
+        const uint32_t hi = 2 * q + 1 < kTaps ? f2bf(w[co * kTaps + 2 * q + 1]) : 0u;
+        w1p[e] = lo | (hi << 16);
+    }
+    if (e < kTaps * 8) {
+        const int t = e / 8, k = e % 8;
+        const float* W4 = w + kParams1 + 2 * kParams2;   // [ci][t]
+        w4p[e] = uint32_t(f2bf(W4[(2 * k) * kTaps + t])) |
+                 (uint32_t(f2bf(W4[(2 * k + 1) * kTaps + t])) << 16);
     }
     constexpr int per = kPairs * 64 * 8;
     if (e >= 4 * per) return;
@@ -784,7 +820,8 @@ struct Net : xamg_cnn {
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
     float *w = nullptr, *g = nullptr, *mo = nullptr, *ve = nullptr;   // masters, grads, Adam
-    float *w1b = nullptr, *w4b = nullptr;
+    float* w4b = nullptr;
+    uint32_t *w1p = nullptr, *w4p = nullptr;   // BF16 pairs for the dot2 layers
     uint16_t* pk = nullptr;
     uint16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
     uint16_t *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
@@ -859,14 +896,14 @@ struct Net : xamg_cnn {
     void repack()
     {
         const int total = std::max(4 * kPairs * 64 * 8, kParams1);
-        hipLaunchKernelGGL(pack_weights, dim3(grid(total)), dim3(256), 0, stream, w, w1b, w4b, pk);
+        hipLaunchKernelGGL(pack_weights, dim3(grid(total)), dim3(256), 0, stream, w, w4b, pk,
+                           w1p, w4p);
     }
 
     // forward of one normalised sample: yout = f(ain) (a1..a3 hold the activations)
     void forward(const uint16_t* ain, float* yout)
     {
-        const dim3 g16 = conv16_grid(N);
-        hipLaunchKernelGGL(conv_in1, g16, dim3(256), 0, stream, ain, w1b, a1, N);
+        hipLaunchKernelGGL(conv_in1, conv_tile_grid(N), dim3(256), 0, stream, ain, w1p, a1, N);
         tbegin(XAMG_CNN_TIMER_CONV16);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, a1, pack(0), a2,
                            static_cast<const uint16_t*>(nullptr), 1, N);
@@ -875,7 +912,7 @@ struct Net : xamg_cnn {
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, a2, pack(2), a3,
                            static_cast<const uint16_t*>(nullptr), 1, N);
         tend(XAMG_CNN_TIMER_CONV16);
-        hipLaunchKernelGGL(conv_out1, g16, dim3(256), 0, stream, a3, w4b, yout, N);
+        hipLaunchKernelGGL(conv_out1, conv_tile_grid(N), dim3(256), 0, stream, a3, w4p, yout, N);
     }
     void forward() { forward(a0, y); }
 
@@ -892,7 +929,7 @@ struct Net : xamg_cnn {
                 allocs.erase(allocs.begin() + long(k));
                 break;
             }
-        hipFree(p);
+        (void)hipFree(p);
     }
     void ensure_cols(int m)
     {
@@ -967,8 +1004,9 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
         net->g = net->alloc<float>(kParams);
         net->mo = net->alloc<float>(kParams);
         net->ve = net->alloc<float>(kParams);
-        net->w1b = net->alloc<float>(kParams1);
         net->w4b = net->alloc<float>(kParams4);
+        net->w1p = net->alloc<uint32_t>(kC * kPairs);
+        net->w4p = net->alloc<uint32_t>(kTaps * 8);
         net->pk = net->alloc<uint16_t>(4 * kPairs * 64 * 8);
         net->a0 = net->alloc<uint16_t>(n);
         net->a1 = net->alloc<uint16_t>(n * kC);
@@ -990,10 +1028,13 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
             int dev = 0, cus = 0, per_cu = 0;
             net->chk(hipGetDevice(&dev), "hipGetDevice");
             net->chk(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CUs");
-            net->chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, conv16_lds, 256, 0),
-                     "occupancy");
-            net->conv_blocks = int(std::min<long>(n / (kTX * kTY * kTZ),
-                                                  long(std::max(1, per_cu)) * std::max(1, cus)));
+            const long ntiles = n / (kTX * kTY * kTZ);
+            auto resident = [&](const void* fn) {
+                net->chk(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0),
+                         "occupancy");
+                return int(std::min<long>(ntiles, long(std::max(1, per_cu)) * std::max(1, cus)));
+            };
+            net->conv_blocks = resident(reinterpret_cast<const void*>(conv16_lds));
         }
         net->chk(hipMemcpy(net->w, w_init, kParams * sizeof(float), hipMemcpyHostToDevice), "weights");
         std::vector<float> zero(kParams, 0.0f);
@@ -1190,16 +1231,15 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
     try {
         const long n = net->n;
         const int N = net->N;
-        const dim3 g16 = conv16_grid(N);
         const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         const uint16_t* i16 = static_cast<const uint16_t*>(in);
         const uint16_t* m16 = static_cast<const uint16_t*>(mask);
         if (mode == 0) {
             if (layer == 1)
-                hipLaunchKernelGGL(conv_in1, g16, dim3(256), 0, net->stream, i16, net->w1b,
+                hipLaunchKernelGGL(conv_in1, conv_tile_grid(N), dim3(256), 0, net->stream, i16, net->w1p,
                                    static_cast<uint16_t*>(out), N);
             else if (layer == 4)
-                hipLaunchKernelGGL(conv_out1, g16, dim3(256), 0, net->stream, i16, net->w4b,
+                hipLaunchKernelGGL(conv_out1, conv_tile_grid(N), dim3(256), 0, net->stream, i16, net->w4p,
                                    static_cast<float*>(out), N);
             else
                 hipLaunchKernelGGL(conv16_lds, dim3(net->conv_blocks), dim3(256), 0, net->stream, i16,
