@@ -408,7 +408,10 @@ __global__ __launch_bounds__(256) void dgrad_out1(const float* __restrict__ dy,
 // Chunks of kChunk voxels along x (one row); the chunk's g values and the
 // 3 x 3 rows (x - 1 .. x + kChunk) of inputs are staged in LDS as floats.
 // G: gradient channels (COUT), I: input channels (CIN); thread (o, i) with
-// o < COUT, i < CIN accumulates the 27 taps.  gsrc_f32: g given as FP32.
+// o < COUT, i < CIN accumulates the 27 taps.  g32: g given as FP32.  With
+// fewer than 256 (o, i) pairs, R = 256 / (COUT CIN) threads share a pair,
+// thread copy c taking the voxels c, c + R, ... of each chunk; the copies'
+// sums are added in copy order at the end.
 template <int COUT, int CIN>
 __global__ __launch_bounds__(256) void wgrad_lds(const uint16_t* __restrict__ g16,
                                                 const float* __restrict__ g32,
@@ -416,13 +419,18 @@ __global__ __launch_bounds__(256) void wgrad_lds(const uint16_t* __restrict__ g1
                                                 float* __restrict__ part)
 {
     constexpr int W = kChunk + 2;
+    constexpr int P = COUT * CIN;
+    constexpr int R = 256 / P;
+    static_assert(R * P == 256 && kChunk % R == 0, "thread copies must tile the block");
     __shared__ float sg[kChunk * COUT];
     __shared__ float si[9 * W * CIN];
+    __shared__ float red[R > 1 ? R * P * kTaps : 1];
     const long n = long(N) * N * N;
     const long nchunks = n / kChunk;
     const int tid = threadIdx.x;
-    const int o = tid / CIN, i = tid % CIN;
-    const bool own = tid < COUT * CIN;
+    const int copy = tid / P, oi = tid % P;
+    const int o = oi / CIN, i = oi % CIN;
+    const bool own = true;
     float acc[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) acc[t] = 0.0f;
@@ -444,7 +452,7 @@ __global__ __launch_bounds__(256) void wgrad_lds(const uint16_t* __restrict__ g1
         }
         __syncthreads();
         if (own) {
-            for (int k = 0; k < kChunk; ++k) {
+            for (int k = R == 1 ? 0 : copy; k < kChunk; k += R) {
                 const float gv = sg[k * COUT + o];
 #pragma unroll
                 for (int t = 0; t < kTaps; ++t) {
@@ -454,21 +462,45 @@ __global__ __launch_bounds__(256) void wgrad_lds(const uint16_t* __restrict__ g1
             }
         }
     }
-    if (own) {
-        float* dst = part + size_t(blockIdx.x) * (COUT * CIN * kTaps);
+    float* dst = part + size_t(blockIdx.x) * (P * kTaps);
+    if constexpr (R == 1) {
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) dst[(o * CIN + i) * kTaps + t] = acc[t];
+        for (int t = 0; t < kTaps; ++t) dst[oi * kTaps + t] = acc[t];
+    } else {
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) red[(copy * P + oi) * kTaps + t] = acc[t];
+        __syncthreads();
+        for (int e = tid; e < P * kTaps; e += blockDim.x) {
+            float sum = 0.0f;
+            for (int c = 0; c < R; ++c) sum += red[c * P * kTaps + e];
+            dst[e] = sum;
+        }
     }
 }
 
 // sum the partials of nb blocks in block order, add into dst (FP32)
+// dst[e] += sum over b of part[b len + e], in two fixed-order stages: the
+// kRedSegs segments of consecutive partials (blockIdx.y = segment) into
+// seg[s len + e], then the segments in order
+constexpr int kRedSegs = 32;
 __global__ void reduce_parts(const float* __restrict__ part, int nb, int len,
-                             float* __restrict__ dst)
+                             float* __restrict__ seg)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    const int sgi = blockIdx.y;
+    const int b0 = int(long(nb) * sgi / kRedSegs), b1 = int(long(nb) * (sgi + 1) / kRedSegs);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += part[size_t(b) * len + e];
+    seg[size_t(sgi) * len + e] = s;
+}
+
+__global__ void reduce_segs(const float* __restrict__ seg, int len, float* __restrict__ dst)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= len) return;
     float s = 0.0f;
-    for (int b = 0; b < nb; ++b) s += part[size_t(b) * len + e];
+    for (int k = 0; k < kRedSegs; ++k) s += seg[size_t(k) * len + e];
     dst[e] += s;
 }
 
@@ -825,7 +857,7 @@ struct Net : xamg_cnn {
     uint16_t* pk = nullptr;
     uint16_t *a0 = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
     uint16_t *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
-    float *y = nullptr, *dy = nullptr, *wpart = nullptr;
+    float *y = nullptr, *dy = nullptr, *wpart = nullptr, *wseg = nullptr;
     float* rres = nullptr;   // residual of the residual loss
     double *lpart = nullptr, *lacc = nullptr, *scales = nullptr, *sums = nullptr;
     double* cpart = nullptr;   // col_sq partials
@@ -892,6 +924,13 @@ struct Net : xamg_cnn {
         return reinterpret_cast<const uint4*>(pk + size_t(which) * kPairs * 64 * 8);
     }
     int grid(long count, int per = 256) const { return int((count + per - 1) / per); }
+    // dst[0 .. len) += the sum of the nb weight-gradient partials in wpart
+    void reduce(int len, int nb, float* dst)
+    {
+        hipLaunchKernelGGL(reduce_parts, dim3(grid(len), kRedSegs), dim3(256), 0, stream, wpart, nb,
+                           len, wseg);
+        hipLaunchKernelGGL(reduce_segs, dim3(grid(len)), dim3(256), 0, stream, wseg, len, dst);
+    }
 
     void repack()
     {
@@ -952,30 +991,26 @@ struct Net : xamg_cnn {
         // layer 4: dW4 and g3 = W4^T dy masked by a3 > 0
         hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, stream,
                            static_cast<const uint16_t*>(nullptr), dy, a3, N, wpart);
-        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams4)), dim3(256), 0, stream, wpart, nbw,
-                           kParams4, g + kParams1 + 2 * kParams2);
+        reduce(kParams4, nbw, g + kParams1 + 2 * kParams2);
         hipLaunchKernelGGL(dgrad_out1, dim3(grid(n)), dim3(256), 0, stream, dy, w4b, a3, g3, N);
         // layer 3: dW3 from (g3, a2); g2 = dgrad masked by a2 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g3,
                            static_cast<const float*>(nullptr), a2, N, wpart);
         tend(XAMG_CNN_TIMER_WGRAD16);
-        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
-                           kParams2, g + kParams1 + kParams2);
+        reduce(kParams2, nbw, g + kParams1 + kParams2);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
         // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
         hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g2,
                            static_cast<const float*>(nullptr), a1, N, wpart);
         tend(XAMG_CNN_TIMER_WGRAD16);
-        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams2)), dim3(256), 0, stream, wpart, nbw,
-                           kParams2, g + kParams1);
+        reduce(kParams2, nbw, g + kParams1);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
         // layer 1: dW1 from (g1, a0)
         hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, stream, g1,
                            static_cast<const float*>(nullptr), a0, N, wpart);
-        hipLaunchKernelGGL(reduce_parts, dim3(grid(kParams1)), dim3(256), 0, stream, wpart, nbw,
-                           kParams1, g);
+        reduce(kParams1, nbw, g);
     }
 };
 
@@ -1019,6 +1054,7 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
         net->dy = net->alloc<float>(n);
         net->rres = net->alloc<float>(n);
         net->wpart = net->alloc<float>(size_t(kWgBlocks) * kParams2);
+        net->wseg = net->alloc<float>(size_t(kRedSegs) * kParams2);
         net->lpart = net->alloc<double>(2 * 1024);
         net->lacc = net->alloc<double>(2);
         net->scales = net->alloc<double>(64);
@@ -1263,21 +1299,16 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
             if (layer == 1) {
                 hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, net->stream, i16,
                                    static_cast<const float*>(nullptr), m16, N, net->wpart);
-                hipLaunchKernelGGL(reduce_parts, dim3(net->grid(kParams1)), dim3(256), 0,
-                                   net->stream, net->wpart, nbw, kParams1, net->g);
+                net->reduce(kParams1, nbw, net->g);
             } else if (layer == 4) {
                 hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, net->stream,
                                    static_cast<const uint16_t*>(nullptr),
                                    static_cast<const float*>(in), m16, N, net->wpart);
-                hipLaunchKernelGGL(reduce_parts, dim3(net->grid(kParams4)), dim3(256), 0,
-                                   net->stream, net->wpart, nbw, kParams4,
-                                   net->g + kParams1 + 2 * kParams2);
+                net->reduce(kParams4, nbw, net->g + kParams1 + 2 * kParams2);
             } else {
                 hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, net->stream, i16,
                                    static_cast<const float*>(nullptr), m16, N, net->wpart);
-                hipLaunchKernelGGL(reduce_parts, dim3(net->grid(kParams2)), dim3(256), 0,
-                                   net->stream, net->wpart, nbw, kParams2,
-                                   net->g + kParams1 + (layer - 2) * kParams2);
+                net->reduce(kParams2, nbw, net->g + kParams1 + (layer - 2) * kParams2);
             }
         }
         net->chk(hipGetLastError(), "layer");
