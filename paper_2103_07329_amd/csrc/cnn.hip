@@ -403,6 +403,96 @@ __global__ __launch_bounds__(256) void dgrad_out1(const float* __restrict__ dy,
 }
 
 // ---------------------------------------------------------------------------
+// 16 -> 16 weight gradient on MFMA: dW[co][ci][t] = sum_r g[r, co] in[r + off(t), ci]
+// as D_t = G^T A_t over voxels, v_mfma_f32_16x16x32_bf16 with K = 32 voxels
+// (two 16-voxel rows of a tile).  Each block walks the 16 x 4 x 4 tiles
+// blockIdx.x, + gridDim.x, ...; per tile, g (256 voxels) and the input halo
+// (18 x 6 x 6, zero outside the volume) are staged in LDS channel-major, the
+// halo as three copies shifted by dx = -1, 0, 1 so that the 8 voxels a lane
+// feeds are one aligned 16-byte word.  Wave w takes the K chunks 2w and
+// 2w + 1 of every tile (z-slice w) and accumulates all 27 taps in registers;
+// each wave writes its sums as one partial, part[(block * 4 + wave) *
+// kParams2 + (co * 16 + ci) * 27 + t].
+// ---------------------------------------------------------------------------
+constexpr int kWgWaves = 4;
+__global__ __launch_bounds__(256, 2) void wgrad16_mfma(const uint16_t* __restrict__ g,
+                                                       const uint16_t* __restrict__ in, int N,
+                                                       float* __restrict__ part)
+{
+    // aT[((d * 16 + ci) * 36 + hz * 6 + hy) * 16 + lx] = in at halo (lx + d, hy, hz)
+    __shared__ __align__(16) uint16_t aT[3 * kC * kHY * kHZ * kTX];
+    // gT[co * 256 + lv] = g at tile voxel lv = (lz * 4 + ly) * 16 + lx
+    __shared__ __align__(16) uint16_t gT[kC * kTX * kTY * kTZ];
+    const int ntiles = (N / kTX) * (N / kTY) * (N / kTZ);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mn = lane & 15, kq = lane >> 4;
+    f32x4 acc[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int x0, y0, z0;
+        tile_origin(tile, N, x0, y0, z0);
+        __syncthreads();   // the previous tile's operands have been read
+        for (int e = threadIdx.x; e < kHalo * 2; e += blockDim.x) {
+            const int h = e >> 1, half = e & 1;
+            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
+                v = *reinterpret_cast<const uint4*>(in + ((long(gz) * N + gy) * N + gx) * kC +
+                                                    half * 8);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const int lx = hx - d;
+                if (lx < 0 || lx >= kTX) continue;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int ci = half * 8 + c;
+                    aT[((d * kC + ci) * (kHY * kHZ) + hz * kHY + hy) * kTX + lx] =
+                        uint16_t(w[c >> 1] >> ((c & 1) * 16));
+                }
+            }
+        }
+        for (int e = threadIdx.x; e < kTX * kTY * kTZ * 2; e += blockDim.x) {
+            const int lv = e >> 1, half = e & 1;
+            const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
+            const uint4 v = *reinterpret_cast<const uint4*>(
+                g + ((long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx) * kC + half * 8);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                gT[(half * 8 + c) * (kTX * kTY * kTZ) + lv] = uint16_t(w[c >> 1] >> ((c & 1) * 16));
+        }
+        __syncthreads();
+        // K chunk c = 2 * wave + q: z-slice lz = wave, rows 2q and 2q + 1;
+        // K index 8 kq + j -> row 2q + (kq >> 1), x = 8 (kq & 1) + j
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int lz = wave, ly = 2 * q + (kq >> 1), lx0 = 8 * (kq & 1);
+            const uint4 a = *reinterpret_cast<const uint4*>(
+                &gT[mn * (kTX * kTY * kTZ) + (lz * kTY + ly) * kTX + lx0]);
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) {
+                const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                const uint4 b = *reinterpret_cast<const uint4*>(
+                    &aT[(((dx + 1) * kC + mn) * (kHY * kHZ) + (lz + 1 + dz) * kHY + (ly + 1 + dy)) *
+                            kTX + lx0]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                __builtin_bit_cast(bf16x8, b),
+                                                                acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds D[co = 4 kq + j][ci = mn]
+    float* dst = part + (size_t(blockIdx.x) * kWgWaves + wave) * kParams2;
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[((4 * kq + j) * kC + mn) * kTaps + t] = acc[t][j];
+}
+
+// ---------------------------------------------------------------------------
 // weight gradients: dW[co][ci][t] = sum_r g[r, co] in[r + off(t), ci]
 // ---------------------------------------------------------------------------
 // Chunks of kChunk voxels along x (one row); the chunk's g values and the
@@ -863,6 +953,7 @@ struct Net : xamg_cnn {
     double* cpart = nullptr;   // col_sq partials
     int64_t adam_t = 0;
     int conv_blocks = 1;   // resident blocks of conv16_lds (at most one per tile)
+    int wg_blocks = 1;     // resident blocks of wgrad16_mfma (at most one per tile)
     // kernel timer (measurement only): event pairs around the selected launches
     int timer_kind = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -995,17 +1086,15 @@ struct Net : xamg_cnn {
         hipLaunchKernelGGL(dgrad_out1, dim3(grid(n)), dim3(256), 0, stream, dy, w4b, a3, g3, N);
         // layer 3: dW3 from (g3, a2); g2 = dgrad masked by a2 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
-        hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g3,
-                           static_cast<const float*>(nullptr), a2, N, wpart);
+        hipLaunchKernelGGL(wgrad16_mfma, dim3(wg_blocks), dim3(256), 0, stream, g3, a2, N, wpart);
         tend(XAMG_CNN_TIMER_WGRAD16);
-        reduce(kParams2, nbw, g + kParams1 + kParams2);
+        reduce(kParams2, kWgWaves * wg_blocks, g + kParams1 + kParams2);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
         // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
-        hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, stream, g2,
-                           static_cast<const float*>(nullptr), a1, N, wpart);
+        hipLaunchKernelGGL(wgrad16_mfma, dim3(wg_blocks), dim3(256), 0, stream, g2, a1, N, wpart);
         tend(XAMG_CNN_TIMER_WGRAD16);
-        reduce(kParams2, nbw, g + kParams1);
+        reduce(kParams2, kWgWaves * wg_blocks, g + kParams1);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
         // layer 1: dW1 from (g1, a0)
         hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, stream, g1,
@@ -1053,7 +1142,6 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
         net->y = net->alloc<float>(n);
         net->dy = net->alloc<float>(n);
         net->rres = net->alloc<float>(n);
-        net->wpart = net->alloc<float>(size_t(kWgBlocks) * kParams2);
         net->wseg = net->alloc<float>(size_t(kRedSegs) * kParams2);
         net->lpart = net->alloc<double>(2 * 1024);
         net->lacc = net->alloc<double>(2);
@@ -1071,7 +1159,11 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
                 return int(std::min<long>(ntiles, long(std::max(1, per_cu)) * std::max(1, cus)));
             };
             net->conv_blocks = resident(reinterpret_cast<const void*>(conv16_lds));
+            net->wg_blocks = resident(reinterpret_cast<const void*>(wgrad16_mfma));
         }
+        // weight-gradient partials: per block of wgrad_lds, or per wave of wgrad16_mfma
+        net->wpart = net->alloc<float>(
+            size_t(std::max(kWgBlocks, kWgWaves * net->wg_blocks)) * kParams2);
         net->chk(hipMemcpy(net->w, w_init, kParams * sizeof(float), hipMemcpyHostToDevice), "weights");
         std::vector<float> zero(kParams, 0.0f);
         net->chk(hipMemcpy(net->mo, zero.data(), kParams * sizeof(float), hipMemcpyHostToDevice), "adam");
@@ -1306,9 +1398,10 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
                                    static_cast<const float*>(in), m16, N, net->wpart);
                 net->reduce(kParams4, nbw, net->g + kParams1 + 2 * kParams2);
             } else {
-                hipLaunchKernelGGL((wgrad_lds<kC, kC>), dim3(nbw), dim3(256), 0, net->stream, i16,
-                                   static_cast<const float*>(nullptr), m16, N, net->wpart);
-                net->reduce(kParams2, nbw, net->g + kParams1 + (layer - 2) * kParams2);
+                hipLaunchKernelGGL(wgrad16_mfma, dim3(net->wg_blocks), dim3(256), 0, net->stream,
+                                   i16, m16, N, net->wpart);
+                net->reduce(kParams2, kWgWaves * net->wg_blocks,
+                            net->g + kParams1 + (layer - 2) * kParams2);
             }
         }
         net->chk(hipGetLastError(), "layer");
