@@ -413,9 +413,15 @@ __global__ __launch_bounds__(256) void dgrad_out1(const float* __restrict__ dy,
 // 2w + 1 of every tile (z-slice w) and accumulates all 27 taps in registers;
 // each wave writes its sums as one partial, part[(block * 4 + wave) *
 // kParams2 + (co * 16 + ci) * 27 + t].
+// DY32: the 16 -> 1 layer's gradient, dW4[ci][t] = sum_r dy[r] in[r + off(t), ci]
+// with dy in FP32: dy = hi + mid + lo exactly (three BF16 parts, each the
+// rounded remainder of the previous) in rows 0, 1, 2 of G^T (the other rows
+// zero), and dW4 = (D[0] + D[1]) + D[2]; partials of kParams4 values.
 // ---------------------------------------------------------------------------
 constexpr int kWgWaves = 4;
+template <bool DY32>
 __global__ __launch_bounds__(256, 2) void wgrad16_mfma(const uint16_t* __restrict__ g,
+                                                       const float* __restrict__ dy,
                                                        const uint16_t* __restrict__ in, int N,
                                                        float* __restrict__ part)
 {
@@ -429,6 +435,11 @@ __global__ __launch_bounds__(256, 2) void wgrad16_mfma(const uint16_t* __restric
     f32x4 acc[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (DY32) {
+        // rows 3..15 of G^T stay zero
+        for (int e = threadIdx.x; e < (kC - 3) * kTX * kTY * kTZ; e += blockDim.x)
+            gT[3 * kTX * kTY * kTZ + e] = 0;
+    }
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         int x0, y0, z0;
         tile_origin(tile, N, x0, y0, z0);
@@ -454,15 +465,30 @@ __global__ __launch_bounds__(256, 2) void wgrad16_mfma(const uint16_t* __restric
                 }
             }
         }
-        for (int e = threadIdx.x; e < kTX * kTY * kTZ * 2; e += blockDim.x) {
-            const int lv = e >> 1, half = e & 1;
-            const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
-            const uint4 v = *reinterpret_cast<const uint4*>(
-                g + ((long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx) * kC + half * 8);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        if constexpr (DY32) {
+            for (int lv = threadIdx.x; lv < kTX * kTY * kTZ; lv += blockDim.x) {
+                const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
+                const float v = dy[(long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx];
+                const uint16_t hi = f2bf(v);
+                const float r1 = v - bf2f(hi);
+                const uint16_t mid = f2bf(r1);
+                const uint16_t lo = f2bf(r1 - bf2f(mid));
+                gT[lv] = hi;
+                gT[kTX * kTY * kTZ + lv] = mid;
+                gT[2 * kTX * kTY * kTZ + lv] = lo;
+            }
+        } else {
+            for (int e = threadIdx.x; e < kTX * kTY * kTZ * 2; e += blockDim.x) {
+                const int lv = e >> 1, half = e & 1;
+                const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
+                const uint4 v = *reinterpret_cast<const uint4*>(
+                    g + ((long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx) * kC + half * 8);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int c = 0; c < 8; ++c)
-                gT[(half * 8 + c) * (kTX * kTY * kTZ) + lv] = uint16_t(w[c >> 1] >> ((c & 1) * 16));
+                for (int c = 0; c < 8; ++c)
+                    gT[(half * 8 + c) * (kTX * kTY * kTZ) + lv] =
+                        uint16_t(w[c >> 1] >> ((c & 1) * 16));
+            }
         }
         __syncthreads();
         // K chunk c = 2 * wave + q: z-slice lz = wave, rows 2q and 2q + 1;
@@ -485,11 +511,19 @@ __global__ __launch_bounds__(256, 2) void wgrad16_mfma(const uint16_t* __restric
         }
     }
     // lane holds D[co = 4 kq + j][ci = mn]
-    float* dst = part + (size_t(blockIdx.x) * kWgWaves + wave) * kParams2;
+    if constexpr (DY32) {
+        float* dst = part + (size_t(blockIdx.x) * kWgWaves + wave) * kParams4;
+        if (kq == 0) {
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t)
+            for (int t = 0; t < kTaps; ++t) dst[mn * kTaps + t] = (acc[t][0] + acc[t][1]) + acc[t][2];
+        }
+    } else {
+        float* dst = part + (size_t(blockIdx.x) * kWgWaves + wave) * kParams2;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) dst[((4 * kq + j) * kC + mn) * kTaps + t] = acc[t][j];
+        for (int t = 0; t < kTaps; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[((4 * kq + j) * kC + mn) * kTaps + t] = acc[t][j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -954,6 +988,7 @@ struct Net : xamg_cnn {
     int64_t adam_t = 0;
     int conv_blocks = 1;   // resident blocks of conv16_lds (at most one per tile)
     int wg_blocks = 1;     // resident blocks of wgrad16_mfma (at most one per tile)
+    int wg4_blocks = 1;    // the same for its 16 -> 1 form
     // kernel timer (measurement only): event pairs around the selected launches
     int timer_kind = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -1080,19 +1115,21 @@ struct Net : xamg_cnn {
     {
         const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         // layer 4: dW4 and g3 = W4^T dy masked by a3 > 0
-        hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, stream,
+        hipLaunchKernelGGL(wgrad16_mfma<true>, dim3(wg4_blocks), dim3(256), 0, stream,
                            static_cast<const uint16_t*>(nullptr), dy, a3, N, wpart);
-        reduce(kParams4, nbw, g + kParams1 + 2 * kParams2);
+        reduce(kParams4, kWgWaves * wg4_blocks, g + kParams1 + 2 * kParams2);
         hipLaunchKernelGGL(dgrad_out1, dim3(grid(n)), dim3(256), 0, stream, dy, w4b, a3, g3, N);
         // layer 3: dW3 from (g3, a2); g2 = dgrad masked by a2 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
-        hipLaunchKernelGGL(wgrad16_mfma, dim3(wg_blocks), dim3(256), 0, stream, g3, a2, N, wpart);
+        hipLaunchKernelGGL(wgrad16_mfma<false>, dim3(wg_blocks), dim3(256), 0, stream, g3,
+                           static_cast<const float*>(nullptr), a2, N, wpart);
         tend(XAMG_CNN_TIMER_WGRAD16);
         reduce(kParams2, kWgWaves * wg_blocks, g + kParams1 + kParams2);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g3, pack(3), g2, a2, 0, N);
         // layer 2: dW2 from (g2, a1); g1 = dgrad masked by a1 > 0
         tbegin(XAMG_CNN_TIMER_WGRAD16);
-        hipLaunchKernelGGL(wgrad16_mfma, dim3(wg_blocks), dim3(256), 0, stream, g2, a1, N, wpart);
+        hipLaunchKernelGGL(wgrad16_mfma<false>, dim3(wg_blocks), dim3(256), 0, stream, g2,
+                           static_cast<const float*>(nullptr), a1, N, wpart);
         tend(XAMG_CNN_TIMER_WGRAD16);
         reduce(kParams2, kWgWaves * wg_blocks, g + kParams1);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
@@ -1159,11 +1196,13 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
                 return int(std::min<long>(ntiles, long(std::max(1, per_cu)) * std::max(1, cus)));
             };
             net->conv_blocks = resident(reinterpret_cast<const void*>(conv16_lds));
-            net->wg_blocks = resident(reinterpret_cast<const void*>(wgrad16_mfma));
+            net->wg_blocks = resident(reinterpret_cast<const void*>(wgrad16_mfma<false>));
+            net->wg4_blocks = resident(reinterpret_cast<const void*>(wgrad16_mfma<true>));
         }
         // weight-gradient partials: per block of wgrad_lds, or per wave of wgrad16_mfma
         net->wpart = net->alloc<float>(
-            size_t(std::max(kWgBlocks, kWgWaves * net->wg_blocks)) * kParams2);
+            size_t(std::max({kWgBlocks, kWgWaves * net->wg_blocks, kWgWaves * net->wg4_blocks})) *
+            kParams2);
         net->chk(hipMemcpy(net->w, w_init, kParams * sizeof(float), hipMemcpyHostToDevice), "weights");
         std::vector<float> zero(kParams, 0.0f);
         net->chk(hipMemcpy(net->mo, zero.data(), kParams * sizeof(float), hipMemcpyHostToDevice), "adam");
@@ -1393,13 +1432,15 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
                                    static_cast<const float*>(nullptr), m16, N, net->wpart);
                 net->reduce(kParams1, nbw, net->g);
             } else if (layer == 4) {
-                hipLaunchKernelGGL((wgrad_lds<1, kC>), dim3(nbw), dim3(256), 0, net->stream,
-                                   static_cast<const uint16_t*>(nullptr),
+                hipLaunchKernelGGL(wgrad16_mfma<true>, dim3(net->wg4_blocks), dim3(256), 0,
+                                   net->stream, static_cast<const uint16_t*>(nullptr),
                                    static_cast<const float*>(in), m16, N, net->wpart);
-                net->reduce(kParams4, nbw, net->g + kParams1 + 2 * kParams2);
+                net->reduce(kParams4, kWgWaves * net->wg4_blocks,
+                            net->g + kParams1 + 2 * kParams2);
             } else {
-                hipLaunchKernelGGL(wgrad16_mfma, dim3(net->wg_blocks), dim3(256), 0, net->stream,
-                                   i16, m16, N, net->wpart);
+                hipLaunchKernelGGL(wgrad16_mfma<false>, dim3(net->wg_blocks), dim3(256), 0,
+                                   net->stream, i16, static_cast<const float*>(nullptr), m16, N,
+                                   net->wpart);
                 net->reduce(kParams2, kWgWaves * net->wg_blocks,
                             net->g + kParams1 + (layer - 2) * kParams2);
             }
