@@ -15,11 +15,14 @@
 // Kernels: the two 16 -> 16 layers (about 94% of the flops) run on the
 // v_mfma_f32_16x16x32_bf16 matrix instruction from an LDS-staged tile of the
 // input: a wavefront computes rows of 16 consecutive voxels x 16 output
-// channels and takes two taps (32 = 2 x 16 input channels) per instruction; the input gradient of these layers is
-// the same kernel with the weights mirrored and transposed, plus the ReLU
-// mask.  The 1 -> 16 and 16 -> 1 layers are VALU kernels.  Weight
-// gradients are LDS-staged FP32 reductions over voxels with per-block
-// partials summed in block order (deterministic).
+// channels and takes two taps (32 = 2 x 16 input channels) per instruction;
+// the input gradient of these layers is the same kernel with the weights
+// mirrored and transposed, plus the ReLU mask.  The 1 -> 16 and 16 -> 1
+// layers are VALU kernels (BF16 dot products).  The weight gradients of the
+// 16 -> 16 and 16 -> 1 layers run on the same MFMA with voxels as the
+// contracted dimension, that of the 1 -> 16 layer as an LDS-staged VALU
+// reduction; per-block (or per-wave) partials are summed in a fixed order
+// (deterministic).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
