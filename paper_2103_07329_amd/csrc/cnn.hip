@@ -39,7 +39,12 @@ namespace cnn {
 
 constexpr int kTaps = 27;
 constexpr int kC = 16;                 // hidden channels
-constexpr int kPairs = 14;             // tap pairs per MFMA layer (27 -> 28)
+constexpr int kPairs = 14;             // tap pairs of the 1 -> 16 layer (27 -> 28)
+// B fragments of a 16 -> 16 MFMA layer: for each dy, the 9 (dz, dx) taps in
+// 5 pairs (the last padded with zeros), so an A fragment of input row hy
+// serves every output row r with hy - r = dy + 1
+constexpr int kDyPairs = 5;
+constexpr int kMPairs = 3 * kDyPairs;  // 15
 constexpr int kChunk = 16;             // voxels per wgrad chunk (N % 16 == 0)
 constexpr int kParams1 = kC * 1 * kTaps;
 constexpr int kParams2 = kC * kC * kTaps;
@@ -203,9 +208,9 @@ __global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
     const int half = kq & 1, tsel = kq >> 1;
-    uint4 b[kPairs];
+    uint4 b[kMPairs];
 #pragma unroll
-    for (int p = 0; p < kPairs; ++p) b[p] = wpk[p * 64 + lane];
+    for (int p = 0; p < kMPairs; ++p) b[p] = wpk[p * 64 + lane];
     uint4 pre[kStageRegs];
     int t = blockIdx.x;
     if (t >= ntiles) return;
@@ -225,19 +230,24 @@ __global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict_
 #pragma unroll
         for (int r = 0; r < kTY; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
         const uint4* plane = tile + half * kHalo;
+        // input row hy of the halo, (dz, dx) pair k: one A fragment for the
+        // output rows r = hy - 2 .. hy (dy = hy - r - 1)
 #pragma unroll
-        for (int p = 0; p < kPairs; ++p) {
-            const int tap = 2 * p + tsel;
-            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-            // voxel (m, row r, slice wave) shifted by the tap, in halo coordinates
-            const int h0 = ((wave + 1 + dz) * kHY + (1 + dy)) * kHX + (m + 1 + dx);
+        for (int hy = 0; hy < kHY; ++hy) {
 #pragma unroll
-            for (int r = 0; r < kTY; ++r) {
+            for (int k = 0; k < kDyPairs; ++k) {
+                const int c = 2 * k + tsel;   // (dz, dx) index of this lane's tap
+                const int dz = c / 3 - 1, dx = c % 3 - 1;
                 uint4 a = make_uint4(0, 0, 0, 0);
-                if (tap < kTaps) a = plane[h0 + r * kHX];
-                acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                                __builtin_bit_cast(bf16x8, b[p]),
-                                                                acc[r], 0, 0, 0);
+                if (c < 9) a = plane[((wave + 1 + dz) * kHY + hy) * kHX + (m + 1 + dx)];
+#pragma unroll
+                for (int r = 0; r < kTY; ++r) {
+                    const int dyi = hy - r;
+                    if (dyi < 0 || dyi > 2) continue;
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        __builtin_bit_cast(bf16x8, a),
+                        __builtin_bit_cast(bf16x8, b[dyi * kDyPairs + k]), acc[r], 0, 0, 0);
+                }
             }
         }
         // lane holds rows (voxels) 4*kq + j of each 16-voxel row, column (channel) m
@@ -762,7 +772,7 @@ __global__ void pack_weights(const float* __restrict__ w, float* __restrict__ w4
                              uint16_t* __restrict__ pk,
                              uint32_t* __restrict__ w1p, uint32_t* __restrict__ w4p)
 {
-    // pk: 4 packs of kPairs*64*8 BF16: [W2 fwd, W2 dgrad, W3 fwd, W3 dgrad]
+    // pk: 4 packs of kMPairs*64*8 BF16: [W2 fwd, W2 dgrad, W3 fwd, W3 dgrad]
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e < kParams4) {
         // W4 [0][ci][t] -> [ci][t]
@@ -780,12 +790,15 @@ __global__ void pack_weights(const float* __restrict__ w, float* __restrict__ w4
         w4p[e] = uint32_t(f2bf(W4[(2 * k) * kTaps + t])) |
                  (uint32_t(f2bf(W4[(2 * k + 1) * kTaps + t])) << 16);
     }
-    constexpr int per = kPairs * 64 * 8;
+    constexpr int per = kMPairs * 64 * 8;
     if (e >= 4 * per) return;
     const int which = e / per, rem = e % per;
     const int p = rem / (64 * 8), lane = (rem / 8) % 64, j = rem % 8;
     const int kq = lane >> 4, col = lane & 15;
-    const int t = 2 * p + (kq >> 1);
+    // fragment p = dyi * kDyPairs + k: taps (dz, dy = dyi - 1, dx) with
+    // (dz + 1) * 3 + (dx + 1) = 2k + kq / 2 (none for 9)
+    const int dyi = p / kDyPairs, c = 2 * (p % kDyPairs) + (kq >> 1);
+    const int t = c < 9 ? (c / 3) * 9 + dyi * 3 + c % 3 : kTaps;
     const int row = (kq & 1) * 8 + j;   // input channel of this pass
     const float* W = w + kParams1 + (which / 2) * kParams2;   // [co][ci][t]
     float val = 0.0f;
@@ -1050,7 +1063,7 @@ struct Net : xamg_cnn {
     }
     const uint4* pack(int which) const
     {
-        return reinterpret_cast<const uint4*>(pk + size_t(which) * kPairs * 64 * 8);
+        return reinterpret_cast<const uint4*>(pk + size_t(which) * kMPairs * 64 * 8);
     }
     int grid(long count, int per = 256) const { return int((count + per - 1) / per); }
     // dst[0 .. len) += the sum of the nb weight-gradient partials in wpart
@@ -1063,7 +1076,7 @@ struct Net : xamg_cnn {
 
     void repack()
     {
-        const int total = std::max(4 * kPairs * 64 * 8, kParams1);
+        const int total = std::max(4 * kMPairs * 64 * 8, kParams1);
         hipLaunchKernelGGL(pack_weights, dim3(grid(total)), dim3(256), 0, stream, w, w4b, pk,
                            w1p, w4p);
     }
@@ -1171,7 +1184,7 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
         net->w4b = net->alloc<float>(kParams4);
         net->w1p = net->alloc<uint32_t>(kC * kPairs);
         net->w4p = net->alloc<uint32_t>(kTaps * 8);
-        net->pk = net->alloc<uint16_t>(4 * kPairs * 64 * 8);
+        net->pk = net->alloc<uint16_t>(4 * kMPairs * 64 * 8);
         net->a0 = net->alloc<uint16_t>(n);
         net->a1 = net->alloc<uint16_t>(n * kC);
         net->a2 = net->alloc<uint16_t>(n * kC);
