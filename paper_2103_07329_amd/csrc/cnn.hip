@@ -45,12 +45,10 @@ constexpr int kPairs = 14;             // tap pairs of the 1 -> 16 layer (27 -> 
 // serves every output row r with hy - r = dy + 1
 constexpr int kDyPairs = 5;
 constexpr int kMPairs = 3 * kDyPairs;  // 15
-constexpr int kChunk = 16;             // voxels per wgrad chunk (N % 16 == 0)
 constexpr int kParams1 = kC * 1 * kTaps;
 constexpr int kParams2 = kC * kC * kTaps;
 constexpr int kParams4 = 1 * kC * kTaps;
 constexpr int kParams = kParams1 + 2 * kParams2 + kParams4;   // 14688
-constexpr int kWgBlocks = 1024;
 constexpr int kColBlocks = 4096;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -540,82 +538,83 @@ __global__ __launch_bounds__(256, 2) void wgrad16_mfma(const uint16_t* __restric
 }
 
 // ---------------------------------------------------------------------------
-// weight gradients: dW[co][ci][t] = sum_r g[r, co] in[r + off(t), ci]
+// 1 -> 16 weight gradient on MFMA: dW1[co][t] = sum_r g[r, co] in[r + off(t)]
+// (one input channel) as D = G^T S over voxels with the taps as the 16
+// columns of S (two MFMAs per 32 voxels: taps 0-15 and 16-26, the rest
+// zero), S[k][t] = in at voxel k shifted by tap t.  Tiles, g staging and the
+// per-wave partials (kParams1 values each) as in wgrad16_mfma; the input
+// halo is staged as three x-shifted copies of its one channel.
 // ---------------------------------------------------------------------------
-// Chunks of kChunk voxels along x (one row); the chunk's g values and the
-// 3 x 3 rows (x - 1 .. x + kChunk) of inputs are staged in LDS as floats.
-// G: gradient channels (COUT), I: input channels (CIN); thread (o, i) with
-// o < COUT, i < CIN accumulates the 27 taps.  g32: g given as FP32.  With
-// fewer than 256 (o, i) pairs, R = 256 / (COUT CIN) threads share a pair,
-// thread copy c taking the voxels c, c + R, ... of each chunk; the copies'
-// sums are added in copy order at the end.
-template <int COUT, int CIN>
-__global__ __launch_bounds__(256) void wgrad_lds(const uint16_t* __restrict__ g16,
-                                                const float* __restrict__ g32,
-                                                const uint16_t* __restrict__ in, int N,
-                                                float* __restrict__ part)
+__global__ __launch_bounds__(256) void wgrad1_mfma(const uint16_t* __restrict__ g,
+                                                  const uint16_t* __restrict__ in, int N,
+                                                  float* __restrict__ part)
 {
-    constexpr int W = kChunk + 2;
-    constexpr int P = COUT * CIN;
-    constexpr int R = 256 / P;
-    static_assert(R * P == 256 && kChunk % R == 0, "thread copies must tile the block");
-    __shared__ float sg[kChunk * COUT];
-    __shared__ float si[9 * W * CIN];
-    __shared__ float red[R > 1 ? R * P * kTaps : 1];
-    const long n = long(N) * N * N;
-    const long nchunks = n / kChunk;
-    const int tid = threadIdx.x;
-    const int copy = tid / P, oi = tid % P;
-    const int o = oi / CIN, i = oi % CIN;
-    const bool own = true;
-    float acc[kTaps];
+    // aT[(d * 36 + hz * 6 + hy) * 16 + lx] = in at halo (lx + d, hy, hz)
+    __shared__ __align__(16) uint16_t aT[3 * kHY * kHZ * kTX];
+    __shared__ __align__(16) uint16_t gT[kC * kTX * kTY * kTZ];
+    const int ntiles = (N / kTX) * (N / kTY) * (N / kTZ);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int mn = lane & 15, kq = lane >> 4;
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int x0, y0, z0;
+        tile_origin(tile, N, x0, y0, z0);
+        __syncthreads();   // the previous tile's operands have been read
+        for (int h = threadIdx.x; h < kHalo; h += blockDim.x) {
+            const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            uint16_t v = 0;
+            if (gx >= 0 && gx < N && gy >= 0 && gy < N && gz >= 0 && gz < N)
+                v = in[(long(gz) * N + gy) * N + gx];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) acc[t] = 0.0f;
-    for (long c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const long r0 = c * kChunk;
-        const int x0 = int(r0 % N), y = int((r0 / N) % N), z = int(r0 / (long(N) * N));
-        __syncthreads();
-        for (int e = tid; e < kChunk * COUT; e += blockDim.x) {
-            const long idx = r0 * COUT + e;
-            sg[e] = g32 ? g32[idx] : bf2f(g16[idx]);
+            for (int d = 0; d < 3; ++d) {
+                const int lx = hx - d;
+                if (lx >= 0 && lx < kTX) aT[(d * (kHY * kHZ) + hz * kHY + hy) * kTX + lx] = v;
+            }
         }
-        for (int e = tid; e < 9 * W * CIN; e += blockDim.x) {
-            const int ch = e % CIN, xw = (e / CIN) % W, seg = e / (CIN * W);
-            const int yy = y + seg % 3 - 1, zz = z + seg / 3 - 1, xx = x0 + xw - 1;
-            float val = 0.0f;
-            if (xx >= 0 && xx < N && yy >= 0 && yy < N && zz >= 0 && zz < N)
-                val = bf2f(in[(xx + long(N) * yy + long(N) * N * zz) * CIN + ch]);
-            si[e] = val;
-        }
-        __syncthreads();
-        if (own) {
-            for (int k = R == 1 ? 0 : copy; k < kChunk; k += R) {
-                const float gv = sg[k * COUT + o];
+        for (int e = threadIdx.x; e < kTX * kTY * kTZ * 2; e += blockDim.x) {
+            const int lv = e >> 1, half = e & 1;
+            const int lx = lv % kTX, ly = (lv / kTX) % kTY, lz = lv / (kTX * kTY);
+            const uint4 v = *reinterpret_cast<const uint4*>(
+                g + ((long(z0 + lz) * N + (y0 + ly)) * N + x0 + lx) * kC + half * 8);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-                for (int t = 0; t < kTaps; ++t) {
-                    const int dx = t % 3, seg = t / 3;   // seg = (dz+1)*3 + (dy+1)
-                    acc[t] += gv * si[(seg * W + k + dx) * CIN + i];
+            for (int c = 0; c < 8; ++c)
+                gT[(half * 8 + c) * (kTX * kTY * kTZ) + lv] = uint16_t(w[c >> 1] >> ((c & 1) * 16));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int lz = wave, ly = 2 * q + (kq >> 1), lx0 = 8 * (kq & 1);
+            const uint4 a = *reinterpret_cast<const uint4*>(
+                &gT[mn * (kTX * kTY * kTZ) + (lz * kTY + ly) * kTX + lx0]);
+#pragma unroll
+            for (int sidx = 0; sidx < 2; ++sidx) {
+                const int t = mn + 16 * sidx;   // this lane's column of S
+                uint4 b = make_uint4(0, 0, 0, 0);
+                if (t < kTaps) {
+                    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                    b = *reinterpret_cast<const uint4*>(
+                        &aT[((dx + 1) * (kHY * kHZ) + (lz + 1 + dz) * kHY + (ly + 1 + dy)) * kTX + lx0]);
                 }
+                acc[sidx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                                   __builtin_bit_cast(bf16x8, b),
+                                                                   acc[sidx], 0, 0, 0);
             }
         }
     }
-    float* dst = part + size_t(blockIdx.x) * (P * kTaps);
-    if constexpr (R == 1) {
+    // lane holds D[co = 4 kq + j][t = mn + 16 s]
+    float* dst = part + (size_t(blockIdx.x) * kWgWaves + wave) * kParams1;
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) dst[oi * kTaps + t] = acc[t];
-    } else {
+    for (int sidx = 0; sidx < 2; ++sidx) {
+        const int t = mn + 16 * sidx;
+        if (t < kTaps) {
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) red[(copy * P + oi) * kTaps + t] = acc[t];
-        __syncthreads();
-        for (int e = tid; e < P * kTaps; e += blockDim.x) {
-            float sum = 0.0f;
-            for (int c = 0; c < R; ++c) sum += red[c * P * kTaps + e];
-            dst[e] = sum;
+            for (int j = 0; j < 4; ++j) dst[(4 * kq + j) * kTaps + t] = acc[sidx][j];
         }
     }
 }
 
-// sum the partials of nb blocks in block order, add into dst (FP32)
 // dst[e] += sum over b of part[b len + e], in two fixed-order stages: the
 // kRedSegs segments of consecutive partials (blockIdx.y = segment) into
 // seg[s len + e], then the segments in order
@@ -1005,6 +1004,7 @@ struct Net : xamg_cnn {
     int conv_blocks = 1;   // resident blocks of conv16_lds (at most one per tile)
     int wg_blocks = 1;     // resident blocks of wgrad16_mfma (at most one per tile)
     int wg4_blocks = 1;    // the same for its 16 -> 1 form
+    int wg1_blocks = 1;    // resident blocks of wgrad1_mfma (at most one per tile)
     // kernel timer (measurement only): event pairs around the selected launches
     int timer_kind = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -1129,7 +1129,6 @@ struct Net : xamg_cnn {
     // backward of one sample (dy set); weight gradients accumulate into g
     void backward()
     {
-        const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         // layer 4: dW4 and g3 = W4^T dy masked by a3 > 0
         hipLaunchKernelGGL(wgrad16_mfma<true>, dim3(wg4_blocks), dim3(256), 0, stream,
                            static_cast<const uint16_t*>(nullptr), dy, a3, N, wpart);
@@ -1150,9 +1149,8 @@ struct Net : xamg_cnn {
         reduce(kParams2, kWgWaves * wg_blocks, g + kParams1);
         hipLaunchKernelGGL(conv16_lds, dim3(conv_blocks), dim3(256), 0, stream, g2, pack(1), g1, a1, 0, N);
         // layer 1: dW1 from (g1, a0)
-        hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, stream, g1,
-                           static_cast<const float*>(nullptr), a0, N, wpart);
-        reduce(kParams1, nbw, g);
+        hipLaunchKernelGGL(wgrad1_mfma, dim3(wg1_blocks), dim3(256), 0, stream, g1, a0, N, wpart);
+        reduce(kParams1, kWgWaves * wg1_blocks, g);
     }
 };
 
@@ -1214,10 +1212,11 @@ int xamg_cnn_create(int32_t N, const float* w_init, void* stream, xamg_cnn_t** o
             net->conv_blocks = resident(reinterpret_cast<const void*>(conv16_lds));
             net->wg_blocks = resident(reinterpret_cast<const void*>(wgrad16_mfma<false>));
             net->wg4_blocks = resident(reinterpret_cast<const void*>(wgrad16_mfma<true>));
+            net->wg1_blocks = resident(reinterpret_cast<const void*>(wgrad1_mfma));
         }
-        // weight-gradient partials: per block of wgrad_lds, or per wave of wgrad16_mfma
+        // weight-gradient partials: one per wave of the weight-gradient kernels
         net->wpart = net->alloc<float>(
-            size_t(std::max({kWgBlocks, kWgWaves * net->wg_blocks, kWgWaves * net->wg4_blocks})) *
+            size_t(kWgWaves) * std::max({net->wg_blocks, net->wg4_blocks, net->wg1_blocks}) *
             kParams2);
         net->chk(hipMemcpy(net->w, w_init, kParams * sizeof(float), hipMemcpyHostToDevice), "weights");
         std::vector<float> zero(kParams, 0.0f);
@@ -1414,7 +1413,6 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
     try {
         const long n = net->n;
         const int N = net->N;
-        const int nbw = int(std::min<long>(kWgBlocks, n / kChunk));
         const uint16_t* i16 = static_cast<const uint16_t*>(in);
         const uint16_t* m16 = static_cast<const uint16_t*>(mask);
         if (mode == 0) {
@@ -1444,9 +1442,9 @@ int xamg_cnn_layer(xamg_cnn_t* h, int32_t layer, int32_t mode, const void* in, c
             if (!mask) return xamg::fail(XAMG_EINVAL, "layer input required");
             net->chk(hipMemsetAsync(net->g, 0, kParams * sizeof(float), net->stream), "grad zero");
             if (layer == 1) {
-                hipLaunchKernelGGL((wgrad_lds<kC, 1>), dim3(nbw), dim3(256), 0, net->stream, i16,
-                                   static_cast<const float*>(nullptr), m16, N, net->wpart);
-                net->reduce(kParams1, nbw, net->g);
+                hipLaunchKernelGGL(wgrad1_mfma, dim3(net->wg1_blocks), dim3(256), 0, net->stream, i16,
+                                   m16, N, net->wpart);
+                net->reduce(kParams1, kWgWaves * net->wg1_blocks, net->g);
             } else if (layer == 4) {
                 hipLaunchKernelGGL(wgrad16_mfma<true>, dim3(net->wg4_blocks), dim3(256), 0,
                                    net->stream, static_cast<const uint16_t*>(nullptr),
