@@ -672,16 +672,32 @@ __global__ __launch_bounds__(256) void loss_parts(const float* __restrict__ y,
 }
 
 // out[0] += e2 / tt / S (the sample's loss); out[1] = 2 / (tt S) (gradient scale)
-__global__ void loss_finish(const double* __restrict__ part, int nb, int S, double* out)
+// one block of 256 threads: thread t adds partials t, t + 256, ... in order,
+// then a fixed halving tree (the same order every run)
+__global__ __launch_bounds__(256) void loss_finish(const double* __restrict__ part, int nb, int S,
+                                                   double* out)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double sa[256], sb[256];
+    const int t = threadIdx.x;
     double a = 0.0, b = 0.0;
-    for (int k = 0; k < nb; ++k) {
+    for (int k = t; k < nb; k += 256) {
         a += part[2 * k];
         b += part[2 * k + 1];
     }
-    out[0] += a / b / S;
-    out[1] = 2.0 / (b * S);
+    sa[t] = a;
+    sb[t] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sa[t] += sa[t + w];
+            sb[t] += sb[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] += sa[0] / sb[0] / S;
+        out[1] = 2.0 / (sb[0] * S);
+    }
 }
 
 __global__ void loss_grad(const float* __restrict__ y, const float* __restrict__ t, long n,
@@ -1288,7 +1304,7 @@ int xamg_cnn_pass(xamg_cnn_t* h, const float* x, const float* t, int32_t S, floa
                 const float* ts = t + size_t(s) * n;
                 hipLaunchKernelGGL(loss_parts, dim3(1024), dim3(256), 0, net->stream, net->y, ts, n,
                                    net->lpart);
-                hipLaunchKernelGGL(loss_finish, dim3(1), dim3(64), 0, net->stream, net->lpart, 1024, S,
+                hipLaunchKernelGGL(loss_finish, dim3(1), dim3(256), 0, net->stream, net->lpart, 1024, S,
                                    net->lacc);
                 hipLaunchKernelGGL(loss_grad, dim3(1024), dim3(256), 0, net->stream, net->y, ts, n,
                                    net->lacc, net->dy);
@@ -1336,7 +1352,7 @@ int xamg_cnn_pass_residual(xamg_cnn_t* h, xamg_handle_t* solver, const float* x,
             net->forward();
             hipLaunchKernelGGL(res_parts, dim3(1024), dim3(256), 0, net->stream, xs, net->y, A.rp,
                                A.ci, av, n, net->rres, net->lpart);
-            hipLaunchKernelGGL(loss_finish, dim3(1), dim3(64), 0, net->stream, net->lpart, 1024, S,
+            hipLaunchKernelGGL(loss_finish, dim3(1), dim3(256), 0, net->stream, net->lpart, 1024, S,
                                net->lacc);
             hipLaunchKernelGGL(res_grad, dim3(1024), dim3(256), 0, net->stream, net->rres, A.rp, A.ci,
                                av, n, net->lacc, net->dy);
