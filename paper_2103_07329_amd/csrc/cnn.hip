@@ -200,8 +200,9 @@ __global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict_
                                                   int N)
 {
     __shared__ uint4 tile[kHalo * 2];
-    static_assert(kTX * kTY * kTZ * kOutPitch * 4 <= int(sizeof(uint4)) * kHalo * 2,
-                  "output staging must fit in the input tile");
+    // output staging, apart from the input tile: a tile needs two barriers,
+    // one after its halo is stored and one after its results are staged
+    __shared__ __align__(16) float stage[kTX * kTY * kTZ * kOutPitch];
     const int ntiles = (N / kTX) * (N / kTY) * (N / kTZ);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
@@ -216,7 +217,8 @@ __global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict_
     tile_origin(t, N, x0, y0, z0);
     load_halo(in, x0, y0, z0, N, pre);
     for (; t < ntiles; t += gridDim.x) {
-        __syncthreads();   // the previous tile's output staging has been read
+        // every wave has passed the previous tile's second barrier, so its
+        // reads of the halo are done
         store_halo(tile, pre);
         __syncthreads();
         const int cx = x0, cy = y0, cz = z0;
@@ -248,9 +250,9 @@ __global__ __launch_bounds__(256, 3) void conv16_lds(const uint16_t* __restrict_
                 }
             }
         }
-        // lane holds rows (voxels) 4*kq + j of each 16-voxel row, column (channel) m
-        __syncthreads();
-        float* stage = reinterpret_cast<float*>(tile);
+        // lane holds rows (voxels) 4*kq + j of each 16-voxel row, column (channel) m;
+        // every wave has passed this tile's first barrier, so the previous
+        // tile's staged results have been read
 #pragma unroll
         for (int r = 0; r < kTY; ++r)
 #pragma unroll
