@@ -893,30 +893,38 @@ __global__ void f32_to_bf16(const float* __restrict__ x, long n, uint16_t* __res
 
 // Per-column sums of squares over a contiguous row range per block:
 // part[(block * m + j) * 2] = sum b_rj^2 and, with a matrix, part[... + 1] =
-// sum (b - A x)_rj^2.  Thread t < g m (g = 256 / m) takes column t % m and
-// rows q, q + g, ... of the range (q = t / m), so loads stay contiguous.
+// sum (b - A x)_rj^2.  With CW adjacent columns a thread (mg = m / CW column
+// groups), thread t < g mg (g = 256 / mg) takes column group t % mg and rows
+// q, q + g, ... of the range (q = t / mg), so loads stay contiguous; the
+// threads' sums of a column are added in q order.
 // With rows stored at one length (rowlen > 0: row r's entries at r rowlen,
 // padded with exact zeros) four rows are taken at a time with their loads
 // interleaved; every sum keeps the same terms in the same order.
+template <int CW>
 __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
                                              const double* __restrict__ X,
                                              const int* __restrict__ rp, const int* __restrict__ ci,
                                              const double* __restrict__ v, int m, long n,
                                              double* __restrict__ part, int rowlen)
 {
-    __shared__ double s0[256], s1[256];
-    const int t = threadIdx.x, g = 256 / m;
-    const int j = t % m, q = t / m;
+    typedef double vec __attribute__((ext_vector_type(CW)));
+    __shared__ double s0[256 * CW], s1[256 * CW];
+    const int mg = m / CW;   // column groups of CW adjacent columns
+    const int t = threadIdx.x, g = 256 / mg;
+    const int jg = t % mg, q = t / mg;
     const long per = (n + gridDim.x - 1) / gridDim.x;
     const long r0 = long(blockIdx.x) * per, r1 = std::min(n, r0 + per);
-    double bb = 0.0, rr = 0.0;
+    vec bb = vec(0.0), rr = vec(0.0);
+    auto ld = [&](const double* p, long row) {
+        return *reinterpret_cast<const vec*>(p + row * m + jg * CW);
+    };
     if (q < g && rp && rowlen > 0) {
         for (long r = r0 + q; r < r1; r += 4L * g) {
-            double bv[4], sv[4];
+            vec bv[4], sv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const long ru = r + long(u) * g;
-                bv[u] = ru < r1 ? B[ru * m + j] : 0.0;
+                bv[u] = ru < r1 ? ld(B, ru) : vec(0.0);
                 sv[u] = bv[u];
             }
             for (int k = 0; k < rowlen; ++k) {
@@ -925,7 +933,7 @@ __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
                     const long ru = r + long(u) * g;
                     if (ru < r1) {
                         const long e = ru * rowlen + k;
-                        sv[u] -= v[e] * X[long(ci[e]) * m + j];
+                        sv[u] -= v[e] * ld(X, ci[e]);
                     }
                 }
             }
@@ -938,17 +946,20 @@ __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
         }
     } else if (q < g) {
         for (long r = r0 + q; r < r1; r += g) {
-            const double b = B[r * m + j];
+            const vec b = ld(B, r);
             bb += b * b;
             if (rp) {
-                double s = b;
-                for (int k = rp[r]; k < rp[r + 1]; ++k) s -= v[k] * X[long(ci[k]) * m + j];
-                rr += s * s;
+                vec sv = b;
+                for (int k = rp[r]; k < rp[r + 1]; ++k) sv -= v[k] * ld(X, ci[k]);
+                rr += sv * sv;
             }
         }
     }
-    s0[t] = bb;
-    s1[t] = rr;
+#pragma unroll
+    for (int c = 0; c < CW; ++c) {
+        s0[t * CW + c] = bb[c];
+        s1[t * CW + c] = rr[c];
+    }
     __syncthreads();
     if (t < m) {
         double a = 0.0, c = 0.0;
@@ -959,6 +970,16 @@ __global__ __launch_bounds__(256) void col_sq(const double* __restrict__ B,
         part[(size_t(blockIdx.x) * m + t) * 2] = a;
         part[(size_t(blockIdx.x) * m + t) * 2 + 1] = c;
     }
+}
+
+// col_sq with two adjacent columns a thread (16-byte loads) when m is even
+inline void launch_col_sq(int nb, hipStream_t st, const double* B, const double* X, const int* rp,
+                          const int* ci, const double* v, int m, long n, double* part, int rowlen)
+{
+    if (m % 2 == 0)
+        hipLaunchKernelGGL(col_sq<2>, dim3(nb), dim3(256), 0, st, B, X, rp, ci, v, m, n, part, rowlen);
+    else
+        hipLaunchKernelGGL(col_sq<1>, dim3(nb), dim3(256), 0, st, B, X, rp, ci, v, m, n, part, rowlen);
 }
 
 // sums[2j + k] = the sum over blocks of part[(b m + j) 2 + k], one block per
@@ -1500,10 +1521,7 @@ int xamg_warmstart(xamg_cnn_t* h, xamg_handle_t* solver, const double* B, double
     try {
         const long n = net->n;
         const int nbc = int(std::min<long>(kColBlocks, std::max<long>(1, n / 64)));
-        hipLaunchKernelGGL(col_sq, dim3(nbc), dim3(256), 0, net->stream, B,
-                           static_cast<const double*>(nullptr), static_cast<const int*>(nullptr),
-                           static_cast<const int*>(nullptr), static_cast<const double*>(nullptr),
-                           m, n, net->cpart, 0);
+        launch_col_sq(nbc, net->stream, B, nullptr, nullptr, nullptr, nullptr, m, n, net->cpart, 0);
         hipLaunchKernelGGL(col_sq_finish, dim3(m), dim3(256), 0, net->stream, net->cpart, nbc, m, n,
                            net->sums, net->scales);
         net->ensure_cols(m);
@@ -1518,8 +1536,8 @@ int xamg_warmstart(xamg_cnn_t* h, xamg_handle_t* solver, const double* B, double
         if (solver) {
             // fallback: ||b_j - A x0_j|| >= ||b_j||  =>  x0_j = 0
             const xamg::DCsr& A = static_cast<xamg::Handle*>(solver)->lev[0].A64;
-            hipLaunchKernelGGL(col_sq, dim3(nbc), dim3(256), 0, net->stream, B, X0, A.rp, A.ci,
-                               static_cast<const double*>(A.v), m, n, net->cpart, A.rowlen);
+            launch_col_sq(nbc, net->stream, B, X0, A.rp, A.ci, static_cast<const double*>(A.v), m, n,
+                          net->cpart, A.rowlen);
             hipLaunchKernelGGL(col_sq_finish, dim3(m), dim3(256), 0, net->stream, net->cpart, nbc, m,
                                n, net->sums, static_cast<double*>(nullptr));
             double sums[2 * 64];
